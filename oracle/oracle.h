@@ -1,0 +1,139 @@
+/*
+ * FP64 CPU oracle for the differentiable shooting-and-bouncing-rays (SBR)
+ * mmWave radar simulator of "Differentiable Radio Frequency Ray Tracing for
+ * Millimeter-Wave Sensing" (DiffSBR, arXiv 2311.13182).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain, obviously
+ * correct definition that the HIP path is checked against.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  It shares no code, header, table or helper with the HIP library.
+ *
+ * Everything is double precision.  Brute-force O(rays x triangles) closest
+ * hit, direct per-path summation of the IF signal, naive O(N^2) DFTs.
+ *
+ * Units: metres, seconds, hertz.  Radar frame: x = array axis, y = up,
+ * z = boresight.  Virtual antenna index v = t * n_rx + m.
+ *
+ * Parity status (what pins each function; the tests under tests/ hold them):
+ *   orc_ray            closed-form solid angle of the grid, boresight symmetry
+ *   orc_trace          independent NumPy brute force, trihedral and plate
+ *                      closed forms, energy invariant
+ *   orc_paths          plate normal incidence (tau = 2R/c), trihedral
+ *                      point-reflection identity, Fresnel special cases
+ *   orc_fresnel        normal incidence, grazing, passivity, conductor limit
+ *   orc_synth          single-path geometric sequence and Dirichlet kernel,
+ *                      range / Doppler / angle peak bins
+ *   orc_synth_adjoint  central differences of orc_synth
+ *   orc_radar_cube     numpy.fft, dot-product (adjoint) identity
+ *   orc_cfar           injected targets, brute force on tiny maps
+ */
+#ifndef SBR_ORACLE_H
+#define SBR_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAXK 8
+
+typedef struct {
+    int nv, nf;
+    const double *verts;     /* [nv][3] world frame, metres                    */
+    const int *faces;        /* [nf][3] vertex indices                          */
+    const int *mat_id;       /* [nf] material index, or NULL: material 0        */
+    int n_mats;              /* 0: every face is a perfect electric conductor   */
+    const int *mat_mode;     /* [n_mats] 0 conductor (r = -1), 1 TE r_s, 2 TM r_p */
+    const double *mat_eps_r; /* [n_mats] relative permittivity                  */
+    const double *mat_sigma; /* [n_mats] conductivity, S/m                      */
+} orc_mesh;
+
+typedef struct {
+    double origin[3];   /* array centre, world frame                          */
+    double rot[9];      /* radar -> world rotation, row-major                  */
+    int n_tx, n_rx;
+    double tx[8][3];    /* radar frame                                         */
+    double rx[16][3];   /* radar frame                                         */
+    double vel[3];      /* rigid scene velocity, world frame, m/s              */
+} orc_radar;
+
+typedef struct {
+    double fc;          /* carrier, Hz                                         */
+    double slope;       /* mu = B / T, Hz/s                                    */
+    double fs;          /* ADC rate, Hz                                        */
+    double t_chirp;     /* chirp repetition period, s                         */
+    int n_samples, n_chirps;
+} orc_chirp;
+
+typedef struct {
+    int nx, ny;
+    double tan_hx, tan_hy;   /* half-width of the tangent-plane grid           */
+    int max_bounces;
+    double t_min;            /* minimum accepted hit distance, metres          */
+} orc_grid;
+
+/* hit flags, one byte per (bounce, ray) */
+#define ORC_F_EDGE     1   /* hit point within delta_k of an edge line          */
+#define ORC_F_TIE      2   /* second-closest candidate within delta_k            */
+#define ORC_F_GRAZE    4   /* |d . n| < 1e-6                                     */
+#define ORC_F_TMIN     8   /* t < 2 t_min                                        */
+#define ORC_F_PARENT  16   /* an earlier bounce of the same ray is flagged       */
+
+/* Ray r = iy * nx + ix of the grid: origin, unit direction, solid-angle weight. */
+void orc_ray(const orc_radar *rd, const orc_grid *g, int r,
+             double o[3], double d[3], double *domega);
+
+/* Brute-force closest hit for every bounce of the listed rays.
+ * rays: [n] ray indices (NULL = all rays 0..nx*ny-1, then n must be nx*ny).
+ * Outputs are [K][n] with K = g->max_bounces: tri (-1 = none), t, barycentric
+ * weights of vertices 1 and 2, flags.  Any output pointer may be NULL except tri.
+ * Returns the number of closest-hit queries issued (a ray's final miss counts). */
+long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g,
+                    const int *rays, int n, int *tri, double *t, double *b1,
+                    double *b2, unsigned char *flags);
+
+/* Reflection coefficient of material `mi` at incidence cosine cos_i (in [0,1]).
+ * out[0] = real part, out[1] = imaginary part. */
+void orc_fresnel(const orc_mesh *m, int mi, double fc, double cos_i, double out[2]);
+
+/* Path quantities from frozen hit triangle IDs (FP64 plane intersections).
+ * One path per (ray, bounce) with a hit, in ray-major then bounce order;
+ * with drop_flagged != 0 a path whose flag byte is non-zero is skipped.
+ * Outputs sized for K*n paths: path_ray [P] (index into `rays`), path_k [P]
+ * (1-based bounce), amp [P][2], tau [P][V] (seconds), taudot [P] (s/s).
+ * Returns P. */
+int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g,
+              const orc_chirp *ch, const int *rays, int n, const int *tri,
+              const unsigned char *flags, int drop_flagged,
+              int *path_ray, int *path_k, double *amp, double *tau, double *taudot);
+
+/* IF signal by direct summation over paths.  rows: [n_rows] indices v*C + c
+ * (NULL = every row, n_rows = V*C).  out: [n_rows][S][2]. */
+void orc_synth(int P, const double *amp, const double *tau, const double *taudot,
+               int V, const orc_chirp *ch, const int *rows, int n_rows, double *out);
+
+/* Adjoint of orc_synth.  G = dL/dRe S + i dL/dIm S, [V][C][S][2].
+ * amp_bar [P][2] (dL/dRe A + i dL/dIm A), tau_bar [P][V], taudot_bar [P]. */
+void orc_synth_adjoint(int P, const double *amp, const double *tau,
+                       const double *taudot, int V, const orc_chirp *ch,
+                       const double *G, double *amp_bar, double *tau_bar,
+                       double *taudot_bar);
+
+/* Range -> Doppler -> angle DFT cube.  dir 0: in [V][C][S][2] -> out [Na][C][S][2].
+ * dir 1 (conjugate transpose): in [Na][C][S][2] -> out [V][C][S][2].
+ * window 0 rectangular, 1 symmetric Hann on the range and Doppler axes. */
+void orc_radar_cube(const double *in, int V, int C, int S, int Na, int window,
+                    int dir, double *out);
+
+/* Cell-averaging CFAR on P[d][r] = sum_a |X[a][d][r]|^2 (X is [Na][C][S][2]).
+ * Doppler axis circular, range axis truncated; alpha = N_t (pfa^(-1/N_t) - 1).
+ * Per cell of the [C][S] map: status bit 0 = detected (P > alpha * mean),
+ * bit 1 = borderline (|P - alpha*mean| <= 1e-6 alpha*mean); argmax over a
+ * (lowest index on ties); power P.  Any output may be NULL.
+ * Returns the number of detections. */
+int orc_cfar(const double *cube, int Na, int C, int S, int guard, int train,
+             double pfa, unsigned char *status, int *argmax, double *power);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,407 @@
+"""Pins of the FP64 oracle against closed forms, invariants, library routines
+and an independent brute force.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2311_13182_amd import scenes as S
+
+C0 = 299792458.0
+
+
+# ----------------------------------------------------------------------------- rays
+def test_solid_angle_of_grid_converges_to_pyramid(orc):
+    # exact solid angle of a rectangular pyramid with half-angles a, b
+    a = b = math.radians(15.0)
+    exact = 4.0 * math.asin(math.sin(a) * math.sin(b))
+    assert abs(exact - 0.26815) < 1e-5
+    errs = []
+    for n in (16, 32, 64):
+        sc = S.trihedral_plate().with_grid(nx=n, ny=n)
+        tot = sum(orc.ray(sc, r)[2] for r in range(n * n))
+        errs.append(abs(tot - exact) / exact)
+    assert errs[2] < 1e-3
+    # midpoint rule: error falls ~4x per halving of the cell
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_grid_symmetry_and_boresight(orc):
+    sc = S.trihedral_plate().with_grid(nx=65, ny=65)
+    o, d, _ = orc.ray(sc, 32 * 65 + 32)
+    assert np.array_equal(d, [0.0, 0.0, 1.0]) and np.array_equal(o, [0.0, 0.0, 0.0])
+    sc = S.trihedral_plate().with_grid(nx=64, ny=64)
+    for r in (0, 5, 100, 2000):
+        ix, iy = r % 64, r // 64
+        _, d1, w1 = orc.ray(sc, r)
+        _, d2, w2 = orc.ray(sc, (63 - iy) * 64 + (63 - ix))
+        assert np.allclose(d1[:2], -d2[:2], atol=1e-15) and abs(d1[2] - d2[2]) < 1e-15 and w1 == w2
+        assert abs(np.linalg.norm(d1) - 1.0) < 1e-15
+
+
+# ----------------------------------------------------------------------- closest hit
+def _np_closest_hits(verts, faces, o, d, K, t_min):
+    """Independent brute force: plane intersection + edge-function inside
+    test (different algorithm from the oracle's Moller-Trumbore)."""
+    A, B, Cc = verts[faces[:, 0]], verts[faces[:, 1]], verts[faces[:, 2]]
+    N = np.cross(B - A, Cc - A)
+    out = []
+    prev = -1
+    o = o.copy()
+    d = d.copy()
+    for _ in range(K):
+        den = N @ d
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = np.einsum("ij,ij->i", N, A - o) / den
+        x = o + t[:, None] * d
+        s0 = np.einsum("ij,ij->i", np.cross(B - A, x - A), N)
+        s1 = np.einsum("ij,ij->i", np.cross(Cc - B, x - B), N)
+        s2 = np.einsum("ij,ij->i", np.cross(A - Cc, x - Cc), N)
+        ok = (den != 0) & (t > t_min) & (s0 >= 0) & (s1 >= 0) & (s2 >= 0)
+        if prev >= 0:
+            ok[prev] = False
+        if not ok.any():
+            out.append((-1, 0.0))
+            break
+        idx = np.flatnonzero(ok)
+        best = idx[np.lexsort((idx, t[idx]))[0]]
+        out.append((int(best), float(t[best])))
+        n = N[best] / np.linalg.norm(N[best])
+        o = x[best]
+        d = d - 2.0 * (d @ n) * n
+        prev = best
+    return out
+
+
+@pytest.mark.parametrize("which", ["trihedral_plate", "icosphere_l2"])
+def test_trace_matches_independent_bruteforce(orc, which):
+    if which == "trihedral_plate":
+        sc = S.trihedral_plate().with_grid(nx=40, ny=40)
+    else:
+        sc = S.icosphere_scene(level=2, n_rays=24, n_chirps=1, jitter=2e-3)
+    tr = orc.trace(sc)
+    v = sc.verts.astype(np.float64)
+    f = sc.faces.astype(np.int64)
+    K = sc.grid.max_bounces
+    checked = 0
+    for r in range(sc.grid.n_rays):
+        o, d, _ = orc.ray(sc, r)
+        ref = _np_closest_hits(v, f, o, d, K, sc.grid.t_min)
+        for k, (tri, t) in enumerate(ref):
+            if tr["flags"][k, r]:
+                break
+            assert tr["tri"][k, r] == tri, (r, k)
+            if tri >= 0:
+                assert abs(tr["t"][k, r] - t) <= 1e-12 * max(1.0, t)
+                checked += 1
+            else:
+                break
+    assert checked > 100
+
+
+def _hit_points(sc, tr, k, r):
+    f = sc.faces[tr["tri"][k, r]]
+    a, b, c = (sc.verts[f[i]].astype(np.float64) for i in range(3))
+    return a + tr["b1"][k, r] * (b - a) + tr["b2"][k, r] * (c - a)
+
+
+def test_trihedral_returns_antiparallel_and_point_reflection(orc):
+    # axis-aligned corner reflector with float32-exact vertices (so its faces
+    # are exactly orthogonal), opening toward the radar along -(1,1,1); a
+    # large catcher plane behind the radar makes the exit direction of a
+    # triple-bounce ray observable as the 4th segment
+    a0, L = 0.578125, 0.125
+    A = np.array([a0, a0, a0])
+    tv = np.array([A, A - [0, L, 0], A - [0, 0, L],      # face x = a0
+                   A, A - [L, 0, 0], A - [0, 0, L],      # face y = a0
+                   A, A - [L, 0, 0], A - [0, L, 0]])     # face z = a0
+    tf = np.arange(9).reshape(3, 3)
+    axis = np.ones(3) / math.sqrt(3.0)
+    rot = S._rot_from_to(np.array([0.0, 0.0, 1.0]), axis)
+    u1, u2 = rot[:, 0], rot[:, 1]
+    c = -0.5 * axis
+    cv = np.array([c - 5 * u1 - 5 * u2, c + 5 * u1 - 5 * u2, c + 5 * u1 + 5 * u2, c - 5 * u1 + 5 * u2])
+    v, f = S._concat([(tv, tf), (cv, np.array([[0, 1, 2], [0, 2, 3]]))])
+    radar = S.Radar(np.zeros(3), rot, np.zeros((1, 3)), np.zeros((1, 3)))
+    th = math.tan(math.radians(5.5))
+    sc = S.Scene("tri_catch", v.astype(np.float32), f.astype(np.int32), radar,
+                 S.Chirp(), S.Grid(64, 64, th, th, 4))
+    assert np.array_equal(sc.verts[:9].astype(np.float64), tv)
+    tr = orc.trace(sc)
+    n3 = 0
+    for r in range(sc.grid.n_rays):
+        t = tr["tri"][:, r]
+        if not ((t[:3] >= 0) & (t[:3] < 3)).all() or t[3] < 3 or tr["flags"][:3, r].any():
+            continue
+        o, d_in, _ = orc.ray(sc, r)
+        x = [o] + [_hit_points(sc, tr, k, r) for k in range(4)]
+        d_out = (x[4] - x[3]) / np.linalg.norm(x[4] - x[3])
+        assert np.abs(d_out + d_in).max() < 1e-12
+        L3 = sum(np.linalg.norm(x[j + 1] - x[j]) for j in range(3))
+        lhs = L3 + (x[3] - o) @ d_in
+        assert abs(lhs - 2.0 * (A - o) @ d_in) < 1e-12
+        n3 += 1
+    assert n3 > 200
+
+
+def test_plate_normal_incidence(orc):
+    v, f = S.plate(0.4, 1.5)
+    sc = S.Scene("plate", v.astype(np.float32), f.astype(np.int32),
+                 S.Radar(np.zeros(3), np.eye(3), np.zeros((1, 3)), np.zeros((1, 3))),
+                 S.Chirp(), S.Grid(65, 65, 0.05, 0.05, 2))
+    rc = 32 * 65 + 32
+    tr = orc.trace(sc, rays=[rc])
+    assert tr["tri"][0, 0] >= 0 and tr["t"][0, 0] == 1.5
+    assert tr["tri"][1, 0] == -1         # reflected straight back, nothing behind the radar
+    # the centre ray lands on the diagonal shared by the plate's two triangles
+    assert tr["flags"][0, 0] == orc.F_EDGE | orc.F_TIE
+    assert len(orc.paths(sc, tr["tri"], tr["flags"], rays=[rc])["amp"]) == 0
+    p = orc.paths(sc, tr["tri"], tr["flags"], rays=[rc], drop=False)
+    assert len(p["amp"]) == 1
+    assert abs(p["tau"][0, 0] - 3.0 / C0) <= 1e-15 * 3.0 / C0 * 4
+    # conductor: I^s = -d_omega * cos / (L R) with cos = 1, L = R = 1.5
+    _, _, dw = orc.ray(sc, rc)
+    assert abs(p["amp"][0] - (-dw / 2.25)) < 1e-15
+
+
+def test_frozen_fd_of_plate_translation(orc):
+    # translating the plate by delta along its normal moves the centre path by
+    # 2 delta: d tau / d delta = 2 / c exactly
+    v, f = S.plate(0.4, 1.5)
+    sc = S.Scene("plate", v.astype(np.float32), f.astype(np.int32),
+                 S.Radar(np.zeros(3), np.eye(3), np.zeros((1, 3)), np.zeros((1, 3))),
+                 S.Chirp(), S.Grid(65, 65, 0.05, 0.05, 1))
+    rc = 32 * 65 + 32
+    tr = orc.trace(sc, rays=[rc])
+    h = 1e-6
+    taus = []
+    for s in (+1, -1):
+        vv = sc.verts.astype(np.float64).copy()
+        vv[:, 2] += s * h
+        taus.append(orc.paths(sc, tr["tri"], tr["flags"], rays=[rc], drop=False,
+                              verts64=vv)["tau"][0, 0])
+    assert abs((taus[0] - taus[1]) / (2 * h) - 2.0 / C0) < 1e-9 * 2.0 / C0
+
+
+# --------------------------------------------------------------------------- Fresnel
+def test_fresnel_special_cases(orc):
+    fc = 77e9
+    eps0 = 8.8541878128e-12
+    for er, sg in [(4.0, 0.0), (2.5, 0.05), (9.0, 1.0), (1.5, 0.0)]:
+        epsc = er - 1j * sg / (2 * math.pi * fc * eps0)
+        n = np.sqrt(epsc)
+        rs = orc.fresnel(S.MAT_TE, er, sg, fc, 1.0)
+        rp = orc.fresnel(S.MAT_TM, er, sg, fc, 1.0)
+        assert abs(rs - (1 - n) / (1 + n)) < 1e-14
+        assert abs(rp - (n - 1) / (n + 1)) < 1e-14
+        for c in (1e-9, 1e-7):
+            assert abs(orc.fresnel(S.MAT_TE, er, sg, fc, c) + 1) < 1e-6
+        for c in np.linspace(0.0, 1.0, 41):
+            assert abs(orc.fresnel(S.MAT_TE, er, sg, fc, c)) <= 1 + 1e-14
+            assert abs(orc.fresnel(S.MAT_TM, er, sg, fc, c)) <= 1 + 1e-14
+    # Brewster angle of a lossless dielectric: tan(theta_B) = n, r_p = 0
+    er = 4.0
+    cb = 1.0 / math.sqrt(1.0 + er)
+    assert abs(orc.fresnel(S.MAT_TM, er, 0.0, fc, cb)) < 1e-14
+    # good conductor limit: r_s -> -1, r_p -> +1
+    assert abs(orc.fresnel(S.MAT_TE, 1.0, 1e9, fc, 0.7) + 1) < 1e-3
+    assert abs(orc.fresnel(S.MAT_TM, 1.0, 1e9, fc, 0.7) - 1) < 1e-3
+    # conductor mode
+    assert orc.fresnel(S.MAT_PEC, 1.0, 0.0, fc, 0.3) == -1
+
+
+def test_energy_does_not_increase_per_bounce(orc):
+    sc = S.trihedral_plate()
+    sc = S.dataclasses.replace(sc, materials=[(S.MAT_TE, 3.0, 0.1), (S.MAT_TM, 5.0, 0.0)],
+                               mat_id=(np.arange(sc.nf) % 2).astype(np.uint16))
+    tr = orc.trace(sc)
+    p = orc.paths(sc, tr["tri"], tr["flags"])
+    pe = orc.paths(S.trihedral_plate(), tr["tri"], tr["flags"])
+    # same geometry, so |A_dielectric / A_conductor| = |prod r_j| (conductor |r| = 1)
+    ratio = np.abs(p["amp"]) / np.abs(pe["amp"])
+    assert (ratio <= 1 + 1e-12).all()
+    for i in range(1, len(ratio)):
+        if p["ray"][i] == p["ray"][i - 1]:
+            assert ratio[i] <= ratio[i - 1] * (1 + 1e-12)
+
+
+# ----------------------------------------------------------------------- IF synthesis
+def _one_path(amp, tau, taudot=0.0, V=1):
+    return {"amp": np.array([amp], complex), "tau": np.full((1, V), tau), "taudot": np.array([taudot]),
+            "ray": np.array([0]), "k": np.array([1])}
+
+
+def test_single_path_is_geometric_sequence(orc):
+    sc = S.trihedral_plate().with_chirp(n_chirps=3)
+    sc = S.dataclasses.replace(sc, radar=S.default_radar(1, 1))
+    ch = sc.chirp
+    A, tau, td = 0.3 - 0.2j, 1.234567e-8, 3.0e-9
+    cube = orc.synth(sc, _one_path(A, tau, td))
+    for c in range(3):
+        tc = tau + c * ch.t_chirp * td
+        z0 = A * np.exp(2j * np.pi * math.fmod(ch.fc * tc, 1.0))
+        w = np.exp(2j * np.pi * ch.slope * tc / ch.fs)
+        ref = z0 * w ** np.arange(ch.n_samples)
+        assert np.abs(cube[0, c] - ref).max() < 1e-12
+
+
+def test_single_path_range_dft_is_dirichlet(orc):
+    sc = S.dataclasses.replace(S.trihedral_plate(), radar=S.default_radar(1, 1))
+    ch = sc.chirp
+    Sn = ch.n_samples
+    A, tau = 1.0, 2 * 1.37 / C0
+    cube = orc.synth(sc, _one_path(A, tau))
+    X = orc.radar_cube(cube, n_angle=1)[0, 0]
+    f = ch.slope * tau / ch.fs
+    phi0 = math.fmod(ch.fc * tau, 1.0)
+    for k in range(Sn):
+        dl = f - k / Sn
+        ref = A * np.exp(2j * np.pi * phi0) * np.exp(1j * np.pi * (Sn - 1) * dl) * \
+            math.sin(math.pi * Sn * dl) / math.sin(math.pi * dl)
+        assert abs(X[k] - ref) < 1e-9 * Sn
+
+
+def test_range_peaks_of_plate_and_trihedral(orc):
+    # beat frequency 2 R mu / c: plate at 1.5 m -> bin 15.37, trihedral apex at 1.0 m -> 10.25
+    for tri_on, plate_on, want in [(False, True, 15), (True, False, 10)]:
+        sc = S.trihedral_plate(tri_on, plate_on)
+        cube, _, _ = orc.forward(sc)
+        X = orc.radar_cube(cube, n_angle=1)[0, 0]
+        assert abs(int(np.argmax(np.abs(X))) - want) <= 1
+    # combined scene: both peaks are local maxima of the profile
+    cube, _, _ = orc.forward(S.trihedral_plate())
+    prof = np.abs(orc.radar_cube(cube, n_angle=1)[0, 0])
+    for want in (10, 15):
+        seg = prof[want - 1:want + 2]
+        j = want - 1 + int(np.argmax(seg))
+        assert prof[j] >= prof[j - 1] and prof[j] >= prof[j + 1]
+
+
+def test_doppler_and_angle_peaks(orc):
+    C = 64
+    sc = S.icosphere_scene(level=1, n_rays=8, n_chirps=C)
+    ch = sc.chirp
+    # Doppler: one path with range rate 2 u / c, u = 3 m/s
+    td = 2 * 3.0 / C0
+    V = sc.radar.n_virtual
+    cube = orc.synth(sc, _one_path(1.0, 2 * 1.2 / C0, td, V=V))
+    X = orc.radar_cube(cube, n_angle=64)
+    want = round(C * ch.t_chirp * ch.fc * td) % C
+    dop = np.abs(X).sum(axis=(0, 2))
+    assert int(np.argmax(dop)) == want
+    # angle: a small plate at azimuth theta seen by the 12-element lambda/2 array
+    theta = math.radians(12.0)
+    v, f = S.plate(0.05, 0.0)
+    v = v @ S._rot_from_to(np.array([0, 0, -1.0]), np.array([-math.sin(theta), 0, -math.cos(theta)])).T
+    v = v + 1.5 * np.array([math.sin(theta), 0.0, math.cos(theta)])
+    sc2 = S.Scene("az_plate", v.astype(np.float32), f.astype(np.int32), S.default_radar(3, 4),
+                  S.Chirp(n_chirps=1), S.Grid(48, 48, 0.3, 0.05, 1))
+    cube, _, p = orc.forward(sc2)
+    assert len(p["amp"]) > 10
+    X = orc.radar_cube(cube, n_angle=64)
+    ang = np.abs(X).sum(axis=(1, 2))
+    # element v at x_v = v lambda/2 sees tau_v = tau_0 - x_v sin(theta) / c, a
+    # phase step of -sin(theta)/2 cycles per element: peak at a = -Na sin(theta)/2
+    want = round(-64 * math.sin(theta) / 2.0) % 64
+    assert abs(int(np.argmax(ang)) - want) <= 1
+
+
+def test_synth_adjoint_matches_central_differences(orc):
+    sc = S.icosphere_scene(level=1, n_rays=8, n_chirps=4)
+    ch = sc.chirp
+    V = sc.radar.n_virtual
+    rng = np.random.default_rng(0)
+    P = 5
+    pth = {"amp": rng.normal(size=P) + 1j * rng.normal(size=P),
+           "tau": 2 * 1.5 / C0 + rng.uniform(0, 1e-10, size=(P, V)),
+           "taudot": rng.uniform(-1e-8, 1e-8, size=P)}
+    T = rng.normal(size=(V, 4, ch.n_samples)) + 1j * rng.normal(size=(V, 4, ch.n_samples))
+
+    def loss(q):
+        Sx = orc.synth(sc, q)
+        return np.sum(np.abs(Sx - T) ** 2)
+
+    G = 2 * (orc.synth(sc, pth) - T)
+    ab, tb, tdb = orc.synth_adjoint(sc, pth, G)
+    for p in range(P):
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            h = 1e-6
+            qp = {k: v.copy() for k, v in pth.items()}
+            qm = {k: v.copy() for k, v in pth.items()}
+            qp["amp"][p] += h * unit
+            qm["amp"][p] -= h * unit
+            fd = (loss(qp) - loss(qm)) / (2 * h)
+            an = ab[p].real if part == "re" else ab[p].imag
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+        for v in (0, V - 1):
+            h = 1e-17
+            qp = {k: x.copy() for k, x in pth.items()}
+            qm = {k: x.copy() for k, x in pth.items()}
+            qp["tau"][p, v] += h
+            qm["tau"][p, v] -= h
+            fd = (loss(qp) - loss(qm)) / (2 * h)
+            assert abs(fd - tb[p, v]) <= 2e-5 * abs(tb[p]).max()
+        h = 1e-14
+        qp = {k: x.copy() for k, x in pth.items()}
+        qm = {k: x.copy() for k, x in pth.items()}
+        qp["taudot"][p] += h
+        qm["taudot"][p] -= h
+        fd = (loss(qp) - loss(qm)) / (2 * h)
+        assert abs(fd - tdb[p]) <= 2e-5 * max(abs(tdb[p]), abs(tb[p]).max() * ch.t_chirp)
+
+
+# ------------------------------------------------------------------------ radar cube
+@pytest.mark.parametrize("window", [0, 1])
+def test_radar_cube_matches_numpy_fft(orc, window):
+    rng = np.random.default_rng(1)
+    V, C, S_, Na = 5, 8, 16, 12
+    x = rng.normal(size=(V, C, S_)) + 1j * rng.normal(size=(V, C, S_))
+    w = (lambda n: np.hanning(n)) if window else (lambda n: np.ones(n))
+    y = x * w(S_)[None, None, :] * w(C)[None, :, None]
+    ref = np.fft.fft(np.fft.fft(np.fft.fft(y, axis=2), axis=1), n=Na, axis=0)
+    X = orc.radar_cube(x, n_angle=Na, window=window)
+    assert np.abs(X - ref).max() <= 1e-12 * np.abs(ref).max()
+    # adjoint: <F x, y> = <x, F^H y>
+    yy = rng.normal(size=(Na, C, S_)) + 1j * rng.normal(size=(Na, C, S_))
+    Fh = orc.radar_cube(yy, n_angle=Na, window=window, direction=1, V=V)
+    lhs = np.vdot(yy, X)
+    rhs = np.vdot(Fh, x)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ------------------------------------------------------------------------------ CFAR
+def _np_cfar(P, guard, train, pfa):
+    C, S_ = P.shape
+    w = guard + train
+    status = np.zeros((C, S_), np.uint8)
+    for d in range(C):
+        for r in range(S_):
+            rows = [(d + dd) % C for dd in range(-w, w + 1)]
+            vals = []
+            for i, dd in enumerate(range(-w, w + 1)):
+                for rr in range(-w, w + 1):
+                    if abs(dd) <= guard and abs(rr) <= guard:
+                        continue
+                    if 0 <= r + rr < S_:
+                        vals.append(P[rows[i], r + rr])
+            nt = len(vals)
+            thr = nt * (pfa ** (-1.0 / nt) - 1.0) * np.mean(vals)
+            status[d, r] = P[d, r] > thr
+    return status
+
+
+def test_cfar_injected_targets_and_bruteforce(orc):
+    rng = np.random.default_rng(7)
+    Na, C, S_ = 4, 16, 32
+    X = (rng.normal(size=(Na, C, S_)) + 1j * rng.normal(size=(Na, C, S_))) / math.sqrt(2)
+    targets = [(3, 5, 2), (10, 20, 1), (15, 30, 3)]
+    for d, r, a in targets:
+        X[a, d, r] += 30.0
+    out = orc.cfar(X, guard=1, train=3, pfa=1e-4)
+    for d, r, a in targets:
+        assert out["status"][d, r] & 1 and out["argmax"][d, r] == a
+    P = (np.abs(X) ** 2).sum(0)
+    ref = _np_cfar(P, 1, 3, 1e-4)
+    mask = (out["status"] & 2) == 0
+    assert np.array_equal((out["status"] & 1)[mask], ref[mask])
+    assert out["count"] <= len(targets) + 3
