@@ -1,0 +1,228 @@
+/*
+ * libsbr -- differentiable shooting-and-bouncing-rays (SBR) mmWave radar
+ * simulator for AMD Instinct MI355X (gfx950).
+ *
+ * Implements the forward simulation and backpropagation of "Differentiable
+ * Radio Frequency Ray Tracing for Millimeter-Wave Sensing" (DiffSBR,
+ * arXiv 2311.13182): ray launch, BVH closest-hit tracing with specular
+ * multi-bounce (Sec. 3.2.1, Eqs. 1-3), per-path time of flight I^t and
+ * strength I^s with Fresnel reflection (Sec. 3.2.2, Eqs. 9-10), the FMCW IF
+ * signal (Eq. 8), the signal-to-image map T of the spatial loss (Sec. 3.4.2,
+ * Eq. 16), and the adjoint chain from dL/dIF to mesh vertices (Eqs. 11-13).
+ *
+ * Conventions shared by every entry point
+ *   - Units: metres, seconds, hertz (SI).
+ *   - Radar frame: x = array axis, y = up, z = boresight.  sbr_radar.rot maps
+ *     radar-frame vectors to the world frame (row-major 3x3).
+ *   - Ray grid: ray r = iy * nx + ix looks along (u, v, 1)/|(u, v, 1)| with
+ *     u = tan_half_x * (2 (ix + 0.5) / nx - 1), v likewise in y; its Monte
+ *     Carlo weight (Eq. 3) is the cell solid angle
+ *     (2 tan_half_x / nx)(2 tan_half_y / ny) / (1 + u^2 + v^2)^(3/2).
+ *   - Virtual antenna v = t * n_rx + m (TX t, RX m).
+ *   - Complex arrays are interleaved float pairs (re, im), C-contiguous.
+ *   - Memory: every pointer inside the structs below and every array argument
+ *     is DEVICE memory owned by the caller, except the structs themselves and
+ *     the sbr_material table, which are host memory read during the call.
+ *     The library never allocates or frees; size queries say how much scratch
+ *     to pass.  Scratch content is not preserved between calls.
+ *   - Streams: `stream` is a hipStream_t (NULL = default stream).  Every call
+ *     only enqueues work on it and returns; results are ready when the stream
+ *     is.  Calls on one stream run in order.
+ *   - Errors: 0 on success, a negative sbr_status otherwise; no C++ exception
+ *     crosses the ABI.  sbr_last_error() gives the calling thread's message.
+ *     Argument checks happen before anything is enqueued.
+ */
+#ifndef SBR_H
+#define SBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SBR_OK = 0,
+    SBR_E_ARG = -1,          /* null pointer, bad size, bounds exceeded          */
+    SBR_E_HIP = -2,          /* HIP launch or API failure (message has the text) */
+    SBR_E_SCRATCH = -3,      /* scratch or BVH buffer too small (message: bytes) */
+    SBR_E_UNSUPPORTED = -4
+} sbr_status;
+
+#define SBR_MAX_BOUNCES 8
+#define SBR_MAX_TX 8
+#define SBR_MAX_RX 16
+#define SBR_MAX_VIRTUAL 64
+#define SBR_MAX_MATERIALS 64
+
+/* Triangle mesh (Sec. 3.1: surface mesh representation).  Device arrays. */
+typedef struct {
+    const float *verts;      /* [nv][3] world frame, metres                      */
+    int32_t nv;
+    const int32_t *faces;    /* [nf][3] vertex indices                            */
+    int32_t nf;
+    const uint16_t *mat_id;  /* [nf] index into the material table, or NULL      */
+} sbr_mesh;
+
+/* Reflection model of one material (Sec. 3.2.2, Eqs. 9-10).  mode 0: perfect
+ * conductor, r = -1; mode 1: r_s (TE); mode 2: r_p (TM), with complex
+ * relative permittivity eps_c = eps_r - j sigma / (2 pi fc eps_0), refractive
+ * index n = sqrt(eps_c) and Snell's law sin(dt) = sin(di) / n.  Host memory. */
+typedef struct {
+    int32_t mode;
+    int32_t reserved;
+    double eps_r;
+    double sigma;            /* S/m */
+} sbr_material;
+
+/* Radar pose and MIMO array (Sec. 3.2: part of the scene parameters Theta). */
+typedef struct {
+    double origin[3];        /* array centre, world frame                        */
+    double rot[9];           /* radar -> world rotation, row-major               */
+    int32_t n_tx, n_rx;      /* n_tx <= 8, n_rx <= 16, n_tx * n_rx <= 64         */
+    double tx[SBR_MAX_TX][3];/* radar frame                                      */
+    double rx[SBR_MAX_RX][3];/* radar frame                                      */
+    double velocity[3];      /* rigid scene velocity, world frame, m/s (Doppler) */
+} sbr_radar;
+
+/* FMCW chirp (Eq. 8: fc, mu = B / T).  Sample s is taken at t = s / fs from
+ * the start of the ramp; chirp c starts c * t_chirp after chirp 0. */
+typedef struct {
+    double fc;               /* carrier, Hz            */
+    double slope;            /* mu, Hz/s               */
+    double fs;               /* ADC sample rate, Hz    */
+    double t_chirp;          /* chirp period, s        */
+    int32_t n_samples;       /* S >= 1                 */
+    int32_t n_chirps;        /* C >= 1                 */
+} sbr_chirp;
+
+/* Ray grid (the samples of Eq. 3) and bounce limit. */
+typedef struct {
+    int32_t nx, ny;          /* nx * ny <= 2^26                                  */
+    double tan_half_x, tan_half_y;
+    int32_t max_bounces;     /* K, 1..8                                          */
+    int32_t reserved;
+    double t_min;            /* hits closer than this are ignored, metres        */
+} sbr_rays;
+
+/* Closest-hit records, structure of arrays, each [K][nx*ny] (device). */
+typedef struct {
+    int32_t *tri;            /* original face index, -1 = no hit (ray ended)     */
+    float *t;                /* hit distance along the bounce's unit direction   */
+    float *u;                /* barycentric weight of face vertex 1              */
+    float *v;                /* barycentric weight of face vertex 2              */
+    uint8_t *flags;          /* SBR_HIT_* bits                                   */
+} sbr_hits;
+
+/* Hit flags.  With delta_k = 1e-6 m * max(1, path length to hit k / 1 m):   */
+#define SBR_HIT_EDGE   1u    /* hit point within delta_k of an edge line          */
+#define SBR_HIT_TIE    2u    /* another candidate hit within delta_k of t          */
+#define SBR_HIT_GRAZE  4u    /* |d . n| < 1e-6                                     */
+#define SBR_HIT_TMIN   8u    /* t < 2 t_min                                        */
+#define SBR_HIT_PARENT 16u   /* an earlier bounce of this ray is flagged           */
+
+/* sbr_synth_if / sbr_backward flags */
+#define SBR_DROP_FLAGGED 1   /* paths whose hit flag byte is non-zero are skipped */
+
+/* scratch-size queries */
+#define SBR_OP_BUILD_BVH 0
+#define SBR_OP_SYNTH 1
+#define SBR_OP_BACKWARD 2
+#define SBR_OP_RADAR_CUBE 3
+#define SBR_OP_CFAR 4
+
+/* Bytes of the BVH buffer for nf triangles. */
+size_t sbr_bvh_bytes(int32_t nf);
+
+/* Scratch bytes an operation needs.  Pointers that the operation does not
+ * depend on may be NULL (BUILD_BVH: mesh; SYNTH/BACKWARD: rays, radar, chirp;
+ * RADAR_CUBE and CFAR: chirp + radar give V, C, S; n_angle is taken as 64 or
+ * V, whichever is larger).  Returns 0 for bad arguments. */
+size_t sbr_scratch_bytes(int32_t op, const sbr_mesh *mesh, const sbr_rays *rays,
+                         const sbr_radar *radar, const sbr_chirp *chirp);
+
+/* Build (mode 0) or refit (mode 1) the bounding volume hierarchy of a mesh.
+ * BUILD sorts triangles by 30-bit Morton code of their centroids, forms the
+ * binary radix tree (Karras, HPG 2012), computes boxes bottom-up and lays
+ * nodes out in depth-first order with escape links for stackless traversal.
+ * REFIT keeps the tree of the last BUILD of this buffer (same faces, new
+ * vertex positions) and recomputes boxes and triangle data.
+ * bvh: device buffer of at least sbr_bvh_bytes(nf).  The BVH is not part of
+ * the paper's method; it accelerates the closest-hit queries of Sec. 3.2.1. */
+int sbr_build_bvh(const sbr_mesh *mesh, void *bvh, size_t bvh_bytes, int32_t mode,
+                  void *scratch, size_t scratch_bytes, void *stream);
+
+/* Ray tracing forward simulation (Sec. 3.2.1): launch the grid from the radar
+ * origin, find the closest hit of each ray (minimum of (t, face index), the
+ * previous face excluded, t > t_min, two-sided, degenerate faces never hit),
+ * reflect specularly about the face normal (recursive term of Eq. 1) and
+ * repeat up to K bounces or the first miss.  Writes out->* for all K*R
+ * records.  counters: NULL or device uint64[3] that receives += (closest-hit
+ * queries issued incl. the final miss, BVH nodes tested, triangles tested). */
+int sbr_trace(const sbr_mesh *mesh, const void *bvh, const sbr_radar *radar,
+              const sbr_rays *rays, const sbr_hits *out, uint64_t *counters, void *stream);
+
+/* IF signal synthesis (Eq. 8).  For every (ray, bounce) hit -- minus flagged
+ * ones with SBR_DROP_FLAGGED -- one path returns to every virtual antenna:
+ *   I^s = d_omega * prod_j r_j * cos(theta_k) / (L_k R_k)
+ *   I^t_v(c) = (|x_1 - tx_t| + sum_{j=2..k} |x_j - x_{j-1}| + |rx_m - x_k|) / c0
+ *              + c * t_chirp * 2 (velocity . d_1) / c0
+ * with hit points x_j recomputed in double precision from the face indices,
+ * L_k the unfolded path length, R_k = |x_k - origin|, theta_k the incidence
+ * angle at the last hit and r_j the material reflection coefficients.
+ *   if_cube[v][c][s] = sum_paths I^s exp(2 pi j (slope s / fs + fc) I^t_v(c))
+ * if_cube: device float [V][C][S][2], overwritten.  mats: host array of
+ * n_mats (<= 64) entries, or NULL / 0 for all-conductor. */
+int sbr_synth_if(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
+                 const sbr_radar *radar, const sbr_rays *rays, const sbr_hits *hits,
+                 const sbr_chirp *chirp, int32_t flags, float *if_cube,
+                 void *scratch, size_t scratch_bytes, void *stream);
+
+/* The signal-to-image map T of the spatial multi-antenna loss (Eq. 16):
+ * range, Doppler and angle DFTs,
+ *   X[a][d][r] = sum_{v,c,s} w(s) w(c) S[v][c][s] e^{-2 pi j (r s/S + d c/C + a v/Na)}
+ * (v zero-padded to n_angle >= V, no normalisation, no shift; window 0 =
+ * rectangular, 1 = symmetric Hann on the range and Doppler axes).
+ * direction 0: in [V][C][S][2] -> out [Na][C][S][2].  direction 1 applies the
+ * conjugate transpose: in [Na][C][S][2] -> out [V][C][S][2] (the gradient of
+ * a real loss with respect to S, given its gradient with respect to X). */
+int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_angle,
+                   int32_t window, int32_t direction, float *out, void *scratch,
+                   size_t scratch_bytes, void *stream);
+
+/* Radar point cloud from the cube: square-law cell-averaging CFAR on
+ * P[d][r] = sum_a |X[a][d][r]|^2 with a (2(guard+train)+1)^2 window minus the
+ * (2 guard+1)^2 guard cells, Doppler axis circular, range axis truncated,
+ * threshold alpha * mean with alpha = N_t (pfa^(-1/N_t) - 1).
+ * cube: device [Na][C][S][2].  points: device int32 [max_points][4] =
+ * (range bin, Doppler bin, argmax_a |X|^2 (lowest on ties), 0) in row-major
+ * (d, r) order; ratio: device float [max_points] = P / threshold, or NULL;
+ * n_points: device int32, total detections (may exceed max_points). */
+int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard,
+             int32_t train, double pfa, int32_t *points, float *ratio, int32_t max_points,
+             int32_t *n_points, void *scratch, size_t scratch_bytes, void *stream);
+
+/* Backpropagation (Sec. 3.2.2 Eqs. 11-12, Sec. 3.3 Eq. 13): given
+ * grad_if = dL/dRe S + i dL/dIm S ([V][C][S][2], device), ADD dL/dverts to
+ * grad_verts ([nv][3], device).  The gradient is the pathwise derivative of
+ * the fixed-grid estimator: each path's geometry is recomputed per bounce
+ * from the hit records (nothing of the forward synthesis is stored) and the
+ * reverse sweep runs through path lengths, ray-plane intersections,
+ * reflections, normals and Fresnel coefficients.  Arguments as for
+ * sbr_synth_if; hits and flags must be those the forward used. */
+int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
+                 const sbr_radar *radar, const sbr_rays *rays, const sbr_hits *hits,
+                 const sbr_chirp *chirp, int32_t flags, const float *grad_if,
+                 float *grad_verts, void *scratch, size_t scratch_bytes, void *stream);
+
+/* Number of paths the last sbr_synth_if / sbr_backward found is left in the
+ * first int32 of their scratch buffer (device) once the stream reaches it. */
+
+/* Message describing the calling thread's last error ("" if none). */
+const char *sbr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

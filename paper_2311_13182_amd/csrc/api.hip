@@ -1,0 +1,338 @@
+// C ABI of libsbr: argument checks, scratch carving, launches.
+#include <stdarg.h>
+
+#include <algorithm>
+#include <string>
+
+#include "sbr_internal.h"
+
+namespace sbr {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+
+// implemented in the kernel sources
+int bvh_build(const sbr_mesh *m, void *bvh, size_t bvh_bytes, int32_t mode, void *scratch,
+              size_t scratch_bytes, hipStream_t st);
+size_t build_scratch_bytes(int32_t nf);
+int trace_launch(const sbr_mesh *m, const void *bvh, const RadarDev &rd, const GridDev &gd,
+                 const sbr_hits *h, uint64_t *counters, hipStream_t st);
+SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S);
+size_t synth_partial_elems(const SynthPlan &p, int32_t V, int32_t C, int32_t S);
+int launch_synth(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial,
+                 float2 *out, hipStream_t s);
+size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V);
+int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
+                    const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
+                    const float2 *G, float *grad, hipStream_t s);
+size_t cube_scratch_bytes(int V, int C, int S, int Na);
+size_t cfar_scratch_bytes(int C, int S);
+int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
+                      void *scratch, hipStream_t s);
+int cfar_launch(const float2 *cube, int Na, int C, int S, int guard, int train, double pfa, int32_t *points,
+                float *ratio_out, int maxp, int32_t *npts, void *scratch, hipStream_t s);
+int fill_zero_f32(float *p, size_t n, hipStream_t s);
+
+int check_mesh(const sbr_mesh *m) {
+    SBR_CHECK_ARG(m, "mesh is NULL");
+    SBR_CHECK_ARG(m->nf >= 0 && m->nv >= 0, "negative mesh size (nv=%d nf=%d)", m->nv, m->nf);
+    SBR_CHECK_ARG(m->nf == 0 || (m->verts && m->faces && m->nv > 0), "mesh verts/faces are NULL");
+    SBR_CHECK_ARG(m->nf <= (1 << 27), "too many faces (%d)", m->nf);
+    return SBR_OK;
+}
+
+static int check_radar(const sbr_radar *r) {
+    SBR_CHECK_ARG(r, "radar is NULL");
+    SBR_CHECK_ARG(r->n_tx >= 1 && r->n_tx <= SBR_MAX_TX, "n_tx=%d out of [1,%d]", r->n_tx, SBR_MAX_TX);
+    SBR_CHECK_ARG(r->n_rx >= 1 && r->n_rx <= SBR_MAX_RX, "n_rx=%d out of [1,%d]", r->n_rx, SBR_MAX_RX);
+    SBR_CHECK_ARG(r->n_tx * r->n_rx <= SBR_MAX_VIRTUAL, "n_tx*n_rx=%d > %d", r->n_tx * r->n_rx,
+                  SBR_MAX_VIRTUAL);
+    return SBR_OK;
+}
+
+static int check_rays(const sbr_rays *g) {
+    SBR_CHECK_ARG(g, "rays is NULL");
+    SBR_CHECK_ARG(g->nx >= 0 && g->ny >= 0, "negative grid (%d x %d)", g->nx, g->ny);
+    SBR_CHECK_ARG((long long)g->nx * g->ny <= (1LL << 26), "grid too large (%d x %d)", g->nx, g->ny);
+    SBR_CHECK_ARG(g->max_bounces >= 1 && g->max_bounces <= SBR_MAX_BOUNCES, "max_bounces=%d out of [1,%d]",
+                  g->max_bounces, SBR_MAX_BOUNCES);
+    SBR_CHECK_ARG(g->tan_half_x > 0 && g->tan_half_y > 0, "grid half-widths must be positive");
+    SBR_CHECK_ARG(g->t_min >= 0, "t_min must be >= 0");
+    return SBR_OK;
+}
+
+static int check_chirp(const sbr_chirp *c) {
+    SBR_CHECK_ARG(c, "chirp is NULL");
+    SBR_CHECK_ARG(c->n_samples >= 1 && c->n_chirps >= 1, "chirp sizes must be >= 1 (S=%d C=%d)",
+                  c->n_samples, c->n_chirps);
+    SBR_CHECK_ARG(c->n_samples <= 4096 && c->n_chirps <= 4096, "chirp sizes must be <= 4096");
+    SBR_CHECK_ARG(c->fs > 0 && c->fc > 0, "fs and fc must be positive");
+    return SBR_OK;
+}
+
+static int check_hits(const sbr_hits *h, const sbr_rays *g) {
+    SBR_CHECK_ARG(h, "hits is NULL");
+    if ((long long)g->nx * g->ny == 0) return SBR_OK;   // nothing is read or written
+    SBR_CHECK_ARG(h->tri && h->t && h->u && h->v && h->flags, "a hits array is NULL");
+    return SBR_OK;
+}
+
+int check_common(const sbr_mesh *m, const sbr_material *mats, int32_t n_mats, const sbr_radar *r,
+                 const sbr_rays *g, const sbr_hits *h, const sbr_chirp *ch) {
+    int rc;
+    if ((rc = check_mesh(m))) return rc;
+    if ((rc = check_radar(r))) return rc;
+    if ((rc = check_rays(g))) return rc;
+    if ((rc = check_hits(h, g))) return rc;
+    if ((rc = check_chirp(ch))) return rc;
+    SBR_CHECK_ARG(n_mats >= 0 && n_mats <= SBR_MAX_MATERIALS, "n_mats=%d out of [0,%d]", n_mats,
+                  SBR_MAX_MATERIALS);
+    SBR_CHECK_ARG(n_mats == 0 || mats, "mats is NULL with n_mats=%d", n_mats);
+    for (int i = 0; i < n_mats; i++)
+        SBR_CHECK_ARG(mats[i].mode >= 0 && mats[i].mode <= 2, "material %d: mode %d not in {0,1,2}", i,
+                      mats[i].mode);
+    return SBR_OK;
+}
+
+MatTable make_mats(const sbr_material *mats, int32_t n_mats) {
+    MatTable t;
+    t.n = mats ? n_mats : 0;
+    for (int i = 0; i < SBR_MAX_MATERIALS; i++) {
+        t.mode[i] = i < t.n ? mats[i].mode : 0;
+        t.eps_r[i] = i < t.n ? mats[i].eps_r : 1.0;
+        t.sigma[i] = i < t.n ? mats[i].sigma : 0.0;
+    }
+    return t;
+}
+
+RadarDev make_radar(const sbr_radar *r) {
+    RadarDev d;
+    for (int i = 0; i < 3; i++) {
+        d.o[i] = r->origin[i];
+        d.vel[i] = r->velocity[i];
+    }
+    for (int i = 0; i < 9; i++) d.rot[i] = r->rot[i];
+    d.n_tx = r->n_tx;
+    d.n_rx = r->n_rx;
+    auto world = [&](const double *p, double *o) {
+        for (int i = 0; i < 3; i++)
+            o[i] = r->origin[i] + r->rot[3 * i] * p[0] + r->rot[3 * i + 1] * p[1] + r->rot[3 * i + 2] * p[2];
+    };
+    for (int t = 0; t < SBR_MAX_TX; t++) {
+        if (t < r->n_tx) world(r->tx[t], d.tx[t]);
+        else d.tx[t][0] = d.tx[t][1] = d.tx[t][2] = 0.0;
+    }
+    for (int m = 0; m < SBR_MAX_RX; m++) {
+        if (m < r->n_rx) world(r->rx[m], d.rx[m]);
+        else d.rx[m][0] = d.rx[m][1] = d.rx[m][2] = 0.0;
+    }
+    return d;
+}
+
+GridDev make_grid(const sbr_rays *g) {
+    GridDev d;
+    d.nx = g->nx;
+    d.ny = g->ny;
+    d.K = g->max_bounces;
+    d.thx = g->tan_half_x;
+    d.thy = g->tan_half_y;
+    d.t_min = g->t_min;
+    return d;
+}
+
+ChirpDev make_chirp(const sbr_chirp *c) {
+    ChirpDev d;
+    d.fc = c->fc;
+    d.slope = c->slope;
+    d.fs = c->fs;
+    d.tc = c->t_chirp;
+    d.S = c->n_samples;
+    d.C = c->n_chirps;
+    return d;
+}
+
+static size_t synth_bytes(int R, int K, int V, int C, int S) {
+    Carver cv(nullptr);
+    carve_path_stage(cv, R, K, V);
+    SynthPlan p = synth_plan(R, K, V, C, S);
+    cv.take<float2>(synth_partial_elems(p, V, C, S));
+    return align_up(cv.off, 256);
+}
+
+static size_t backward_bytes(int R, int K, int V) {
+    Carver cv(nullptr);
+    carve_path_stage(cv, R, K, V);
+    return align_up(cv.off, 256) + backward_extra_bytes(R, K, V) + 256;
+}
+
+}  // namespace sbr
+
+using namespace sbr;
+
+extern "C" {
+
+const char *sbr_last_error(void) { return g_err.c_str(); }
+
+size_t sbr_bvh_bytes(int32_t nf) {
+    if (nf < 1) return 0;
+    size_t b = 0;
+    bvh_view(nullptr, nf, &b);
+    return b;
+}
+
+size_t sbr_scratch_bytes(int32_t op, const sbr_mesh *mesh, const sbr_rays *rays, const sbr_radar *radar,
+                         const sbr_chirp *chirp) {
+    switch (op) {
+    case SBR_OP_BUILD_BVH:
+        if (!mesh || mesh->nf < 1) return 0;
+        return build_scratch_bytes(mesh->nf);
+    case SBR_OP_SYNTH:
+    case SBR_OP_BACKWARD: {
+        if (!rays || !radar || !chirp) return 0;
+        long long R = (long long)rays->nx * rays->ny;
+        if (R < 0 || rays->max_bounces < 1 || radar->n_tx < 1 || radar->n_rx < 1) return 0;
+        int V = radar->n_tx * radar->n_rx;
+        if (op == SBR_OP_SYNTH)
+            return synth_bytes((int)R, rays->max_bounces, V, chirp->n_chirps, chirp->n_samples);
+        return backward_bytes((int)R, rays->max_bounces, V);
+    }
+    case SBR_OP_RADAR_CUBE: {
+        if (!radar || !chirp) return 0;
+        int V = radar->n_tx * radar->n_rx;
+        return cube_scratch_bytes(V, chirp->n_chirps, chirp->n_samples, std::max(64, V));
+    }
+    case SBR_OP_CFAR:
+        if (!chirp) return 0;
+        return cfar_scratch_bytes(chirp->n_chirps, chirp->n_samples);
+    default:
+        return 0;
+    }
+}
+
+int sbr_build_bvh(const sbr_mesh *mesh, void *bvh, size_t bvh_bytes, int32_t mode, void *scratch,
+                  size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_mesh(mesh))) return rc;
+    SBR_CHECK_ARG(mesh->nf >= 1, "BVH needs at least one face");
+    SBR_CHECK_ARG(bvh, "bvh is NULL");
+    SBR_CHECK_ARG(mode == 0 || mode == 1, "mode must be 0 (build) or 1 (refit)");
+    return bvh_build(mesh, bvh, bvh_bytes, mode, scratch, scratch_bytes, (hipStream_t)stream);
+}
+
+int sbr_trace(const sbr_mesh *mesh, const void *bvh, const sbr_radar *radar, const sbr_rays *rays,
+              const sbr_hits *out, uint64_t *counters, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_mesh(mesh))) return rc;
+    if ((rc = check_radar(radar))) return rc;
+    if ((rc = check_rays(rays))) return rc;
+    if ((rc = check_hits(out, rays))) return rc;
+    SBR_CHECK_ARG(mesh->nf == 0 || bvh, "bvh is NULL");
+    if ((long long)rays->nx * rays->ny == 0) return SBR_OK;
+    RadarDev rd = make_radar(radar);
+    GridDev gd = make_grid(rays);
+    return trace_launch(mesh, bvh, rd, gd, out, counters, (hipStream_t)stream);
+}
+
+int sbr_synth_if(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats, const sbr_radar *radar,
+                 const sbr_rays *rays, const sbr_hits *hits, const sbr_chirp *chirp, int32_t flags,
+                 float *if_cube, void *scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
+    SBR_CHECK_ARG(if_cube, "if_cube is NULL");
+    const int R = rays->nx * rays->ny, K = rays->max_bounces;
+    const int V = radar->n_tx * radar->n_rx, C = chirp->n_chirps, S = chirp->n_samples;
+    hipStream_t s = (hipStream_t)stream;
+    size_t need = synth_bytes(R, K, V, C, S);
+    if (!scratch || scratch_bytes < need) {
+        set_error("synth scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    if (R == 0) return fill_zero_f32(if_cube, (size_t)2 * V * C * S, s);
+    Carver cv(scratch);
+    PathStage st = carve_path_stage(cv, R, K, V);
+    SynthPlan p = synth_plan(R, K, V, C, S);
+    float2 *partial = cv.take<float2>(synth_partial_elems(p, V, C, S));
+    if ((rc = launch_paths(mesh, make_mats(mats, n_mats), make_radar(radar), make_grid(rays), make_chirp(chirp),
+                           hits, flags, st, s)))
+        return rc;
+    return launch_synth(st, p, V, C, S, partial, reinterpret_cast<float2 *>(if_cube), s);
+}
+
+int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_angle, int32_t window,
+                   int32_t direction, float *out, void *scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(in && out, "in/out is NULL");
+    SBR_CHECK_ARG(V >= 1 && C >= 1 && S >= 1, "sizes must be >= 1 (V=%d C=%d S=%d)", V, C, S);
+    SBR_CHECK_ARG(V <= 4096 && C <= 4096 && S <= 4096 && n_angle <= 4096, "sizes must be <= 4096");
+    SBR_CHECK_ARG(n_angle >= V, "n_angle=%d < V=%d", n_angle, V);
+    SBR_CHECK_ARG(window == 0 || window == 1, "window must be 0 or 1");
+    SBR_CHECK_ARG(direction == 0 || direction == 1, "direction must be 0 or 1");
+    SBR_CHECK_ARG((size_t)C * 32 * 8 + (size_t)C * 8 <= 60000 && (size_t)std::max(V, n_angle) * 32 * 8 +
+                      (size_t)n_angle * 8 <= 60000, "C or n_angle too large for the LDS tiles");
+    size_t need = cube_scratch_bytes(V, C, S, n_angle);
+    if (!scratch || scratch_bytes < need) {
+        set_error("radar cube scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    return radar_cube_launch(reinterpret_cast<const float2 *>(in), V, C, S, n_angle, window, direction,
+                             reinterpret_cast<float2 *>(out), scratch, (hipStream_t)stream);
+}
+
+int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard, int32_t train, double pfa,
+             int32_t *points, float *ratio, int32_t max_points, int32_t *n_points, void *scratch,
+             size_t scratch_bytes, void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(cube && n_points, "cube/n_points is NULL");
+    SBR_CHECK_ARG(max_points >= 0 && (max_points == 0 || points), "points is NULL");
+    SBR_CHECK_ARG(Na >= 1 && C >= 1 && S >= 1, "sizes must be >= 1");
+    SBR_CHECK_ARG(guard >= 0 && train >= 1, "guard >= 0 and train >= 1 required");
+    SBR_CHECK_ARG(pfa > 0.0 && pfa < 1.0, "pfa must be in (0, 1)");
+    size_t need = cfar_scratch_bytes(C, S);
+    if (!scratch || scratch_bytes < need) {
+        set_error("cfar scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    return cfar_launch(reinterpret_cast<const float2 *>(cube), Na, C, S, guard, train, pfa, points, ratio,
+                       max_points, n_points, scratch, (hipStream_t)stream);
+}
+
+int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats, const sbr_radar *radar,
+                 const sbr_rays *rays, const sbr_hits *hits, const sbr_chirp *chirp, int32_t flags,
+                 const float *grad_if, float *grad_verts, void *scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
+    SBR_CHECK_ARG(grad_if && grad_verts, "grad_if/grad_verts is NULL");
+    const int R = rays->nx * rays->ny, K = rays->max_bounces;
+    const int V = radar->n_tx * radar->n_rx;
+    size_t need = backward_bytes(R, K, V);
+    if (!scratch || scratch_bytes < need) {
+        set_error("backward scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    if (R == 0 || mesh->nf == 0) return SBR_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Carver cv(scratch);
+    PathStage st = carve_path_stage(cv, R, K, V);
+    MatTable mt = make_mats(mats, n_mats);
+    RadarDev rd = make_radar(radar);
+    GridDev gd = make_grid(rays);
+    ChirpDev cd = make_chirp(chirp);
+    if ((rc = launch_paths(mesh, mt, rd, gd, cd, hits, flags, st, s))) return rc;
+    return launch_backward(mesh, mt, rd, gd, cd, hits, st, cv, reinterpret_cast<const float2 *>(grad_if),
+                           grad_verts, s);
+}
+
+}  // extern "C"

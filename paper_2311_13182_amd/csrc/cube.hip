@@ -1,0 +1,252 @@
+// The signal-to-image map T of the spatial loss (Eq. 16): range, Doppler and
+// angle DFTs and their conjugate transpose; and the CA-CFAR point extraction.
+// Direct DFTs with exact twiddle indices (k n mod N) held in LDS; the stage
+// moves a few MiB and is bound by memory traffic, not arithmetic.
+#include "sbr_internal.h"
+
+namespace sbr {
+
+namespace {
+
+// twiddle table e^{sign 2 pi j k / N}, k < N, built in double
+__device__ void make_twiddles(float2 *tw, int N, int sign) {
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * k / N, &s, &c);
+        tw[k] = make_float2((float)c, (float)(sign * s));
+    }
+}
+
+__device__ __forceinline__ float window_at(int window, int i, int N) {
+    if (window == 1 && N > 1) return (float)(0.5 - 0.5 * cospi(2.0 * i / (N - 1)));
+    return 1.0f;
+}
+
+// Transform along the innermost axis: rows of length N -> rows of length N.
+// pre-window on the input (forward) or post-window on the output (adjoint).
+__global__ __launch_bounds__(256) void k_dft_inner(const float2 *in, float2 *out, int rows, int N, int sign,
+                                                    int window, int post) {
+    extern __shared__ float2 sm[];
+    float2 *tw = sm, *x = sm + N;
+    make_twiddles(tw, N, sign);
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            float2 v = in[(size_t)row * N + i];
+            float w = post ? 1.0f : window_at(window, i, N);
+            x[i] = make_float2(v.x * w, v.y * w);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            float re = 0.0f, im = 0.0f;
+            int idx = 0;
+            for (int n = 0; n < N; n++) {
+                float2 t = tw[idx];
+                float2 v = x[n];
+                re = fmaf(v.x, t.x, fmaf(-v.y, t.y, re));
+                im = fmaf(v.x, t.y, fmaf(v.y, t.x, im));
+                idx += k;
+                if (idx >= N) idx -= N;
+            }
+            float w = post ? window_at(window, k, N) : 1.0f;
+            out[(size_t)row * N + k] = make_float2(re * w, im * w);
+        }
+    }
+}
+
+// Transform along a middle axis of [outer][N][inner] -> [outer][M][inner]
+// (output index k < M, input index n < N, twiddle index (k n) mod Nt).
+// A block owns one outer index and 32 inner columns, staged in LDS.
+__global__ __launch_bounds__(256) void k_dft_mid(const float2 *in, float2 *out, int outer, int N, int M,
+                                                  int Nt, int inner, int sign, int window, int post) {
+    extern __shared__ float2 sm[];
+    float2 *tw = sm, *x = sm + Nt;
+    make_twiddles(tw, Nt, sign);
+    const int cols = 32;
+    const int nct = (inner + cols - 1) / cols;
+    for (int job = blockIdx.x; job < outer * nct; job += gridDim.x) {
+        const int o = job / nct, j0 = (job % nct) * cols;
+        __syncthreads();
+        for (int i = threadIdx.x; i < N * cols; i += blockDim.x) {
+            int n = i / cols, j = i % cols;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (j0 + j < inner) v = in[((size_t)o * N + n) * inner + j0 + j];
+            float w = post ? 1.0f : window_at(window, n, N);
+            x[i] = make_float2(v.x * w, v.y * w);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < M * cols; i += blockDim.x) {
+            int k = i / cols, j = i % cols;
+            if (j0 + j >= inner) continue;
+            float re = 0.0f, im = 0.0f;
+            int idx = 0;
+            for (int n = 0; n < N; n++) {
+                float2 t = tw[idx];
+                float2 v = x[n * cols + j];
+                re = fmaf(v.x, t.x, fmaf(-v.y, t.y, re));
+                im = fmaf(v.x, t.y, fmaf(v.y, t.x, im));
+                idx += k;
+                while (idx >= Nt) idx -= Nt;
+            }
+            float w = post ? window_at(window, k, M) : 1.0f;
+            out[((size_t)o * M + k) * inner + j0 + j] = make_float2(re * w, im * w);
+        }
+    }
+}
+
+// ---- CFAR ------------------------------------------------------------------
+__global__ void k_power(const float2 *X, int Na, int plane, float *P, int *am) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= plane) return;
+    float acc = 0.0f, best = -1.0f;
+    int ba = 0;
+    for (int a = 0; a < Na; a++) {
+        float2 x = X[(size_t)a * plane + e];
+        float q = x.x * x.x + x.y * x.y;
+        acc += q;
+        if (q > best) {
+            best = q;
+            ba = a;
+        }
+    }
+    P[e] = acc;
+    am[e] = ba;
+}
+
+__global__ void k_cfar_cells(const float *P, int C, int S, int guard, int train, double pfa, float *ratio) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= C * S) return;
+    const int d = e / S, r = e % S, w = guard + train;
+    float sum = 0.0f;
+    int nt = 0;
+    for (int dd = -w; dd <= w; dd++) {
+        int d2 = ((d + dd) % C + C) % C;
+        for (int rr = -w; rr <= w; rr++) {
+            if (abs(dd) <= guard && abs(rr) <= guard) continue;
+            int r2 = r + rr;
+            if (r2 < 0 || r2 >= S) continue;
+            sum += P[(size_t)d2 * S + r2];
+            nt++;
+        }
+    }
+    float rt = 0.0f;
+    if (nt > 0) {
+        double alpha = nt * (pow(pfa, -1.0 / nt) - 1.0);
+        double thr = alpha * (double)sum / nt;
+        rt = thr > 0.0 ? (float)((double)P[e] / thr) : (P[e] > 0.0f ? INFINITY : 0.0f);
+    }
+    ratio[e] = rt;
+}
+
+// ordered compaction of detections (ratio > 1), one block
+__global__ __launch_bounds__(1024) void k_cfar_compact(const float *ratio, const int *am, int n, int S,
+                                                       int32_t *points, float *pratio, int maxp,
+                                                       int32_t *npts) {
+    __shared__ int wsum[16];
+    __shared__ int base;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) base = 0;
+    __syncthreads();
+    for (int e0 = 0; e0 < n; e0 += 1024) {
+        int e = e0 + t;
+        int hit = (e < n && ratio[e] > 1.0f) ? 1 : 0;
+        uint64_t m = __ballot(hit);
+        int before = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+        if (lane == 0) wsum[w] = __popcll(m);
+        __syncthreads();
+        int off = base;
+        for (int i = 0; i < w; i++) off += wsum[i];
+        int pos = off + before;
+        if (hit && pos < maxp) {
+            points[4 * pos] = e % S;
+            points[4 * pos + 1] = e / S;
+            points[4 * pos + 2] = am[e];
+            points[4 * pos + 3] = 0;
+            if (pratio) pratio[pos] = ratio[e];
+        }
+        __syncthreads();
+        if (t == 0) {
+            int tot = 0;
+            for (int i = 0; i < 16; i++) tot += wsum[i];
+            base += tot;
+        }
+        __syncthreads();
+    }
+    if (t == 0) *npts = base;
+}
+
+}  // namespace
+
+size_t cube_scratch_bytes(int V, int C, int S, int Na) {
+    Carver cv(nullptr);
+    size_t big = (size_t)std::max(V, Na) * C * S;
+    cv.take<float2>(big);
+    cv.take<float2>(big);
+    return align_up(cv.off, 256);
+}
+
+size_t cfar_scratch_bytes(int C, int S) {
+    Carver cv(nullptr);
+    cv.take<float>((size_t)C * S);
+    cv.take<int>((size_t)C * S);
+    cv.take<float>((size_t)C * S);
+    return align_up(cv.off, 256);
+}
+
+static int launch_inner(const float2 *in, float2 *out, int rows, int N, int sign, int window, int post,
+                        hipStream_t s) {
+    int blocks = std::min(rows, 4096);
+    size_t lds = sizeof(float2) * 2 * N;
+    hipLaunchKernelGGL(k_dft_inner, dim3(blocks), dim3(256), lds, s, in, out, rows, N, sign, window, post);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+static int launch_mid(const float2 *in, float2 *out, int outer, int N, int M, int Nt, int inner, int sign,
+                      int window, int post, hipStream_t s) {
+    int jobs = outer * ((inner + 31) / 32);
+    int blocks = std::min(jobs, 4096);
+    size_t lds = sizeof(float2) * (Nt + (size_t)N * 32);
+    hipLaunchKernelGGL(k_dft_mid, dim3(blocks), dim3(256), lds, s, in, out, outer, N, M, Nt, inner, sign,
+                       window, post);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
+                      void *scratch, hipStream_t s) {
+    Carver cv(scratch);
+    size_t big = (size_t)std::max(V, Na) * C * S;
+    float2 *y1 = cv.take<float2>(big);
+    float2 *y2 = cv.take<float2>(big);
+    int rc;
+    if (dir == 0) {
+        // range (inner), Doppler (middle), angle (outer, zero-padded V -> Na)
+        if ((rc = launch_inner(in, y1, V * C, S, -1, window, 0, s))) return rc;
+        if ((rc = launch_mid(y1, y2, V, C, C, C, S, -1, window, 0, s))) return rc;
+        if ((rc = launch_mid(y2, out, 1, V, Na, Na, C * S, -1, 0, 0, s))) return rc;
+    } else {
+        if ((rc = launch_mid(in, y2, 1, Na, V, Na, C * S, +1, 0, 0, s))) return rc;
+        if ((rc = launch_mid(y2, y1, V, C, C, C, S, +1, window, 1, s))) return rc;
+        if ((rc = launch_inner(y1, out, V * C, S, +1, window, 1, s))) return rc;
+    }
+    return SBR_OK;
+}
+
+int cfar_launch(const float2 *cube, int Na, int C, int S, int guard, int train, double pfa, int32_t *points,
+                float *ratio_out, int maxp, int32_t *npts, void *scratch, hipStream_t s) {
+    Carver cv(scratch);
+    const int plane = C * S;
+    float *P = cv.take<float>(plane);
+    int *am = cv.take<int>(plane);
+    float *ratio = cv.take<float>(plane);
+    hipLaunchKernelGGL(k_power, dim3((plane + 255) / 256), dim3(256), 0, s, cube, Na, plane, P, am);
+    hipLaunchKernelGGL(k_cfar_cells, dim3((plane + 255) / 256), dim3(256), 0, s, P, C, S, guard, train, pfa,
+                       ratio);
+    hipLaunchKernelGGL(k_cfar_compact, dim3(1), dim3(1024), 0, s, ratio, am, plane, S, points, ratio_out, maxp,
+                       npts);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+}  // namespace sbr

@@ -1,0 +1,73 @@
+// Device helpers shared by the path stage and the backward pass.
+#pragma once
+
+#include "sbr_internal.h"
+
+namespace sbr {
+
+// ------------------------------------------------------------------ helpers
+struct cd {
+    double re, im;
+};
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd cdivz(cd a, cd b) {
+    double q = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / q, (a.im * b.re - a.re * b.im) / q};
+}
+__device__ __forceinline__ cd csqrtp(cd z) {   // principal branch
+    double r = sqrt(z.re * z.re + z.im * z.im);
+    double x = sqrt(0.5 * (r + fabs(z.re)));
+    if (x == 0.0) return {0.0, 0.0};
+    double y = 0.5 * z.im / x;
+    if (z.re >= 0.0) return {x, y};
+    return {fabs(y), z.im >= 0.0 ? x : -x};
+}
+
+// Reflection coefficient (Eqs. 9-10 with n = sqrt(eps_c), Snell
+// sin(dt) = sin(di)/n) and its derivative with respect to cos(di).
+__device__ inline void reflect_coef(const MatTable &mt, int mi, double fc, double ci, cd &r, cd &dr) {
+    int mode = (mt.n > 0 && mi < mt.n) ? mt.mode[mi] : 0;
+    if (mode == 0) {
+        r = {-1.0, 0.0};
+        dr = {0.0, 0.0};
+        return;
+    }
+    cd eps = {mt.eps_r[mi], -mt.sigma[mi] / (2.0 * kPi * fc * kEps0)};
+    cd n = csqrtp(eps);
+    // cos(dt) = sqrt(1 - (1 - ci^2) / eps)
+    cd s2 = cdivz({1.0 - ci * ci, 0.0}, eps);
+    cd ct = csqrtp({1.0 - s2.re, -s2.im});
+    // d ct / d ci = (ci / eps) / ct
+    cd dct = cdivz(cdivz({ci, 0.0}, eps), ct);
+    if (mode == 1) {
+        cd nct = cmul(n, ct), ndct = cmul(n, dct);
+        cd num = {ci - nct.re, -nct.im}, den = {ci + nct.re, nct.im};
+        r = cdivz(num, den);
+        // d/dci (ci - n ct)/(ci + n ct) = 2 n (ct - ci dct) / den^2
+        cd t = {ct.re - ci * dct.re, ct.im - ci * dct.im};
+        cd top = cmul({2.0 * n.re, 2.0 * n.im}, t);
+        dr = cdivz(top, cmul(den, den));
+    } else {
+        cd nci = {n.re * ci, n.im * ci};
+        cd num = {nci.re - ct.re, nci.im - ct.im}, den = {nci.re + ct.re, nci.im + ct.im};
+        r = cdivz(num, den);
+        // d/dci (n ci - ct)/(n ci + ct) = 2 n (ct - ci dct) / den^2
+        cd t = {ct.re - ci * dct.re, ct.im - ci * dct.im};
+        cd top = cmul({2.0 * n.re, 2.0 * n.im}, t);
+        dr = cdivz(top, cmul(den, den));
+    }
+}
+
+__device__ __forceinline__ void grid_ray(const GridDev &g, const RadarDev &rd, int ix, int iy,
+                                         double d[3], double *dw) {
+    double u = g.thx * (2.0 * (ix + 0.5) / g.nx - 1.0);
+    double v = g.thy * (2.0 * (iy + 0.5) / g.ny - 1.0);
+    double q = 1.0 + u * u + v * v;
+    double s = 1.0 / sqrt(q);
+    double dr[3] = {u * s, v * s, s};
+    for (int i = 0; i < 3; i++) d[i] = rd.rot[3 * i] * dr[0] + rd.rot[3 * i + 1] * dr[1] + rd.rot[3 * i + 2] * dr[2];
+    *dw = (2.0 * g.thx / g.nx) * (2.0 * g.thy / g.ny) / (q * sqrt(q));
+}
+
+
+}  // namespace sbr

@@ -1,0 +1,171 @@
+// Internal definitions shared by the libsbr HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <string>
+
+#include "sbr.h"
+
+namespace sbr {
+
+// ----------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define SBR_CHECK_ARG(cond, ...)              \
+    do {                                      \
+        if (!(cond)) {                        \
+            ::sbr::set_error(__VA_ARGS__);    \
+            return SBR_E_ARG;                 \
+        }                                     \
+    } while (0)
+
+#define SBR_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::sbr::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                  \
+            return SBR_E_HIP;                                                      \
+        }                                                                          \
+    } while (0)
+
+#define SBR_LAUNCHED()                                                                \
+    do {                                                                              \
+        hipError_t e_ = hipGetLastError();                                            \
+        if (e_ != hipSuccess) {                                                       \
+            ::sbr::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                     \
+            return SBR_E_HIP;                                                         \
+        }                                                                             \
+    } while (0)
+
+static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Carve sub-buffers out of a caller-provided byte buffer.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        off = align_up(off, 256);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// ----------------------------------------------------------------- BVH
+// Node of the depth-first layout: box, escape index (next node after this
+// subtree; == node count ends traversal), leaf slot (-1 for internal nodes;
+// the left child of an internal node is the next node).
+struct __align__(32) BvhNode {
+    float lo[3];
+    float hi[3];
+    int32_t escape;
+    int32_t leaf;
+};
+
+// Triangle of a leaf: three vertices, .w of the first = original face id bits.
+struct __align__(16) LeafTri {
+    float4 a, b, c;
+};
+
+struct BvhView {
+    int32_t n;          // triangles
+    int32_t n_nodes;    // 2n - 1
+    BvhNode *nodes;     // [n_nodes], depth-first order
+    LeafTri *tris;      // [n], Morton order (leaf slot order)
+    int32_t *order;     // [n] leaf slot -> original face
+    int32_t *parent;    // [n_nodes] radix-tree parent (tree indices; -1 root)
+    int2 *child;        // [n-1] radix-tree children
+    int32_t *dfs_of;    // [n_nodes] radix-tree index -> depth-first index
+    uint32_t *visits;   // [n-1] bottom-up arrival counters
+    int32_t *header;    // [16] n, built flag
+};
+
+BvhView bvh_view(void *buf, int32_t nf, size_t *bytes_out);
+
+// ----------------------------------------------------------------- constants
+constexpr double kC0 = 299792458.0;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+
+// Arguments of the path stage, passed by value to kernels.
+struct MatTable {
+    int32_t n;
+    int32_t mode[SBR_MAX_MATERIALS];
+    double eps_r[SBR_MAX_MATERIALS];
+    double sigma[SBR_MAX_MATERIALS];
+};
+
+struct RadarDev {
+    double o[3];
+    double rot[9];
+    int32_t n_tx, n_rx;
+    double tx[SBR_MAX_TX][3];   // world frame
+    double rx[SBR_MAX_RX][3];   // world frame
+    double vel[3];
+};
+
+struct GridDev {
+    int32_t nx, ny, K;
+    double thx, thy, t_min;
+};
+
+struct ChirpDev {
+    double fc, slope, fs, tc;
+    int32_t S, C;
+};
+
+// Device-side path records (structure of arrays, capacity = K * R).
+struct PathSoA {
+    int32_t cap;
+    int32_t V;
+    float *alpha;     // [V][cap] frac(fc * tau_v), cycles
+    float *gamma;     // [V][cap] slope * tau_v / fs, cycles per sample
+    float2 *amp;      // [cap] I^s
+    float *beta;      // [cap] frac(fc * tc * taudot), cycles per chirp
+    float *epsd;      // [cap] slope * tc * taudot / fs, cycles per sample per chirp
+};
+
+// Scratch layout of the path stage (compaction + records).
+struct PathStage {
+    int32_t *count;       // [4]: [0] = number of paths P
+    int32_t *ray_first;   // [R + 1] first path index of each ray
+    int32_t *blk;         // [nblk] per-block path counts then offsets
+    int32_t nblk;
+    PathSoA rec;
+};
+
+constexpr int kPathBlock = 256;   // rays per block of the compaction kernels
+
+// Launch shape of the IF synthesis: L samples per lane, SB sample blocks per
+// chirp row, tiles_per_v wavefronts per antenna, n_chunks path chunks.
+struct SynthPlan {
+    int32_t L, SB, tiles_per_v, n_chunks;
+};
+
+PathStage carve_path_stage(Carver &cv, int32_t R, int32_t K, int32_t V);
+
+// host-side conversions / validation shared by the entry points
+int check_mesh(const sbr_mesh *m);
+int check_common(const sbr_mesh *m, const sbr_material *mats, int32_t n_mats,
+                 const sbr_radar *r, const sbr_rays *g, const sbr_hits *h,
+                 const sbr_chirp *ch);
+MatTable make_mats(const sbr_material *mats, int32_t n_mats);
+RadarDev make_radar(const sbr_radar *r);
+GridDev make_grid(const sbr_rays *g);
+ChirpDev make_chirp(const sbr_chirp *c);
+
+// enqueue path compaction + FP64 refinement; records go to st.rec
+int launch_paths(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
+                 const ChirpDev &cd, const sbr_hits *h, int32_t flags, const PathStage &st,
+                 hipStream_t s);
+
+}  // namespace sbr

@@ -1,0 +1,384 @@
+// Path stage (FP64 refinement of every hit into I^t / I^s, compacted in
+// ray-major order) and the IF synthesis of Eq. (8).
+#include "sbr_internal.h"
+#include "sbr_device.h"
+
+namespace sbr {
+
+namespace {
+
+struct PathArgs {
+    const float *verts;
+    const int32_t *faces;
+    const uint16_t *mat_id;
+    const int32_t *tri;
+    const uint8_t *flags;
+    int32_t drop;
+    int32_t R;
+    MatTable mt;
+    RadarDev rd;
+    GridDev g;
+    ChirpDev ch;
+    PathStage st;
+};
+
+__device__ __forceinline__ int ray_npaths(const PathArgs &a, size_t r) {
+    int n = 0;
+    for (int k = 0; k < a.g.K; k++) {
+        size_t slot = (size_t)k * a.R + r;
+        if (a.tri[slot] < 0) break;
+        if (a.drop && a.flags[slot]) break;
+        n++;
+    }
+    return n;
+}
+
+__device__ __forceinline__ int block_sum(int x, int *sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+    if (lane == 0) sh[w] = x;
+    __syncthreads();
+    int t = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// inclusive prefix within the block (wave scan + wave offsets)
+__device__ __forceinline__ int block_incl_scan(int x, int *sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    int add = 0;
+    for (int i = 0; i < w; i++) add += sh[i];
+    __syncthreads();
+    return x + add;
+}
+
+__global__ __launch_bounds__(kPathBlock) void k_path_count(PathArgs a) {
+    __shared__ int sh[kPathBlock / 64];
+    size_t r = (size_t)blockIdx.x * kPathBlock + threadIdx.x;
+    int n = r < (size_t)a.R ? ray_npaths(a, r) : 0;
+    int t = block_sum(n, sh);
+    if (threadIdx.x == 0) a.st.blk[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void k_path_scan(PathArgs a) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x, nb = a.st.nblk;
+    int chunk = (nb + 1023) / 1024;
+    int b = t * chunk, e = min(nb, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; i++) s += a.st.blk[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int i = b; i < e; i++) {
+        int x = a.st.blk[i];
+        a.st.blk[i] = run;
+        run += x;
+    }
+    if (t == 1023) {
+        a.st.count[0] = part[1023];
+        a.st.ray_first[a.R] = part[1023];
+    }
+}
+
+__device__ __forceinline__ double frac_d(double x) { return x - floor(x); }
+
+__global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
+    __shared__ int sh[kPathBlock / 64];
+    const size_t r = (size_t)blockIdx.x * kPathBlock + threadIdx.x;
+    const bool act = r < (size_t)a.R;
+    int n = act ? ray_npaths(a, r) : 0;
+    int incl = block_incl_scan(n, sh);
+    if (!act) return;
+    int p = a.st.blk[blockIdx.x] + incl - n;
+    a.st.ray_first[r] = p;
+    if (n == 0) return;
+    const int ix = (int)(r % a.g.nx), iy = (int)(r / a.g.nx);
+    double d[3], dw;
+    grid_ray(a.g, a.rd, ix, iy, d, &dw);
+    double o[3] = {a.rd.o[0], a.rd.o[1], a.rd.o[2]};
+    const double taudot = 2.0 * (a.rd.vel[0] * d[0] + a.rd.vel[1] * d[1] + a.rd.vel[2] * d[2]) / kC0;
+    const double beta = frac_d(a.ch.fc * a.ch.tc * taudot);
+    const double epsd = a.ch.slope * a.ch.tc * taudot / a.ch.fs;
+    double xp[3] = {o[0], o[1], o[2]}, x1[3] = {0, 0, 0};
+    double L = 0.0, Lmid = 0.0;
+    cd pr = {1.0, 0.0};
+    const int cap = a.st.rec.cap;
+    const int ntx = a.rd.n_tx, nrx = a.rd.n_rx;
+    for (int k = 0; k < n; k++, p++) {
+        const int f = a.tri[(size_t)k * a.R + r];
+        double va[3], vb[3], vc[3];
+        for (int i = 0; i < 3; i++) {
+            va[i] = a.verts[3 * a.faces[3 * f] + i];
+            vb[i] = a.verts[3 * a.faces[3 * f + 1] + i];
+            vc[i] = a.verts[3 * a.faces[3 * f + 2] + i];
+        }
+        double e1[3] = {vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]};
+        double e2[3] = {vc[0] - va[0], vc[1] - va[1], vc[2] - va[2]};
+        double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        double nd = N[0] * d[0] + N[1] * d[1] + N[2] * d[2];
+        double th = (N[0] * (va[0] - o[0]) + N[1] * (va[1] - o[1]) + N[2] * (va[2] - o[2])) / nd;
+        double x[3] = {o[0] + th * d[0], o[1] + th * d[1], o[2] + th * d[2]};
+        double nl = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        double dn = nd / nl;
+        double ci = fabs(dn);
+        cd rc, drc;
+        reflect_coef(a.mt, a.mat_id ? (int)a.mat_id[f] : 0, a.ch.fc, ci, rc, drc);
+        pr = cmul(pr, rc);
+        double seg = sqrt((x[0] - xp[0]) * (x[0] - xp[0]) + (x[1] - xp[1]) * (x[1] - xp[1]) +
+                          (x[2] - xp[2]) * (x[2] - xp[2]));
+        L += seg;
+        if (k == 0) {
+            x1[0] = x[0];
+            x1[1] = x[1];
+            x1[2] = x[2];
+        } else {
+            Lmid += seg;
+        }
+        double Rk = sqrt((x[0] - a.rd.o[0]) * (x[0] - a.rd.o[0]) + (x[1] - a.rd.o[1]) * (x[1] - a.rd.o[1]) +
+                         (x[2] - a.rd.o[2]) * (x[2] - a.rd.o[2]));
+        double sc = dw * ci / (L * Rk);
+        a.st.rec.amp[p] = make_float2((float)(pr.re * sc), (float)(pr.im * sc));
+        a.st.rec.beta[p] = (float)beta;
+        a.st.rec.epsd[p] = (float)epsd;
+        double dtx[SBR_MAX_TX], drx[SBR_MAX_RX];
+        for (int t = 0; t < ntx; t++)
+            dtx[t] = sqrt((x1[0] - a.rd.tx[t][0]) * (x1[0] - a.rd.tx[t][0]) +
+                          (x1[1] - a.rd.tx[t][1]) * (x1[1] - a.rd.tx[t][1]) +
+                          (x1[2] - a.rd.tx[t][2]) * (x1[2] - a.rd.tx[t][2]));
+        for (int m = 0; m < nrx; m++)
+            drx[m] = sqrt((x[0] - a.rd.rx[m][0]) * (x[0] - a.rd.rx[m][0]) +
+                          (x[1] - a.rd.rx[m][1]) * (x[1] - a.rd.rx[m][1]) +
+                          (x[2] - a.rd.rx[m][2]) * (x[2] - a.rd.rx[m][2]));
+        for (int t = 0; t < ntx; t++)
+            for (int m = 0; m < nrx; m++) {
+                double tau = (dtx[t] + Lmid + drx[m]) / kC0;
+                int v = t * nrx + m;
+                a.st.rec.alpha[(size_t)v * cap + p] = (float)frac_d(a.ch.fc * tau);
+                a.st.rec.gamma[(size_t)v * cap + p] = (float)(a.ch.slope * tau / a.ch.fs);
+            }
+        for (int i = 0; i < 3; i++) {
+            o[i] = x[i];
+            xp[i] = x[i];
+            d[i] = d[i] - 2.0 * dn * N[i] / nl;
+        }
+    }
+}
+
+}  // namespace
+
+PathStage carve_path_stage(Carver &cv, int32_t R, int32_t K, int32_t V) {
+    PathStage st;
+    st.nblk = (R + kPathBlock - 1) / kPathBlock;
+    st.count = cv.take<int32_t>(64);
+    st.ray_first = cv.take<int32_t>((size_t)R + 1);
+    st.blk = cv.take<int32_t>(st.nblk);
+    long long cap = (long long)R * K;
+    st.rec.cap = (int32_t)cap;
+    st.rec.V = V;
+    st.rec.alpha = cv.take<float>((size_t)V * cap);
+    st.rec.gamma = cv.take<float>((size_t)V * cap);
+    st.rec.amp = cv.take<float2>(cap);
+    st.rec.beta = cv.take<float>(cap);
+    st.rec.epsd = cv.take<float>(cap);
+    return st;
+}
+
+int launch_paths(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
+                 const ChirpDev &cd, const sbr_hits *h, int32_t flags, const PathStage &st,
+                 hipStream_t s) {
+    PathArgs a;
+    a.verts = m->verts;
+    a.faces = m->faces;
+    a.mat_id = m->mat_id;
+    a.tri = h->tri;
+    a.flags = h->flags;
+    a.drop = (flags & SBR_DROP_FLAGGED) ? 1 : 0;
+    a.R = gd.nx * gd.ny;
+    a.mt = mt;
+    a.rd = rd;
+    a.g = gd;
+    a.ch = cd;
+    a.st = st;
+    hipLaunchKernelGGL(k_path_count, dim3(st.nblk), dim3(kPathBlock), 0, s, a);
+    hipLaunchKernelGGL(k_path_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_path_refine, dim3(st.nblk), dim3(kPathBlock), 0, s, a);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+// ------------------------------------------------------------------ Eq. (8)
+namespace {
+
+struct SynthArgs {
+    const int32_t *count;
+    PathSoA rec;
+    int32_t V, C, S;
+    int32_t SB;          // sample blocks per chirp row
+    int32_t tiles_per_v; // wavefront tiles per antenna
+    int32_t n_chunks;
+    float2 *partial;     // [n_chunks][V][C][S]
+};
+
+__device__ __forceinline__ float frac_f(float x) { return x - floorf(x); }
+
+// exact fractional part of an integer n times f (n < 2^24): the product is
+// formed exactly inside the fma before the nearest integer is removed
+__device__ __forceinline__ float frac_mul(float n, float f) {
+    float p = n * f;
+    return fmaf(n, f, -rintf(p));
+}
+
+// One wavefront owns 64 (chirp, sample-block) lanes of one antenna; each lane
+// accumulates L consecutive samples over a chunk of paths.  Per path the lane
+// restarts the phase exactly (hardware sin/cos in revolutions) and advances it
+// with the real three-term recurrence z[s+1] = 2 cos(2 pi delta) z[s] - z[s-1].
+template <int L>
+__global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
+    const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int lane = threadIdx.x & 63;
+    const int v = __builtin_amdgcn_readfirstlane(wv / a.tiles_per_v);
+    if (v >= a.V) return;
+    const int e = (wv % a.tiles_per_v) * 64 + lane;
+    const int c = e / a.SB, b = e % a.SB;
+    const int chunk = blockIdx.y;
+    const int P = __builtin_amdgcn_readfirstlane(a.count[0]);
+    const long long per = ((long long)P + a.n_chunks - 1) / a.n_chunks;
+    const int p0 = (int)min((long long)P, per * chunk);
+    const int p1 = (int)min((long long)P, per * (chunk + 1));
+    const float cf = (float)c;
+    const float s0 = (float)(b * L);
+    float ar[L], ai[L];
+#pragma unroll
+    for (int i = 0; i < L; i++) {
+        ar[i] = 0.0f;
+        ai[i] = 0.0f;
+    }
+    const float *al = a.rec.alpha + (size_t)v * a.rec.cap;
+    const float *ga = a.rec.gamma + (size_t)v * a.rec.cap;
+    for (int p = p0; p < p1; p++) {
+        const float alpha = al[p], gamma = ga[p];
+        const float2 A = a.rec.amp[p];
+        const float beta = a.rec.beta[p], epsd = a.rec.epsd[p];
+        const float delta = fmaf(cf, epsd, gamma);            // cycles per sample
+        float ph = alpha + frac_mul(cf, beta) + frac_mul(s0, delta);
+        ph = ph - rintf(ph);
+        float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+        float dph = delta - rintf(delta);
+        float ws = __builtin_amdgcn_sinf(dph), wc = __builtin_amdgcn_cosf(dph);
+        float zr = A.x * cs - A.y * sn, zi = A.x * sn + A.y * cs;   // z[s0]
+        float yr = zr * wc - zi * ws, yi = zr * ws + zi * wc;       // z[s0 + 1]
+        const float k2 = 2.0f * wc;
+        ar[0] += zr;
+        ai[0] += zi;
+        if (L > 1) {
+            ar[1] += yr;
+            ai[1] += yi;
+        }
+#pragma unroll
+        for (int i = 2; i < L; i++) {
+            float nr = fmaf(k2, yr, -zr);
+            float ni = fmaf(k2, yi, -zi);
+            zr = yr;
+            zi = yi;
+            yr = nr;
+            yi = ni;
+            ar[i] += nr;
+            ai[i] += ni;
+        }
+    }
+    if (c < a.C) {
+        float2 *out = a.partial + ((size_t)chunk * a.V + v) * (size_t)a.C * a.S + (size_t)c * a.S;
+        int sb = b * L;
+#pragma unroll
+        for (int i = 0; i < L; i++)
+            if (sb + i < a.S) out[sb + i] = make_float2(ar[i], ai[i]);
+    }
+}
+
+__global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, float2 *out) {
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float sr = 0.0f, si = 0.0f;
+    for (int c = 0; c < n_chunks; c++) {
+        float2 x = partial[(size_t)c * n + e];
+        sr += x.x;
+        si += x.y;
+    }
+    out[e] = make_float2(sr, si);
+}
+
+}  // namespace
+
+__global__ void k_zero_f32(float *p, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+int fill_zero_f32(float *p, size_t n, hipStream_t s) {
+    if (n == 0) return SBR_OK;
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+constexpr int kSynthL = 64;
+
+SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
+    SynthPlan p;
+    p.L = S >= 64 ? kSynthL : (S >= 32 ? 32 : 16);
+    p.SB = (S + p.L - 1) / p.L;
+    p.tiles_per_v = (C * p.SB + 63) / 64;
+    long long waves = (long long)V * p.tiles_per_v;
+    long long cap = (long long)R * K;
+    long long want = (16384 + waves - 1) / waves;
+    long long maxc = (cap + 63) / 64;
+    p.n_chunks = (int32_t)std::max(1LL, std::min(std::min(want, maxc), 1024LL));
+    return p;
+}
+
+size_t synth_partial_elems(const SynthPlan &p, int32_t V, int32_t C, int32_t S) {
+    return (size_t)p.n_chunks * V * C * S;
+}
+
+int launch_synth(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial,
+                 float2 *out, hipStream_t s) {
+    SynthArgs a;
+    a.count = st.count;
+    a.rec = st.rec;
+    a.V = V;
+    a.C = C;
+    a.S = S;
+    a.SB = p.SB;
+    a.tiles_per_v = p.tiles_per_v;
+    a.n_chunks = p.n_chunks;
+    a.partial = partial;
+    long long waves = (long long)V * p.tiles_per_v;
+    dim3 grid((unsigned)((waves + 3) / 4), (unsigned)p.n_chunks);
+    if (p.L == 64)
+        hipLaunchKernelGGL(k_synth<64>, grid, dim3(256), 0, s, a);
+    else if (p.L == 32)
+        hipLaunchKernelGGL(k_synth<32>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_synth<16>, grid, dim3(256), 0, s, a);
+    size_t n = (size_t)V * C * S;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial,
+                       p.n_chunks, n, out);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+}  // namespace sbr

@@ -1,0 +1,273 @@
+"""Python binding of libsbr with the C ABI's names.
+
+PyTorch provides device memory and the HIP stream; every step of the
+simulation runs in libsbr's HIP kernels.  Functions enqueue on
+`torch.cuda.current_stream()` and return without synchronising.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import scenes as S
+
+EXPORTS = L.EXPORTS
+
+
+def _lib():
+    return L.load()
+
+
+def _p(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ----------------------------------------------------------------- structs
+def radar_struct(r: S.Radar) -> L.sbr_radar:
+    s = L.sbr_radar()
+    if r.n_tx > L.SBR_MAX_TX or r.n_rx > L.SBR_MAX_RX:
+        raise ValueError("too many TX / RX antennas")
+    for i in range(3):
+        s.origin[i] = float(r.origin[i])
+        s.velocity[i] = float(r.vel[i])
+    rot = np.asarray(r.rot, dtype=np.float64).reshape(-1)
+    for i in range(9):
+        s.rot[i] = float(rot[i])
+    s.n_tx, s.n_rx = r.n_tx, r.n_rx
+    for t in range(r.n_tx):
+        for j in range(3):
+            s.tx[t][j] = float(r.tx[t][j])
+    for m in range(r.n_rx):
+        for j in range(3):
+            s.rx[m][j] = float(r.rx[m][j])
+    return s
+
+
+def chirp_struct(c: S.Chirp) -> L.sbr_chirp:
+    return L.sbr_chirp(c.fc, c.slope, c.fs, c.t_chirp, c.n_samples, c.n_chirps)
+
+
+def rays_struct(g: S.Grid) -> L.sbr_rays:
+    return L.sbr_rays(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces, 0, g.t_min)
+
+
+def materials_struct(mats: Sequence[Tuple[int, float, float]]):
+    n = len(mats)
+    if n == 0:
+        return None, 0
+    arr = (L.sbr_material * n)()
+    for i, (mode, er, sg) in enumerate(mats):
+        arr[i].mode, arr[i].eps_r, arr[i].sigma = int(mode), float(er), float(sg)
+    return arr, n
+
+
+class DeviceMesh:
+    """Mesh resident on the device: verts float32 [nv,3], faces int32 [nf,3],
+    optional per-face material ids (uint16 stored as int16)."""
+
+    def __init__(self, verts, faces, mat_id=None, materials=(), device="cuda"):
+        self.verts = torch.as_tensor(np.ascontiguousarray(verts, np.float32) if isinstance(verts, np.ndarray)
+                                     else verts, dtype=torch.float32, device=device).contiguous()
+        self.faces = torch.as_tensor(np.ascontiguousarray(faces, np.int32) if isinstance(faces, np.ndarray)
+                                     else faces, dtype=torch.int32, device=device).contiguous()
+        self.mat_id = None
+        if mat_id is not None:
+            self.mat_id = torch.as_tensor(np.asarray(mat_id).astype(np.int16), device=device).contiguous()
+        self.materials = list(materials)
+
+    @property
+    def nv(self):
+        return int(self.verts.shape[0])
+
+    @property
+    def nf(self):
+        return int(self.faces.shape[0])
+
+    def struct(self) -> L.sbr_mesh:
+        return L.sbr_mesh(self.verts.data_ptr(), self.nv, self.faces.data_ptr(), self.nf,
+                          self.mat_id.data_ptr() if self.mat_id is not None else None)
+
+    @classmethod
+    def from_scene(cls, sc: S.Scene, device="cuda"):
+        return cls(sc.verts, sc.faces, sc.mat_id, sc.materials, device)
+
+
+@dataclasses.dataclass
+class Hits:
+    tri: torch.Tensor      # int32 [K, R]
+    t: torch.Tensor        # float32 [K, R]
+    u: torch.Tensor
+    v: torch.Tensor
+    flags: torch.Tensor    # uint8 [K, R]
+
+    @classmethod
+    def empty(cls, K: int, R: int, device="cuda"):
+        return cls(torch.empty((K, R), dtype=torch.int32, device=device),
+                   torch.empty((K, R), dtype=torch.float32, device=device),
+                   torch.empty((K, R), dtype=torch.float32, device=device),
+                   torch.empty((K, R), dtype=torch.float32, device=device),
+                   torch.empty((K, R), dtype=torch.uint8, device=device))
+
+    def struct(self) -> L.sbr_hits:
+        return L.sbr_hits(self.tri.data_ptr(), self.t.data_ptr(), self.u.data_ptr(), self.v.data_ptr(),
+                          self.flags.data_ptr())
+
+
+# ----------------------------------------------------------------- entry points
+def sbr_bvh_bytes(nf: int) -> int:
+    return int(_lib().sbr_bvh_bytes(int(nf)))
+
+
+def sbr_scratch_bytes(op: int, mesh: Optional[DeviceMesh] = None, rays: Optional[S.Grid] = None,
+                      radar: Optional[S.Radar] = None, chirp: Optional[S.Chirp] = None) -> int:
+    m = mesh.struct() if mesh is not None else None
+    g = rays_struct(rays) if rays is not None else None
+    r = radar_struct(radar) if radar is not None else None
+    c = chirp_struct(chirp) if chirp is not None else None
+    return int(_lib().sbr_scratch_bytes(int(op), ct.byref(m) if m else None, ct.byref(g) if g else None,
+                                        ct.byref(r) if r else None, ct.byref(c) if c else None))
+
+
+def sbr_build_bvh(mesh: DeviceMesh, bvh: torch.Tensor, mode: int = 0, scratch: Optional[torch.Tensor] = None):
+    m = mesh.struct()
+    L.check(_lib().sbr_build_bvh(ct.byref(m), _p(bvh), bvh.numel() * bvh.element_size(), int(mode), _p(scratch),
+                                 0 if scratch is None else scratch.numel() * scratch.element_size(), _stream()))
+
+
+def sbr_trace(mesh: DeviceMesh, bvh: Optional[torch.Tensor], radar: S.Radar, rays: S.Grid, hits: Hits,
+              counters: Optional[torch.Tensor] = None):
+    m, r, g, h = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct()
+    L.check(_lib().sbr_trace(ct.byref(m), _p(bvh), ct.byref(r), ct.byref(g), ct.byref(h), _p(counters),
+                             _stream()))
+
+
+def sbr_synth_if(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: S.Chirp, flags: int,
+                 if_cube: torch.Tensor, scratch: torch.Tensor):
+    m, r, g, h, c = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct(), chirp_struct(chirp)
+    mats, nm = materials_struct(mesh.materials)
+    L.check(_lib().sbr_synth_if(ct.byref(m), mats, nm, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c),
+                                int(flags), _p(if_cube), _p(scratch), scratch.numel() * scratch.element_size(),
+                                _stream()))
+
+
+def sbr_radar_cube(x: torch.Tensor, V: int, C: int, Sn: int, n_angle: int, window: int, direction: int,
+                   out: torch.Tensor, scratch: torch.Tensor):
+    L.check(_lib().sbr_radar_cube(_p(x), V, C, Sn, n_angle, window, direction, _p(out), _p(scratch),
+                                  scratch.numel() * scratch.element_size(), _stream()))
+
+
+def sbr_cfar(cube: torch.Tensor, Na: int, C: int, Sn: int, guard: int, train: int, pfa: float,
+             points: torch.Tensor, ratio: Optional[torch.Tensor], n_points: torch.Tensor, scratch: torch.Tensor):
+    L.check(_lib().sbr_cfar(_p(cube), Na, C, Sn, guard, train, float(pfa), _p(points), _p(ratio),
+                            int(points.shape[0]), _p(n_points), _p(scratch),
+                            scratch.numel() * scratch.element_size(), _stream()))
+
+
+def sbr_backward(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: S.Chirp, flags: int,
+                 grad_if: torch.Tensor, grad_verts: torch.Tensor, scratch: torch.Tensor):
+    m, r, g, h, c = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct(), chirp_struct(chirp)
+    mats, nm = materials_struct(mesh.materials)
+    L.check(_lib().sbr_backward(ct.byref(m), mats, nm, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c),
+                                int(flags), _p(grad_if), _p(grad_verts), _p(scratch),
+                                scratch.numel() * scratch.element_size(), _stream()))
+
+
+def last_error() -> str:
+    return _lib().sbr_last_error().decode()
+
+
+# ----------------------------------------------------------------- convenience
+class Simulator:
+    """One scene resident on the device: mesh, BVH, hit records, one scratch
+    buffer shared by all stages (stages on one stream run in order)."""
+
+    def __init__(self, scene: S.Scene, device="cuda", drop_flagged: bool = True, n_angle: int = 64):
+        self.scene = scene
+        self.device = torch.device(device)
+        self.mesh = DeviceMesh.from_scene(scene, self.device)
+        self.flags = L.SBR_DROP_FLAGGED if drop_flagged else 0
+        g, rd, ch = scene.grid, scene.radar, scene.chirp
+        self.K, self.R = g.max_bounces, g.nx * g.ny
+        self.V, self.C, self.S = rd.n_virtual, ch.n_chirps, ch.n_samples
+        self.n_angle = max(n_angle, self.V)
+        need = max(sbr_scratch_bytes(L.SBR_OP_BUILD_BVH, self.mesh),
+                   sbr_scratch_bytes(L.SBR_OP_SYNTH, self.mesh, g, rd, ch),
+                   sbr_scratch_bytes(L.SBR_OP_BACKWARD, self.mesh, g, rd, ch),
+                   sbr_scratch_bytes(L.SBR_OP_RADAR_CUBE, None, g, rd, dataclasses.replace(ch)),
+                   sbr_scratch_bytes(L.SBR_OP_CFAR, None, g, rd, ch))
+        # the cube stage needs room for max(V, n_angle) planes
+        need = max(need, 2 * 8 * self.n_angle * self.C * self.S + 1024)
+        self.scratch = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.bvh = torch.empty(max(1, sbr_bvh_bytes(self.mesh.nf)), dtype=torch.uint8, device=self.device)
+        self.hits = Hits.empty(self.K, self.R, self.device)
+        self.counters = torch.zeros(3, dtype=torch.int64, device=self.device)
+        self.built = False
+
+    # ---- geometry
+    def set_verts(self, verts: torch.Tensor):
+        self.mesh.verts.copy_(verts.detach().to(torch.float32).reshape(-1, 3))
+
+    def build(self, refit: bool = False):
+        if self.mesh.nf == 0:
+            return
+        sbr_build_bvh(self.mesh, self.bvh, 1 if (refit and self.built) else 0, self.scratch)
+        self.built = True
+
+    # ---- forward
+    def trace(self, count: bool = False):
+        if not self.built:
+            self.build()
+        sbr_trace(self.mesh, self.bvh if self.mesh.nf else None, self.scene.radar, self.scene.grid, self.hits,
+                  self.counters if count else None)
+        return self.hits
+
+    def synth(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.V, self.C, self.S, 2), dtype=torch.float32, device=self.device)
+        sbr_synth_if(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, self.flags, out,
+                     self.scratch)
+        return out
+
+    def forward(self) -> torch.Tensor:
+        self.trace()
+        return torch.view_as_complex(self.synth())
+
+    def radar_cube(self, x: torch.Tensor, direction: int = 0, window: int = 0) -> torch.Tensor:
+        xf = torch.view_as_real(x) if x.is_complex() else x
+        xf = xf.contiguous()
+        if direction == 0:
+            out = torch.empty((self.n_angle, self.C, self.S, 2), dtype=torch.float32, device=self.device)
+        else:
+            out = torch.empty((self.V, self.C, self.S, 2), dtype=torch.float32, device=self.device)
+        sbr_radar_cube(xf, self.V, self.C, self.S, self.n_angle, window, direction, out, self.scratch)
+        return torch.view_as_complex(out)
+
+    def cfar(self, X: torch.Tensor, guard=2, train=8, pfa=1e-4, max_points=65536):
+        xf = (torch.view_as_real(X) if X.is_complex() else X).contiguous()
+        pts = torch.empty((max_points, 4), dtype=torch.int32, device=self.device)
+        ratio = torch.empty(max_points, dtype=torch.float32, device=self.device)
+        n = torch.zeros(1, dtype=torch.int32, device=self.device)
+        sbr_cfar(xf, int(xf.shape[0]), self.C, self.S, guard, train, pfa, pts, ratio, n, self.scratch)
+        return pts, ratio, n
+
+    def backward(self, grad_if: torch.Tensor, grad_verts: Optional[torch.Tensor] = None) -> torch.Tensor:
+        gf = (torch.view_as_real(grad_if) if grad_if.is_complex() else grad_if).contiguous().to(torch.float32)
+        if grad_verts is None:
+            grad_verts = torch.zeros((self.mesh.nv, 3), dtype=torch.float32, device=self.device)
+        sbr_backward(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, self.flags, gf,
+                     grad_verts, self.scratch)
+        return grad_verts
+
+    def n_paths(self) -> int:
+        return int(self.scratch[:4].view(torch.int32)[0].item())

@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports every symbol include/sbr.h declares, and
+rejects bad arguments before enqueueing anything.  CPU only: no call here
+reaches a GPU kernel."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "sbr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sbr_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2311_13182_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2311_13182_amd import build
+        build.build()
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_2311_13182_amd import _lib as L
+    decl = _declared()
+    assert len(decl) == 9
+    assert sorted(L.EXPORTS) == decl
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_size_queries(lib):
+    from paper_2311_13182_amd import _lib as L
+    from paper_2311_13182_amd import scenes as S
+    from paper_2311_13182_amd import sbr
+    assert lib.sbr_bvh_bytes(0) == 0
+    b1, b2 = lib.sbr_bvh_bytes(1), lib.sbr_bvh_bytes(1000)
+    assert 0 < b1 < b2
+    sc = S.icosphere_scene(level=1, n_rays=16, n_chirps=4)
+    r, g, c = sbr.radar_struct(sc.radar), sbr.rays_struct(sc.grid), sbr.chirp_struct(sc.chirp)
+    syn = lib.sbr_scratch_bytes(L.SBR_OP_SYNTH, None, ct.byref(g), ct.byref(r), ct.byref(c))
+    bwd = lib.sbr_scratch_bytes(L.SBR_OP_BACKWARD, None, ct.byref(g), ct.byref(r), ct.byref(c))
+    assert syn > 0 and bwd > 0
+    # paths scale with rays x bounces
+    g2 = sbr.rays_struct(sc.grid.__class__(32, 32, 0.1, 0.1, 3))
+    assert lib.sbr_scratch_bytes(L.SBR_OP_SYNTH, None, ct.byref(g2), ct.byref(r), ct.byref(c)) > syn
+    assert lib.sbr_scratch_bytes(99, None, None, None, None) == 0
+    assert lib.sbr_scratch_bytes(L.SBR_OP_SYNTH, None, None, None, None) == 0
+
+
+def test_argument_errors_are_reported(lib):
+    from paper_2311_13182_amd import _lib as L
+    from paper_2311_13182_amd import scenes as S
+    from paper_2311_13182_amd import sbr
+    fake = ct.c_void_p(0x10000)   # never dereferenced: checks fail first
+    assert lib.sbr_trace(None, None, None, None, None, None, None) == L.SBR_E_ARG
+    assert b"mesh" in lib.sbr_last_error()
+    sc = S.icosphere_scene(level=1, n_rays=16, n_chirps=4)
+    m = L.sbr_mesh(0x10000, sc.nv, 0x20000, sc.nf, None)
+    r, g, c = sbr.radar_struct(sc.radar), sbr.rays_struct(sc.grid), sbr.chirp_struct(sc.chirp)
+    h = L.sbr_hits(0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
+    bad = sbr.rays_struct(sc.grid.__class__(16, 16, 0.1, 0.1, 9))
+    assert lib.sbr_trace(ct.byref(m), fake, ct.byref(r), ct.byref(bad), ct.byref(h), None, None) == L.SBR_E_ARG
+    assert b"max_bounces" in lib.sbr_last_error()
+    # scratch too small -> SBR_E_SCRATCH with the required size in the message
+    rc = lib.sbr_synth_if(ct.byref(m), None, 0, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
+                          fake, 16, None)
+    assert rc == L.SBR_E_SCRATCH and b"needed" in lib.sbr_last_error()
+    rc = lib.sbr_backward(ct.byref(m), None, 0, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
+                          fake, fake, 16, None)
+    assert rc == L.SBR_E_SCRATCH
+    # radar cube: n_angle below V, bad window, bad direction
+    assert lib.sbr_radar_cube(fake, 12, 8, 16, 8, 0, 0, fake, fake, 1 << 30, None) == L.SBR_E_ARG
+    assert lib.sbr_radar_cube(fake, 12, 8, 16, 64, 2, 0, fake, fake, 1 << 30, None) == L.SBR_E_ARG
+    assert lib.sbr_radar_cube(fake, 12, 8, 16, 64, 0, 5, fake, fake, 1 << 30, None) == L.SBR_E_ARG
+    # too many antennas
+    rr = sbr.radar_struct(sc.radar)
+    rr.n_tx, rr.n_rx = 8, 16
+    assert lib.sbr_synth_if(ct.byref(m), None, 0, ct.byref(rr), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
+                            fake, 1 << 40, None) == L.SBR_E_ARG
+    # material modes outside {0,1,2}
+    mats = (L.sbr_material * 1)()
+    mats[0].mode = 7
+    assert lib.sbr_synth_if(ct.byref(m), mats, 1, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
+                            fake, 1 << 40, None) == L.SBR_E_ARG
+    # CFAR: bad pfa
+    assert lib.sbr_cfar(fake, 4, 8, 16, 2, 8, ct.c_double(2.0), fake, None, 10, fake, fake, 1 << 30,
+                        None) == L.SBR_E_ARG
+    # BVH: empty mesh
+    m0 = L.sbr_mesh(None, 0, None, 0, None)
+    assert lib.sbr_build_bvh(ct.byref(m0), fake, 1 << 20, 0, fake, 1 << 20, None) == L.SBR_E_ARG
+
+
+def test_product_path_fails_loudly_without_library(tmp_path):
+    from paper_2311_13182_amd import _lib as L
+    with pytest.raises(ImportError):
+        L._lib_backup = L._lib
+        try:
+            L._lib = None
+            L.load(str(tmp_path / "missing.so"))
+        finally:
+            L._lib = L._lib_backup
