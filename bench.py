@@ -1,0 +1,197 @@
+#!/usr/bin/env python
+"""Benchmark: one full forward + backward pass of the SBR radar simulator per
+step on one MI355X, on a seeded synthetic scene.
+
+Step = BVH build, trace (ray launch, traversal, multi-bounce), FP64 path
+refinement + IF synthesis (Eq. 8), radar cube (Eq. 16's T), CA-CFAR points,
+IF-loss gradient, backward (synthesis adjoint, Eqs. 11-12, and geometry
+adjoint to the vertices, Eq. 13).  Inputs are resident in device memory before
+the timed region.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+FLOP_PER_PATH_SAMPLE = {"synth": 8.0, "synth_adj": 20.0}
+
+
+def make_workload(name: str):
+    from paper_2311_13182_amd import scenes as S
+    if name == "clutter_50k":
+        return S.clutter_scene()
+    if name == "icosphere_20k":
+        return S.icosphere_scene()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(scene, queries_full: int, budget_rows: int = 16, chirp_stride: int = 16):
+    """The FP64 oracle (trace + paths + synthesis + synthesis adjoint) on a
+    bounded sample: every `budget_rows`-th ray row and column, every
+    `chirp_stride`-th chirp; scaled linearly to the full workload."""
+    import numpy as np
+    from oracle import pyoracle as orc
+    g = scene.grid
+    sub = np.arange(budget_rows // 2, g.nx, budget_rows)
+    rows = np.arange(budget_rows // 2, g.ny, budget_rows)
+    rays = (rows[:, None] * g.nx + sub[None, :]).reshape(-1).astype(np.int32)
+    Cs = max(1, scene.chirp.n_chirps // chirp_stride)
+    sc_s = scene.with_chirp(n_chirps=Cs)
+    t0 = time.perf_counter()
+    tr = orc.trace(scene, rays=rays)
+    t1 = time.perf_counter()
+    p = orc.paths(sc_s, tr["tri"], tr["flags"], rays=rays)
+    cube = orc.synth(sc_s, p)
+    t2 = time.perf_counter()
+    G = np.random.default_rng(0).normal(size=cube.shape) + 1j * np.random.default_rng(1).normal(size=cube.shape)
+    orc.synth_adjoint(sc_s, p, G)
+    t3 = time.perf_counter()
+    fr = g.n_rays / len(rays)
+    fc = scene.chirp.n_chirps / Cs
+    est = (t1 - t0) * fr + (t3 - t1) * fr * fc
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": queries_full / est,
+        "unit": "ray-bounces/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{len(rays)} of {g.n_rays} rays (every {budget_rows}th row/col), {Cs} of "
+                   f"{scene.chirp.n_chirps} chirps, {len(p['amp'])} paths; measured {t3 - t0:.1f} s "
+                   f"(trace {t1 - t0:.1f} s, synth {t2 - t1:.1f} s, adjoint {t3 - t2:.1f} s); "
+                   f"full fwd+bwd time extrapolated linearly in rays and chirps: {est:.0f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="clutter_50k", choices=["clutter_50k", "icosphere_20k"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the ray-sharded multi-GPU split is a design "
+              "note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2311_13182_amd import _lib
+    from paper_2311_13182_amd import scenes as S
+    from paper_2311_13182_amd.sbr import Simulator, sbr_profile, sbr_profile_read
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    _lib.load()
+    dev = torch.device("cuda:0")
+    scene = make_workload(args.workload)
+    g, ch, rd = scene.grid, scene.chirp, scene.radar
+    V, C, Sn = rd.n_virtual, ch.n_chirps, ch.n_samples
+
+    # target IF cube of the same scene with 2 mm vertex jitter (untimed)
+    tsim = Simulator(S.jitter(scene, 2e-3, 33), dev)
+    target = tsim.forward().clone()
+    del tsim
+    torch.cuda.empty_cache()
+
+    sim = Simulator(scene, dev)
+    cube = torch.empty((V, C, Sn, 2), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(cube)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    gv = torch.empty((sim.mesh.nv, 3), dtype=torch.float32, device=dev)
+
+    def step():
+        sim.build()
+        sim.trace()
+        sim.synth(cube)
+        X = sim.radar_cube(cube)
+        sim.cfar(X, max_points=4096)
+        sim.loss_grad(cube, target, grad, loss)
+        gv.zero_()
+        sim.backward(grad, gv)
+
+    # path and query counts of this scene (counted on the device)
+    sim.build()
+    sim.counters.zero_()
+    sim.trace(count=True)
+    sim.synth(cube)
+    torch.cuda.synchronize()
+    n_paths = sim.n_paths()
+    cnt = sim.counters.cpu().numpy()
+    queries = int(cnt[0])
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sbr_profile(2)
+    sbr_profile(1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    sbr_profile(0)
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    k_ms = {}
+    for name, kid in (("synth", _lib.PROF_SYNTH), ("synth_adj", _lib.PROF_SYNTH_ADJ), ("trace", _lib.PROF_TRACE)):
+        tot, n = sbr_profile_read(kid)
+        k_ms[name] = tot / max(n, 1)
+    ps = float(n_paths) * V * C * Sn          # path-samples per launch
+    dominant = max(("synth", "synth_adj"), key=lambda k: k_ms[k])
+    achieved = FLOP_PER_PATH_SAMPLE[dominant] * ps / (k_ms[dominant] * 1e-3) / 1e12
+    roof = {
+        "bound": "alu",
+        "kernel": "k_synth_adj" if dominant == "synth_adj" else "k_synth",
+        "achieved": round(achieved, 3),
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+        "traffic": None,
+    }
+    out = {
+        "metric": "ray-bounces/s fwd+bwd",
+        "value": queries / (ms_step * 1e-3),
+        "unit": "ray-bounces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}_fwd_bwd", "triangles": scene.nf, "rays": g.n_rays,
+                   "max_bounces": g.max_bounces, "virtual_antennas": V, "chirps": C, "samples": Sn,
+                   "parallelism": "single-gpu"},
+        "ray_bounces_per_step": queries,
+        "paths": n_paths,
+        "if_path_samples_per_s": ps / (ms_step * 1e-3),
+        "if_output_samples_per_s": V * C * Sn / (ms_step * 1e-3),
+        "kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
+        "wall_ms_per_step": (w1 - w0) * 1e3 / args.steps,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, queries)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

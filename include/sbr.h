@@ -219,6 +219,27 @@ int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
 /* Number of paths the last sbr_synth_if / sbr_backward found is left in the
  * first int32 of their scratch buffer (device) once the stream reaches it. */
 
+/* Loss of the inverse problem (Sec. 3.4.1, Eq. 14) and its gradient, the
+ * entry point of the backward pass.  n complex elements, device arrays.
+ * mode 0 (IF loss):      L = sum |a - b|^2,                 grad = 2 (a - b)
+ * mode 1 (heatmap loss, the MSE of Eq. 16 on the image |X|^2, with a = X and
+ *   b = the target heatmap H as float [n]): L = mean (|a|^2 - H)^2,
+ *   grad = 4 (|a|^2 - H) a / n
+ * grad: device float [n][2] = dL/dRe a + i dL/dIm a (overwritten; may be NULL);
+ * loss: device float[1] (overwritten; may be NULL).  The sum is reduced in a
+ * fixed order (deterministic). */
+int sbr_loss_grad(int32_t mode, const float *a, const float *b, int64_t n, float *grad,
+                  float *loss, void *stream);
+
+/* Kernel timing for benchmarks.  sbr_profile(1) starts bracketing every launch
+ * of the IF synthesis kernel (id 0), the synthesis-adjoint kernel (id 1) and
+ * the trace kernel (id 2) with HIP events on the launching stream;
+ * sbr_profile(0) stops; sbr_profile(2) discards what was recorded.
+ * sbr_profile_read waits for the recorded events of one kernel id and returns
+ * the summed milliseconds and the number of launches, then discards them. */
+int sbr_profile(int32_t op);
+int sbr_profile_read(int32_t kernel, double *total_ms, int64_t *launches);
+
 /* Message describing the calling thread's last error ("" if none). */
 const char *sbr_last_error(void);
 

@@ -20,7 +20,9 @@ SBR_OP_BUILD_BVH, SBR_OP_SYNTH, SBR_OP_BACKWARD, SBR_OP_RADAR_CUBE, SBR_OP_CFAR 
 
 # every function declared in include/sbr.h
 EXPORTS = ("sbr_bvh_bytes", "sbr_scratch_bytes", "sbr_build_bvh", "sbr_trace", "sbr_synth_if",
-           "sbr_radar_cube", "sbr_cfar", "sbr_backward", "sbr_last_error")
+           "sbr_radar_cube", "sbr_cfar", "sbr_backward", "sbr_last_error", "sbr_loss_grad", "sbr_profile",
+           "sbr_profile_read")
+PROF_SYNTH, PROF_SYNTH_ADJ, PROF_TRACE = 0, 1, 2
 
 
 class SbrError(RuntimeError):
@@ -94,6 +96,12 @@ def load(path: str = LIB_PATH):
     L.sbr_backward.restype = ct.c_int
     L.sbr_backward.argtypes = [P(sbr_mesh), P(sbr_material), i32, P(sbr_radar), P(sbr_rays), P(sbr_hits),
                                P(sbr_chirp), i32, vp, vp, vp, sz, vp]
+    L.sbr_loss_grad.restype = ct.c_int
+    L.sbr_loss_grad.argtypes = [i32, vp, vp, ct.c_int64, vp, vp, vp]
+    L.sbr_profile.restype = ct.c_int
+    L.sbr_profile.argtypes = [i32]
+    L.sbr_profile_read.restype = ct.c_int
+    L.sbr_profile_read.argtypes = [i32, P(ct.c_double), P(ct.c_int64)]
     _lib = L
     return L
 

@@ -14,6 +14,7 @@ struct AdjArgs {
     const float2 *G;       // [V][C][S]
     int32_t V, C, S;
     int32_t rows;          // G rows per LDS stage
+    int32_t Sp;            // S rounded up to a multiple of 8
     int32_t v_per;         // antennas per y-block
     int32_t nvs;           // y-blocks
     float fcf, sl_fs, tc;  // fc, slope / fs, chirp period
@@ -30,7 +31,7 @@ constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time (at most 64 K
 //   dL/dA    += conj(z0 P(x))                                  (Eq. 12)
 //   dL/dtau  += -2 pi Im(A (fc z0 P + (slope/fs) z0 x P'))       (Eq. 11)
 __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
-    extern __shared__ float2 gsh[];   // [rows][S]
+    extern __shared__ float2 gsh[];   // [rows][Sp]
     const int P = a.count[0];
     const int blk_p0 = blockIdx.x * 256;
     if (blk_p0 >= P) return;   // uniform over the block
@@ -49,8 +50,13 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
         for (int c0 = 0; c0 < a.C; c0 += a.rows) {
             const int nr = min(a.rows, a.C - c0);
             __syncthreads();
+            // rows padded with zeros to Sp = S rounded up to 8: leading zero
+            // coefficients leave Horner's recurrences unchanged
             const float2 *src = a.G + ((size_t)v * a.C + c0) * S;
-            for (int i = threadIdx.x; i < nr * S; i += 256) gsh[i] = src[i];
+            for (int i = threadIdx.x; i < nr * a.Sp; i += 256) {
+                const int rr = i / a.Sp, ss = i - rr * a.Sp;
+                gsh[i] = ss < S ? src[(size_t)rr * S + ss] : make_float2(0.0f, 0.0f);
+            }
             __syncthreads();
             for (int cc = 0; cc < nr; cc++) {
                 const int c = c0 + cc;
@@ -62,22 +68,32 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
                 const float zs = __builtin_amdgcn_sinf(ph), zc = __builtin_amdgcn_cosf(ph);
                 const float dd = delta - rintf(delta);
                 const float xs = __builtin_amdgcn_sinf(dd), xc = __builtin_amdgcn_cosf(dd);
-                const float2 *g = gsh + cc * S;
-                float2 gl = g[S - 1];
-                float pr = gl.x, pi = -gl.y;   // conj(G)
-                float qr = 0.0f, qi = 0.0f;
-                for (int s = S - 2; s >= 0; s--) {
-                    const float2 gs = g[s];
-                    // q = q x + p ;  p = p x + conj(g_s)
-                    float nqr = fmaf(qr, xc, fmaf(-qi, xs, pr));
-                    float nqi = fmaf(qr, xs, fmaf(qi, xc, pi));
-                    float npr = fmaf(pr, xc, fmaf(-pi, xs, gs.x));
-                    float npi = fmaf(pr, xs, fmaf(pi, xc, -gs.y));
-                    qr = nqr;
-                    qi = nqi;
-                    pr = npr;
-                    pi = npi;
+                const float4 *g4 = reinterpret_cast<const float4 *>(gsh + cc * a.Sp);
+                float pr = 0.0f, pi = 0.0f, qr = 0.0f, qi = 0.0f;
+                // q = q x + p ;  p = p x + conj(g_s), s descending
+#define SBR_HORNER_STEP(GR, GI)                                 \
+    {                                                          \
+        float nqr = fmaf(qr, xc, fmaf(-qi, xs, pr));           \
+        float nqi = fmaf(qr, xs, fmaf(qi, xc, pi));            \
+        float npr = fmaf(pr, xc, fmaf(-pi, xs, (GR)));         \
+        float npi = fmaf(pr, xs, fmaf(pi, xc, -(GI)));         \
+        qr = nqr;                                              \
+        qi = nqi;                                              \
+        pr = npr;                                              \
+        pi = npi;                                              \
+    }
+                for (int j = a.Sp / 2 - 4; j >= 0; j -= 4) {
+                    const float4 h3 = g4[j + 3], h2 = g4[j + 2], h1 = g4[j + 1], h0 = g4[j];
+                    SBR_HORNER_STEP(h3.z, h3.w)
+                    SBR_HORNER_STEP(h3.x, h3.y)
+                    SBR_HORNER_STEP(h2.z, h2.w)
+                    SBR_HORNER_STEP(h2.x, h2.y)
+                    SBR_HORNER_STEP(h1.z, h1.w)
+                    SBR_HORNER_STEP(h1.x, h1.y)
+                    SBR_HORNER_STEP(h0.z, h0.w)
+                    SBR_HORNER_STEP(h0.x, h0.y)
                 }
+#undef SBR_HORNER_STEP
                 // Q0 = z0 P, Q1 = z0 x P'
                 const float q0r = zc * pr - zs * pi, q0i = zc * pi + zs * pr;
                 const float xqr = xc * qr - xs * qi, xqi = xc * qi + xs * qr;
@@ -365,9 +381,13 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     a.tau_bar = tau_bar;
     a.abar_part = part;
     dim3 grid((unsigned)((cap + 255) / 256), (unsigned)bp.nvs);
-    a.rows = std::max(1, std::min(kAdjRowsMax, 8192 / cd.S));
-    size_t lds = sizeof(float2) * a.rows * cd.S;
-    hipLaunchKernelGGL(k_synth_adj, grid, dim3(256), lds, s, a);
+    a.Sp = (cd.S + 7) / 8 * 8;
+    a.rows = std::max(1, std::min(kAdjRowsMax, 8192 / a.Sp));
+    size_t lds = sizeof(float2) * a.rows * a.Sp;
+    {
+        ProfScope ps(kProfSynthAdj, s);
+        hipLaunchKernelGGL(k_synth_adj, grid, dim3(256), lds, s, a);
+    }
     hipLaunchKernelGGL(k_reduce_abar, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st.count, part,
                        bp.nvs, (int)cap, abar);
     SBR_LAUNCHED();

@@ -1,0 +1,157 @@
+// Loss entry of the backward pass and benchmark timing hooks.
+#include <mutex>
+#include <vector>
+
+#include "sbr_internal.h"
+
+namespace sbr {
+
+namespace {
+
+__global__ void k_loss_grad(int mode, const float2 *a, const float *b, long long n, float2 *grad) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float2 x = a[i];
+    if (mode == 0) {
+        float2 y = reinterpret_cast<const float2 *>(b)[i];
+        grad[i] = make_float2(2.0f * (x.x - y.x), 2.0f * (x.y - y.y));
+    } else {
+        float e = x.x * x.x + x.y * x.y - b[i];
+        float s = 4.0f * e / (float)n;
+        grad[i] = make_float2(s * x.x, s * x.y);
+    }
+}
+
+// fixed-order reduction in one block, double accumulation
+__global__ __launch_bounds__(1024) void k_loss(int mode, const float2 *a, const float *b, long long n,
+                                               float *loss) {
+    __shared__ double part[1024];
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 1024) {
+        float2 x = a[i];
+        double e;
+        if (mode == 0) {
+            float2 y = reinterpret_cast<const float2 *>(b)[i];
+            double dr = (double)x.x - y.x, di = (double)x.y - y.y;
+            e = dr * dr + di * di;
+        } else {
+            double q = (double)x.x * x.x + (double)x.y * x.y - b[i];
+            e = q * q;
+        }
+        s += e;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 512; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(mode == 0 ? part[0] : part[0] / (double)n);
+}
+
+struct ProfRec {
+    hipEvent_t a, b;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<ProfRec> g_rec[3];
+
+}  // namespace
+
+ProfScope::ProfScope(int id, hipStream_t s) : id_(id), s_(s), active_(false) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_on || id < 0 || id > 2) return;
+    if (hipEventCreate(&a_) != hipSuccess) return;
+    if (hipEventCreate(&b_) != hipSuccess) {
+        (void)hipEventDestroy(a_);
+        return;
+    }
+    if (hipEventRecord(a_, s_) != hipSuccess) return;
+    active_ = true;
+}
+
+ProfScope::~ProfScope() {
+    if (!active_) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (hipEventRecord(b_, s_) == hipSuccess) g_rec[id_].push_back({a_, b_});
+}
+
+int fill_zero_f32(float *p, size_t n, hipStream_t s);
+
+}  // namespace sbr
+
+using namespace sbr;
+
+extern "C" {
+
+int sbr_loss_grad(int32_t mode, const float *a, const float *b, int64_t n, float *grad, float *loss,
+                  void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(mode == 0 || mode == 1, "mode must be 0 (IF) or 1 (heatmap)");
+    SBR_CHECK_ARG(n >= 0, "n must be >= 0");
+    SBR_CHECK_ARG(n == 0 || (a && b), "a/b is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        if (loss) return fill_zero_f32(loss, 1, s);
+        return SBR_OK;
+    }
+    const float2 *a2 = reinterpret_cast<const float2 *>(a);
+    if (grad)
+        hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int)mode, a2, b,
+                           (long long)n, reinterpret_cast<float2 *>(grad));
+    if (loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, (int)mode, a2, b, (long long)n, loss);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+int sbr_profile(int32_t op) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (op == 0 || op == 1) {
+        g_on = op == 1;
+        return SBR_OK;
+    }
+    if (op == 2) {
+        for (auto &v : g_rec) {
+            for (auto &r : v) {
+                (void)hipEventSynchronize(r.b);
+                (void)hipEventDestroy(r.a);
+                (void)hipEventDestroy(r.b);
+            }
+            v.clear();
+        }
+        return SBR_OK;
+    }
+    set_error("sbr_profile: op must be 0, 1 or 2");
+    return SBR_E_ARG;
+}
+
+int sbr_profile_read(int32_t kernel, double *total_ms, int64_t *launches) {
+    clear_error();
+    SBR_CHECK_ARG(kernel >= 0 && kernel <= 2, "kernel id must be 0, 1 or 2");
+    SBR_CHECK_ARG(total_ms && launches, "outputs are NULL");
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        recs.swap(g_rec[kernel]);
+    }
+    double tot = 0.0;
+    int rc = SBR_OK;
+    for (auto &r : recs) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && rc == SBR_OK) {
+            set_error("event timing failed: %s", hipGetErrorString(e));
+            rc = SBR_E_HIP;
+        }
+        tot += ms;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    *total_ms = tot;
+    *launches = (int64_t)recs.size();
+    return rc;
+}
+
+}  // extern "C"

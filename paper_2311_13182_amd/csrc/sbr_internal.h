@@ -163,6 +163,20 @@ RadarDev make_radar(const sbr_radar *r);
 GridDev make_grid(const sbr_rays *g);
 ChirpDev make_chirp(const sbr_chirp *c);
 
+// Brackets one kernel launch with HIP events while sbr_profile(1) is on.
+class ProfScope {
+   public:
+    ProfScope(int id, hipStream_t s);
+    ~ProfScope();
+
+   private:
+    int id_;
+    hipStream_t s_;
+    bool active_;
+    hipEvent_t a_{}, b_{};
+};
+enum { kProfSynth = 0, kProfSynthAdj = 1, kProfTrace = 2 };
+
 // enqueue path compaction + FP64 refinement; records go to st.rec
 int launch_paths(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                  const ChirpDev &cd, const sbr_hits *h, int32_t flags, const PathStage &st,

@@ -269,10 +269,27 @@ __global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
     }
     const float *al = a.rec.alpha + (size_t)v * a.rec.cap;
     const float *ga = a.rec.gamma + (size_t)v * a.rec.cap;
+    // path records are wavefront-uniform (scalar loads); the next path's
+    // record is fetched while the current one is accumulated
+    float n_al = 0.f, n_ga = 0.f, n_be = 0.f, n_ep = 0.f;
+    float2 n_A = make_float2(0.f, 0.f);
+    if (p0 < p1) {
+        n_al = al[p0];
+        n_ga = ga[p0];
+        n_A = a.rec.amp[p0];
+        n_be = a.rec.beta[p0];
+        n_ep = a.rec.epsd[p0];
+    }
     for (int p = p0; p < p1; p++) {
-        const float alpha = al[p], gamma = ga[p];
-        const float2 A = a.rec.amp[p];
-        const float beta = a.rec.beta[p], epsd = a.rec.epsd[p];
+        const float alpha = n_al, gamma = n_ga, beta = n_be, epsd = n_ep;
+        const float2 A = n_A;
+        if (p + 1 < p1) {
+            n_al = al[p + 1];
+            n_ga = ga[p + 1];
+            n_A = a.rec.amp[p + 1];
+            n_be = a.rec.beta[p + 1];
+            n_ep = a.rec.epsd[p + 1];
+        }
         const float delta = fmaf(cf, epsd, gamma);            // cycles per sample
         float ph = alpha + frac_mul(cf, beta) + frac_mul(s0, delta);
         ph = ph - rintf(ph);
@@ -368,12 +385,15 @@ int launch_synth(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, 
     a.partial = partial;
     long long waves = (long long)V * p.tiles_per_v;
     dim3 grid((unsigned)((waves + 3) / 4), (unsigned)p.n_chunks);
-    if (p.L == 64)
-        hipLaunchKernelGGL(k_synth<64>, grid, dim3(256), 0, s, a);
-    else if (p.L == 32)
-        hipLaunchKernelGGL(k_synth<32>, grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_synth<16>, grid, dim3(256), 0, s, a);
+    {
+        ProfScope ps(kProfSynth, s);
+        if (p.L == 64)
+            hipLaunchKernelGGL(k_synth<64>, grid, dim3(256), 0, s, a);
+        else if (p.L == 32)
+            hipLaunchKernelGGL(k_synth<32>, grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_synth<16>, grid, dim3(256), 0, s, a);
+    }
     size_t n = (size_t)V * C * S;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial,
                        p.n_chunks, n, out);

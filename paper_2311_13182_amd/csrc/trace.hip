@@ -259,10 +259,13 @@ int trace_launch(const sbr_mesh *m, const void *bvh, const RadarDev &rd, const G
     long long tiles = (long long)((gd.nx + 7) / 8) * ((gd.ny + 7) / 8);
     long long threads = tiles * 64;
     int blocks = (int)((threads + 255) / 256);
-    if (counters)
-        hipLaunchKernelGGL(k_trace<true>, dim3(blocks), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_trace<false>, dim3(blocks), dim3(256), 0, st, a);
+    {
+        ProfScope ps(kProfTrace, st);
+        if (counters)
+            hipLaunchKernelGGL(k_trace<true>, dim3(blocks), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_trace<false>, dim3(blocks), dim3(256), 0, st, a);
+    }
     SBR_LAUNCHED();
     return SBR_OK;
 }

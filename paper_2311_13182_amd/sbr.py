@@ -183,6 +183,22 @@ def sbr_backward(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chi
                                 scratch.numel() * scratch.element_size(), _stream()))
 
 
+def sbr_loss_grad(mode: int, a: torch.Tensor, b: torch.Tensor, n: int, grad: Optional[torch.Tensor],
+                  loss: Optional[torch.Tensor]):
+    L.check(_lib().sbr_loss_grad(int(mode), _p(a), _p(b), int(n), _p(grad), _p(loss), _stream()))
+
+
+def sbr_profile(op: int):
+    L.check(_lib().sbr_profile(int(op)))
+
+
+def sbr_profile_read(kernel: int):
+    """(summed milliseconds, launches) of the recorded launches of one kernel."""
+    ms, n = ct.c_double(), ct.c_int64()
+    L.check(_lib().sbr_profile_read(int(kernel), ct.byref(ms), ct.byref(n)))
+    return ms.value, n.value
+
+
 def last_error() -> str:
     return _lib().sbr_last_error().decode()
 
@@ -268,6 +284,19 @@ class Simulator:
         sbr_backward(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, self.flags, gf,
                      grad_verts, self.scratch)
         return grad_verts
+
+    def loss_grad(self, cube: torch.Tensor, target: torch.Tensor, grad: Optional[torch.Tensor] = None,
+                  loss: Optional[torch.Tensor] = None, mode: int = 0):
+        """IF loss sum |S - target|^2 (mode 0) or heatmap MSE (mode 1) and its gradient."""
+        a = (torch.view_as_real(cube) if cube.is_complex() else cube).contiguous()
+        b = (torch.view_as_real(target) if target.is_complex() else target).contiguous()
+        n = a.numel() // 2
+        if grad is None:
+            grad = torch.empty_like(a)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        sbr_loss_grad(mode, a, b, n, grad, loss)
+        return grad, loss
 
     def n_paths(self) -> int:
         return int(self.scratch[:4].view(torch.int32)[0].item())

@@ -312,3 +312,23 @@ def test_backward_fresnel_coordinates(torch_cuda, orc):
     e = rel_l2(got.reshape(-1)[coords], fd)
     log(f"backward fresnel: rel L2 {e:.3e}")
     assert e <= GRAD_TOL
+
+
+def test_loss_grad_entry(torch_cuda):
+    import torch
+    from paper_2311_13182_amd.sbr import Simulator
+    rng = np.random.default_rng(2)
+    a = (rng.normal(size=(3, 4, 50)) + 1j * rng.normal(size=(3, 4, 50))).astype(np.complex64)
+    b = (rng.normal(size=(3, 4, 50)) + 1j * rng.normal(size=(3, 4, 50))).astype(np.complex64)
+    sim = _sim(S.icosphere_scene(level=1, n_rays=8, n_chirps=4).with_chirp(n_samples=50))
+    g, l = sim.loss_grad(torch.as_tensor(a, device="cuda"), torch.as_tensor(b, device="cuda"))
+    torch.cuda.synchronize()
+    d = a.astype(np.complex128) - b
+    assert abs(float(l.item()) - np.sum(np.abs(d) ** 2)) <= 1e-5 * np.sum(np.abs(d) ** 2)
+    assert np.allclose(torch.view_as_complex(g).cpu().numpy(), 2 * d, rtol=1e-6, atol=1e-6)
+    H = rng.uniform(size=(3, 4, 50)).astype(np.float32)
+    g, l = sim.loss_grad(torch.as_tensor(a, device="cuda"), torch.as_tensor(H, device="cuda"), mode=1)
+    q = np.abs(a.astype(np.complex128)) ** 2 - H
+    assert abs(float(l.item()) - np.mean(q ** 2)) <= 1e-5 * np.mean(q ** 2)
+    ref = 4 * q * a / a.size
+    assert np.allclose(torch.view_as_complex(g).cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
