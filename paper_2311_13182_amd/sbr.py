@@ -99,8 +99,24 @@ class DeviceMesh:
                           self.mat_id.data_ptr() if self.mat_id is not None else None)
 
     @classmethod
-    def from_scene(cls, sc: S.Scene, device="cuda"):
-        return cls(sc.verts, sc.faces, sc.mat_id, sc.materials, device)
+    def from_scene(cls, sc: S.Scene, device="cuda", non_blocking: bool = False):
+        if not non_blocking:
+            return cls(sc.verts, sc.faces, sc.mat_id, sc.materials, device)
+        # pinned staging + asynchronous copies on the current stream; the
+        # staging tensors live as long as the mesh
+        self = cls.__new__(cls)
+        vs = torch.from_numpy(np.ascontiguousarray(sc.verts, np.float32)).pin_memory()
+        fs = torch.from_numpy(np.ascontiguousarray(sc.faces, np.int32)).pin_memory()
+        self.verts = vs.to(device, non_blocking=True)
+        self.faces = fs.to(device, non_blocking=True)
+        self._staging = [vs, fs]
+        self.mat_id = None
+        if sc.mat_id is not None:
+            ms = torch.from_numpy(np.asarray(sc.mat_id).astype(np.int16)).pin_memory()
+            self.mat_id = ms.to(device, non_blocking=True)
+            self._staging.append(ms)
+        self.materials = list(sc.materials)
+        return self
 
 
 @dataclasses.dataclass
@@ -208,10 +224,11 @@ class Simulator:
     """One scene resident on the device: mesh, BVH, hit records, one scratch
     buffer shared by all stages (stages on one stream run in order)."""
 
-    def __init__(self, scene: S.Scene, device="cuda", drop_flagged: bool = True, n_angle: int = 64):
+    def __init__(self, scene: S.Scene, device="cuda", drop_flagged: bool = True, n_angle: int = 64,
+                 mesh: Optional[DeviceMesh] = None, bvh: Optional[torch.Tensor] = None):
         self.scene = scene
         self.device = torch.device(device)
-        self.mesh = DeviceMesh.from_scene(scene, self.device)
+        self.mesh = mesh if mesh is not None else DeviceMesh.from_scene(scene, self.device)
         self.flags = L.SBR_DROP_FLAGGED if drop_flagged else 0
         g, rd, ch = scene.grid, scene.radar, scene.chirp
         self.K, self.R = g.max_bounces, g.nx * g.ny
@@ -225,10 +242,11 @@ class Simulator:
         # the cube stage needs room for max(V, n_angle) planes
         need = max(need, 2 * 8 * self.n_angle * self.C * self.S + 1024)
         self.scratch = torch.empty(need, dtype=torch.uint8, device=self.device)
-        self.bvh = torch.empty(max(1, sbr_bvh_bytes(self.mesh.nf)), dtype=torch.uint8, device=self.device)
+        self.bvh = bvh if bvh is not None else torch.empty(max(1, sbr_bvh_bytes(self.mesh.nf)), dtype=torch.uint8,
+                                                           device=self.device)
         self.hits = Hits.empty(self.K, self.R, self.device)
         self.counters = torch.zeros(3, dtype=torch.int64, device=self.device)
-        self.built = False
+        self.built = bvh is not None
 
     # ---- geometry
     def set_verts(self, verts: torch.Tensor):

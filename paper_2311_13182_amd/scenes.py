@@ -222,19 +222,19 @@ def superquadric(n_lon: int, n_lat: int, axes, e1: float, e2: float):
     north = np.array([[0.0, 0.0, a3]])
     verts = np.concatenate([ring, south, north])
     S, N = len(ring), len(ring) + 1
-    faces = []
     nr = n_lat - 1
-    for i in range(nr - 1):
-        for j in range(n_lon):
-            j2 = (j + 1) % n_lon
-            a, b = i * n_lon + j, i * n_lon + j2
-            c, d = (i + 1) * n_lon + j, (i + 1) * n_lon + j2
-            faces += [[a, b, d], [a, d, c]]
-    for j in range(n_lon):
-        j2 = (j + 1) % n_lon
-        faces.append([S, j2, j])
-        top = (nr - 1) * n_lon
-        faces.append([N, top + j, top + j2])
+    i, j = np.meshgrid(np.arange(nr - 1), np.arange(n_lon), indexing="ij")
+    j2 = (j + 1) % n_lon
+    a, b = i * n_lon + j, i * n_lon + j2
+    c, d = (i + 1) * n_lon + j, (i + 1) * n_lon + j2
+    band = np.stack([np.stack([a, b, d], -1), np.stack([a, d, c], -1)], 2).reshape(-1, 3)
+    jj = np.arange(n_lon)
+    jj2 = (jj + 1) % n_lon
+    top = (nr - 1) * n_lon
+    south = np.stack([np.full(n_lon, S), jj2, jj], -1)
+    north = np.stack([np.full(n_lon, N), top + jj, top + jj2], -1)
+    caps = np.stack([south, north], 1).reshape(-1, 3)
+    faces = np.concatenate([band, caps])
     faces = np.asarray(faces, np.int64)
     return verts, _orient_outward(verts, faces)
 
@@ -459,6 +459,7 @@ class Request:
     arrival: float
     scene: Scene
     backward: bool
+    target: Optional[np.ndarray] = None     # filled in by the caller for backward requests
 
 
 def serving_requests(n: int = 512, qps: float = 10.0, seed: int = 5,

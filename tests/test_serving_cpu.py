@@ -1,0 +1,151 @@
+"""Scheduler logic of the serving loop, driven by a fake CPU executor and a
+manual clock (no GPU): admission by footprint, FIFO order, continuous
+batching, failure isolation, shutdown."""
+import types
+
+import pytest
+
+from paper_2311_13182_amd.serve import Request, Scheduler
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeExecutor:
+    """Each request carries .fp (bytes) and .dur (seconds of virtual time);
+    .fail_launch / .fail_poll force errors from the host side."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.live = {}
+        self.peak_used = 0
+        self.launched = []
+
+    def footprint(self, req):
+        return req.scene.fp
+
+    def launch(self, req):
+        if getattr(req.scene, "fail_launch", False):
+            raise RuntimeError("launch failed (forced)")
+        h = types.SimpleNamespace(req=req, t_end=self.clock() + req.scene.dur)
+        self.live[id(h)] = h
+        self.launched.append(req.rid)
+        self.peak_used = max(self.peak_used, sum(x.req.scene.fp for x in self.live.values()))
+        return h
+
+    def poll(self, h):
+        if getattr(h.req.scene, "fail_poll", False) and self.clock() >= h.t_end:
+            raise RuntimeError("device error (forced)")
+        return self.clock() >= h.t_end
+
+    def collect(self, h):
+        return {"cube": ("cube", h.req.rid), "n_paths": h.req.rid}
+
+    def release(self, h):
+        self.live.pop(id(h), None)
+
+
+def _req(rid, fp, dur, arrival=0.0, **kw):
+    return Request(rid, types.SimpleNamespace(fp=fp, dur=dur, **kw), arrival=arrival)
+
+
+def _run(sch, clock, until, dt=0.001):
+    while clock.t < until:
+        sch.tick()
+        clock.t += dt
+    sch.tick()
+
+
+def test_admission_respects_budget_and_fifo():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=100, max_active=8, clock=clock)
+    futs = [sch.submit(_req(i, fp, 0.05, arrival=0.001 * (i + 1))) for i, fp in enumerate([40, 40, 40, 10, 30])]
+    _run(sch, clock, 1.0)
+    res = [f.result() for f in futs]
+    assert all(r.status == "ok" for r in res)
+    assert ex.peak_used <= 100
+    # FIFO: request 3 (small) waits behind request 2 (head of line)
+    assert ex.launched == [0, 1, 2, 3, 4]
+    assert res[2].t_admit >= res[0].t_done - 1e-9
+    assert res[3].t_admit >= res[2].t_admit
+    assert sch.used_bytes == 0
+
+
+def test_continuous_batching_admits_while_others_run():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=1000, max_active=4, clock=clock)
+    long = sch.submit(_req(0, 100, 0.5, arrival=0.001))
+    short = [sch.submit(_req(i, 100, 0.01, arrival=0.01 * i)) for i in range(1, 10)]
+    _run(sch, clock, 1.0)
+    L = long.result()
+    S = [f.result() for f in short]
+    # short requests that arrived after the long one finished before it
+    assert sum(r.t_done < L.t_done for r in S) >= 8
+    assert max(len([1 for r in S + [L] if r.t_admit <= t < r.t_done]) for t in [0.05, 0.1, 0.2]) <= 4
+
+
+def test_max_active_slots():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=10 ** 9, max_active=2, clock=clock)
+    futs = [sch.submit(_req(i, 1, 0.1, arrival=0.001)) for i in range(6)]
+    _run(sch, clock, 1.0)
+    res = [f.result() for f in futs]
+    for t in [0.05, 0.15, 0.25]:
+        assert sum(r.t_admit <= t < r.t_done for r in res) <= 2
+
+
+def test_oversized_request_rejected_others_served():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=100, clock=clock)
+    f_big = sch.submit(_req(0, 1000, 0.01, arrival=0.001))
+    f_ok = sch.submit(_req(1, 50, 0.01, arrival=0.002))
+    _run(sch, clock, 0.2)
+    assert f_big.result().status == "rejected" and "exceeds" in f_big.result().error
+    assert f_ok.result().status == "ok"
+
+
+def test_failures_are_isolated_and_free_memory():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=100, clock=clock)
+    fa = sch.submit(_req(0, 60, 0.02, arrival=0.001, fail_launch=True))
+    fb = sch.submit(_req(1, 60, 0.02, arrival=0.002, fail_poll=True))
+    fc = sch.submit(_req(2, 60, 0.02, arrival=0.003))
+    _run(sch, clock, 0.5)
+    assert fa.result().status == "failed" and "launch failed" in fa.result().error
+    assert fb.result().status == "failed" and "device error" in fb.result().error
+    assert fc.result().status == "ok" and fc.result().n_paths == 2
+    assert sch.used_bytes == 0 and not ex.live
+
+
+def test_stop_fails_what_is_left():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=100, clock=clock)
+    f1 = sch.submit(_req(0, 60, 10.0, arrival=0.001))
+    f2 = sch.submit(_req(1, 60, 10.0, arrival=0.002))
+    _run(sch, clock, 0.01)
+    sch.stop(drain=False)
+    assert f1.result().status == "failed" and f2.result().status == "failed"
+    assert sch.used_bytes == 0
+
+
+def test_threaded_loop_with_real_clock():
+    import time
+    ex = FakeExecutor(time.perf_counter)
+    sch = Scheduler(ex, budget_bytes=300, max_active=3)
+    sch.start()
+    futs = [sch.submit(_req(i, 100, 0.002)) for i in range(12)]
+    res = [f.result(timeout=10) for f in futs]
+    sch.stop()
+    assert all(r.status == "ok" for r in res)
+    assert ex.peak_used <= 300
