@@ -25,6 +25,7 @@ import collections
 import concurrent.futures
 import dataclasses
 import hashlib
+import json
 import threading
 import time
 from typing import Any, Deque, Dict, List, Optional
@@ -330,8 +331,14 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
                       max_active: int = 16, grids=(256, 512, 1024, 2048), nf_range=(1000, 200000)):
     """Sequential FIFO solves vs the continuous-batching server on the same
     Poisson request stream (QPS = 1.25 x the measured sequential rate)."""
+    import sys
     import torch
+
+    def say(msg):
+        print(f"[serving] {msg}", file=sys.stderr, flush=True)
+
     reqs = S.serving_requests(n=n, qps=1.0, seed=seed, grids=grids, nf_range=nf_range)
+    say(f"{n} requests generated")
     ex = GPUExecutor(n_streams=n_streams)
     # targets of the backward requests: jittered-mesh cubes (untimed)
     for r in reqs:
@@ -345,11 +352,13 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
     ex.collect(h)
     ex.release(h)
     torch.cuda.synchronize()
+    say("targets ready")
     t0 = time.perf_counter()
     seq_all = run_sequential(ex, plain)
     seq_wall = time.perf_counter() - t0
     mu = n / seq_wall
-    out = {"mu_seq_rps": mu}
+    say(f"sequential service rate {mu:.2f} req/s")
+    out = {"mu_seq_rps": mu, "n_backward": sum(r.backward for r in reqs)}
     for tag, qps in (("main", 1.25 * mu), ("low", 0.5 * mu)):
         rng = np.random.default_rng(seed + 1)
         arr = np.cumsum(rng.exponential(1.0 / qps, size=n))
@@ -364,6 +373,7 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
         sch.stop()
         srv_w = max(r.t_done for r in res)
         out[tag] = {"qps": qps, "sequential": summarize(seq, seq_w), "server": summarize(res, srv_w)}
+        say(f"{tag}: {json.dumps(out[tag])}")
     return out
 
 
