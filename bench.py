@@ -26,6 +26,32 @@ PEAK_HBM_GBS = 8000.0
 FLOP_PER_PATH_SAMPLE = {"synth": 8.0, "synth_adj": 20.0}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__k_synth_adj__clutter_50k_fwd_bwd.md")
+KERNEL_SOURCES = {
+    "k_synth_adj": ["backward.hip", "sbr_internal.h", "sbr_device.h"],
+    "k_synth": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
+}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs (FETCH_SIZE
+    + WRITE_SIZE, calibrated against a plain copy), or None when the kernel's
+    sources changed since the counters were taken or the workload differs."""
+    import hashlib
+    if workload != "clutter_50k" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith(kernel + ".") and "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip().split(".", 1)[1]] = v.strip()
+    src = b"".join(open(os.path.join(ROOT, "paper_2311_13182_amd", "csrc", f), "rb").read()
+                   for f in KERNEL_SOURCES[kernel])
+    if kv.get("source_sha1") != hashlib.sha1(src).hexdigest():
+        return None
+    return float(kv["traffic_bytes"])
+
+
 def make_workload(name: str):
     from paper_2311_13182_amd import scenes as S
     if name == "clutter_50k":
@@ -79,6 +105,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="clutter_50k", choices=["clutter_50k", "icosphere_20k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the ray-sharded multi-GPU split is a design "
@@ -121,6 +149,12 @@ def main():
         gv.zero_()
         sim.backward(grad, gv)
 
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     # path and query counts of this scene (counted on the device)
     sim.build()
     sim.counters.zero_()
@@ -162,7 +196,7 @@ def main():
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-        "traffic": None,
+        "traffic": measured_traffic("k_synth_adj" if dominant == "synth_adj" else "k_synth", args.workload),
     }
     out = {
         "metric": "ray-bounces/s fwd+bwd",

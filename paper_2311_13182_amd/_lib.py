@@ -73,6 +73,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libsbr.so not found at {path}; build it with "
                           f"`python -m paper_2311_13182_amd.build` (hipcc, gfx950)")
+    # The library shares device memory and streams with PyTorch, so it must bind
+    # to the HIP runtime PyTorch loads: import torch before the library.
+    import torch  # noqa: F401
     L = ct.CDLL(path)
     P = ct.POINTER
     vp, i32, sz = ct.c_void_p, ct.c_int32, ct.c_size_t

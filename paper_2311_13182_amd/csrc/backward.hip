@@ -23,6 +23,7 @@ struct AdjArgs {
 };
 
 constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time (at most 64 KiB)
+constexpr int kAdjPPL = 2;       // paths per lane
 
 // Path-stationary adjoint of Eq. (8).  For each (path, v, c) the sums
 //   P(x) = sum_s conj(G_s) x^s,  P'(x)   with x = e^{2 pi j delta}
@@ -30,23 +31,40 @@ constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time (at most 64 K
 //   sum_s w_s = z0 P(x),  sum_s s w_s = z0 x P'(x),  w_s = conj(G_s) e^{j phi_s}
 //   dL/dA    += conj(z0 P(x))                                  (Eq. 12)
 //   dL/dtau  += -2 pi Im(A (fc z0 P + (slope/fs) z0 x P'))       (Eq. 11)
+// Each lane carries PPL paths (256 apart) so every G sample read from LDS
+// feeds 8 * PPL fused multiply-adds.
+template <int PPL>
 __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
     extern __shared__ float2 gsh[];   // [rows][Sp]
     const int P = a.count[0];
-    const int blk_p0 = blockIdx.x * 256;
+    const int blk_p0 = blockIdx.x * 256 * PPL;
     if (blk_p0 >= P) return;   // uniform over the block
-    const int p = blk_p0 + threadIdx.x;
-    const bool act = p < P;
-    const int pc = act ? p : blk_p0;
+    int pp[PPL];
+    bool act[PPL];
+    float2 A[PPL];
+    float beta[PPL], epsd[PPL], abr[PPL], abi[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; i++) {
+        pp[i] = blk_p0 + i * 256 + threadIdx.x;
+        act[i] = pp[i] < P;
+        const int pc = act[i] ? pp[i] : blk_p0;
+        A[i] = a.rec.amp[pc];
+        beta[i] = a.rec.beta[pc];
+        epsd[i] = a.rec.epsd[pc];
+        abr[i] = 0.0f;
+        abi[i] = 0.0f;
+        pp[i] = pc;
+    }
     const int v0 = blockIdx.y * a.v_per, v1 = min(a.V, v0 + a.v_per);
-    const float2 A = a.rec.amp[pc];
-    const float beta = a.rec.beta[pc], epsd = a.rec.epsd[pc];
-    float abr = 0.0f, abi = 0.0f;
     const int S = a.S;
     for (int v = v0; v < v1; v++) {
-        const float alpha = a.rec.alpha[(size_t)v * a.rec.cap + pc];
-        const float gamma = a.rec.gamma[(size_t)v * a.rec.cap + pc];
-        float tb = 0.0f;
+        float alpha[PPL], gamma[PPL], tb[PPL];
+#pragma unroll
+        for (int i = 0; i < PPL; i++) {
+            alpha[i] = a.rec.alpha[(size_t)v * a.rec.cap + pp[i]];
+            gamma[i] = a.rec.gamma[(size_t)v * a.rec.cap + pp[i]];
+            tb[i] = 0.0f;
+        }
         for (int c0 = 0; c0 < a.C; c0 += a.rows) {
             const int nr = min(a.rows, a.C - c0);
             __syncthreads();
@@ -61,26 +79,32 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
             for (int cc = 0; cc < nr; cc++) {
                 const int c = c0 + cc;
                 const float cf = (float)c;
-                const float delta = fmaf(cf, epsd, gamma);
-                float cb = cf * beta;
-                float ph = alpha + fmaf(cf, beta, -rintf(cb));
-                ph -= rintf(ph);
-                const float zs = __builtin_amdgcn_sinf(ph), zc = __builtin_amdgcn_cosf(ph);
-                const float dd = delta - rintf(delta);
-                const float xs = __builtin_amdgcn_sinf(dd), xc = __builtin_amdgcn_cosf(dd);
+                float zs[PPL], zc[PPL], xs[PPL], xc[PPL], pr[PPL], pi[PPL], qr[PPL], qi[PPL];
+#pragma unroll
+                for (int i = 0; i < PPL; i++) {
+                    const float delta = fmaf(cf, epsd[i], gamma[i]);
+                    const float cb = cf * beta[i];
+                    float ph = alpha[i] + fmaf(cf, beta[i], -rintf(cb));
+                    ph -= rintf(ph);
+                    zs[i] = __builtin_amdgcn_sinf(ph);
+                    zc[i] = __builtin_amdgcn_cosf(ph);
+                    const float dd = delta - rintf(delta);
+                    xs[i] = __builtin_amdgcn_sinf(dd);
+                    xc[i] = __builtin_amdgcn_cosf(dd);
+                    pr[i] = pi[i] = qr[i] = qi[i] = 0.0f;
+                }
                 const float4 *g4 = reinterpret_cast<const float4 *>(gsh + cc * a.Sp);
-                float pr = 0.0f, pi = 0.0f, qr = 0.0f, qi = 0.0f;
                 // q = q x + p ;  p = p x + conj(g_s), s descending
-#define SBR_HORNER_STEP(GR, GI)                                 \
-    {                                                          \
-        float nqr = fmaf(qr, xc, fmaf(-qi, xs, pr));           \
-        float nqi = fmaf(qr, xs, fmaf(qi, xc, pi));            \
-        float npr = fmaf(pr, xc, fmaf(-pi, xs, (GR)));         \
-        float npi = fmaf(pr, xs, fmaf(pi, xc, -(GI)));         \
-        qr = nqr;                                              \
-        qi = nqi;                                              \
-        pr = npr;                                              \
-        pi = npi;                                              \
+#define SBR_HORNER_STEP(GR, GI)                                                 \
+    _Pragma("unroll") for (int i = 0; i < PPL; i++) {                          \
+        float nqr = fmaf(qr[i], xc[i], fmaf(-qi[i], xs[i], pr[i]));            \
+        float nqi = fmaf(qr[i], xs[i], fmaf(qi[i], xc[i], pi[i]));             \
+        float npr = fmaf(pr[i], xc[i], fmaf(-pi[i], xs[i], (GR)));             \
+        float npi = fmaf(pr[i], xs[i], fmaf(pi[i], xc[i], -(GI)));             \
+        qr[i] = nqr;                                                           \
+        qi[i] = nqi;                                                           \
+        pr[i] = npr;                                                           \
+        pi[i] = npi;                                                           \
     }
                 for (int j = a.Sp / 2 - 4; j >= 0; j -= 4) {
                     const float4 h3 = g4[j + 3], h2 = g4[j + 2], h1 = g4[j + 1], h0 = g4[j];
@@ -94,20 +118,27 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
                     SBR_HORNER_STEP(h0.x, h0.y)
                 }
 #undef SBR_HORNER_STEP
-                // Q0 = z0 P, Q1 = z0 x P'
-                const float q0r = zc * pr - zs * pi, q0i = zc * pi + zs * pr;
-                const float xqr = xc * qr - xs * qi, xqi = xc * qi + xs * qr;
-                const float q1r = zc * xqr - zs * xqi, q1i = zc * xqi + zs * xqr;
-                abr += q0r;
-                abi -= q0i;
-                const float mr = a.fcf * q0r + a.sl_fs * q1r;
-                const float mi = a.fcf * q0i + a.sl_fs * q1i;
-                tb += -2.0f * (float)kPi * (A.x * mi + A.y * mr);
+#pragma unroll
+                for (int i = 0; i < PPL; i++) {
+                    // Q0 = z0 P, Q1 = z0 x P'
+                    const float q0r = zc[i] * pr[i] - zs[i] * pi[i], q0i = zc[i] * pi[i] + zs[i] * pr[i];
+                    const float xqr = xc[i] * qr[i] - xs[i] * qi[i], xqi = xc[i] * qi[i] + xs[i] * qr[i];
+                    const float q1r = zc[i] * xqr - zs[i] * xqi, q1i = zc[i] * xqi + zs[i] * xqr;
+                    abr[i] += q0r;
+                    abi[i] -= q0i;
+                    const float mr = a.fcf * q0r + a.sl_fs * q1r;
+                    const float mi = a.fcf * q0i + a.sl_fs * q1i;
+                    tb[i] += -2.0f * (float)kPi * (A[i].x * mi + A[i].y * mr);
+                }
             }
         }
-        if (act) a.tau_bar[(size_t)v * a.rec.cap + p] = tb;
+#pragma unroll
+        for (int i = 0; i < PPL; i++)
+            if (act[i]) a.tau_bar[(size_t)v * a.rec.cap + pp[i]] = tb[i];
     }
-    if (act) a.abar_part[(size_t)blockIdx.y * a.rec.cap + p] = make_float2(abr, abi);
+#pragma unroll
+    for (int i = 0; i < PPL; i++)
+        if (act[i]) a.abar_part[(size_t)blockIdx.y * a.rec.cap + pp[i]] = make_float2(abr[i], abi[i]);
 }
 
 __global__ void k_reduce_abar(const int32_t *count, const float2 *part, int nvs, int cap, float2 *abar) {
@@ -339,7 +370,7 @@ struct BackPlan {
 };
 
 static BackPlan back_plan(long long cap, int V) {
-    long long blocks = (cap + 255) / 256;
+    long long blocks = (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL);
     long long want = (4096 + blocks - 1) / std::max(1LL, blocks);
     int nvs = (int)std::max(1LL, std::min((long long)V, want));
     int v_per = (V + nvs - 1) / nvs;
@@ -380,13 +411,13 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     a.tc = (float)cd.tc;
     a.tau_bar = tau_bar;
     a.abar_part = part;
-    dim3 grid((unsigned)((cap + 255) / 256), (unsigned)bp.nvs);
+    dim3 grid((unsigned)((cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL)), (unsigned)bp.nvs);
     a.Sp = (cd.S + 7) / 8 * 8;
     a.rows = std::max(1, std::min(kAdjRowsMax, 8192 / a.Sp));
     size_t lds = sizeof(float2) * a.rows * a.Sp;
     {
         ProfScope ps(kProfSynthAdj, s);
-        hipLaunchKernelGGL(k_synth_adj, grid, dim3(256), lds, s, a);
+        hipLaunchKernelGGL(k_synth_adj<kAdjPPL>, grid, dim3(256), lds, s, a);
     }
     hipLaunchKernelGGL(k_reduce_abar, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st.count, part,
                        bp.nvs, (int)cap, abar);

@@ -352,11 +352,14 @@ int fill_zero_f32(float *p, size_t n, hipStream_t s) {
     return SBR_OK;
 }
 
-constexpr int kSynthL = 64;
+#ifndef SBR_SYNTH_L
+#define SBR_SYNTH_L 64
+#endif
+constexpr int kSynthL = SBR_SYNTH_L;
 
 SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
     SynthPlan p;
-    p.L = S >= 64 ? kSynthL : (S >= 32 ? 32 : 16);
+    p.L = S >= kSynthL ? kSynthL : (S >= 64 ? 64 : (S >= 32 ? 32 : 16));
     p.SB = (S + p.L - 1) / p.L;
     p.tiles_per_v = (C * p.SB + 63) / 64;
     long long waves = (long long)V * p.tiles_per_v;
@@ -387,7 +390,9 @@ int launch_synth(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, 
     dim3 grid((unsigned)((waves + 3) / 4), (unsigned)p.n_chunks);
     {
         ProfScope ps(kProfSynth, s);
-        if (p.L == 64)
+        if (p.L == 128)
+            hipLaunchKernelGGL(k_synth<128>, grid, dim3(256), 0, s, a);
+        else if (p.L == 64)
             hipLaunchKernelGGL(k_synth<64>, grid, dim3(256), 0, s, a);
         else if (p.L == 32)
             hipLaunchKernelGGL(k_synth<32>, grid, dim3(256), 0, s, a);
