@@ -62,7 +62,7 @@ typedef struct {
     int32_t nv;
     const int32_t *faces;    /* [nf][3] vertex indices                            */
     int32_t nf;
-    const uint16_t *mat_id;  /* [nf] index into the material table, or NULL      */
+    const uint16_t *mat_id;  /* [nf] material table index (>= n_mats: conductor), or NULL */
 } sbr_mesh;
 
 /* Reflection model of one material (Sec. 3.2.2, Eqs. 9-10).  mode 0: perfect

@@ -189,7 +189,8 @@ static cplx csqrt_p(cplx z) {
 }
 
 void orc_fresnel(const orc_mesh *m, int mi, double fc, double cos_i, double out[2]) {
-    int mode = (m->n_mats > 0) ? m->mat_mode[mi] : 0;
+    /* a material index outside the table means a perfect conductor */
+    int mode = (mi >= 0 && mi < m->n_mats) ? m->mat_mode[mi] : 0;
     if (mode == 0) { out[0] = -1.0; out[1] = 0.0; return; }
     double er = m->mat_eps_r[mi], sg = m->mat_sigma[mi];
     /* complex relative permittivity eps_c = eps_r - j sigma / (omega eps_0) */

@@ -171,194 +171,222 @@ struct GeomArgs {
     float *grad;            // [nv][3]
 };
 
-struct d3 {
-    double x, y, z;
-};
-__device__ __forceinline__ d3 mk(double x, double y, double z) { return {x, y, z}; }
-__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ d3 operator*(double s, d3 a) { return {s * a.x, s * a.y, s * a.z}; }
-__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ d3 cross(d3 a, d3 b) {
-    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator*(float s, float3 a) { return f3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
-__device__ __forceinline__ double nrm(d3 a) { return sqrt(dot(a, a)); }
-__device__ __forceinline__ d3 vload(const float *v, int i) { return {v[3 * i], v[3 * i + 1], v[3 * i + 2]}; }
+__device__ __forceinline__ float len3(float3 a) { return sqrtf(dot3(a, a)); }
+__device__ __forceinline__ float3 vload3(const float *v, int i) { return f3(v[3 * i], v[3 * i + 1], v[3 * i + 2]); }
 
-__device__ __forceinline__ void scatter(float *g, int vi, d3 x) {
-    atomicAdd(&g[3 * vi], (float)x.x);
-    atomicAdd(&g[3 * vi + 1], (float)x.y);
-    atomicAdd(&g[3 * vi + 2], (float)x.z);
+__device__ __forceinline__ void atomic_add3(float *g, int vi, float3 x) {
+    atomicAdd(&g[3 * vi], x.x);
+    atomicAdd(&g[3 * vi + 1], x.y);
+    atomicAdd(&g[3 * vi + 2], x.z);
 }
 
+// Sum of x over the run of consecutive lanes that share `key` (segmented
+// inclusive scan, lanes in order); valid in the last lane of each run.
+__device__ __forceinline__ float seg_sum(float x, int lane, int s0) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        float y = __shfl_up(x, off);
+        if (lane - off >= s0) x += y;
+    }
+    return x;
+}
+
+// Per ray: single-precision forward recompute of its bounces from the face
+// ids (nothing is stored per path), path adjoints -> dL/dx_j and dL/dcos_j,
+// then one reverse sweep through x = o + t d, t = N.(a - o)/(N.d), the
+// specular reflection, the normalisation and the cross product, Fresnel
+// coefficients included.  Rays of a wavefront are consecutive in a grid row,
+// so neighbouring lanes often hit the same face: their vertex gradients are
+// summed over runs of equal face ids first and added by one atomic per run.
 template <int K>
-__global__ __launch_bounds__(128) void k_geom_adj(GeomArgs a) {
+__global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.R) return;
-    const int first = a.ray_first[r];
-    const int n = a.ray_first[r + 1] - first;
-    if (n <= 0) return;
+    const int lane = threadIdx.x & 63;
+    int first = 0, n = 0;
+    if (r < a.R) {
+        first = a.ray_first[r];
+        n = a.ray_first[r + 1] - first;
+    }
+    if (__ballot(n > 0) == 0) return;   // uniform over the wavefront
     const int ix = r % a.g.nx, iy = r / a.g.nx;
-    double d0[3], dw;
-    grid_ray(a.g, a.rd, ix, iy, d0, &dw);
-    const d3 O = mk(a.rd.o[0], a.rd.o[1], a.rd.o[2]);
-    // ---- forward recompute (double), kept per bounce
-    d3 X[K], D[K];
-    double T[K], Lc[K];
+    double d0[3], dwd;
+    grid_ray(a.g, a.rd, ix, iy, d0, &dwd);
+    const float dw = (float)dwd;
+    const float3 O = f3((float)a.rd.o[0], (float)a.rd.o[1], (float)a.rd.o[2]);
+    // ---- forward recompute, cached per bounce
+    float3 X[K], D[K], VA[K], E1[K], E2[K];
+    float T[K], CI[K], SG[K], LC[K];
+    float2 RC[K], DRC[K];
     int F[K];
-    d3 dir = mk(d0[0], d0[1], d0[2]);
-    d3 o = O;
-    double L = 0.0;
+    float3 dir = f3((float)d0[0], (float)d0[1], (float)d0[2]);
+    float3 o = O;
+    float L = 0.0f;
 #pragma unroll
     for (int k = 0; k < K; k++) {
+        F[k] = -1;
         if (k < n) {
             const int f = a.tri[(size_t)k * a.R + r];
-            d3 va = vload(a.verts, a.faces[3 * f]), vb = vload(a.verts, a.faces[3 * f + 1]),
-               vc = vload(a.verts, a.faces[3 * f + 2]);
-            d3 N = cross(vb - va, vc - va);
-            double t = dot(N, va - o) / dot(N, dir);
-            d3 x = o + t * dir;
-            L += nrm(x - o);
+            const float3 va = vload3(a.verts, a.faces[3 * f]);
+            const float3 e1 = vload3(a.verts, a.faces[3 * f + 1]) - va;
+            const float3 e2 = vload3(a.verts, a.faces[3 * f + 2]) - va;
+            const float3 N = cross3(e1, e2);
+            const float den = dot3(N, dir);
+            const float t = dot3(N, va - o) / den;
+            const float3 x = o + t * dir;
+            L += len3(x - o);
+            const float nl = len3(N);
+            const float dn = den / nl;
             X[k] = x;
             D[k] = dir;
+            VA[k] = va;
+            E1[k] = e1;
+            E2[k] = e2;
             T[k] = t;
-            Lc[k] = L;
+            LC[k] = L;
             F[k] = f;
-            double nl = nrm(N);
-            d3 nh = (1.0 / nl) * N;
-            dir = dir - (2.0 * dot(dir, nh)) * nh;
+            CI[k] = fabsf(dn);
+            SG[k] = dn >= 0.0f ? 1.0f : -1.0f;
+            cd rc = {-1.0, 0.0}, drc = {0.0, 0.0};
+            if (a.any_fresnel) reflect_coef(a.mt, a.mat_id ? (int)a.mat_id[f] : 0, a.ch.fc, (double)CI[k], rc, drc);
+            RC[k] = make_float2((float)rc.re, (float)rc.im);
+            DRC[k] = make_float2((float)drc.re, (float)drc.im);
+            dir = dir - (2.0f * dn / nl) * N;
             o = x;
         }
     }
     // ---- path adjoints -> dL/dx_j, dL/dcos_j
-    d3 xb[K];
-    double cib[K];
+    float3 xb[K];
+    float cib[K];
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        xb[k] = mk(0, 0, 0);
-        cib[k] = 0.0;
+        xb[k] = f3(0.f, 0.f, 0.f);
+        cib[k] = 0.0f;
     }
     const int ntx = a.rd.n_tx, nrx = a.rd.n_rx;
-    const double ic0 = 1.0 / kC0;
+    const float ic0 = (float)(1.0 / kC0);
 #pragma unroll
     for (int k = 0; k < K; k++) {
         if (k < n) {
             const int p = first + k;
             const float2 ab = a.abar[p];
-            // amplitude pieces of bounce k
-            double ci[K];
-            cd rj[K], drj[K];
-            cd prod = {1.0, 0.0};
+            float2 prod = make_float2(1.0f, 0.0f);
 #pragma unroll
-            for (int j = 0; j <= k; j++) {
-                d3 va = vload(a.verts, a.faces[3 * F[j]]), vb = vload(a.verts, a.faces[3 * F[j] + 1]),
-                   vc = vload(a.verts, a.faces[3 * F[j] + 2]);
-                d3 N = cross(vb - va, vc - va);
-                ci[j] = fabs(dot(D[j], N)) / nrm(N);
-                reflect_coef(a.mt, a.mat_id ? (int)a.mat_id[F[j]] : 0, a.ch.fc, ci[j], rj[j], drj[j]);
-                prod = {prod.re * rj[j].re - prod.im * rj[j].im, prod.re * rj[j].im + prod.im * rj[j].re};
-            }
-            const double Lk = Lc[k];
-            const double Rk = nrm(X[k] - O);
-            // A = dw * prod * ci_k / (L R);  u = Re(conj(Abar) * dw * prod / (L R))
-            const double s = dw / (Lk * Rk);
-            const double u = s * (ab.x * prod.re + ab.y * prod.im);
-            const double g = u * ci[k];      // Re(conj(Abar) A)
+            for (int j = 0; j <= k; j++)
+                prod = make_float2(prod.x * RC[j].x - prod.y * RC[j].y, prod.x * RC[j].y + prod.y * RC[j].x);
+            const float Rk = len3(X[k] - O);
+            // A = dw prod ci_k / (L R);  u = Re(conj(Abar) dw prod / (L R))
+            const float sc = dw / (LC[k] * Rk);
+            const float u = sc * (ab.x * prod.x + ab.y * prod.y);
+            const float gk = u * CI[k];
             cib[k] += u;
-            const double Lb = -g / Lk, Rb = -g / Rk;
+            const float Lb = -gk / LC[k], Rb = -gk / Rk;
             if (a.any_fresnel) {
 #pragma unroll
                 for (int j = 0; j <= k; j++) {
-                    cd ex = {s * ci[k], 0.0};
+                    float2 ex = make_float2(sc * CI[k], 0.0f);
 #pragma unroll
                     for (int i = 0; i <= k; i++)
-                        if (i != j) ex = {ex.re * rj[i].re - ex.im * rj[i].im, ex.re * rj[i].im + ex.im * rj[i].re};
-                    cd dA = {ex.re * drj[j].re - ex.im * drj[j].im, ex.re * drj[j].im + ex.im * drj[j].re};
-                    cib[j] += ab.x * dA.re + ab.y * dA.im;
+                        if (i != j) ex = make_float2(ex.x * RC[i].x - ex.y * RC[i].y, ex.x * RC[i].y + ex.y * RC[i].x);
+                    const float2 dA = make_float2(ex.x * DRC[j].x - ex.y * DRC[j].y, ex.x * DRC[j].y + ex.y * DRC[j].x);
+                    cib[j] += ab.x * dA.x + ab.y * dA.y;
                 }
             }
-            // L_k = sum_{j<=k} |x_j - x_{j-1}| (x_{-1} = O);  R_k = |x_k - O|
-            d3 prv = O;
+            float3 prv = O;
 #pragma unroll
             for (int j = 0; j <= k; j++) {
-                d3 sg = X[j] - prv;
-                d3 uj = (1.0 / nrm(sg)) * sg;
-                xb[j] = xb[j] + Lb * uj;
-                if (j > 0) xb[j - 1] = xb[j - 1] - Lb * uj;
+                const float3 sg = X[j] - prv;
+                const float3 uj = (Lb / len3(sg)) * sg;
+                xb[j] = xb[j] + uj;
+                if (j > 0) xb[j - 1] = xb[j - 1] - uj;
                 prv = X[j];
             }
             xb[k] = xb[k] + (Rb / Rk) * (X[k] - O);
-            // time of flight: tx_t -> x_0 -> ... -> x_k -> rx_m
-            double TS[SBR_MAX_TX], RS[SBR_MAX_RX], Tt = 0.0;
-            for (int t = 0; t < ntx; t++) TS[t] = 0.0;
-            for (int m = 0; m < nrx; m++) RS[m] = 0.0;
+            float TS[SBR_MAX_TX], RS[SBR_MAX_RX], Tt = 0.0f;
+            for (int t = 0; t < ntx; t++) TS[t] = 0.0f;
+            for (int m = 0; m < nrx; m++) RS[m] = 0.0f;
             for (int t = 0; t < ntx; t++)
                 for (int m = 0; m < nrx; m++) {
-                    double tb = a.tau_bar[(size_t)(t * nrx + m) * a.cap + p];
+                    const float tb = a.tau_bar[(size_t)(t * nrx + m) * a.cap + p];
                     TS[t] += tb;
                     RS[m] += tb;
                     Tt += tb;
                 }
             for (int t = 0; t < ntx; t++) {
-                d3 q = X[0] - mk(a.rd.tx[t][0], a.rd.tx[t][1], a.rd.tx[t][2]);
-                xb[0] = xb[0] + (TS[t] * ic0 / nrm(q)) * q;
+                const float3 q = X[0] - f3((float)a.rd.tx[t][0], (float)a.rd.tx[t][1], (float)a.rd.tx[t][2]);
+                xb[0] = xb[0] + (TS[t] * ic0 / len3(q)) * q;
             }
             for (int m = 0; m < nrx; m++) {
-                d3 q = X[k] - mk(a.rd.rx[m][0], a.rd.rx[m][1], a.rd.rx[m][2]);
-                xb[k] = xb[k] + (RS[m] * ic0 / nrm(q)) * q;
+                const float3 q = X[k] - f3((float)a.rd.rx[m][0], (float)a.rd.rx[m][1], (float)a.rd.rx[m][2]);
+                xb[k] = xb[k] + (RS[m] * ic0 / len3(q)) * q;
             }
 #pragma unroll
             for (int j = 1; j <= k; j++) {
-                d3 sg = X[j] - X[j - 1];
-                d3 uj = (Tt * ic0 / nrm(sg)) * sg;
+                const float3 sg = X[j] - X[j - 1];
+                const float3 uj = (Tt * ic0 / len3(sg)) * sg;
                 xb[j] = xb[j] + uj;
                 xb[j - 1] = xb[j - 1] - uj;
             }
         }
     }
     // ---- reverse sweep over bounces
-    d3 dnext = mk(0, 0, 0);   // dL/d d_{j+1}
+    float3 dnext = f3(0.f, 0.f, 0.f);   // dL/d d_{j+1}
 #pragma unroll
     for (int j = K - 1; j >= 0; j--) {
-        if (j < n) {
-            const int f = F[j];
-            const int ia = a.faces[3 * f], ibv = a.faces[3 * f + 1], icv = a.faces[3 * f + 2];
-            d3 va = vload(a.verts, ia), vb = vload(a.verts, ibv), vc = vload(a.verts, icv);
-            d3 e1 = vb - va, e2 = vc - va;
-            d3 N = cross(e1, e2);
-            double nl = nrm(N);
-            d3 nh = (1.0 / nl) * N;
-            d3 d = D[j];
-            double dn = dot(d, nh);
-            double sgn = dn >= 0.0 ? 1.0 : -1.0;
-            double t = T[j];
-            d3 ob = xb[j];                    // x = o + t d
-            double tbar = dot(xb[j], d);
-            d3 db = t * xb[j];
-            d3 nhb = mk(0, 0, 0);
-            db = db + (cib[j] * sgn) * nh;    // cos = |d . n|
-            nhb = nhb + (cib[j] * sgn) * d;
-            // d_{j+1} = d - 2 (d.n) n
-            double ndn = dot(nh, dnext);
-            db = db + dnext - (2.0 * ndn) * nh;
-            nhb = nhb - 2.0 * (dn * dnext + ndn * d);
-            // t = N.(a - o) / (N.d)
-            double den = dot(N, d);
-            d3 Nb = (tbar / den) * (va - X[j]);
-            d3 ab = (tbar / den) * N;
-            ob = ob - (tbar / den) * N;
-            db = db - (tbar * t / den) * N;
-            // n = N / |N|
-            Nb = Nb + (1.0 / nl) * (nhb - dot(nhb, nh) * nh);
-            // N = e1 x e2
-            d3 e1b = cross(e2, Nb), e2b = cross(Nb, e1);
-            d3 bb = e1b, cb = e2b;
-            ab = ab - e1b - e2b;
-            scatter(a.grad, ia, ab);
-            scatter(a.grad, ibv, bb);
-            scatter(a.grad, icv, cb);
+        const bool act = j < n;
+        float3 ga = f3(0.f, 0.f, 0.f), gb = ga, gc = ga;
+        if (act) {
+            const float3 e1 = E1[j], e2 = E2[j];
+            const float3 N = cross3(e1, e2);
+            const float nl = len3(N);
+            const float3 nh = (1.0f / nl) * N;
+            const float3 d = D[j];
+            const float dn = dot3(d, nh);
+            const float t = T[j];
+            float3 ob = xb[j];                     // x = o + t d
+            const float tbar = dot3(xb[j], d);
+            float3 db = t * xb[j];
+            float3 nhb = (cib[j] * SG[j]) * d;      // cos = |d . n|
+            db = db + (cib[j] * SG[j]) * nh;
+            const float ndn = dot3(nh, dnext);      // d_{j+1} = d - 2 (d.n) n
+            db = db + dnext - (2.0f * ndn) * nh;
+            nhb = nhb - 2.0f * (dn * dnext + ndn * d);
+            const float den = dot3(N, d);           // t = N.(a - o) / (N.d)
+            const float w = tbar / den;
+            float3 Nb = w * (VA[j] - X[j]);
+            ga = w * N;
+            ob = ob - w * N;
+            db = db - (w * t) * N;
+            Nb = Nb + (1.0f / nl) * (nhb - dot3(nhb, nh) * nh);   // n = N / |N|
+            gb = cross3(e2, Nb);                    // N = e1 x e2
+            gc = cross3(Nb, e1);
+            ga = ga - gb - gc;
             if (j > 0) xb[j - 1] = xb[j - 1] + ob;
             dnext = db;
+        }
+        // sum over runs of lanes that hit the same face, one atomic per run
+        const int key = act ? F[j] : -1;
+        const int kprev = __shfl_up(key, 1);
+        int s0 = (lane == 0 || kprev != key) ? lane : 0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) s0 = max(s0, __shfl_up(s0, off));
+        const int knext = __shfl_down(key, 1);
+        const bool tail = act && (lane == 63 || knext != key);
+        float v9[9] = {ga.x, ga.y, ga.z, gb.x, gb.y, gb.z, gc.x, gc.y, gc.z};
+#pragma unroll
+        for (int q = 0; q < 9; q++) v9[q] = seg_sum(v9[q], lane, s0);
+        if (tail) {
+            const int f = F[j];
+            atomic_add3(a.grad, a.faces[3 * f], f3(v9[0], v9[1], v9[2]));
+            atomic_add3(a.grad, a.faces[3 * f + 1], f3(v9[3], v9[4], v9[5]));
+            atomic_add3(a.grad, a.faces[3 * f + 2], f3(v9[6], v9[7], v9[8]));
         }
     }
 }
@@ -440,16 +468,16 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     g.tau_bar = tau_bar;
     g.cap = (int32_t)cap;
     g.grad = grad;
-    dim3 gg((unsigned)((g.R + 127) / 128));
+    dim3 gg((unsigned)((g.R + 255) / 256));
     switch (gd.K) {
-    case 1: hipLaunchKernelGGL(k_geom_adj<1>, gg, dim3(128), 0, s, g); break;
-    case 2: hipLaunchKernelGGL(k_geom_adj<2>, gg, dim3(128), 0, s, g); break;
-    case 3: hipLaunchKernelGGL(k_geom_adj<3>, gg, dim3(128), 0, s, g); break;
-    case 4: hipLaunchKernelGGL(k_geom_adj<4>, gg, dim3(128), 0, s, g); break;
-    case 5: hipLaunchKernelGGL(k_geom_adj<5>, gg, dim3(128), 0, s, g); break;
-    case 6: hipLaunchKernelGGL(k_geom_adj<6>, gg, dim3(128), 0, s, g); break;
-    case 7: hipLaunchKernelGGL(k_geom_adj<7>, gg, dim3(128), 0, s, g); break;
-    default: hipLaunchKernelGGL(k_geom_adj<8>, gg, dim3(128), 0, s, g); break;
+    case 1: hipLaunchKernelGGL(k_geom_adj<1>, gg, dim3(256), 0, s, g); break;
+    case 2: hipLaunchKernelGGL(k_geom_adj<2>, gg, dim3(256), 0, s, g); break;
+    case 3: hipLaunchKernelGGL(k_geom_adj<3>, gg, dim3(256), 0, s, g); break;
+    case 4: hipLaunchKernelGGL(k_geom_adj<4>, gg, dim3(256), 0, s, g); break;
+    case 5: hipLaunchKernelGGL(k_geom_adj<5>, gg, dim3(256), 0, s, g); break;
+    case 6: hipLaunchKernelGGL(k_geom_adj<6>, gg, dim3(256), 0, s, g); break;
+    case 7: hipLaunchKernelGGL(k_geom_adj<7>, gg, dim3(256), 0, s, g); break;
+    default: hipLaunchKernelGGL(k_geom_adj<8>, gg, dim3(256), 0, s, g); break;
     }
     SBR_LAUNCHED();
     return SBR_OK;

@@ -332,3 +332,83 @@ def test_loss_grad_entry(torch_cuda):
     assert abs(float(l.item()) - np.mean(q ** 2)) <= 1e-5 * np.mean(q ** 2)
     ref = 4 * q * a / a.size
     assert np.allclose(torch.view_as_complex(g).cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
+
+
+# ----------------------------------------------------------------- edge cases
+def test_degenerate_duplicate_and_single_faces(torch_cuda, orc):
+    """A zero-area face is never hit; a duplicated face resolves to the lower
+    id on both sides (and is flagged as a tie); a one-face mesh builds and
+    traces; material ids beyond the table act as conductors."""
+    v, f = S.plate(0.3, 1.2)
+    deg = np.array([[-0.05, 0.0, 1.1], [0.0, 0.0, 1.1], [0.05, 0.0, 1.1]])   # collinear
+    verts = np.concatenate([v, deg])
+    faces = np.concatenate([f, [[4, 5, 6]], f[:1]])       # face 3 degenerate, face 4 == face 0
+    sc = S.Scene("edge", verts.astype(np.float32), faces.astype(np.int32), S.default_radar(1, 2),
+                 S.Chirp(n_chirps=2), S.Grid(41, 37, 0.15, 0.12, 3),
+                 mat_id=np.array([0, 1, 0, 0, 7], np.uint16), materials=[(S.MAT_PEC, 1, 0), (S.MAT_TE, 4.0, 0.1)])
+    sim = _sim(sc)
+    sim.build()
+    sim.trace()
+    torch_cuda.cuda.synchronize()
+    g = _gpu_hits_np(sim)
+    o = orc.trace(sc)
+    assert not (g["tri"] == 3).any() and not (o["tri"] == 3).any()
+    assert not (g["tri"] == 4).any() and (g["tri"] == 0).any()
+    assert (g["flags"][0][g["tri"][0] == 0] & 2).all()          # the duplicate is a tie
+    compare_trace(g, o)
+    p = orc.paths(sc, o["tri"], o["flags"], drop=False)
+    ref = orc.synth(sc, p)
+    sim2 = _sim(sc, drop=False)
+    sim2.hits = device_hits_from_oracle(o)
+    assert rel_l2(_cube_np(sim2.synth()), ref) <= IF_TOL
+    # one face
+    one = S.single_triangle()
+    s1 = _sim(one)
+    s1.build()
+    s1.trace()
+    torch_cuda.cuda.synchronize()
+    compare_trace(_gpu_hits_np(s1), orc.trace(one))
+
+
+def test_max_bounces_and_max_antennas(torch_cuda, orc):
+    # 8 bounces inside a closed box of mirrors seen through a hole-free grid
+    sc = S.trihedral_plate().with_grid(nx=48, ny=48, max_bounces=8)
+    sim = _sim(sc)
+    sim.build()
+    sim.trace()
+    torch_cuda.cuda.synchronize()
+    compare_trace(_gpu_hits_np(sim), orc.trace(sc))
+    # 4 TX x 16 RX = 64 virtual antennas, the ABI maximum
+    sc = S.icosphere_scene(level=2, n_rays=24, n_chirps=2)
+    sc = dataclasses.replace(sc, radar=S.default_radar(4, 16, vel=(0.0, 0.0, 1.0)))
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    ref = orc.synth(sc, p)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    e = rel_l2(_cube_np(sim.synth()), ref)
+    log(f"V=64 synth rel L2 {e:.2e}")
+    assert e <= IF_TOL
+    # a single sample per chirp
+    sc1 = sc.with_chirp(n_samples=1, n_chirps=3)
+    ref1 = orc.synth(sc1, orc.paths(sc1, o["tri"], o["flags"]))
+    sim1 = _sim(sc1)
+    sim1.hits = device_hits_from_oracle(o)
+    assert rel_l2(_cube_np(sim1.synth()), ref1) <= IF_TOL
+
+
+@pytest.mark.parametrize("K", [1, 4])
+def test_backward_bounce_counts(torch_cuda, orc, K):
+    import torch
+    sc = S.trihedral_plate().with_grid(nx=40, ny=40, max_bounces=K)
+    o = orc.trace(sc)
+    tgt = _target(orc, sc, 1e-3, 17)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    G = 2.0 * (orc.synth(sc, p) - tgt)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    got = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda")).cpu().numpy().astype(np.float64)
+    fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, h=1e-9).reshape(-1, 3)
+    e = rel_l2(got, fd)
+    log(f"backward K={K}: rel L2 {e:.2e}")
+    assert e <= GRAD_TOL
