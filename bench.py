@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="clutter_50k", choices=["clutter_50k", "icosphere_20k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-latency measurement")
+    ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -222,6 +224,23 @@ def main():
         "wall_ms_per_step": (w1 - w0) * 1e3 / args.steps,
         "roofline": roof,
     }
+    if not args.no_serving:
+        # request latency of the serving loop on the mixed request stream
+        # (meshes of 1k-200k triangles, 256^2-2048^2 rays, 2-4 bounces, 4-12
+        # antennas x 32-128 chirps, 30 % with backward), Poisson arrivals at
+        # 1.25x the measured one-at-a-time service rate
+        del sim, cube, grad, gv, target
+        torch.cuda.empty_cache()
+        from paper_2311_13182_amd.serve import serving_benchmark
+        sv = serving_benchmark(n=args.serving_requests, phases=(("main", 1.25),), quiet=True)
+        m = sv["main"]
+        out["serving"] = {"requests": args.serving_requests, "qps": round(m["qps"], 2),
+                          "throughput_rps": round(m["server"]["throughput_rps"], 2),
+                          "p50_latency_ms": round(m["server"]["p50_latency_ms"], 1),
+                          "p99_latency_ms": round(m["server"]["p99_latency_ms"], 1),
+                          "sequential_throughput_rps": round(m["sequential"]["throughput_rps"], 2),
+                          "sequential_p50_latency_ms": round(m["sequential"]["p50_latency_ms"], 1),
+                          "sequential_p99_latency_ms": round(m["sequential"]["p99_latency_ms"], 1)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, queries)
     print(json.dumps(out), flush=True)

@@ -298,23 +298,25 @@ __global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
         float ws = __builtin_amdgcn_sinf(dph), wc = __builtin_amdgcn_cosf(dph);
         float zr = A.x * cs - A.y * sn, zi = A.x * sn + A.y * cs;   // z[s0]
         float yr = zr * wc - zi * ws, yi = zr * ws + zi * wc;       // z[s0 + 1]
-        const float k2 = 2.0f * wc;
         ar[0] += zr;
         ai[0] += zi;
         if (L > 1) {
             ar[1] += yr;
             ai[1] += yi;
         }
+        {
+            const float k2 = 2.0f * wc;
 #pragma unroll
-        for (int i = 2; i < L; i++) {
-            float nr = fmaf(k2, yr, -zr);
-            float ni = fmaf(k2, yi, -zi);
-            zr = yr;
-            zi = yi;
-            yr = nr;
-            yi = ni;
-            ar[i] += nr;
-            ai[i] += ni;
+            for (int i = 2; i < L; i++) {
+                float nr = fmaf(k2, yr, -zr);
+                float ni = fmaf(k2, yi, -zi);
+                zr = yr;
+                zi = yi;
+                yr = nr;
+                yi = ni;
+                ar[i] += nr;
+                ai[i] += ni;
+            }
         }
     }
     if (c < a.C) {
@@ -352,10 +354,7 @@ int fill_zero_f32(float *p, size_t n, hipStream_t s) {
     return SBR_OK;
 }
 
-#ifndef SBR_SYNTH_L
-#define SBR_SYNTH_L 64
-#endif
-constexpr int kSynthL = SBR_SYNTH_L;
+constexpr int kSynthL = 64;   // samples per lane (128 measured slower: occupancy 1)
 
 SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
     SynthPlan p;

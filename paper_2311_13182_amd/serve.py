@@ -328,14 +328,16 @@ def summarize(results: List[Result], wall: float) -> Dict[str, float]:
 
 
 def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_streams: int = 4,
-                      max_active: int = 16, grids=(256, 512, 1024, 2048), nf_range=(1000, 200000)):
+                      max_active: int = 16, grids=(256, 512, 1024, 2048), nf_range=(1000, 200000),
+                      phases=(("main", 1.25), ("low", 0.5)), quiet: bool = False):
     """Sequential FIFO solves vs the continuous-batching server on the same
     Poisson request stream (QPS = 1.25 x the measured sequential rate)."""
     import sys
     import torch
 
     def say(msg):
-        print(f"[serving] {msg}", file=sys.stderr, flush=True)
+        if not quiet:
+            print(f"[serving] {msg}", file=sys.stderr, flush=True)
 
     reqs = S.serving_requests(n=n, qps=1.0, seed=seed, grids=grids, nf_range=nf_range)
     say(f"{n} requests generated")
@@ -359,7 +361,8 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
     mu = n / seq_wall
     say(f"sequential service rate {mu:.2f} req/s")
     out = {"mu_seq_rps": mu, "n_backward": sum(r.backward for r in reqs)}
-    for tag, qps in (("main", 1.25 * mu), ("low", 0.5 * mu)):
+    for tag, factor in phases:
+        qps = factor * mu
         rng = np.random.default_rng(seed + 1)
         arr = np.cumsum(rng.exponential(1.0 / qps, size=n))
         timed = [Request(r.rid, r.scene, r.backward, r.target, float(a)) for r, a in zip(reqs, arr)]
