@@ -203,6 +203,17 @@ int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard,
              int32_t train, double pfa, int32_t *points, float *ratio, int32_t max_points,
              int32_t *n_points, void *scratch, size_t scratch_bytes, void *stream);
 
+/* Gradients with respect to scene parameters other than the vertices (the
+ * material, pose and dynamics entries of Theta, Sec. 3.2).  Device arrays,
+ * accumulated (+=); either pointer may be NULL. */
+typedef struct {
+    float *materials;        /* [n_mats][2]: dL/d eps_r, dL/d sigma per table entry */
+    float *radar;            /* [6]: dL/d origin (world x, y, z), dL/d velocity (x, y, z) */
+    float *rot;              /* [9]: dL/d rot, row-major like sbr_radar.rot (the full
+                                3x3 matrix; project onto a rotation parameterisation
+                                outside, e.g. dL/d omega = axial part of G R^T) */
+} sbr_param_grads;
+
 /* Backpropagation (Sec. 3.2.2 Eqs. 11-12, Sec. 3.3 Eq. 13): given
  * grad_if = dL/dRe S + i dL/dIm S ([V][C][S][2], device), ADD dL/dverts to
  * grad_verts ([nv][3], device).  The gradient is the pathwise derivative of
@@ -210,11 +221,16 @@ int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard,
  * from the hit records (nothing of the forward synthesis is stored) and the
  * reverse sweep runs through path lengths, ray-plane intersections,
  * reflections, normals and Fresnel coefficients.  Arguments as for
- * sbr_synth_if; hits and flags must be those the forward used. */
+ * sbr_synth_if; hits and flags must be those the forward used.  params: NULL,
+ * or where to ADD the gradients of the material table (Eqs. 9-10 through
+ * eps_c), of the radar origin (ray origins, TX and RX positions, return
+ * distances), of the radar rotation (ray directions, TX and RX positions,
+ * Doppler direction) and of the scene velocity (Doppler term of I^t). */
 int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
                  const sbr_radar *radar, const sbr_rays *rays, const sbr_hits *hits,
                  const sbr_chirp *chirp, int32_t flags, const float *grad_if,
-                 float *grad_verts, void *scratch, size_t scratch_bytes, void *stream);
+                 float *grad_verts, const sbr_param_grads *params, void *scratch,
+                 size_t scratch_bytes, void *stream);
 
 /* Number of paths the last sbr_synth_if / sbr_backward found is left in the
  * first int32 of their scratch buffer (device) once the stream reaches it. */

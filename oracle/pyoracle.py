@@ -292,6 +292,17 @@ def fd_directional(scene, tri, flags, target, direction, h=1e-9, rays=None, drop
     return (Ls[0] - Ls[1]) / (2.0 * h)
 
 
+def fd_scene(scene, tri, flags, target, perturb, h, rays=None, drop=True):
+    """Central difference of the IF loss with respect to a scalar scene
+    parameter: perturb(scene, delta) returns the scene with the parameter
+    moved by delta (hit-triangle sequences frozen)."""
+    Ls = []
+    for sgn in (+1.0, -1.0):
+        sp = perturb(scene, sgn * h)
+        Ls.append(if_loss(synth(sp, paths(sp, tri, flags, rays, drop)), target))
+    return (Ls[0] - Ls[1]) / (2.0 * h)
+
+
 def fd_grad(scene, tri, flags, target, coords=None, h=1e-9, rays=None, drop=True):
     """Central differences of the IF loss for every vertex coordinate in
     `coords` (flat indices into [nv*3]; None = all)."""

@@ -57,6 +57,10 @@ class sbr_rays(ct.Structure):
                 ("t_min", ct.c_double)]
 
 
+class sbr_param_grads(ct.Structure):
+    _fields_ = [("materials", ct.c_void_p), ("radar", ct.c_void_p), ("rot", ct.c_void_p)]
+
+
 class sbr_hits(ct.Structure):
     _fields_ = [("tri", ct.c_void_p), ("t", ct.c_void_p), ("u", ct.c_void_p), ("v", ct.c_void_p),
                 ("flags", ct.c_void_p)]
@@ -98,7 +102,7 @@ def load(path: str = LIB_PATH):
     L.sbr_cfar.argtypes = [vp, i32, i32, i32, i32, i32, ct.c_double, vp, vp, i32, vp, vp, sz, vp]
     L.sbr_backward.restype = ct.c_int
     L.sbr_backward.argtypes = [P(sbr_mesh), P(sbr_material), i32, P(sbr_radar), P(sbr_rays), P(sbr_hits),
-                               P(sbr_chirp), i32, vp, vp, vp, sz, vp]
+                               P(sbr_chirp), i32, vp, vp, P(sbr_param_grads), vp, sz, vp]
     L.sbr_loss_grad.restype = ct.c_int
     L.sbr_loss_grad.argtypes = [i32, vp, vp, ct.c_int64, vp, vp, vp]
     L.sbr_profile.restype = ct.c_int

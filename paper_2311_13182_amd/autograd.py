@@ -97,3 +97,21 @@ class HeatmapLoss(torch.autograd.Function):
 
 def simulate(verts: torch.Tensor, sim: Simulator, refit: bool = True) -> torch.Tensor:
     return SBRFunction.apply(verts, sim, refit)
+
+
+def skew(w: torch.Tensor) -> torch.Tensor:
+    """[w]x, the cross-product matrix of a 3-vector."""
+    z = torch.zeros((), dtype=w.dtype, device=w.device)
+    return torch.stack([torch.stack([z, -w[2], w[1]]), torch.stack([w[2], z, -w[0]]),
+                        torch.stack([-w[1], w[0], z])])
+
+
+def rigid_pose(base: torch.Tensor, omega: torch.Tensor, trans: torch.Tensor,
+               center: torch.Tensor = None) -> torch.Tensor:
+    """Object-transform parameterisation of the geometry (Sec. 3.1 (i)):
+    verts = exp([omega]x) (base - c) + c + trans, c = the vertex centroid
+    unless given.  The gradients with respect to omega (axis-angle) and trans
+    follow from dL/dverts by the chain rule (torch autograd)."""
+    c = base.mean(dim=0) if center is None else center
+    R = torch.linalg.matrix_exp(skew(omega))
+    return (base - c) @ R.T + c + trans

@@ -33,7 +33,8 @@ int launch_synth(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, 
 size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V);
 int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                     const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
-                    const float2 *G, float *grad, hipStream_t s);
+                    const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
+                    hipStream_t s);
 size_t cube_scratch_bytes(int V, int C, int S, int Na);
 size_t cfar_scratch_bytes(int C, int S);
 int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
@@ -310,11 +311,14 @@ int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard,
 
 int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats, const sbr_radar *radar,
                  const sbr_rays *rays, const sbr_hits *hits, const sbr_chirp *chirp, int32_t flags,
-                 const float *grad_if, float *grad_verts, void *scratch, size_t scratch_bytes, void *stream) {
+                 const float *grad_if, float *grad_verts, const sbr_param_grads *params, void *scratch,
+                 size_t scratch_bytes, void *stream) {
     clear_error();
     int rc;
     if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
     SBR_CHECK_ARG(grad_if && grad_verts, "grad_if/grad_verts is NULL");
+    SBR_CHECK_ARG(!params || !params->materials || (mats && n_mats > 0),
+                  "material gradients requested without a material table");
     const int R = rays->nx * rays->ny, K = rays->max_bounces;
     const int V = radar->n_tx * radar->n_rx;
     size_t need = backward_bytes(R, K, V);
@@ -332,7 +336,7 @@ int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
     ChirpDev cd = make_chirp(chirp);
     if ((rc = launch_paths(mesh, mt, rd, gd, cd, hits, flags, st, s))) return rc;
     return launch_backward(mesh, mt, rd, gd, cd, hits, st, cv, reinterpret_cast<const float2 *>(grad_if),
-                           grad_verts, s);
+                           grad_verts, radar, params, s);
 }
 
 }  // extern "C"

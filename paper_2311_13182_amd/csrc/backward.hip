@@ -20,6 +20,7 @@ struct AdjArgs {
     float fcf, sl_fs, tc;  // fc, slope / fs, chirp period
     float *tau_bar;        // [V][cap]
     float2 *abar_part;     // [nvs][cap]
+    float *tdb_part;       // [nvs][cap] dL/d taudot partials
 };
 
 constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time (at most 64 KiB)
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
     int pp[PPL];
     bool act[PPL];
     float2 A[PPL];
-    float beta[PPL], epsd[PPL], abr[PPL], abi[PPL];
+    float beta[PPL], epsd[PPL], abr[PPL], abi[PPL], tdb[PPL];
 #pragma unroll
     for (int i = 0; i < PPL; i++) {
         pp[i] = blk_p0 + i * 256 + threadIdx.x;
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
         epsd[i] = a.rec.epsd[pc];
         abr[i] = 0.0f;
         abi[i] = 0.0f;
+        tdb[i] = 0.0f;
         pp[i] = pc;
     }
     const int v0 = blockIdx.y * a.v_per, v1 = min(a.V, v0 + a.v_per);
@@ -128,7 +130,9 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
                     abi[i] -= q0i;
                     const float mr = a.fcf * q0r + a.sl_fs * q1r;
                     const float mi = a.fcf * q0i + a.sl_fs * q1i;
-                    tb[i] += -2.0f * (float)kPi * (A[i].x * mi + A[i].y * mr);
+                    const float dq = -2.0f * (float)kPi * (A[i].x * mi + A[i].y * mr);
+                    tb[i] += dq;
+                    tdb[i] += dq * (cf * a.tc);   // tau(c) = tau + c t_chirp taudot
                 }
             }
         }
@@ -138,19 +142,25 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < PPL; i++)
-        if (act[i]) a.abar_part[(size_t)blockIdx.y * a.rec.cap + pp[i]] = make_float2(abr[i], abi[i]);
+        if (act[i]) {
+            a.abar_part[(size_t)blockIdx.y * a.rec.cap + pp[i]] = make_float2(abr[i], abi[i]);
+            a.tdb_part[(size_t)blockIdx.y * a.rec.cap + pp[i]] = tdb[i];
+        }
 }
 
-__global__ void k_reduce_abar(const int32_t *count, const float2 *part, int nvs, int cap, float2 *abar) {
+__global__ void k_reduce_abar(const int32_t *count, const float2 *part, const float *tpart, int nvs, int cap,
+                              float2 *abar, float *tdbar) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= count[0]) return;
-    float r = 0.0f, i = 0.0f;
+    float r = 0.0f, i = 0.0f, t = 0.0f;
     for (int s = 0; s < nvs; s++) {
         float2 x = part[(size_t)s * cap + p];
         r += x.x;
         i += x.y;
+        t += tpart[(size_t)s * cap + p];
     }
     abar[p] = make_float2(r, i);
+    tdbar[p] = t;
 }
 
 struct GeomArgs {
@@ -167,8 +177,14 @@ struct GeomArgs {
     const int32_t *ray_first;
     const float2 *abar;
     const float *tau_bar;   // [V][cap]
+    const float *tdbar;     // [cap] dL/d taudot
     int32_t cap;
     float *grad;            // [nv][3]
+    float *g_mats;          // [n_mats][2] or NULL
+    float *g_radar;         // [6] or NULL
+    float *g_rot;           // [9] or NULL
+    float txl[SBR_MAX_TX][3];   // antenna positions in the radar frame
+    float rxl[SBR_MAX_RX][3];
 };
 
 __device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
@@ -217,21 +233,23 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     }
     if (__ballot(n > 0) == 0) return;   // uniform over the wavefront
     const int ix = r % a.g.nx, iy = r / a.g.nx;
-    double d0[3], dwd;
-    grid_ray(a.g, a.rd, ix, iy, d0, &dwd);
+    double d0[3], dl[3], dwd;
+    grid_dir_local(a.g, ix, iy, dl, &dwd);
+    for (int i = 0; i < 3; i++) d0[i] = a.rd.rot[3 * i] * dl[0] + a.rd.rot[3 * i + 1] * dl[1] + a.rd.rot[3 * i + 2] * dl[2];
     const float dw = (float)dwd;
     const float3 O = f3((float)a.rd.o[0], (float)a.rd.o[1], (float)a.rd.o[2]);
     // ---- forward recompute, cached per bounce
     float3 X[K], D[K], VA[K], E1[K], E2[K];
     float T[K], CI[K], SG[K], LC[K];
-    float2 RC[K], DRC[K];
-    int F[K];
+    float2 RC[K], DRC[K], DEPS[K];
+    int F[K], MAT[K];
     float3 dir = f3((float)d0[0], (float)d0[1], (float)d0[2]);
     float3 o = O;
     float L = 0.0f;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         F[k] = -1;
+        MAT[k] = -1;
         if (k < n) {
             const int f = a.tri[(size_t)k * a.R + r];
             const float3 va = vload3(a.verts, a.faces[3 * f]);
@@ -254,10 +272,16 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
             F[k] = f;
             CI[k] = fabsf(dn);
             SG[k] = dn >= 0.0f ? 1.0f : -1.0f;
-            cd rc = {-1.0, 0.0}, drc = {0.0, 0.0};
-            if (a.any_fresnel) reflect_coef(a.mt, a.mat_id ? (int)a.mat_id[f] : 0, a.ch.fc, (double)CI[k], rc, drc);
+            cd rc = {-1.0, 0.0}, drc = {0.0, 0.0}, de = {0.0, 0.0};
+            const int mi = a.mat_id ? (int)a.mat_id[f] : 0;
+            if (a.any_fresnel) {
+                reflect_coef(a.mt, mi, a.ch.fc, (double)CI[k], rc, drc);
+                if (a.g_mats) de = reflect_deps(a.mt, mi, a.ch.fc, (double)CI[k]);
+                if (mi < a.mt.n && a.mt.mode[mi] != 0) MAT[k] = mi;
+            }
             RC[k] = make_float2((float)rc.re, (float)rc.im);
             DRC[k] = make_float2((float)drc.re, (float)drc.im);
+            DEPS[k] = make_float2((float)de.re, (float)de.im);
             dir = dir - (2.0f * dn / nl) * N;
             o = x;
         }
@@ -265,11 +289,22 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     // ---- path adjoints -> dL/dx_j, dL/dcos_j
     float3 xb[K];
     float cib[K];
+    float2 gm[K];                           // dL/d (eps_r, sigma) of the material at bounce j
+    float3 go = f3(0.f, 0.f, 0.f);          // dL/d radar origin
+    float3 gu = f3(0.f, 0.f, 0.f);          // dL/d scene velocity
+    float3 gd0 = f3(0.f, 0.f, 0.f);         // dL/d first ray direction (Doppler part)
+    float gR[9];                            // dL/d rot from the antenna positions
+#pragma unroll
+    for (int q = 0; q < 9; q++) gR[q] = 0.0f;
+    const bool want_rot = a.g_rot != nullptr;
+    const float3 U = f3((float)a.rd.vel[0], (float)a.rd.vel[1], (float)a.rd.vel[2]);
 #pragma unroll
     for (int k = 0; k < K; k++) {
         xb[k] = f3(0.f, 0.f, 0.f);
         cib[k] = 0.0f;
+        gm[k] = make_float2(0.f, 0.f);
     }
+    const float inv_we0 = (float)(1.0 / (2.0 * kPi * a.ch.fc * kEps0));
     const int ntx = a.rd.n_tx, nrx = a.rd.n_rx;
     const float ic0 = (float)(1.0 / kC0);
 #pragma unroll
@@ -297,6 +332,14 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
                         if (i != j) ex = make_float2(ex.x * RC[i].x - ex.y * RC[i].y, ex.x * RC[i].y + ex.y * RC[i].x);
                     const float2 dA = make_float2(ex.x * DRC[j].x - ex.y * DRC[j].y, ex.x * DRC[j].y + ex.y * DRC[j].x);
                     cib[j] += ab.x * dA.x + ab.y * dA.y;
+                    if (a.g_mats) {
+                        // eps_c = eps_r - j sigma / (omega eps_0): d/deps_r = d/deps_c,
+                        // d/dsigma = -j / (omega eps_0) d/deps_c
+                        const float2 W = make_float2(ex.x * DEPS[j].x - ex.y * DEPS[j].y,
+                                                     ex.x * DEPS[j].y + ex.y * DEPS[j].x);
+                        gm[j].x += ab.x * W.x + ab.y * W.y;
+                        gm[j].y += (ab.x * W.y - ab.y * W.x) * inv_we0;
+                    }
                 }
             }
             float3 prv = O;
@@ -306,6 +349,7 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
                 const float3 uj = (Lb / len3(sg)) * sg;
                 xb[j] = xb[j] + uj;
                 if (j > 0) xb[j - 1] = xb[j - 1] - uj;
+                else go = go - uj;                  // first segment starts at the origin
                 prv = X[j];
             }
             xb[k] = xb[k] + (Rb / Rk) * (X[k] - O);
@@ -321,12 +365,37 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
                 }
             for (int t = 0; t < ntx; t++) {
                 const float3 q = X[0] - f3((float)a.rd.tx[t][0], (float)a.rd.tx[t][1], (float)a.rd.tx[t][2]);
-                xb[0] = xb[0] + (TS[t] * ic0 / len3(q)) * q;
+                const float3 gq = (TS[t] * ic0 / len3(q)) * q;
+                xb[0] = xb[0] + gq;
+                go = go - gq;                       // TX positions move with the origin
+                if (want_rot) {                     // tx_world = origin + rot tx_local
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        gR[c] -= gq.x * a.txl[t][c];
+                        gR[3 + c] -= gq.y * a.txl[t][c];
+                        gR[6 + c] -= gq.z * a.txl[t][c];
+                    }
+                }
             }
             for (int m = 0; m < nrx; m++) {
                 const float3 q = X[k] - f3((float)a.rd.rx[m][0], (float)a.rd.rx[m][1], (float)a.rd.rx[m][2]);
-                xb[k] = xb[k] + (RS[m] * ic0 / len3(q)) * q;
+                const float3 gq = (RS[m] * ic0 / len3(q)) * q;
+                xb[k] = xb[k] + gq;
+                go = go - gq;                       // RX positions move with the origin
+                if (want_rot) {
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        gR[c] -= gq.x * a.rxl[m][c];
+                        gR[3 + c] -= gq.y * a.rxl[m][c];
+                        gR[6 + c] -= gq.z * a.rxl[m][c];
+                    }
+                }
             }
+            go = go - (Rb / Rk) * (X[k] - O);        // R_k = |x_k - origin|
+            // taudot = 2 (u . d_1) / c
+            const float tdq = a.tdbar[p] * 2.0f * ic0;
+            gu = gu + tdq * f3((float)d0[0], (float)d0[1], (float)d0[2]);
+            gd0 = gd0 + tdq * U;
 #pragma unroll
             for (int j = 1; j <= k; j++) {
                 const float3 sg = X[j] - X[j - 1];
@@ -369,6 +438,7 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
             gc = cross3(Nb, e1);
             ga = ga - gb - gc;
             if (j > 0) xb[j - 1] = xb[j - 1] + ob;
+            else go = go + ob;                      // rays start at the origin
             dnext = db;
         }
         // sum over runs of lanes that hit the same face, one atomic per run
@@ -387,6 +457,48 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
             atomic_add3(a.grad, a.faces[3 * f], f3(v9[0], v9[1], v9[2]));
             atomic_add3(a.grad, a.faces[3 * f + 1], f3(v9[3], v9[4], v9[5]));
             atomic_add3(a.grad, a.faces[3 * f + 2], f3(v9[6], v9[7], v9[8]));
+        }
+        if (a.g_mats) {
+            // one wavefront sum per distinct material of this bounce
+            const int km = act ? MAT[j] : -1;
+            uint64_t pending = __ballot(km >= 0);
+            while (pending) {
+                const int leader = __ffsll((unsigned long long)pending) - 1;
+                const int m = __shfl(km, leader);
+                const bool mine = km == m;
+                float e0 = mine ? gm[j].x : 0.0f, e1 = mine ? gm[j].y : 0.0f;
+                for (int off = 32; off >= 1; off >>= 1) {
+                    e0 += __shfl_xor(e0, off);
+                    e1 += __shfl_xor(e1, off);
+                }
+                if (lane == leader) {
+                    atomicAdd(&a.g_mats[2 * m], e0);
+                    atomicAdd(&a.g_mats[2 * m + 1], e1);
+                }
+                pending &= ~__ballot(mine);
+            }
+        }
+    }
+    if (a.g_radar) {
+        float v6[6] = {go.x, go.y, go.z, gu.x, gu.y, gu.z};
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+            for (int off = 32; off >= 1; off >>= 1) v6[q] += __shfl_xor(v6[q], off);
+            if (lane == 0) atomicAdd(&a.g_radar[q], v6[q]);
+        }
+    }
+    if (want_rot) {
+        // d_0 = rot d_local: dL/drot += (dL/dd_0) d_local^T, where dL/dd_0 is
+        // what the reverse sweep left for the first segment plus the Doppler part
+        const float3 g0 = dnext + gd0;
+        const float l0 = (float)dl[0], l1 = (float)dl[1], l2 = (float)dl[2];
+        float v9[9] = {gR[0] + g0.x * l0, gR[1] + g0.x * l1, gR[2] + g0.x * l2,
+                       gR[3] + g0.y * l0, gR[4] + g0.y * l1, gR[5] + g0.y * l2,
+                       gR[6] + g0.z * l0, gR[7] + g0.z * l1, gR[8] + g0.z * l2};
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            for (int off = 32; off >= 1; off >>= 1) v9[q] += __shfl_xor(v9[q], off);
+            if (lane == 0) atomicAdd(&a.g_rot[q], v9[q]);
         }
     }
 }
@@ -413,18 +525,23 @@ size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V) {
     cv.take<float>((size_t)V * cap);
     cv.take<float2>((size_t)bp.nvs * cap);
     cv.take<float2>(cap);
+    cv.take<float>((size_t)bp.nvs * cap);
+    cv.take<float>(cap);
     return align_up(cv.off, 256);
 }
 
 int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                     const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
-                    const float2 *G, float *grad, hipStream_t s) {
+                    const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
+                    hipStream_t s) {
     const int V = rd.n_tx * rd.n_rx;
     const long long cap = st.rec.cap;
     BackPlan bp = back_plan(cap, V);
     float *tau_bar = cv.take<float>((size_t)V * cap);
     float2 *part = cv.take<float2>((size_t)bp.nvs * cap);
     float2 *abar = cv.take<float2>(cap);
+    float *tpart = cv.take<float>((size_t)bp.nvs * cap);
+    float *tdbar = cv.take<float>(cap);
     AdjArgs a;
     a.count = st.count;
     a.rec = st.rec;
@@ -439,6 +556,7 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     a.tc = (float)cd.tc;
     a.tau_bar = tau_bar;
     a.abar_part = part;
+    a.tdb_part = tpart;
     dim3 grid((unsigned)((cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL)), (unsigned)bp.nvs);
     a.Sp = (cd.S + 7) / 8 * 8;
     a.rows = std::max(1, std::min(kAdjRowsMax, 8192 / a.Sp));
@@ -447,8 +565,8 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
         ProfScope ps(kProfSynthAdj, s);
         hipLaunchKernelGGL(k_synth_adj<kAdjPPL>, grid, dim3(256), lds, s, a);
     }
-    hipLaunchKernelGGL(k_reduce_abar, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st.count, part,
-                       bp.nvs, (int)cap, abar);
+    hipLaunchKernelGGL(k_reduce_abar, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st.count, part, tpart,
+                       bp.nvs, (int)cap, abar, tdbar);
     SBR_LAUNCHED();
     GeomArgs g;
     g.verts = m->verts;
@@ -466,8 +584,16 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     g.ray_first = st.ray_first;
     g.abar = abar;
     g.tau_bar = tau_bar;
+    g.tdbar = tdbar;
     g.cap = (int32_t)cap;
     g.grad = grad;
+    g.g_mats = params ? params->materials : nullptr;
+    g.g_radar = params ? params->radar : nullptr;
+    g.g_rot = params ? params->rot : nullptr;
+    for (int t = 0; t < SBR_MAX_TX; t++)
+        for (int c = 0; c < 3; c++) g.txl[t][c] = t < radar->n_tx ? (float)radar->tx[t][c] : 0.0f;
+    for (int q = 0; q < SBR_MAX_RX; q++)
+        for (int c = 0; c < 3; c++) g.rxl[q][c] = q < radar->n_rx ? (float)radar->rx[q][c] : 0.0f;
     dim3 gg((unsigned)((g.R + 255) / 256));
     switch (gd.K) {
     case 1: hipLaunchKernelGGL(k_geom_adj<1>, gg, dim3(256), 0, s, g); break;

@@ -58,15 +58,52 @@ __device__ inline void reflect_coef(const MatTable &mt, int mi, double fc, doubl
     }
 }
 
-__device__ __forceinline__ void grid_ray(const GridDev &g, const RadarDev &rd, int ix, int iy,
-                                         double d[3], double *dw) {
+// d r / d eps_c of the reflection coefficient above (holomorphic in eps_c);
+// zero for the conductor.
+__device__ inline cd reflect_deps(const MatTable &mt, int mi, double fc, double ci) {
+    int mode = (mt.n > 0 && mi < mt.n) ? mt.mode[mi] : 0;
+    if (mode == 0) return {0.0, 0.0};
+    cd eps = {mt.eps_r[mi], -mt.sigma[mi] / (2.0 * kPi * fc * kEps0)};
+    cd n = csqrtp(eps);
+    cd s2 = cdivz({1.0 - ci * ci, 0.0}, eps);
+    cd ct = csqrtp({1.0 - s2.re, -s2.im});
+    cd dn = cdivz({0.5, 0.0}, n);                                   // 1 / (2 n)
+    cd dct = cdivz(cdivz(s2, eps), {2.0 * ct.re, 2.0 * ct.im});     // (s^2 / eps^2) / (2 ct)
+    if (mode == 1) {
+        // r = (ci - K)/(ci + K), K = n ct
+        cd K = cmul(n, ct);
+        cd dK = {dn.re * ct.re - dn.im * ct.im + (n.re * dct.re - n.im * dct.im),
+                 dn.re * ct.im + dn.im * ct.re + (n.re * dct.im + n.im * dct.re)};
+        cd den = {ci + K.re, K.im};
+        cd drdK = cdivz({-2.0 * ci, 0.0}, cmul(den, den));
+        return cmul(drdK, dK);
+    }
+    // r = (a - b)/(a + b), a = n ci, b = ct:  dr = 2 (a' b - a b') / (a + b)^2
+    cd a = {n.re * ci, n.im * ci}, b = ct;
+    cd da = {dn.re * ci, dn.im * ci};
+    cd t1 = cmul(da, b), t2 = cmul(a, dct);
+    cd num = {2.0 * (t1.re - t2.re), 2.0 * (t1.im - t2.im)};
+    cd den = {a.re + b.re, a.im + b.im};
+    return cdivz(num, cmul(den, den));
+}
+
+// Unit direction of grid cell (ix, iy) in the radar frame and its solid angle.
+__device__ __forceinline__ void grid_dir_local(const GridDev &g, int ix, int iy, double dr[3], double *dw) {
     double u = g.thx * (2.0 * (ix + 0.5) / g.nx - 1.0);
     double v = g.thy * (2.0 * (iy + 0.5) / g.ny - 1.0);
     double q = 1.0 + u * u + v * v;
     double s = 1.0 / sqrt(q);
-    double dr[3] = {u * s, v * s, s};
-    for (int i = 0; i < 3; i++) d[i] = rd.rot[3 * i] * dr[0] + rd.rot[3 * i + 1] * dr[1] + rd.rot[3 * i + 2] * dr[2];
+    dr[0] = u * s;
+    dr[1] = v * s;
+    dr[2] = s;
     *dw = (2.0 * g.thx / g.nx) * (2.0 * g.thy / g.ny) / (q * sqrt(q));
+}
+
+__device__ __forceinline__ void grid_ray(const GridDev &g, const RadarDev &rd, int ix, int iy,
+                                         double d[3], double *dw) {
+    double dr[3];
+    grid_dir_local(g, ix, iy, dr, dw);
+    for (int i = 0; i < 3; i++) d[i] = rd.rot[3 * i] * dr[0] + rd.rot[3 * i + 1] * dr[1] + rd.rot[3 * i + 2] * dr[2];
 }
 
 

@@ -21,7 +21,7 @@ import numpy as np
 import torch
 
 from . import scenes as S
-from .autograd import HeatmapLoss, IFLoss, RadarCubeFunction, SBRFunction
+from .autograd import HeatmapLoss, IFLoss, RadarCubeFunction, SBRFunction, rigid_pose
 from .sbr import Simulator
 
 
@@ -142,6 +142,52 @@ def reconstruct(start: S.Scene, target: S.Scene, steps: int = 200, lr: float = 1
     c0 = chamfer(start.verts, start.faces, target.verts, target.faces, device=dev)
     c1 = chamfer(final, start.faces, target.verts, target.faces, device=dev)
     return ReconResult(losses, times, c0, c1, lam, final)
+
+
+@dataclasses.dataclass
+class PoseResult:
+    losses: List[float]
+    omega: np.ndarray
+    trans: np.ndarray
+    step_ms: List[float]
+
+
+def fit_pose(scene: S.Scene, target_cube: torch.Tensor, steps: int = 100, lr: float = 2e-3,
+             omega0=(0.0, 0.0, 0.0), trans0=(0.0, 0.0, 0.0), objective: str = "heatmap",
+             device="cuda", rebuild_every: int = 20) -> PoseResult:
+    """Object pose from a radar IF cube (the object-transform parameterisation
+    of Sec. 3.1 (i) driven by the loss of Eqs. 14/16): the mesh of `scene` is
+    posed by exp([omega]x) about its centroid plus a translation, and Adam
+    fits (omega, trans) so that its simulated signal matches `target_cube`."""
+    dev = torch.device(device)
+    sim = Simulator(scene, dev)
+    if objective == "heatmap":
+        tgt = (sim.radar_cube(target_cube).abs() ** 2).contiguous()
+        tnorm = float((tgt ** 2).mean().item())
+    elif objective == "if":
+        tgt = target_cube
+        tnorm = float((tgt.abs() ** 2).sum().item())
+    else:
+        raise ValueError(f"objective must be 'heatmap' or 'if', not {objective!r}")
+    base = torch.as_tensor(scene.verts, dtype=torch.float32, device=dev)
+    omega = torch.tensor(omega0, dtype=torch.float32, device=dev, requires_grad=True)
+    trans = torch.tensor(trans0, dtype=torch.float32, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([omega, trans], lr=lr)
+    losses, times = [], []
+    for it in range(steps):
+        t0 = time.perf_counter()
+        cube = SBRFunction.apply(rigid_pose(base, omega, trans), sim, (it % rebuild_every) != 0)
+        if objective == "heatmap":
+            loss = HeatmapLoss.apply(RadarCubeFunction.apply(cube, sim, 0), tgt, sim, 1.0 / tnorm)
+        else:
+            loss = IFLoss.apply(cube, tgt, sim, 1.0 / tnorm)
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        losses.append(float(loss.item()))
+    return PoseResult(losses, omega.detach().cpu().numpy(), trans.detach().cpu().numpy(), times)
 
 
 def main(argv=None):

@@ -191,12 +191,21 @@ def sbr_cfar(cube: torch.Tensor, Na: int, C: int, Sn: int, guard: int, train: in
 
 
 def sbr_backward(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: S.Chirp, flags: int,
-                 grad_if: torch.Tensor, grad_verts: torch.Tensor, scratch: torch.Tensor):
+                 grad_if: torch.Tensor, grad_verts: torch.Tensor, scratch: torch.Tensor,
+                 grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,
+                 grad_rot: Optional[torch.Tensor] = None):
     m, r, g, h, c = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct(), chirp_struct(chirp)
     mats, nm = materials_struct(mesh.materials)
+    pg = None
+    if grad_materials is not None or grad_radar is not None or grad_rot is not None:
+        for t, n in ((grad_materials, 2 * len(mesh.materials or [])), (grad_radar, 6), (grad_rot, 9)):
+            if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n):
+                raise ValueError(f"parameter gradient buffer must be contiguous float32 with {n} elements")
+        pg = L.sbr_param_grads(*[t.data_ptr() if t is not None else None
+                                 for t in (grad_materials, grad_radar, grad_rot)])
     L.check(_lib().sbr_backward(ct.byref(m), mats, nm, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c),
-                                int(flags), _p(grad_if), _p(grad_verts), _p(scratch),
-                                scratch.numel() * scratch.element_size(), _stream()))
+                                int(flags), _p(grad_if), _p(grad_verts), ct.byref(pg) if pg is not None else None,
+                                _p(scratch), scratch.numel() * scratch.element_size(), _stream()))
 
 
 def sbr_loss_grad(mode: int, a: torch.Tensor, b: torch.Tensor, n: int, grad: Optional[torch.Tensor],
@@ -295,12 +304,17 @@ class Simulator:
         sbr_cfar(xf, int(xf.shape[0]), self.C, self.S, guard, train, pfa, pts, ratio, n, self.scratch)
         return pts, ratio, n
 
-    def backward(self, grad_if: torch.Tensor, grad_verts: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def backward(self, grad_if: torch.Tensor, grad_verts: Optional[torch.Tensor] = None,
+                 grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,
+                 grad_rot: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """dL/dverts (accumulated into grad_verts); optionally also accumulates
+        dL/d(eps_r, sigma) per material [n_mats,2], dL/d(origin, velocity) [6]
+        and dL/d rot [3,3] (radar -> world, row-major)."""
         gf = (torch.view_as_real(grad_if) if grad_if.is_complex() else grad_if).contiguous().to(torch.float32)
         if grad_verts is None:
             grad_verts = torch.zeros((self.mesh.nv, 3), dtype=torch.float32, device=self.device)
         sbr_backward(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, self.flags, gf,
-                     grad_verts, self.scratch)
+                     grad_verts, self.scratch, grad_materials, grad_radar, grad_rot)
         return grad_verts
 
     def loss_grad(self, cube: torch.Tensor, target: torch.Tensor, grad: Optional[torch.Tensor] = None,

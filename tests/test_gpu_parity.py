@@ -412,3 +412,72 @@ def test_backward_bounce_counts(torch_cuda, orc, K):
     e = rel_l2(got, fd)
     log(f"backward K={K}: rel L2 {e:.2e}")
     assert e <= GRAD_TOL
+
+
+def test_backward_material_origin_velocity(torch_cuda, orc):
+    """Gradients of the material table (eps_r, sigma through Eqs. 9-10), the
+    radar origin, the radar rotation (along three infinitesimal rotations) and
+    the scene velocity vs central differences of the oracle."""
+    import torch
+    sc = _synth_case("fresnel_mixed").with_grid(nx=40, ny=40)
+    sc = dataclasses.replace(sc, radar=S.default_radar(3, 4, vel=(0.4, -0.3, 1.0)))
+    o = orc.trace(sc)
+    tgt = _target(orc, sc, 1e-3, 23)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    G = 2.0 * (orc.synth(sc, p) - tgt)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    gm = torch.zeros((len(sc.materials), 2), dtype=torch.float32, device="cuda")
+    gr = torch.zeros(6, dtype=torch.float32, device="cuda")
+    gR = torch.zeros(9, dtype=torch.float32, device="cuda")
+    sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda"), grad_materials=gm, grad_radar=gr,
+                 grad_rot=gR)
+    torch.cuda.synchronize()
+    gm, gr = gm.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
+    gR = gR.cpu().numpy().astype(np.float64).reshape(3, 3)
+
+    def mat(i, k):
+        def f(s, d):
+            m = [list(x) for x in s.materials]
+            m[i][1 + k] += d
+            return dataclasses.replace(s, materials=[tuple(x) for x in m])
+        return f
+
+    def origin(k):
+        def f(s, d):
+            r = dataclasses.replace(s.radar, origin=s.radar.origin + d * np.eye(3)[k])
+            return dataclasses.replace(s, radar=r)
+        return f
+
+    def vel(k):
+        def f(s, d):
+            r = dataclasses.replace(s.radar, vel=s.radar.vel + d * np.eye(3)[k])
+            return dataclasses.replace(s, radar=r)
+        return f
+
+    def skew(w):
+        return np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+
+    def rotate(k):
+        # rot' = exp(delta [e_k]x) rot (Rodrigues, exactly orthonormal)
+        def f(s, d):
+            K = skew(np.eye(3)[k])
+            Rk = np.eye(3) + math.sin(d) * K + (1.0 - math.cos(d)) * (K @ K)
+            r = dataclasses.replace(s.radar, rot=Rk @ np.asarray(s.radar.rot, float))
+            return dataclasses.replace(s, radar=r)
+        return f
+
+    fm = np.array([[orc.fd_scene(sc, o["tri"], o["flags"], tgt, mat(i, k), 1e-6) for k in range(2)]
+                   for i in range(len(sc.materials))])
+    fo = np.array([orc.fd_scene(sc, o["tri"], o["flags"], tgt, origin(k), 1e-9) for k in range(3)])
+    fv = np.array([orc.fd_scene(sc, o["tri"], o["flags"], tgt, vel(k), 1e-4) for k in range(3)])
+    log(f"materials gpu {gm.tolist()} fd {fm.tolist()}")
+    R0 = np.asarray(sc.radar.rot, float)
+    an = np.array([(gR * (skew(np.eye(3)[k]) @ R0)).sum() for k in range(3)])
+    fr = np.array([orc.fd_scene(sc, o["tri"], o["flags"], tgt, rotate(k), 1e-7) for k in range(3)])
+    log(f"origin gpu {gr[:3]} fd {fo}; velocity gpu {gr[3:]} fd {fv}; rotation gpu {an} fd {fr}")
+    assert np.abs(fm[0]).max() == 0.0 and np.abs(gm[0]).max() == 0.0     # conductor: no parameters
+    assert rel_l2(gm[1:], fm[1:]) <= GRAD_TOL
+    assert rel_l2(gr[:3], fo) <= GRAD_TOL
+    assert rel_l2(gr[3:], fv) <= GRAD_TOL
+    assert rel_l2(an, fr) <= GRAD_TOL

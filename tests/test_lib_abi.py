@@ -72,8 +72,12 @@ def test_argument_errors_are_reported(lib):
                           fake, 16, None)
     assert rc == L.SBR_E_SCRATCH and b"needed" in lib.sbr_last_error()
     rc = lib.sbr_backward(ct.byref(m), None, 0, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
-                          fake, fake, 16, None)
+                          fake, None, fake, 16, None)
     assert rc == L.SBR_E_SCRATCH
+    pg = L.sbr_param_grads(0x10000, None)     # material gradients need a material table
+    rc = lib.sbr_backward(ct.byref(m), None, 0, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
+                          fake, ct.byref(pg), fake, 1 << 30, None)
+    assert rc == L.SBR_E_ARG and b"material" in lib.sbr_last_error()
     # radar cube: n_angle below V, bad window, bad direction
     assert lib.sbr_radar_cube(fake, 12, 8, 16, 8, 0, 0, fake, fake, 1 << 30, None) == L.SBR_E_ARG
     assert lib.sbr_radar_cube(fake, 12, 8, 16, 64, 2, 0, fake, fake, 1 << 30, None) == L.SBR_E_ARG
