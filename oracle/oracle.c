@@ -212,9 +212,45 @@ void orc_fresnel(const orc_mesh *m, int mi, double fc, double cos_i, double out[
 }
 
 /* ---------- per-path time of flight (I^t) and strength (I^s) ---------- */
+/* ---------- Eqs. (6)-(7): a transform T that attaches each sample to its first hit ----------
+ * Solid angle per unit of barycentric area at the point x of a triangle with
+ * (unnormalised) normal N seen from o:  |N . (x - o)| / |x - o|^3. */
+static double attach_density(const double N[3], const double x[3], const double o[3]) {
+    double q[3];
+    sub3(x, o, q);
+    double r = norm3(q);
+    return fabs(dot3(N, q)) / (r * r * r);
+}
+
+void orc_attach(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const int *rays, int n,
+                const int *tri, double *attach) {
+    for (int i = 0; i < n; i++) {
+        int r = rays ? rays[i] : i;
+        double *out = attach + 3 * (size_t)i;
+        int f = tri[i];
+        if (f < 0) { out[0] = out[1] = out[2] = 0.0; continue; }
+        double o[3], d[3], dw, a[3], b[3], c[3], e1[3], e2[3], N[3], av[3], x[3], w[3], cx[3];
+        orc_ray(rd, g, r, o, d, &dw);
+        tri_verts(m, f, a, b, c);
+        sub3(b, a, e1); sub3(c, a, e2); cross3(e1, e2, N);
+        sub3(a, o, av);
+        double th = dot3(N, av) / dot3(N, d);
+        for (int j = 0; j < 3; j++) x[j] = o[j] + th * d[j];
+        /* barycentrics of x: x - a = b1 e1 + b2 e2 */
+        double nn = dot3(N, N);
+        sub3(x, a, w);
+        cross3(w, e2, cx);
+        out[0] = dot3(cx, N) / nn;
+        cross3(e1, w, cx);
+        out[1] = dot3(cx, N) / nn;
+        out[2] = attach_density(N, x, o);
+    }
+}
+
 int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const orc_chirp *ch,
               const int *rays, int n, const int *tri, const unsigned char *flags, int drop_flagged,
-              int *path_ray, int *path_k, double *amp, double *tau, double *taudot) {
+              const double *attach, int *path_ray, int *path_k, double *amp, double *tau,
+              double *taudot, double *weight) {
     const int K = g->max_bounces;
     const int V = rd->n_tx * rd->n_rx;
     double txw[8][3], rxw[16][3];
@@ -227,6 +263,23 @@ int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const o
         double o[3], d[3], dw;
         orc_ray(rd, g, r, o, d, &dw);
         double O[3] = {o[0], o[1], o[2]};
+        const double *att = NULL;
+        double xa[3] = {0, 0, 0};
+        if (attach && tri[i] >= 0) {
+            /* the sample follows its first hit: fixed barycentrics on the
+             * (moved) triangle, the direction through that point, and the
+             * cell's solid angle scaled by |det J_T| = density / density_0 */
+            att = attach + 3 * (size_t)i;
+            double a[3], b[3], c[3];
+            tri_verts(m, tri[i], a, b, c);
+            for (int j = 0; j < 3; j++) xa[j] = a[j] + att[0] * (b[j] - a[j]) + att[1] * (c[j] - a[j]);
+            double q[3], e1[3], e2[3], N[3];
+            sub3(xa, O, q);
+            double rq = norm3(q);
+            for (int j = 0; j < 3; j++) d[j] = q[j] / rq;
+            sub3(b, a, e1); sub3(c, a, e2); cross3(e1, e2, N);
+            dw *= attach_density(N, xa, O) / att[2];
+        }
         /* Doppler of the path: rate of change of the round trip for a rigidly
          * moving scene, 2 (u . d_1) / c */
         double tdot = 2.0 * dot3(rd->vel, d) / C0;
@@ -243,7 +296,7 @@ int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const o
             /* plane intersection along the current ray */
             sub3(a, o, av);
             double th = dot3(N, av) / dot3(N, d);
-            for (int j = 0; j < 3; j++) x[j] = o[j] + th * d[j];
+            for (int j = 0; j < 3; j++) x[j] = (k == 0 && att) ? xa[j] : o[j] + th * d[j];
             double nl = norm3(N), nh[3] = {N[0] / nl, N[1] / nl, N[2] / nl};
             double dn = dot3(d, nh);
             double cos_i = fabs(dn);
@@ -269,6 +322,7 @@ int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const o
                         tau[(size_t)P * V + t * rd->n_rx + q] = len / C0;
                     }
                 taudot[P] = tdot;
+                if (weight) weight[P] = dw;
                 path_ray[P] = i;
                 path_k[P] = k + 1;
                 P++;

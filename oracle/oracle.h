@@ -20,6 +20,10 @@
  *                      closed forms, energy invariant
  *   orc_paths          plate normal incidence (tau = 2R/c), trihedral
  *                      point-reflection identity, Fresnel special cases
+ *   orc_attach         summed attached weights vs the closed-form solid angle
+ *                      of a triangle (Van Oosterom-Strackee) and its
+ *                      derivative; attached estimator == fixed one at theta_0;
+ *                      dense re-traced grid (loose)
  *   orc_fresnel        normal incidence, grazing, passivity, conductor limit
  *   orc_synth          single-path geometric sequence and Dirichlet kernel,
  *                      range / Doppler / angle peak bins
@@ -103,8 +107,20 @@ void orc_fresnel(const orc_mesh *m, int mi, double fc, double cos_i, double out[
  * Returns P. */
 int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g,
               const orc_chirp *ch, const int *rays, int n, const int *tri,
-              const unsigned char *flags, int drop_flagged,
-              int *path_ray, int *path_k, double *amp, double *tau, double *taudot);
+              const unsigned char *flags, int drop_flagged, const double *attach,
+              int *path_ray, int *path_k, double *amp, double *tau, double *taudot,
+              double *weight);
+
+/* Reparameterisation of Eqs. (6)-(7) that attaches every sample to its first
+ * hit.  For each of the n rays whose first hit triangle tri[i] (bounce-0 row
+ * of the hit ids) exists: attach[i] = (b1, b2, D0) with x = a + b1 (b - a) +
+ * b2 (c - a) the hit point and D0 = |N . (x - o)| / |x - o|^3 the solid angle
+ * per unit barycentric area there.  Given to orc_paths (with the geometry
+ * moved), the first hit stays at (b1, b2) of its triangle, the ray turns to
+ * pass through it, and the cell weight is multiplied by |det J_T| = D / D0;
+ * weight (NULL-able, [P]) receives that weight per path.  Misses: zeros. */
+void orc_attach(const orc_mesh *m, const orc_radar *rd, const orc_grid *g,
+                const int *rays, int n, const int *tri, double *attach);
 
 /* IF signal by direct summation over paths.  rows: [n_rows] indices v*C + c
  * (NULL = every row, n_rows = V*C).  out: [n_rows][S][2]. */

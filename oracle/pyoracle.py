@@ -75,7 +75,10 @@ def lib():
         L.orc_fresnel.argtypes = [ct.POINTER(_Mesh), ct.c_int, ct.c_double, ct.c_double, dp]
         L.orc_paths.restype = ct.c_int
         L.orc_paths.argtypes = [ct.POINTER(_Mesh), ct.POINTER(_Radar), ct.POINTER(_Grid),
-                                ct.POINTER(_Chirp), ip, ct.c_int, ip, bp, ct.c_int, ip, ip, dp, dp, dp]
+                                ct.POINTER(_Chirp), ip, ct.c_int, ip, bp, ct.c_int, dp, ip, ip, dp, dp,
+                                dp, dp]
+        L.orc_attach.argtypes = [ct.POINTER(_Mesh), ct.POINTER(_Radar), ct.POINTER(_Grid), ip, ct.c_int,
+                                 ip, dp]
         L.orc_synth.argtypes = [ct.c_int, dp, dp, dp, ct.c_int, ct.POINTER(_Chirp), ip, ct.c_int, dp]
         L.orc_synth_adjoint.argtypes = [ct.c_int, dp, dp, dp, ct.c_int, ct.POINTER(_Chirp), dp,
                                         dp, dp, dp]
@@ -173,7 +176,22 @@ def trace(scene, rays=None, verts64=None):
     return {"tri": tri, "t": t, "b1": b1, "b2": b2, "flags": fl, "queries": int(q)}
 
 
-def paths(scene, tri, flags=None, rays=None, drop=True, verts64=None):
+def attach(scene, tri, rays=None, verts64=None):
+    """(b1, b2, D0) per ray of the first hit (Eqs. 6-7 transform attached to
+    it); tri is the [K][n] hit-id array of the unperturbed scene."""
+    ids = None if rays is None else np.ascontiguousarray(rays, dtype=np.int32)
+    t0 = np.ascontiguousarray(tri[0], dtype=np.int32)
+    out = np.empty((len(t0), 3))
+    m, keep = _mesh(scene, verts64)
+    lib().orc_attach(ct.byref(m), ct.byref(_radar(scene.radar)), ct.byref(_grid(scene.grid)),
+                     _p(ids, ct.c_int), len(t0), _p(t0, ct.c_int), _p(out, ct.c_double))
+    return out
+
+
+def paths(scene, tri, flags=None, rays=None, drop=True, verts64=None, att=None):
+    """Per-path amplitude, delays and Doppler from frozen hit ids.  att: None
+    (fixed ray directions) or the per-ray array of attach() (first hit at
+    fixed barycentrics, cell weight times |det J_T|)."""
     g = scene.grid
     K = g.max_bounces
     V = scene.radar.n_virtual
@@ -187,14 +205,16 @@ def paths(scene, tri, flags=None, rays=None, drop=True, verts64=None):
     amp = np.empty((cap, 2))
     tau = np.empty((cap, V))
     td = np.empty(cap)
+    wt = np.empty(cap)
+    at = None if att is None else np.ascontiguousarray(att, dtype=np.float64)
     m, keep = _mesh(scene, verts64)
     P = lib().orc_paths(ct.byref(m), ct.byref(_radar(scene.radar)), ct.byref(_grid(g)),
                         ct.byref(_chirp(scene.chirp)), _p(ids, ct.c_int), n, _p(tri, ct.c_int),
-                        _p(fl, ct.c_ubyte), int(bool(drop) and fl is not None), _p(pr, ct.c_int),
-                        _p(pk, ct.c_int), _p(amp, ct.c_double), _p(tau, ct.c_double),
-                        _p(td, ct.c_double))
+                        _p(fl, ct.c_ubyte), int(bool(drop) and fl is not None), _p(at, ct.c_double),
+                        _p(pr, ct.c_int), _p(pk, ct.c_int), _p(amp, ct.c_double), _p(tau, ct.c_double),
+                        _p(td, ct.c_double), _p(wt, ct.c_double))
     return {"ray": pr[:P].copy(), "k": pk[:P].copy(), "amp": amp[:P, 0] + 1j * amp[:P, 1],
-            "tau": tau[:P].copy(), "taudot": td[:P].copy()}
+            "tau": tau[:P].copy(), "taudot": td[:P].copy(), "weight": wt[:P].copy()}
 
 
 def synth(scene, pth, rows=None):
@@ -281,29 +301,29 @@ def if_loss(S, target):
     return float(np.sum(d.real ** 2 + d.imag ** 2))
 
 
-def fd_directional(scene, tri, flags, target, direction, h=1e-9, rays=None, drop=True):
+def fd_directional(scene, tri, flags, target, direction, h=1e-9, rays=None, drop=True, att=None):
     """Central difference of L = sum |S - target|^2 along `direction` ([nv][3])
-    with the hit-triangle sequences frozen."""
+    with the hit-triangle sequences frozen (att: see paths())."""
     v0 = scene.verts.astype(np.float64)
     Ls = []
     for sgn in (+1.0, -1.0):
-        p = paths(scene, tri, flags, rays, drop, verts64=v0 + sgn * h * direction)
+        p = paths(scene, tri, flags, rays, drop, verts64=v0 + sgn * h * direction, att=att)
         Ls.append(if_loss(synth(scene, p), target))
     return (Ls[0] - Ls[1]) / (2.0 * h)
 
 
-def fd_scene(scene, tri, flags, target, perturb, h, rays=None, drop=True):
+def fd_scene(scene, tri, flags, target, perturb, h, rays=None, drop=True, att=None):
     """Central difference of the IF loss with respect to a scalar scene
     parameter: perturb(scene, delta) returns the scene with the parameter
     moved by delta (hit-triangle sequences frozen)."""
     Ls = []
     for sgn in (+1.0, -1.0):
         sp = perturb(scene, sgn * h)
-        Ls.append(if_loss(synth(sp, paths(sp, tri, flags, rays, drop)), target))
+        Ls.append(if_loss(synth(sp, paths(sp, tri, flags, rays, drop, att=att)), target))
     return (Ls[0] - Ls[1]) / (2.0 * h)
 
 
-def fd_grad(scene, tri, flags, target, coords=None, h=1e-9, rays=None, drop=True):
+def fd_grad(scene, tri, flags, target, coords=None, h=1e-9, rays=None, drop=True, att=None):
     """Central differences of the IF loss for every vertex coordinate in
     `coords` (flat indices into [nv*3]; None = all)."""
     nv = scene.nv
@@ -312,5 +332,19 @@ def fd_grad(scene, tri, flags, target, coords=None, h=1e-9, rays=None, drop=True
     for i, c in enumerate(coords):
         e = np.zeros((nv, 3))
         e.reshape(-1)[c] = 1.0
-        g[i] = fd_directional(scene, tri, flags, target, e, h, rays, drop)
+        g[i] = fd_directional(scene, tri, flags, target, e, h, rays, drop, att)
     return g
+
+
+def fd_retraced(scene, target, direction, h, rays=None):
+    """Central difference of the IF loss along `direction` with the scene
+    traced again at each side (hit sets free to change, nothing dropped): the
+    derivative of the estimator itself, visibility changes included."""
+    v0 = scene.verts.astype(np.float64)
+    Ls = []
+    for sgn in (+1.0, -1.0):
+        v = v0 + sgn * h * direction
+        tr = trace(scene, rays, verts64=v)
+        p = paths(scene, tr["tri"], tr["flags"], rays, False, verts64=v)
+        Ls.append(if_loss(synth(scene, p), target))
+    return (Ls[0] - Ls[1]) / (2.0 * h)
