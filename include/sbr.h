@@ -124,6 +124,14 @@ typedef struct {
 
 /* sbr_synth_if / sbr_backward flags */
 #define SBR_DROP_FLAGGED 1   /* paths whose hit flag byte is non-zero are skipped */
+#define SBR_ATTACHED 2       /* sbr_backward only: differentiate the reparameterised
+                                estimator of Sec. 3.2.1 Eqs. 6-7 in which every sample
+                                follows its first hit (fixed barycentrics on the moving
+                                triangle, ray turned through it, cell weight times
+                                |det J_T| = D / D_0 with D = |N . (x - o)| / |x - o|^3);
+                                moving silhouettes then contribute.  The forward
+                                signal is the same; without the flag the gradient is
+                                the pathwise one with fixed ray directions. */
 
 /* scratch-size queries */
 #define SBR_OP_BUILD_BVH 0

@@ -16,6 +16,7 @@ SBR_OK, SBR_E_ARG, SBR_E_HIP, SBR_E_SCRATCH, SBR_E_UNSUPPORTED = 0, -1, -2, -3, 
 SBR_MAX_BOUNCES, SBR_MAX_TX, SBR_MAX_RX, SBR_MAX_VIRTUAL, SBR_MAX_MATERIALS = 8, 8, 16, 64, 64
 SBR_HIT_EDGE, SBR_HIT_TIE, SBR_HIT_GRAZE, SBR_HIT_TMIN, SBR_HIT_PARENT = 1, 2, 4, 8, 16
 SBR_DROP_FLAGGED = 1
+SBR_ATTACHED = 2
 SBR_OP_BUILD_BVH, SBR_OP_SYNTH, SBR_OP_BACKWARD, SBR_OP_RADAR_CUBE, SBR_OP_CFAR = 0, 1, 2, 3, 4
 
 # every function declared in include/sbr.h

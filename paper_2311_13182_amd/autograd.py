@@ -20,16 +20,19 @@ class SBRFunction(torch.autograd.Function):
     Each call traces into fresh hit records kept by the graph, so several
     forwards may be in flight before their backwards run.  With refit=True
     the BVH of the previous build is refit to the new vertices (same faces).
+    With attached=True the gradient is that of the reparameterised estimator
+    (Eqs. 6-7, samples follow their first hit), which moves silhouettes.
     """
 
     @staticmethod
-    def forward(ctx, verts: torch.Tensor, sim: Simulator, refit: bool = True):
+    def forward(ctx, verts: torch.Tensor, sim: Simulator, refit: bool = True, attached: bool = False):
         sim.set_verts(verts)
         sim.build(refit=refit)
         sim.hits = Hits.empty(sim.K, sim.R, sim.device)
         sim.trace()
         cube = torch.view_as_complex(sim.synth())
         ctx.sim = sim
+        ctx.attached = attached
         ctx.hits = sim.hits
         ctx.verts = sim.mesh.verts.clone()
         return cube
@@ -42,11 +45,11 @@ class SBRFunction(torch.autograd.Function):
         sim.hits = ctx.hits
         sim.mesh.verts.copy_(ctx.verts)
         try:
-            g = sim.backward(grad_cube.contiguous())
+            g = sim.backward(grad_cube.contiguous(), attached=ctx.attached)
         finally:
             sim.hits = cur_hits
             sim.mesh.verts.copy_(cur_verts)
-        return g, None, None
+        return g, None, None, None
 
 
 class RadarCubeFunction(torch.autograd.Function):
@@ -95,8 +98,8 @@ class HeatmapLoss(torch.autograd.Function):
         return torch.view_as_complex(grad) * (gl * ctx.scale), None, None, None
 
 
-def simulate(verts: torch.Tensor, sim: Simulator, refit: bool = True) -> torch.Tensor:
-    return SBRFunction.apply(verts, sim, refit)
+def simulate(verts: torch.Tensor, sim: Simulator, refit: bool = True, attached: bool = False) -> torch.Tensor:
+    return SBRFunction.apply(verts, sim, refit, attached)
 
 
 def skew(w: torch.Tensor) -> torch.Tensor:

@@ -34,7 +34,7 @@ size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V);
 int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                     const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
                     const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
-                    hipStream_t s);
+                    bool attached, hipStream_t s);
 size_t cube_scratch_bytes(int V, int C, int S, int Na);
 size_t cfar_scratch_bytes(int C, int S);
 int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
@@ -336,7 +336,7 @@ int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
     ChirpDev cd = make_chirp(chirp);
     if ((rc = launch_paths(mesh, mt, rd, gd, cd, hits, flags, st, s))) return rc;
     return launch_backward(mesh, mt, rd, gd, cd, hits, st, cv, reinterpret_cast<const float2 *>(grad_if),
-                           grad_verts, radar, params, s);
+                           grad_verts, radar, params, (flags & SBR_ATTACHED) != 0, s);
 }
 
 }  // extern "C"

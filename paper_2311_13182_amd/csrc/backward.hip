@@ -183,6 +183,7 @@ struct GeomArgs {
     float *g_mats;          // [n_mats][2] or NULL
     float *g_radar;         // [6] or NULL
     float *g_rot;           // [9] or NULL
+    int32_t attached;       // 1: first hits follow their triangle (Eqs. 6-7)
     float txl[SBR_MAX_TX][3];   // antenna positions in the radar frame
     float rxl[SBR_MAX_RX][3];
 };
@@ -297,6 +298,7 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
 #pragma unroll
     for (int q = 0; q < 9; q++) gR[q] = 0.0f;
     const bool want_rot = a.g_rot != nullptr;
+    float wJ = 0.0f;                        // sum over the ray's paths of Re(conj(Abar) A)
     const float3 U = f3((float)a.rd.vel[0], (float)a.rd.vel[1], (float)a.rd.vel[2]);
 #pragma unroll
     for (int k = 0; k < K; k++) {
@@ -321,6 +323,7 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
             const float sc = dw / (LC[k] * Rk);
             const float u = sc * (ab.x * prod.x + ab.y * prod.y);
             const float gk = u * CI[k];
+            wJ += gk;                               // Re(conj(Abar) A): dL/d log(cell weight)
             cib[k] += u;
             const float Lb = -gk / LC[k], Rb = -gk / Rk;
             if (a.any_fresnel) {
@@ -411,7 +414,39 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     for (int j = K - 1; j >= 0; j--) {
         const bool act = j < n;
         float3 ga = f3(0.f, 0.f, 0.f), gb = ga, gc = ga;
-        if (act) {
+        if (act && j == 0 && a.attached) {
+            // Eqs. 6-7 with T attached to the first hit: x_0 = a + b1 e1 + b2 e2 at
+            // fixed (b1, b2), d_0 = (x_0 - o) / |x_0 - o|, cell weight times
+            // D / D_0 with D = |N . (x_0 - o)| / |x_0 - o|^3
+            const float3 e1 = E1[0], e2 = E2[0];
+            const float3 N = cross3(e1, e2);
+            const float nl = len3(N);
+            const float3 nh = (1.0f / nl) * N;
+            const float3 d = D[0];
+            const float dn = dot3(d, nh);
+            const float3 q = X[0] - O;
+            const float r0 = len3(q);
+            const float nn = dot3(N, N);
+            const float3 w0 = X[0] - VA[0];
+            const float b1 = dot3(cross3(w0, e2), N) / nn, b2 = dot3(cross3(e1, w0), N) / nn;
+            float3 db = (cib[0] * SG[0]) * nh + gd0;   // cos_0 = |d_0 . n|, Doppler 2 u.d_0 / c
+            float3 nhb = (cib[0] * SG[0]) * d;
+            const float ndn = dot3(nh, dnext);          // d_1 = d_0 - 2 (d_0.n) n
+            db = db + dnext - (2.0f * ndn) * nh;
+            nhb = nhb - 2.0f * (dn * dnext + ndn * d);
+            const float3 dq = (1.0f / r0) * (db - dot3(db, d) * d);
+            const float sN = dot3(N, q);
+            const float3 lj = wJ * ((1.0f / sN) * N - (3.0f / (r0 * r0)) * q);
+            const float3 xb0 = xb[0] + dq + lj;
+            go = go - dq - lj;
+            const float3 Nb = (wJ / sN) * q + (1.0f / nl) * (nhb - dot3(nhb, nh) * nh);
+            const float3 gbN = cross3(e2, Nb), gcN = cross3(Nb, e1);
+            ga = (1.0f - b1 - b2) * xb0 - gbN - gcN;
+            gb = b1 * xb0 + gbN;
+            gc = b2 * xb0 + gcN;
+            dnext = f3(0.f, 0.f, 0.f);                  // d_0 no longer depends on the grid
+            gd0 = f3(0.f, 0.f, 0.f);
+        } else if (act) {
             const float3 e1 = E1[j], e2 = E2[j];
             const float3 N = cross3(e1, e2);
             const float nl = len3(N);
@@ -533,7 +568,7 @@ size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V) {
 int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                     const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
                     const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
-                    hipStream_t s) {
+                    bool attached, hipStream_t s) {
     const int V = rd.n_tx * rd.n_rx;
     const long long cap = st.rec.cap;
     BackPlan bp = back_plan(cap, V);
@@ -590,6 +625,7 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     g.g_mats = params ? params->materials : nullptr;
     g.g_radar = params ? params->radar : nullptr;
     g.g_rot = params ? params->rot : nullptr;
+    g.attached = attached ? 1 : 0;
     for (int t = 0; t < SBR_MAX_TX; t++)
         for (int c = 0; c < 3; c++) g.txl[t][c] = t < radar->n_tx ? (float)radar->tx[t][c] : 0.0f;
     for (int q = 0; q < SBR_MAX_RX; q++)
