@@ -98,8 +98,56 @@ static double line_dist(const double x[3], const double a[3], const double b[3])
     return norm3(cr) / norm3(ab);
 }
 
+/* distance from x to the segment [a, b] */
+static double seg_dist(const double x[3], const double a[3], const double b[3]) {
+    double ab[3], ax[3];
+    sub3(b, a, ab); sub3(x, a, ax);
+    double s = dot3(ax, ab) / dot3(ab, ab);
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+    double y[3] = {a[0] + s * ab[0], a[1] + s * ab[1], a[2] + s * ab[2]};
+    return dist3(x, y);
+}
+
+/* Occlusion of the segment from x (on face `self`) to the array centre O.
+ * Sets *edge when the decision is within delta of changing. */
+static int occluded(const orc_mesh *m, const double x[3], const double O[3], int self, double t_min,
+                    double delta, int *edge) {
+    double s[3];
+    sub3(O, x, s);
+    double D = norm3(s);
+    for (int j = 0; j < 3; j++) s[j] /= D;
+    int occ = 0;
+    *edge = 0;
+    for (int f = 0; f < m->nf; f++) {
+        if (f == self) continue;
+        double a[3], b[3], c[3], th, uh, vh;
+        tri_verts(m, f, a, b, c);
+        if (mt_hit(x, s, a, b, c, &th, &uh, &vh) && th > t_min && th < D - t_min) occ = 1;
+        /* borderline: the line meets the plane near the triangle's boundary,
+         * or a hit sits near the ends of the accepted interval */
+        double e1[3], e2[3], N[3], av[3];
+        sub3(b, a, e1); sub3(c, a, e2); cross3(e1, e2, N);
+        double den = dot3(N, s);
+        if (den == 0.0) continue;
+        sub3(a, x, av);
+        double tp = dot3(N, av) / den;
+        if (tp < t_min - delta || tp > D - t_min + delta) continue;
+        double y[3] = {x[0] + tp * s[0], x[1] + tp * s[1], x[2] + tp * s[2]};
+        double de = seg_dist(y, a, b), d2 = seg_dist(y, b, c);
+        if (d2 < de) de = d2;
+        d2 = seg_dist(y, c, a);
+        if (d2 < de) de = d2;
+        int inside = mt_hit(x, s, a, b, c, &th, &uh, &vh);
+        if (de < delta) *edge = 1;
+        if (inside && (fabs(tp - t_min) < delta || fabs(tp - (D - t_min)) < delta)) *edge = 1;
+    }
+    return occ;
+}
+
 long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const int *rays, int n,
-                    int *tri, double *t_out, double *b1_out, double *b2_out, unsigned char *flags) {
+                    int *tri, double *t_out, double *b1_out, double *b2_out, unsigned char *flags,
+                    unsigned char *shadow_edge) {
     const int K = g->max_bounces;
     long long queries = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : queries)
@@ -118,6 +166,7 @@ long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, c
             if (b1_out) b1_out[slot] = 0.0;
             if (b2_out) b2_out[slot] = 0.0;
             if (flags) flags[slot] = 0;
+            if (shadow_edge) shadow_edge[slot] = 0;
             if (!alive) continue;
             queries++;
             /* closest hit = lexicographic minimum of (t, triangle id) */
@@ -158,8 +207,15 @@ long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, c
             if (t_out) t_out[slot] = bt;
             if (b1_out) b1_out[slot] = bu;
             if (b2_out) b2_out[slot] = bv;
-            if (flags) flags[slot] = fl;
             anc |= fl;
+            if (g->shadow && k > 0) {
+                int edge;
+                double lr = Lpath + dist3(x, rd->origin);
+                if (occluded(m, x, rd->origin, best, g->t_min, 1e-6 * (lr > 1.0 ? lr : 1.0), &edge))
+                    fl |= ORC_F_OCCLUDED;
+                if (shadow_edge) shadow_edge[slot] = (unsigned char)edge;
+            }
+            if (flags) flags[slot] = fl;
             /* specular reflection, continue from the hit point */
             for (int j = 0; j < 3; j++) { o[j] = x[j]; d[j] = d[j] - 2.0 * dn * nn[j]; }
             prev = best;
@@ -248,7 +304,7 @@ void orc_attach(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const
 }
 
 int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const orc_chirp *ch,
-              const int *rays, int n, const int *tri, const unsigned char *flags, int drop_flagged,
+              const int *rays, int n, const int *tri, const unsigned char *flags, int options,
               const double *attach, int *path_ray, int *path_k, double *amp, double *tau,
               double *taudot, double *weight) {
     const int K = g->max_bounces;
@@ -310,7 +366,11 @@ int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const o
             if (k == 0) { x1[0] = x[0]; x1[1] = x[1]; x1[2] = x[2]; }
             else Lmid += seg;
             double Rk = dist3(x, O);
-            if (!(drop_flagged && flags && flags[slot])) {
+            int keep = 1;
+            if (flags && (flags[slot] & ORC_F_OCCLUDED)) keep = 0;
+            if ((options & ORC_DROP_FLAGGED) && flags && (flags[slot] & ~ORC_F_OCCLUDED)) keep = 0;
+            if ((options & ORC_EXIT_ONLY) && k + 1 < K && tri[slot + n] >= 0) keep = 0;
+            if (keep) {
                 /* I^s = d_omega * prod r_j * cos(theta_k) / (L_k R_k) */
                 double s = dw * cos_i / (Lk * Rk);
                 amp[2 * P] = pr_re * s;

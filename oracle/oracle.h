@@ -17,7 +17,10 @@
  * Parity status (what pins each function; the tests under tests/ hold them):
  *   orc_ray            closed-form solid angle of the grid, boresight symmetry
  *   orc_trace          independent NumPy brute force, trihedral and plate
- *                      closed forms, energy invariant
+ *                      closed forms, energy invariant; shadow test: no
+ *                      occlusion inside a convex room, independent NumPy
+ *                      segment test with occluders, no inheritance
+ *   orc_paths (exit)   exit-only == last record of each ray of the full model
  *   orc_paths          plate normal incidence (tau = 2R/c), trihedral
  *                      point-reflection identity, Fresnel special cases
  *   orc_attach         summed attached weights vs the closed-form solid angle
@@ -73,6 +76,9 @@ typedef struct {
     double tan_hx, tan_hy;   /* half-width of the tangent-plane grid           */
     int max_bounces;
     double t_min;            /* minimum accepted hit distance, metres          */
+    int shadow;              /* 1: test the return segment of every hit after
+                                the first for occlusion (any hit strictly
+                                between it and the array centre)              */
 } orc_grid;
 
 /* hit flags, one byte per (bounce, ray) */
@@ -81,6 +87,11 @@ typedef struct {
 #define ORC_F_GRAZE    4   /* |d . n| < 1e-6                                     */
 #define ORC_F_TMIN     8   /* t < 2 t_min                                        */
 #define ORC_F_PARENT  16   /* an earlier bounce of the same ray is flagged       */
+#define ORC_F_OCCLUDED 32  /* return segment to the array centre is blocked      */
+
+/* orc_paths options */
+#define ORC_DROP_FLAGGED 1 /* skip records with any flag other than OCCLUDED     */
+#define ORC_EXIT_ONLY    2 /* only the last hit of each ray returns              */
 
 /* Ray r = iy * nx + ix of the grid: origin, unit direction, solid-angle weight. */
 void orc_ray(const orc_radar *rd, const orc_grid *g, int r,
@@ -90,24 +101,33 @@ void orc_ray(const orc_radar *rd, const orc_grid *g, int r,
  * rays: [n] ray indices (NULL = all rays 0..nx*ny-1, then n must be nx*ny).
  * Outputs are [K][n] with K = g->max_bounces: tri (-1 = none), t, barycentric
  * weights of vertices 1 and 2, flags.  Any output pointer may be NULL except tri.
+ * With g->shadow the return of every hit after the first (the first one's
+ * return retraces its incoming, unobstructed ray) is tested: a hit of another
+ * triangle with t in (t_min, D - t_min) along the segment of length D to the
+ * array centre sets ORC_F_OCCLUDED (not inherited by later bounces).
+ * shadow_edge ([K][n], NULL-able): 1 where that decision is borderline -- some
+ * other triangle meets the segment's line within delta_k of its boundary, or
+ * a hit lies within delta_k of the segment's ends.
  * Returns the number of closest-hit queries issued (a ray's final miss counts). */
 long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g,
                     const int *rays, int n, int *tri, double *t, double *b1,
-                    double *b2, unsigned char *flags);
+                    double *b2, unsigned char *flags, unsigned char *shadow_edge);
 
 /* Reflection coefficient of material `mi` at incidence cosine cos_i (in [0,1]).
  * out[0] = real part, out[1] = imaginary part. */
 void orc_fresnel(const orc_mesh *m, int mi, double fc, double cos_i, double out[2]);
 
 /* Path quantities from frozen hit triangle IDs (FP64 plane intersections).
- * One path per (ray, bounce) with a hit, in ray-major then bounce order;
- * with drop_flagged != 0 a path whose flag byte is non-zero is skipped.
+ * One path per (ray, bounce) with a hit, in ray-major then bounce order.
+ * Records flagged ORC_F_OCCLUDED never return.  options: ORC_DROP_FLAGGED
+ * skips records with any other flag bit; ORC_EXIT_ONLY keeps only the last
+ * hit of each ray (classic exit-ray SBR), and none if that one is skipped.
  * Outputs sized for K*n paths: path_ray [P] (index into `rays`), path_k [P]
  * (1-based bounce), amp [P][2], tau [P][V] (seconds), taudot [P] (s/s).
  * Returns P. */
 int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g,
               const orc_chirp *ch, const int *rays, int n, const int *tri,
-              const unsigned char *flags, int drop_flagged, const double *attach,
+              const unsigned char *flags, int options, const double *attach,
               int *path_ray, int *path_k, double *amp, double *tau, double *taudot,
               double *weight);
 

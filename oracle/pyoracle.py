@@ -22,7 +22,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-F_EDGE, F_TIE, F_GRAZE, F_TMIN, F_PARENT = 1, 2, 4, 8, 16
+F_EDGE, F_TIE, F_GRAZE, F_TMIN, F_PARENT, F_OCCLUDED = 1, 2, 4, 8, 16, 32
+DROP_FLAGGED, EXIT_ONLY = 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -56,7 +57,8 @@ class _Chirp(ct.Structure):
 
 class _Grid(ct.Structure):
     _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("tan_hx", ct.c_double),
-                ("tan_hy", ct.c_double), ("max_bounces", ct.c_int), ("t_min", ct.c_double)]
+                ("tan_hy", ct.c_double), ("max_bounces", ct.c_int), ("t_min", ct.c_double),
+                ("shadow", ct.c_int)]
 
 
 _lib = None
@@ -71,7 +73,7 @@ def lib():
         L.orc_ray.argtypes = [ct.POINTER(_Radar), ct.POINTER(_Grid), ct.c_int, dp, dp, dp]
         L.orc_trace.restype = ct.c_longlong
         L.orc_trace.argtypes = [ct.POINTER(_Mesh), ct.POINTER(_Radar), ct.POINTER(_Grid), ip,
-                                ct.c_int, ip, dp, dp, dp, bp]
+                                ct.c_int, ip, dp, dp, dp, bp, bp]
         L.orc_fresnel.argtypes = [ct.POINTER(_Mesh), ct.c_int, ct.c_double, ct.c_double, dp]
         L.orc_paths.restype = ct.c_int
         L.orc_paths.argtypes = [ct.POINTER(_Mesh), ct.POINTER(_Radar), ct.POINTER(_Grid),
@@ -149,7 +151,7 @@ def _chirp(ch):
 
 
 def _grid(g):
-    return _Grid(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces, g.t_min)
+    return _Grid(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces, g.t_min, int(getattr(g, "shadow", False)))
 
 
 def ray(scene, r):
@@ -169,11 +171,12 @@ def trace(scene, rays=None, verts64=None):
     b1 = np.empty((K, n))
     b2 = np.empty((K, n))
     fl = np.empty((K, n), np.uint8)
+    se = np.empty((K, n), np.uint8)
     m, keep = _mesh(scene, verts64)
     q = lib().orc_trace(ct.byref(m), ct.byref(_radar(scene.radar)), ct.byref(_grid(g)),
                         _p(ids, ct.c_int), n, _p(tri, ct.c_int), _p(t, ct.c_double),
-                        _p(b1, ct.c_double), _p(b2, ct.c_double), _p(fl, ct.c_ubyte))
-    return {"tri": tri, "t": t, "b1": b1, "b2": b2, "flags": fl, "queries": int(q)}
+                        _p(b1, ct.c_double), _p(b2, ct.c_double), _p(fl, ct.c_ubyte), _p(se, ct.c_ubyte))
+    return {"tri": tri, "t": t, "b1": b1, "b2": b2, "flags": fl, "shadow_edge": se, "queries": int(q)}
 
 
 def attach(scene, tri, rays=None, verts64=None):
@@ -188,10 +191,12 @@ def attach(scene, tri, rays=None, verts64=None):
     return out
 
 
-def paths(scene, tri, flags=None, rays=None, drop=True, verts64=None, att=None):
+def paths(scene, tri, flags=None, rays=None, drop=True, verts64=None, att=None, exit_only=False):
     """Per-path amplitude, delays and Doppler from frozen hit ids.  att: None
     (fixed ray directions) or the per-ray array of attach() (first hit at
-    fixed barycentrics, cell weight times |det J_T|)."""
+    fixed barycentrics, cell weight times |det J_T|).  Occluded records never
+    return; drop skips the other flagged ones; exit_only keeps only the last
+    hit of each ray."""
     g = scene.grid
     K = g.max_bounces
     V = scene.radar.n_virtual
@@ -210,7 +215,8 @@ def paths(scene, tri, flags=None, rays=None, drop=True, verts64=None, att=None):
     m, keep = _mesh(scene, verts64)
     P = lib().orc_paths(ct.byref(m), ct.byref(_radar(scene.radar)), ct.byref(_grid(g)),
                         ct.byref(_chirp(scene.chirp)), _p(ids, ct.c_int), n, _p(tri, ct.c_int),
-                        _p(fl, ct.c_ubyte), int(bool(drop) and fl is not None), _p(at, ct.c_double),
+                        _p(fl, ct.c_ubyte), (DROP_FLAGGED if drop and fl is not None else 0) |
+                        (EXIT_ONLY if exit_only else 0), _p(at, ct.c_double),
                         _p(pr, ct.c_int), _p(pk, ct.c_int), _p(amp, ct.c_double), _p(tau, ct.c_double),
                         _p(td, ct.c_double), _p(wt, ct.c_double))
     return {"ray": pr[:P].copy(), "k": pk[:P].copy(), "amp": amp[:P, 0] + 1j * amp[:P, 1],
@@ -290,9 +296,9 @@ def fresnel(mode, eps_r, sigma, fc, cos_i):
     return complex(out[0], out[1])
 
 
-def forward(scene, rays=None, drop=True):
+def forward(scene, rays=None, drop=True, exit_only=False):
     tr = trace(scene, rays)
-    pth = paths(scene, tr["tri"], tr["flags"], rays, drop)
+    pth = paths(scene, tr["tri"], tr["flags"], rays, drop, exit_only=exit_only)
     return synth(scene, pth), tr, pth
 
 
@@ -301,13 +307,14 @@ def if_loss(S, target):
     return float(np.sum(d.real ** 2 + d.imag ** 2))
 
 
-def fd_directional(scene, tri, flags, target, direction, h=1e-9, rays=None, drop=True, att=None):
+def fd_directional(scene, tri, flags, target, direction, h=1e-9, rays=None, drop=True, att=None,
+                   exit_only=False):
     """Central difference of L = sum |S - target|^2 along `direction` ([nv][3])
     with the hit-triangle sequences frozen (att: see paths())."""
     v0 = scene.verts.astype(np.float64)
     Ls = []
     for sgn in (+1.0, -1.0):
-        p = paths(scene, tri, flags, rays, drop, verts64=v0 + sgn * h * direction, att=att)
+        p = paths(scene, tri, flags, rays, drop, verts64=v0 + sgn * h * direction, att=att, exit_only=exit_only)
         Ls.append(if_loss(synth(scene, p), target))
     return (Ls[0] - Ls[1]) / (2.0 * h)
 
@@ -323,7 +330,7 @@ def fd_scene(scene, tri, flags, target, perturb, h, rays=None, drop=True, att=No
     return (Ls[0] - Ls[1]) / (2.0 * h)
 
 
-def fd_grad(scene, tri, flags, target, coords=None, h=1e-9, rays=None, drop=True, att=None):
+def fd_grad(scene, tri, flags, target, coords=None, h=1e-9, rays=None, drop=True, att=None, exit_only=False):
     """Central differences of the IF loss for every vertex coordinate in
     `coords` (flat indices into [nv*3]; None = all)."""
     nv = scene.nv
@@ -332,7 +339,7 @@ def fd_grad(scene, tri, flags, target, coords=None, h=1e-9, rays=None, drop=True
     for i, c in enumerate(coords):
         e = np.zeros((nv, 3))
         e.reshape(-1)[c] = 1.0
-        g[i] = fd_directional(scene, tri, flags, target, e, h, rays, drop, att)
+        g[i] = fd_directional(scene, tri, flags, target, e, h, rays, drop, att, exit_only)
     return g
 
 

@@ -42,6 +42,7 @@ class Grid:
     tan_hy: float = math.tan(math.radians(15.0))
     max_bounces: int = 3
     t_min: float = 1e-5
+    shadow: bool = False          # occlusion test of every return after the first bounce
 
     @property
     def n_rays(self) -> int:

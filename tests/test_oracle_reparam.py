@@ -102,3 +102,99 @@ def test_attached_derivative_matches_dense_retraced_grid(orc):
         pw = orc.fd_directional(sc, tr["tri"], tr["flags"], tgt, w, h=1e-7, drop=False)
         assert abs(an - ref) <= 0.03 * abs(ref), (an, ref)   # 0.7 % at 640^2, 3-4 % at 320^2
         assert abs(pw - ref) > 0.5 * abs(ref), (pw, ref)
+
+
+# ----------------------------------------------------------------------------- occlusion-tested returns
+def _cube(c, h):
+    v = np.array([[x, y, z] for x in (-h, h) for y in (-h, h) for z in (-h, h)], float) + np.asarray(c, float)
+    f = np.array([[0, 1, 3], [0, 3, 2], [4, 6, 7], [4, 7, 5], [0, 4, 5], [0, 5, 1],
+                  [2, 3, 7], [2, 7, 6], [0, 2, 6], [0, 6, 4], [1, 5, 7], [1, 7, 3]])
+    return v, f
+
+
+def _room_scene(with_box, n=48):
+    rv, rf = S.room(n_a=8, n_b=4)
+    parts = [(rv, rf)]
+    if with_box:
+        parts += [_cube([0.6, -0.5, 2.2], 0.45), _cube([-1.0, 0.2, 1.4], 0.25)]
+    v, f = S._concat(parts)
+    g = S.Grid(n, n, 0.9, 0.7, 4, shadow=True)
+    return S.Scene("room", v.astype(np.float32), f.astype(np.int32), S.default_radar(1, 2),
+                   S.Chirp(n_chirps=2, n_samples=16), g)
+
+
+def _segment_blocked(v, f, x, O, self_id, t_min):
+    """Independent NumPy segment test against every triangle but self_id."""
+    s = O - x
+    D = np.linalg.norm(s)
+    s = s / D
+    a, b, c = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    e1, e2 = b - a, c - a
+    p = np.cross(s, e2)
+    det = np.einsum("ij,ij->i", e1, p)
+    ok = det != 0
+    inv = np.where(ok, 1.0 / np.where(ok, det, 1.0), 0.0)
+    tv = x - a
+    u = np.einsum("ij,ij->i", tv, p) * inv
+    q = np.cross(tv, e1)
+    w = (q @ s) * inv
+    t = np.einsum("ij,ij->i", e2, q) * inv
+    hit = ok & (u >= 0) & (w >= 0) & (u + w <= 1) & (t > t_min) & (t < D - t_min)
+    hit[self_id] = False
+    return bool(hit.any())
+
+
+def test_shadow_convex_room_never_occluded(orc):
+    sc = _room_scene(False)
+    tr = orc.trace(sc)
+    hits = tr["tri"] >= 0
+    assert hits[1:].sum() > 1000                       # plenty of later bounces
+    assert not (tr["flags"] & orc.F_OCCLUDED).any()
+
+
+def test_shadow_bits_vs_independent_brute_force(orc):
+    sc = _room_scene(True)
+    tr = orc.trace(sc)
+    v = sc.verts.astype(np.float64)
+    f = sc.faces
+    occ = (tr["flags"] & orc.F_OCCLUDED) != 0
+    assert not occ[0].any()                            # a first hit's return retraces its ray
+    K, n = tr["tri"].shape
+    checked = disagree = 0
+    for k in range(1, K):
+        for i in np.nonzero(tr["tri"][k] >= 0)[0]:
+            if tr["shadow_edge"][k, i]:
+                continue
+            fid = tr["tri"][k, i]
+            a, b, c = v[f[fid, 0]], v[f[fid, 1]], v[f[fid, 2]]
+            x = a + tr["b1"][k, i] * (b - a) + tr["b2"][k, i] * (c - a)
+            want = _segment_blocked(v, f, x, np.zeros(3), fid, sc.grid.t_min)
+            checked += 1
+            disagree += int(want != occ[k, i])
+    assert checked > 1000 and occ.sum() > 100
+    assert disagree == 0
+    # occlusion is not inherited: a later bounce after an occluded one can return
+    later = occ[1:-1] & (tr["tri"][2:] >= 0) & ~occ[2:]
+    assert later.any()
+    own = tr["flags"] & ~np.uint8(orc.F_OCCLUDED | orc.F_PARENT)       # geometric flags of each bounce
+    inherited = np.logical_or.accumulate(own != 0, axis=0)
+    parent = (tr["flags"] & orc.F_PARENT) != 0
+    hit = tr["tri"] >= 0
+    assert np.array_equal(parent[1:][hit[1:]], inherited[:-1][hit[1:]])
+
+
+def test_exit_only_keeps_last_hit_of_each_ray(orc):
+    sc = _room_scene(True, n=24)
+    tr = orc.trace(sc)
+    full = orc.paths(sc, tr["tri"], tr["flags"], drop=False)
+    ex = orc.paths(sc, tr["tri"], tr["flags"], drop=False, exit_only=True)
+    nb = (tr["tri"] >= 0).sum(axis=0)                 # hits per ray
+    last = nb - 1
+    occ_last = np.array([tr["flags"][last[i], i] & orc.F_OCCLUDED if nb[i] else 0 for i in range(len(nb))])
+    want = np.nonzero((nb > 0) & (occ_last == 0))[0]
+    assert np.array_equal(ex["ray"], want)
+    assert np.array_equal(ex["k"], nb[want])
+    # the same records as in the full model
+    key = {(r, k): j for j, (r, k) in enumerate(zip(full["ray"], full["k"]))}
+    idx = np.array([key[(r, k)] for r, k in zip(ex["ray"], ex["k"])])
+    assert np.array_equal(ex["amp"], full["amp"][idx]) and np.array_equal(ex["tau"], full["tau"][idx])
