@@ -102,9 +102,17 @@ typedef struct {
     int32_t nx, ny;          /* nx * ny <= 2^26                                  */
     double tan_half_x, tan_half_y;
     int32_t max_bounces;     /* K, 1..8                                          */
-    int32_t reserved;
+    int32_t options;         /* SBR_RAYS_* bits (0 = none)                       */
     double t_min;            /* hits closer than this are ignored, metres        */
 } sbr_rays;
+
+/* sbr_rays.options */
+#define SBR_RAYS_SHADOW 1    /* sbr_trace tests the return of every hit after the
+                                first (whose return retraces its own incoming ray)
+                                for occlusion: a hit of another triangle at
+                                t in (t_min, D - t_min) along the segment of length D
+                                from the hit point to the array centre sets
+                                SBR_HIT_OCCLUDED.  Any-hit traversal, early exit. */
 
 /* Closest-hit records, structure of arrays, each [K][nx*ny] (device). */
 typedef struct {
@@ -120,10 +128,16 @@ typedef struct {
 #define SBR_HIT_TIE    2u    /* another candidate hit within delta_k of t          */
 #define SBR_HIT_GRAZE  4u    /* |d . n| < 1e-6                                     */
 #define SBR_HIT_TMIN   8u    /* t < 2 t_min                                        */
-#define SBR_HIT_PARENT 16u   /* an earlier bounce of this ray is flagged           */
+#define SBR_HIT_PARENT 16u   /* an earlier bounce of this ray is flagged (bits 1-8) */
+#define SBR_HIT_OCCLUDED 32u /* return segment blocked (SBR_RAYS_SHADOW); this record
+                                returns no path, later bounces of the ray still do;
+                                not inherited through SBR_HIT_PARENT               */
 
 /* sbr_synth_if / sbr_backward flags */
-#define SBR_DROP_FLAGGED 1   /* paths whose hit flag byte is non-zero are skipped */
+#define SBR_DROP_FLAGGED 1   /* a record with a flag other than SBR_HIT_OCCLUDED
+                                ends the ray's paths (it and later bounces)         */
+#define SBR_EXIT_ONLY 4      /* only the last hit of each ray returns (classic SBR
+                                exit ray); none if that record is skipped           */
 #define SBR_ATTACHED 2       /* sbr_backward only: differentiate the reparameterised
                                 estimator of Sec. 3.2.1 Eqs. 6-7 in which every sample
                                 follows its first hit (fixed barycentrics on the moving
@@ -171,8 +185,9 @@ int sbr_build_bvh(const sbr_mesh *mesh, void *bvh, size_t bvh_bytes, int32_t mod
 int sbr_trace(const sbr_mesh *mesh, const void *bvh, const sbr_radar *radar,
               const sbr_rays *rays, const sbr_hits *out, uint64_t *counters, void *stream);
 
-/* IF signal synthesis (Eq. 8).  For every (ray, bounce) hit -- minus flagged
- * ones with SBR_DROP_FLAGGED -- one path returns to every virtual antenna:
+/* IF signal synthesis (Eq. 8).  For every (ray, bounce) hit -- minus
+ * occluded records, flagged ones with SBR_DROP_FLAGGED and all but the last
+ * with SBR_EXIT_ONLY -- one path returns to every virtual antenna:
  *   I^s = d_omega * prod_j r_j * cos(theta_k) / (L_k R_k)
  *   I^t_v(c) = (|x_1 - tx_t| + sum_{j=2..k} |x_j - x_{j-1}| + |rx_m - x_k|) / c0
  *              + c * t_chirp * 2 (velocity . d_1) / c0

@@ -15,8 +15,11 @@ LIB_PATH = os.path.join(PKG, "libsbr.so")
 SBR_OK, SBR_E_ARG, SBR_E_HIP, SBR_E_SCRATCH, SBR_E_UNSUPPORTED = 0, -1, -2, -3, -4
 SBR_MAX_BOUNCES, SBR_MAX_TX, SBR_MAX_RX, SBR_MAX_VIRTUAL, SBR_MAX_MATERIALS = 8, 8, 16, 64, 64
 SBR_HIT_EDGE, SBR_HIT_TIE, SBR_HIT_GRAZE, SBR_HIT_TMIN, SBR_HIT_PARENT = 1, 2, 4, 8, 16
+SBR_HIT_OCCLUDED = 32
+SBR_RAYS_SHADOW = 1
 SBR_DROP_FLAGGED = 1
 SBR_ATTACHED = 2
+SBR_EXIT_ONLY = 4
 SBR_OP_BUILD_BVH, SBR_OP_SYNTH, SBR_OP_BACKWARD, SBR_OP_RADAR_CUBE, SBR_OP_CFAR = 0, 1, 2, 3, 4
 
 # every function declared in include/sbr.h
@@ -54,7 +57,7 @@ class sbr_chirp(ct.Structure):
 
 class sbr_rays(ct.Structure):
     _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("tan_half_x", ct.c_double),
-                ("tan_half_y", ct.c_double), ("max_bounces", ct.c_int32), ("reserved", ct.c_int32),
+                ("tan_half_y", ct.c_double), ("max_bounces", ct.c_int32), ("options", ct.c_int32),
                 ("t_min", ct.c_double)]
 
 

@@ -34,7 +34,7 @@ size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V);
 int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                     const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
                     const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
-                    bool attached, hipStream_t s);
+                    int32_t flags, hipStream_t s);
 size_t cube_scratch_bytes(int V, int C, int S, int Na);
 size_t cfar_scratch_bytes(int C, int S);
 int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
@@ -66,6 +66,7 @@ static int check_rays(const sbr_rays *g) {
     SBR_CHECK_ARG((long long)g->nx * g->ny <= (1LL << 26), "grid too large (%d x %d)", g->nx, g->ny);
     SBR_CHECK_ARG(g->max_bounces >= 1 && g->max_bounces <= SBR_MAX_BOUNCES, "max_bounces=%d out of [1,%d]",
                   g->max_bounces, SBR_MAX_BOUNCES);
+    SBR_CHECK_ARG((g->options & ~SBR_RAYS_SHADOW) == 0, "unknown sbr_rays.options bits 0x%x", g->options);
     SBR_CHECK_ARG(g->tan_half_x > 0 && g->tan_half_y > 0, "grid half-widths must be positive");
     SBR_CHECK_ARG(g->t_min >= 0, "t_min must be >= 0");
     return SBR_OK;
@@ -144,6 +145,7 @@ GridDev make_grid(const sbr_rays *g) {
     d.nx = g->nx;
     d.ny = g->ny;
     d.K = g->max_bounces;
+    d.options = g->options;
     d.thx = g->tan_half_x;
     d.thy = g->tan_half_y;
     d.t_min = g->t_min;
@@ -252,6 +254,7 @@ int sbr_synth_if(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
     int rc;
     if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
     SBR_CHECK_ARG(if_cube, "if_cube is NULL");
+    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_EXIT_ONLY)) == 0, "unknown flags 0x%x", flags);
     const int R = rays->nx * rays->ny, K = rays->max_bounces;
     const int V = radar->n_tx * radar->n_rx, C = chirp->n_chirps, S = chirp->n_samples;
     hipStream_t s = (hipStream_t)stream;
@@ -317,6 +320,7 @@ int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
     int rc;
     if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
     SBR_CHECK_ARG(grad_if && grad_verts, "grad_if/grad_verts is NULL");
+    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY)) == 0, "unknown flags 0x%x", flags);
     SBR_CHECK_ARG(!params || !params->materials || (mats && n_mats > 0),
                   "material gradients requested without a material table");
     const int R = rays->nx * rays->ny, K = rays->max_bounces;
@@ -336,7 +340,7 @@ int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
     ChirpDev cd = make_chirp(chirp);
     if ((rc = launch_paths(mesh, mt, rd, gd, cd, hits, flags, st, s))) return rc;
     return launch_backward(mesh, mt, rd, gd, cd, hits, st, cv, reinterpret_cast<const float2 *>(grad_if),
-                           grad_verts, radar, params, (flags & SBR_ATTACHED) != 0, s);
+                           grad_verts, radar, params, flags, s);
 }
 
 }  // extern "C"

@@ -175,6 +175,8 @@ struct GeomArgs {
     GridDev g;
     ChirpDev ch;
     const int32_t *ray_first;
+    const uint8_t *flags;
+    int32_t drop, exit_only;
     const float2 *abar;
     const float *tau_bar;   // [V][cap]
     const float *tdbar;     // [cap] dL/d taudot
@@ -227,10 +229,11 @@ template <int K>
 __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    int first = 0, n = 0;
+    int first = 0, n = 0;               // n: bounces to recompute (last returning one + 1)
+    uint32_t mask = 0;                  // bounces that return a path
     if (r < a.R) {
         first = a.ray_first[r];
-        n = a.ray_first[r + 1] - first;
+        mask = ray_path_mask(a.tri, a.flags, (size_t)a.R, (size_t)r, a.g.K, a.drop != 0, a.exit_only != 0, &n);
     }
     if (__ballot(n > 0) == 0) return;   // uniform over the wavefront
     const int ix = r % a.g.nx, iy = r / a.g.nx;
@@ -311,8 +314,8 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     const float ic0 = (float)(1.0 / kC0);
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        if (k < n) {
-            const int p = first + k;
+        if ((mask >> k) & 1u) {
+            const int p = first + __popc(mask & ((1u << k) - 1u));
             const float2 ab = a.abar[p];
             float2 prod = make_float2(1.0f, 0.0f);
 #pragma unroll
@@ -568,7 +571,8 @@ size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V) {
 int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                     const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
                     const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
-                    bool attached, hipStream_t s) {
+                    int32_t flags, hipStream_t s) {
+    const bool attached = (flags & SBR_ATTACHED) != 0;
     const int V = rd.n_tx * rd.n_rx;
     const long long cap = st.rec.cap;
     BackPlan bp = back_plan(cap, V);
@@ -617,6 +621,9 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     g.g = gd;
     g.ch = cd;
     g.ray_first = st.ray_first;
+    g.flags = h->flags;
+    g.drop = (flags & SBR_DROP_FLAGGED) ? 1 : 0;
+    g.exit_only = (flags & SBR_EXIT_ONLY) ? 1 : 0;
     g.abar = abar;
     g.tau_bar = tau_bar;
     g.tdbar = tdbar;

@@ -114,7 +114,7 @@ struct RadarDev {
 };
 
 struct GridDev {
-    int32_t nx, ny, K;
+    int32_t nx, ny, K, options;
     double thx, thy, t_min;
 };
 

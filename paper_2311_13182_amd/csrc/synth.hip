@@ -14,6 +14,7 @@ struct PathArgs {
     const int32_t *tri;
     const uint8_t *flags;
     int32_t drop;
+    int32_t exit_only;
     int32_t R;
     MatTable mt;
     RadarDev rd;
@@ -22,15 +23,8 @@ struct PathArgs {
     PathStage st;
 };
 
-__device__ __forceinline__ int ray_npaths(const PathArgs &a, size_t r) {
-    int n = 0;
-    for (int k = 0; k < a.g.K; k++) {
-        size_t slot = (size_t)k * a.R + r;
-        if (a.tri[slot] < 0) break;
-        if (a.drop && a.flags[slot]) break;
-        n++;
-    }
-    return n;
+__device__ __forceinline__ uint32_t ray_mask(const PathArgs &a, size_t r, int *nb) {
+    return ray_path_mask(a.tri, a.flags, (size_t)a.R, r, a.g.K, a.drop != 0, a.exit_only != 0, nb);
 }
 
 __device__ __forceinline__ int block_sum(int x, int *sh) {
@@ -62,7 +56,8 @@ __device__ __forceinline__ int block_incl_scan(int x, int *sh) {
 __global__ __launch_bounds__(kPathBlock) void k_path_count(PathArgs a) {
     __shared__ int sh[kPathBlock / 64];
     size_t r = (size_t)blockIdx.x * kPathBlock + threadIdx.x;
-    int n = r < (size_t)a.R ? ray_npaths(a, r) : 0;
+    int nb;
+    int n = r < (size_t)a.R ? __popc(ray_mask(a, r, &nb)) : 0;
     int t = block_sum(n, sh);
     if (threadIdx.x == 0) a.st.blk[blockIdx.x] = t;
 }
@@ -100,7 +95,9 @@ __global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
     __shared__ int sh[kPathBlock / 64];
     const size_t r = (size_t)blockIdx.x * kPathBlock + threadIdx.x;
     const bool act = r < (size_t)a.R;
-    int n = act ? ray_npaths(a, r) : 0;
+    int nb = 0;
+    const uint32_t mask = act ? ray_mask(a, r, &nb) : 0u;
+    const int n = __popc(mask);
     int incl = block_incl_scan(n, sh);
     if (!act) return;
     int p = a.st.blk[blockIdx.x] + incl - n;
@@ -118,7 +115,7 @@ __global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
     cd pr = {1.0, 0.0};
     const int cap = a.st.rec.cap;
     const int ntx = a.rd.n_tx, nrx = a.rd.n_rx;
-    for (int k = 0; k < n; k++, p++) {
+    for (int k = 0; k < nb; k++) {
         const int f = a.tri[(size_t)k * a.R + r];
         double va[3], vb[3], vc[3];
         for (int i = 0; i < 3; i++) {
@@ -148,6 +145,14 @@ __global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
         } else {
             Lmid += seg;
         }
+        if (!((mask >> k) & 1u)) {            // this bounce returns no path
+            for (int i = 0; i < 3; i++) {
+                o[i] = x[i];
+                xp[i] = x[i];
+                d[i] = d[i] - 2.0 * dn * N[i] / nl;
+            }
+            continue;
+        }
         double Rk = sqrt((x[0] - a.rd.o[0]) * (x[0] - a.rd.o[0]) + (x[1] - a.rd.o[1]) * (x[1] - a.rd.o[1]) +
                          (x[2] - a.rd.o[2]) * (x[2] - a.rd.o[2]));
         double sc = dw * ci / (L * Rk);
@@ -170,6 +175,7 @@ __global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
                 a.st.rec.alpha[(size_t)v * cap + p] = (float)frac_d(a.ch.fc * tau);
                 a.st.rec.gamma[(size_t)v * cap + p] = (float)(a.ch.slope * tau / a.ch.fs);
             }
+        p++;
         for (int i = 0; i < 3; i++) {
             o[i] = x[i];
             xp[i] = x[i];
@@ -207,6 +213,7 @@ int launch_paths(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, cons
     a.tri = h->tri;
     a.flags = h->flags;
     a.drop = (flags & SBR_DROP_FLAGGED) ? 1 : 0;
+    a.exit_only = (flags & SBR_EXIT_ONLY) ? 1 : 0;
     a.R = gd.nx * gd.ny;
     a.mt = mt;
     a.rd = rd;

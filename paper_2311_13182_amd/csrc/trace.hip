@@ -58,7 +58,68 @@ __device__ __forceinline__ bool wt_hit(const Shear &sh, float3 o, float3 a, floa
     return true;
 }
 
-template <bool COUNT>
+__device__ __forceinline__ Shear make_shear(float3 d) {
+    Shear sh;
+    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    sh.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    sh.kx = sh.kz == 2 ? 0 : sh.kz + 1;
+    sh.ky = sh.kx == 2 ? 0 : sh.kx + 1;
+    float dz = sel3(d, sh.kz);
+    if (dz < 0.0f) {
+        int tmp = sh.kx;
+        sh.kx = sh.ky;
+        sh.ky = tmp;
+    }
+    sh.sx = sel3(d, sh.kx) / dz;
+    sh.sy = sel3(d, sh.ky) / dz;
+    sh.sz = 1.0f / dz;
+    return sh;
+}
+
+// Any hit of a triangle other than `self` at t in (tmin, tmax) along the unit
+// direction s from x: the occlusion test of a return segment.  Same stackless
+// walk as the closest-hit query, leaving at the first accepted hit.
+__device__ bool any_hit(const TraceArgs &a, float3 x, float3 s, float tmin, float tmax, int self) {
+    const Shear sh = make_shear(s);
+    float3 id;
+    id.x = 1.0f / (fabsf(s.x) > 1e-30f ? s.x : copysignf(1e-30f, s.x));
+    id.y = 1.0f / (fabsf(s.y) > 1e-30f ? s.y : copysignf(1e-30f, s.y));
+    id.z = 1.0f / (fabsf(s.z) > 1e-30f ? s.z : copysignf(1e-30f, s.z));
+    const float3 oid = make_float3(x.x * id.x, x.y * id.y, x.z * id.z);
+    int i = 0;
+    while (i < a.n_nodes) {
+        const BvhNode nd = a.nodes[i];
+        float tx0 = fmaf(nd.lo[0], id.x, -oid.x), tx1 = fmaf(nd.hi[0], id.x, -oid.x);
+        float ty0 = fmaf(nd.lo[1], id.y, -oid.y), ty1 = fmaf(nd.hi[1], id.y, -oid.y);
+        float tz0 = fmaf(nd.lo[2], id.z, -oid.z), tz1 = fmaf(nd.hi[2], id.z, -oid.z);
+        float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+        float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+        tf *= 1.0000005f;
+        const bool hit = tn <= tf && tn <= tmax;
+        const int esc = nd.escape > i ? nd.escape : i + 1;
+        if (!hit) {
+            i = esc;
+            continue;
+        }
+        if (nd.leaf < 0) {
+            i++;
+            continue;
+        }
+        if (nd.leaf < a.n_tris) {
+            const LeafTri lt = a.tris[nd.leaf];
+            float th, c0, c1, c2;
+            if (__float_as_int(lt.a.w) != self &&
+                wt_hit(sh, x, make_float3(lt.a.x, lt.a.y, lt.a.z), make_float3(lt.b.x, lt.b.y, lt.b.z),
+                       make_float3(lt.c.x, lt.c.y, lt.c.z), th, c0, c1, c2) &&
+                th > tmin && th < tmax)
+                return true;
+        }
+        i = esc;
+    }
+    return false;
+}
+
+template <bool COUNT, bool SHADOW>
 __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int tile = gid >> 6, l = gid & 63;
@@ -80,6 +141,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         d.y = (float)(a.rot[3] * dr[0] + a.rot[4] * dr[1] + a.rot[5] * dr[2]);
         d.z = (float)(a.rot[6] * dr[0] + a.rot[7] * dr[1] + a.rot[8] * dr[2]);
         o = make_float3((float)a.o[0], (float)a.o[1], (float)a.o[2]);
+        const float3 o0 = o;   // array centre: where every return ends
         const float tmin = (float)a.g.t_min;
         int prev = -1;
         float Lprev = 0.0f;
@@ -97,20 +159,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
             }
             n_q++;
             // per-ray shear constants of the watertight test
-            Shear sh;
-            float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
-            sh.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-            sh.kx = sh.kz == 2 ? 0 : sh.kz + 1;
-            sh.ky = sh.kx == 2 ? 0 : sh.kx + 1;
-            float dz = sel3(d, sh.kz);
-            if (dz < 0.0f) {
-                int tmp = sh.kx;
-                sh.kx = sh.ky;
-                sh.ky = tmp;
-            }
-            sh.sx = sel3(d, sh.kx) / dz;
-            sh.sy = sel3(d, sh.ky) / dz;
-            sh.sz = 1.0f / dz;
+            const Shear sh = make_shear(d);
             // slab-test reciprocals (zero components replaced by tiny values)
             float3 id;
             id.x = 1.0f / (fabsf(d.x) > 1e-30f ? d.x : copysignf(1e-30f, d.x));
@@ -203,16 +252,22 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
             if (t2 - t1 < delta) fl |= SBR_HIT_TIE;
             if (fabsf(dn) < 1e-6f) fl |= SBR_HIT_GRAZE;
             if (t1 < 2.0f * tmin) fl |= SBR_HIT_TMIN;
+            anc |= fl;
+            // the hit point (barycentric, lies on the face): the return's start
+            // and the next bounce's origin
+            o = make_float3(bb0 * v0.x + bb1 * v1.x + bb2 * v2.x, bb0 * v0.y + bb1 * v1.y + bb2 * v2.y,
+                            bb0 * v0.z + bb1 * v1.z + bb2 * v2.z);
+            if (SHADOW && k > 0) {
+                const float3 q = make_float3(o0.x - o.x, o0.y - o.y, o0.z - o.z);
+                const float D = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z);
+                const float3 sd = make_float3(q.x / D, q.y / D, q.z / D);
+                if (any_hit(a, o, sd, tmin, D - tmin, best)) fl |= SBR_HIT_OCCLUDED;
+            }
             a.tri[slot] = best;
             a.t[slot] = t1;
             a.u[slot] = bb1;
             a.v[slot] = bb2;
             a.flags[slot] = fl;
-            anc |= fl;
-            // continue from the hit point (barycentric, lies on the face) with
-            // the specular direction
-            o = make_float3(bb0 * v0.x + bb1 * v1.x + bb2 * v2.x, bb0 * v0.y + bb1 * v1.y + bb2 * v2.y,
-                            bb0 * v0.z + bb1 * v1.z + bb2 * v2.z);
             d = make_float3(d.x - 2.0f * dn * nh.x, d.y - 2.0f * dn * nh.y, d.z - 2.0f * dn * nh.z);
             float dl = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
             d = make_float3(d.x * dl, d.y * dl, d.z * dl);
@@ -261,10 +316,15 @@ int trace_launch(const sbr_mesh *m, const void *bvh, const RadarDev &rd, const G
     int blocks = (int)((threads + 255) / 256);
     {
         ProfScope ps(kProfTrace, st);
-        if (counters)
-            hipLaunchKernelGGL(k_trace<true>, dim3(blocks), dim3(256), 0, st, a);
+        const bool shadow = (gd.options & SBR_RAYS_SHADOW) != 0;
+        if (counters && shadow)
+            hipLaunchKernelGGL((k_trace<true, true>), dim3(blocks), dim3(256), 0, st, a);
+        else if (counters)
+            hipLaunchKernelGGL((k_trace<true, false>), dim3(blocks), dim3(256), 0, st, a);
+        else if (shadow)
+            hipLaunchKernelGGL((k_trace<false, true>), dim3(blocks), dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL(k_trace<false>, dim3(blocks), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_trace<false, false>), dim3(blocks), dim3(256), 0, st, a);
     }
     SBR_LAUNCHED();
     return SBR_OK;

@@ -59,7 +59,8 @@ def chirp_struct(c: S.Chirp) -> L.sbr_chirp:
 
 
 def rays_struct(g: S.Grid) -> L.sbr_rays:
-    return L.sbr_rays(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces, 0, g.t_min)
+    return L.sbr_rays(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces,
+                      L.SBR_RAYS_SHADOW if getattr(g, "shadow", False) else 0, g.t_min)
 
 
 def materials_struct(mats: Sequence[Tuple[int, float, float]]):
@@ -234,11 +235,11 @@ class Simulator:
     buffer shared by all stages (stages on one stream run in order)."""
 
     def __init__(self, scene: S.Scene, device="cuda", drop_flagged: bool = True, n_angle: int = 64,
-                 mesh: Optional[DeviceMesh] = None, bvh: Optional[torch.Tensor] = None):
+                 mesh: Optional[DeviceMesh] = None, bvh: Optional[torch.Tensor] = None, exit_only: bool = False):
         self.scene = scene
         self.device = torch.device(device)
         self.mesh = mesh if mesh is not None else DeviceMesh.from_scene(scene, self.device)
-        self.flags = L.SBR_DROP_FLAGGED if drop_flagged else 0
+        self.flags = (L.SBR_DROP_FLAGGED if drop_flagged else 0) | (L.SBR_EXIT_ONLY if exit_only else 0)
         g, rd, ch = scene.grid, scene.radar, scene.chirp
         self.K, self.R = g.max_bounces, g.nx * g.ny
         self.V, self.C, self.S = rd.n_virtual, ch.n_chirps, ch.n_samples

@@ -314,6 +314,14 @@ def room(half_w=2.0, floor_y=-1.0, ceil_y=2.0, back_z=4.0, n_a=16, n_b=8):
     return _concat(parts)
 
 
+def cube(center, half: float):
+    """Axis-aligned cube, 12 triangles."""
+    v = np.array([[x, y, z] for x in (-half, half) for y in (-half, half) for z in (-half, half)], float)
+    f = np.array([[0, 1, 3], [0, 3, 2], [4, 6, 7], [4, 7, 5], [0, 4, 5], [0, 5, 1],
+                  [2, 3, 7], [2, 7, 6], [0, 2, 6], [0, 6, 4], [1, 5, 7], [1, 7, 3]])
+    return v + np.asarray(center, float), f
+
+
 def _concat(parts):
     vs, fs, off = [], [], 0
     for v, f in parts:
@@ -498,6 +506,21 @@ def jitter(scene: Scene, sigma: float, seed: int) -> Scene:
     v = scene.verts.astype(np.float64)
     v = v + np.random.default_rng(seed).normal(0.0, sigma, v.shape)
     return scene.with_verts(v)
+
+
+def room_scene(n_rays: int = 48, boxes: bool = True, shadow: bool = True, n_chirps: int = 2,
+               n_samples: int = 16) -> Scene:
+    """Radar at the open front of a room (floor, side and back walls of 8 x 4
+    quads each) with two boxes inside that hide parts of the walls from it;
+    4 bounces over a wide (+-42 x +-35 deg) grid, 1 TX x 2 RX.  A scene rich in
+    returns whose way back to the radar is blocked."""
+    parts = [room(n_a=8, n_b=4)]
+    if boxes:
+        parts += [cube([0.6, -0.5, 2.2], 0.45), cube([-1.0, 0.2, 1.4], 0.25)]
+    v, f = _concat(parts)
+    return Scene("room_boxes" if boxes else "room", v.astype(np.float32), f.astype(np.int32),
+                 default_radar(1, 2), Chirp(n_chirps=n_chirps, n_samples=n_samples),
+                 Grid(n_rays, n_rays, 0.9, 0.7, 4, shadow=shadow))
 
 
 def single_triangle(z: float = 1.0, size: float = 0.1) -> Scene:

@@ -7,6 +7,7 @@ import time
 import numpy as np
 
 FLAG_MASK = 0xFF
+GEOM_FLAGS = 0x1F      # edge, tie, graze, t_min, parent (not the occlusion bit)
 
 
 def log(msg: str):
@@ -42,13 +43,13 @@ def scatter_sampled_hits(tr_sub, rays, K, R):
 
 
 def compare_trace(gpu, orc, rays=None, L_prev=None):
-    """IDs bit-exact except flagged rays (either side); t within
+    """IDs bit-exact except rays with a geometric flag (either side); t within
     1e-5 (L_{k-1} + t).  Returns (n_checked, n_flagged)."""
     tri_g = gpu["tri"] if rays is None else gpu["tri"][:, rays]
     t_g = gpu["t"] if rays is None else gpu["t"][:, rays]
     fl_g = gpu["flags"] if rays is None else gpu["flags"][:, rays]
     K, n = orc["tri"].shape
-    flagged = (fl_g != 0) | (orc["flags"] != 0)
+    flagged = ((fl_g & GEOM_FLAGS) != 0) | ((orc["flags"] & GEOM_FLAGS) != 0)
     # once a bounce is flagged on either side, later bounces are not comparable
     anc = np.logical_or.accumulate(flagged, axis=0)
     ok = ~anc

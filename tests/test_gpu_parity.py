@@ -579,3 +579,71 @@ def test_backward_attached_moves_silhouettes(torch_cuda, orc):
         log(f"silhouette: attached {an:.5e} fixed {pw:.3e} dense re-traced FD {ref:.5e}")
         assert abs(an - ref) <= 0.03 * abs(ref)
         assert abs(pw) < 0.01 * abs(ref)
+
+
+# ----------------------------------------------------------------- occlusion-tested and exit-only returns
+def test_trace_shadow_bits_vs_oracle(torch_cuda, orc):
+    """SBR_RAYS_SHADOW: the occlusion bit of every comparable record (same hit
+    ids, no geometric flag, not borderline for the oracle) is bit-exact."""
+    sc = S.room_scene(n_rays=64)
+    sim = _sim(sc)
+    sim.build()
+    sim.trace(count=True)
+    torch_cuda.cuda.synchronize()
+    g = _gpu_hits_np(sim)
+    o = orc.trace(sc)
+    n_ok, n_fl = compare_trace(g, o)
+    geom = np.logical_or.accumulate(((g["flags"] & 0x1F) != 0) | ((o["flags"] & 0x1F) != 0), axis=0)
+    comp = (o["tri"] >= 0) & (g["tri"] == o["tri"]) & ~geom & (o["shadow_edge"] == 0)
+    occ_g = (g["flags"] & 32) != 0
+    occ_o = (o["flags"] & orc.F_OCCLUDED) != 0
+    bad = comp & (occ_g != occ_o)
+    log(f"shadow: {n_ok} hits checked, {comp.sum()} occlusion bits compared, {occ_o[comp].sum()} occluded, "
+        f"{(o['shadow_edge'] != 0).sum()} borderline skipped, {bad.sum()} differ")
+    assert comp[1:].sum() > 3000 and occ_o[comp].sum() > 500
+    assert not bad.any()
+    assert not occ_g[0].any()
+    q = int(sim.counters[0].item())
+    assert abs(q - o["queries"]) <= n_fl
+
+
+@pytest.mark.parametrize("mode", ["shadow", "shadow_exit_only", "exit_only_drop"])
+def test_synth_shadow_and_exit_only(torch_cuda, orc, mode):
+    sc = S.room_scene(n_rays=40, n_samples=64, shadow=mode != "exit_only_drop")
+    exit_only = mode != "shadow"
+    drop = mode == "exit_only_drop"
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"], drop=drop, exit_only=exit_only)
+    want = orc.synth(sc, p)
+    from paper_2311_13182_amd.sbr import Simulator
+    sim = Simulator(sc, "cuda", drop_flagged=drop, exit_only=exit_only)
+    sim.hits = device_hits_from_oracle(o)
+    got = _cube_np(sim.synth())
+    torch_cuda.cuda.synchronize()
+    e = rel_l2(got, want)
+    log(f"synth {mode}: {len(p['amp'])} paths (gpu {sim.n_paths()}), rel L2 {e:.3e}")
+    assert sim.n_paths() == len(p["amp"])
+    assert e <= 1e-4
+
+
+@pytest.mark.parametrize("mode", ["shadow", "exit_only"])
+def test_backward_shadow_and_exit_only(torch_cuda, orc, mode):
+    import torch
+    sc = S.room_scene(n_rays=32, n_samples=32, shadow=mode == "shadow")
+    exit_only = mode == "exit_only"
+    o = orc.trace(sc)
+    tgt, _, _ = orc.forward(S.jitter(sc, 1e-3, 15), exit_only=exit_only)
+    p = orc.paths(sc, o["tri"], o["flags"], exit_only=exit_only)
+    G = 2.0 * (orc.synth(sc, p) - tgt)
+    from paper_2311_13182_amd.sbr import Simulator
+    sim = Simulator(sc, "cuda", exit_only=exit_only)
+    sim.hits = device_hits_from_oracle(o)
+    got = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda")).cpu().numpy().astype(np.float64)
+    hit_v = np.unique(sc.faces[np.unique(o["tri"][1:][o["tri"][1:] >= 0])].reshape(-1))
+    rng = np.random.default_rng(6)
+    coords = (rng.choice(hit_v, 16, replace=False)[:, None] * 3 + np.arange(3)[None, :]).reshape(-1)
+    fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, coords=coords, h=1e-9, exit_only=exit_only)
+    e = rel_l2(got.reshape(-1)[coords], fd)
+    log(f"backward {mode}: rel L2 {e:.3e} over {len(coords)} coordinates")
+    assert e <= GRAD_TOL
+

@@ -105,22 +105,8 @@ def test_attached_derivative_matches_dense_retraced_grid(orc):
 
 
 # ----------------------------------------------------------------------------- occlusion-tested returns
-def _cube(c, h):
-    v = np.array([[x, y, z] for x in (-h, h) for y in (-h, h) for z in (-h, h)], float) + np.asarray(c, float)
-    f = np.array([[0, 1, 3], [0, 3, 2], [4, 6, 7], [4, 7, 5], [0, 4, 5], [0, 5, 1],
-                  [2, 3, 7], [2, 7, 6], [0, 2, 6], [0, 6, 4], [1, 5, 7], [1, 7, 3]])
-    return v, f
-
-
 def _room_scene(with_box, n=48):
-    rv, rf = S.room(n_a=8, n_b=4)
-    parts = [(rv, rf)]
-    if with_box:
-        parts += [_cube([0.6, -0.5, 2.2], 0.45), _cube([-1.0, 0.2, 1.4], 0.25)]
-    v, f = S._concat(parts)
-    g = S.Grid(n, n, 0.9, 0.7, 4, shadow=True)
-    return S.Scene("room", v.astype(np.float32), f.astype(np.int32), S.default_radar(1, 2),
-                   S.Chirp(n_chirps=2, n_samples=16), g)
+    return S.room_scene(n_rays=n, boxes=with_box)
 
 
 def _segment_blocked(v, f, x, O, self_id, t_min):
