@@ -51,9 +51,9 @@ typedef enum {
 } sbr_status;
 
 #define SBR_MAX_BOUNCES 8
-#define SBR_MAX_TX 8
-#define SBR_MAX_RX 16
-#define SBR_MAX_VIRTUAL 64
+#define SBR_MAX_TX 20
+#define SBR_MAX_RX 20
+#define SBR_MAX_VIRTUAL 400
 #define SBR_MAX_MATERIALS 64
 
 /* Triangle mesh (Sec. 3.1: surface mesh representation).  Device arrays. */
@@ -80,7 +80,7 @@ typedef struct {
 typedef struct {
     double origin[3];        /* array centre, world frame                        */
     double rot[9];           /* radar -> world rotation, row-major               */
-    int32_t n_tx, n_rx;      /* n_tx <= 8, n_rx <= 16, n_tx * n_rx <= 64         */
+    int32_t n_tx, n_rx;      /* n_tx <= 20, n_rx <= 20 (n_tx * n_rx <= 400)      */
     double tx[SBR_MAX_TX][3];/* radar frame                                      */
     double rx[SBR_MAX_RX][3];/* radar frame                                      */
     double velocity[3];      /* rigid scene velocity, world frame, m/s (Doppler) */

@@ -309,7 +309,7 @@ int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const o
               double *taudot, double *weight) {
     const int K = g->max_bounces;
     const int V = rd->n_tx * rd->n_rx;
-    double txw[8][3], rxw[16][3];
+    double txw[ORC_MAXTX][3], rxw[ORC_MAXRX][3];
     for (int t = 0; t < rd->n_tx; t++) to_world(rd, rd->tx[t], txw[t]);
     for (int q = 0; q < rd->n_rx; q++) to_world(rd, rd->rx[q], rxw[q]);
     int P = 0;
@@ -476,6 +476,12 @@ static void twiddle(long long k, int N, int sign, double *re, double *im) {
 }
 
 void orc_radar_cube(const double *in, int V, int C, int S, int Na, int window, int dir, double *out) {
+    orc_radar_cube2(in, V, 1, C, S, Na, 1, window, dir, out);
+}
+
+void orc_radar_cube2(const double *in, int Vx, int Vy, int C, int S, int Nax, int Nay, int window, int dir,
+                     double *out) {
+    const int V = Vx * Vy, Na = Nax * Nay;
     size_t plane = (size_t)C * S;
     if (dir == 0) {
         double *y1 = (double *)calloc((size_t)V * plane * 2, sizeof(double));
@@ -509,16 +515,21 @@ void orc_radar_cube(const double *in, int V, int C, int S, int Na, int window, i
                     size_t ox = ((size_t)v * plane + (size_t)dd * S + r) * 2;
                     y2[ox] = re; y2[ox + 1] = im;
                 }
-        /* angle: over v, zero-padded to Na */
+        /* angle: over the array grid (vy, vx), zero-padded to (Nay, Nax);
+         * v = vy Vx + vx in, a = ay Nax + ax out */
 #pragma omp parallel for collapse(2)
         for (int a = 0; a < Na; a++)
             for (size_t e = 0; e < plane; e++) {
+                int ax = a % Nax, ay = a / Nax;
                 double re = 0.0, im = 0.0;
                 for (int v = 0; v < V; v++) {
-                    double tr, ti;
-                    twiddle((long long)a * v, Na, -1, &tr, &ti);
+                    int vx = v % Vx, vy = v / Vx;
+                    double tr, ti, ur, ui;
+                    twiddle((long long)ax * vx, Nax, -1, &tr, &ti);
+                    twiddle((long long)ay * vy, Nay, -1, &ur, &ui);
+                    double wr = tr * ur - ti * ui, wi = tr * ui + ti * ur;
                     size_t ix = ((size_t)v * plane + e) * 2;
-                    re += y2[ix] * tr - y2[ix + 1] * ti; im += y2[ix] * ti + y2[ix + 1] * tr;
+                    re += y2[ix] * wr - y2[ix + 1] * wi; im += y2[ix] * wi + y2[ix + 1] * wr;
                 }
                 out[((size_t)a * plane + e) * 2] = re; out[((size_t)a * plane + e) * 2 + 1] = im;
             }
@@ -530,12 +541,16 @@ void orc_radar_cube(const double *in, int V, int C, int S, int Na, int window, i
 #pragma omp parallel for collapse(2)
         for (int v = 0; v < V; v++)
             for (size_t e = 0; e < plane; e++) {
+                int vx = v % Vx, vy = v / Vx;
                 double re = 0.0, im = 0.0;
                 for (int a = 0; a < Na; a++) {
-                    double tr, ti;
-                    twiddle((long long)a * v, Na, +1, &tr, &ti);
+                    int ax = a % Nax, ay = a / Nax;
+                    double tr, ti, ur, ui;
+                    twiddle((long long)ax * vx, Nax, +1, &tr, &ti);
+                    twiddle((long long)ay * vy, Nay, +1, &ur, &ui);
+                    double wr = tr * ur - ti * ui, wi = tr * ui + ti * ur;
                     size_t ix = ((size_t)a * plane + e) * 2;
-                    re += in[ix] * tr - in[ix + 1] * ti; im += in[ix] * ti + in[ix + 1] * tr;
+                    re += in[ix] * wr - in[ix + 1] * wi; im += in[ix] * wi + in[ix + 1] * wr;
                 }
                 z2[((size_t)v * plane + e) * 2] = re; z2[((size_t)v * plane + e) * 2 + 1] = im;
             }

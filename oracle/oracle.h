@@ -31,7 +31,8 @@
  *   orc_synth          single-path geometric sequence and Dirichlet kernel,
  *                      range / Doppler / angle peak bins
  *   orc_synth_adjoint  central differences of orc_synth
- *   orc_radar_cube     numpy.fft, dot-product (adjoint) identity
+ *   orc_radar_cube     numpy.fft, dot-product (adjoint) identity (1D and 2D
+ *                      arrays)
  *   orc_cfar           injected targets, brute force on tiny maps
  */
 #ifndef SBR_ORACLE_H
@@ -42,6 +43,8 @@ extern "C" {
 #endif
 
 #define ORC_MAXK 8
+#define ORC_MAXTX 20
+#define ORC_MAXRX 20
 
 typedef struct {
     int nv, nf;
@@ -58,8 +61,8 @@ typedef struct {
     double origin[3];   /* array centre, world frame                          */
     double rot[9];      /* radar -> world rotation, row-major                  */
     int n_tx, n_rx;
-    double tx[8][3];    /* radar frame                                         */
-    double rx[16][3];   /* radar frame                                         */
+    double tx[ORC_MAXTX][3];  /* radar frame                                   */
+    double rx[ORC_MAXRX][3];  /* radar frame                                   */
     double vel[3];      /* rigid scene velocity, world frame, m/s              */
 } orc_radar;
 
@@ -159,6 +162,13 @@ void orc_synth_adjoint(int P, const double *amp, const double *tau,
  * window 0 rectangular, 1 symmetric Hann on the range and Doppler axes. */
 void orc_radar_cube(const double *in, int V, int C, int S, int Na, int window,
                     int dir, double *out);
+
+/* The same for a planar array whose virtual antennas form a Vy x Vx grid
+ * (v = vy * Vx + vx): the angle stage is the 2D DFT over (vy, vx), zero-padded
+ * to (Nay, Nax), output angle index a = ay * Nax + ax.  Vy = Nay = 1 is
+ * orc_radar_cube. */
+void orc_radar_cube2(const double *in, int Vx, int Vy, int C, int S, int Nax, int Nay,
+                     int window, int dir, double *out);
 
 /* Cell-averaging CFAR on P[d][r] = sum_a |X[a][d][r]|^2 (X is [Na][C][S][2]).
  * Doppler axis circular, range axis truncated; alpha = N_t (pfa^(-1/N_t) - 1).

@@ -46,7 +46,7 @@ class _Mesh(ct.Structure):
 
 class _Radar(ct.Structure):
     _fields_ = [("origin", ct.c_double * 3), ("rot", ct.c_double * 9), ("n_tx", ct.c_int),
-                ("n_rx", ct.c_int), ("tx", (ct.c_double * 3) * 8), ("rx", (ct.c_double * 3) * 16),
+                ("n_rx", ct.c_int), ("tx", (ct.c_double * 3) * 20), ("rx", (ct.c_double * 3) * 20),
                 ("vel", ct.c_double * 3)]
 
 
@@ -86,6 +86,8 @@ def lib():
                                         dp, dp, dp]
         L.orc_radar_cube.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
                                      ct.c_int, dp]
+        L.orc_radar_cube2.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                                      ct.c_int, ct.c_int, dp]
         L.orc_cfar.restype = ct.c_int
         L.orc_cfar.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_double,
                                bp, ip, dp]
@@ -271,6 +273,18 @@ def radar_cube(x, n_angle=64, window=0, direction=0, V=None):
     inp = np.ascontiguousarray(np.stack([x.real, x.imag], -1))
     lib().orc_radar_cube(_p(inp, ct.c_double), V_, C, S, n_angle, window, direction,
                          _p(out, ct.c_double))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def radar_cube2(x, vx, vy, n_ax=64, n_ay=64, window=0, direction=0):
+    """Planar array.  direction 0: [Vy*Vx][C][S] -> [Nay*Nax][C][S];  1: back."""
+    x = np.asarray(x, np.complex128)
+    _, C, S = x.shape
+    n_out = n_ax * n_ay if direction == 0 else vx * vy
+    out = np.empty((n_out, C, S, 2))
+    inp = np.ascontiguousarray(np.stack([x.real, x.imag], -1))
+    lib().orc_radar_cube2(_p(inp, ct.c_double), vx, vy, C, S, n_ax, n_ay, window, direction,
+                          _p(out, ct.c_double))
     return out[..., 0] + 1j * out[..., 1]
 
 

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsbr.so")
 
 SBR_OK, SBR_E_ARG, SBR_E_HIP, SBR_E_SCRATCH, SBR_E_UNSUPPORTED = 0, -1, -2, -3, -4
-SBR_MAX_BOUNCES, SBR_MAX_TX, SBR_MAX_RX, SBR_MAX_VIRTUAL, SBR_MAX_MATERIALS = 8, 8, 16, 64, 64
+SBR_MAX_BOUNCES, SBR_MAX_TX, SBR_MAX_RX, SBR_MAX_VIRTUAL, SBR_MAX_MATERIALS = 8, 20, 20, 400, 64
 SBR_HIT_EDGE, SBR_HIT_TIE, SBR_HIT_GRAZE, SBR_HIT_TMIN, SBR_HIT_PARENT = 1, 2, 4, 8, 16
 SBR_HIT_OCCLUDED = 32
 SBR_RAYS_SHADOW = 1

@@ -13,7 +13,7 @@ LIB = os.path.join(PKG, "libsbr.so")
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
-    # packed FP32 instructions stay off (hardware notes)
+    # no packed FP32 code generation: plain scalar FP32 VALU only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]

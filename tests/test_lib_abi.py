@@ -84,7 +84,7 @@ def test_argument_errors_are_reported(lib):
     assert lib.sbr_radar_cube(fake, 12, 8, 16, 64, 0, 5, fake, fake, 1 << 30, None) == L.SBR_E_ARG
     # too many antennas
     rr = sbr.radar_struct(sc.radar)
-    rr.n_tx, rr.n_rx = 8, 16
+    rr.n_tx, rr.n_rx = L.SBR_MAX_TX + 1, 4
     assert lib.sbr_synth_if(ct.byref(m), None, 0, ct.byref(rr), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
                             fake, 1 << 40, None) == L.SBR_E_ARG
     # material modes outside {0,1,2}

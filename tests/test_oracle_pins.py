@@ -369,6 +369,26 @@ def test_radar_cube_matches_numpy_fft(orc, window):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+@pytest.mark.parametrize("window", [0, 1])
+def test_radar_cube_2d_matches_numpy_fft(orc, window):
+    """Planar array: the angle stage is the 2D DFT over the (vy, vx) grid."""
+    rng = np.random.default_rng(2)
+    Vx, Vy, C, S_, Nax, Nay = 5, 4, 6, 10, 8, 7
+    x = rng.normal(size=(Vy * Vx, C, S_)) + 1j * rng.normal(size=(Vy * Vx, C, S_))
+    w = (lambda n: np.hanning(n)) if window else (lambda n: np.ones(n))
+    y = (x * w(S_)[None, None, :] * w(C)[None, :, None]).reshape(Vy, Vx, C, S_)
+    ref = np.fft.fftn(y, s=(Nay, Nax, C, S_), axes=(0, 1, 2, 3)).reshape(Nay * Nax, C, S_)
+    X = orc.radar_cube2(x, Vx, Vy, Nax, Nay, window=window)
+    assert np.abs(X - ref).max() <= 1e-12 * np.abs(ref).max()
+    yy = rng.normal(size=X.shape) + 1j * rng.normal(size=X.shape)
+    Fh = orc.radar_cube2(yy, Vx, Vy, Nax, Nay, window=window, direction=1)
+    assert abs(np.vdot(yy, X) - np.vdot(Fh, x)) <= 1e-12 * abs(np.vdot(yy, X))
+    # Vy = Nay = 1 is the linear-array transform
+    x1 = x[:Vx]
+    assert np.array_equal(orc.radar_cube2(x1, Vx, 1, Nax, 1, window=window),
+                          orc.radar_cube(x1, n_angle=Nax, window=window))
+
+
 # ------------------------------------------------------------------------------ CFAR
 def _np_cfar(P, guard, train, pfa):
     C, S_ = P.shape
