@@ -58,6 +58,8 @@ def make_workload(name: str):
         return S.clutter_scene()
     if name == "icosphere_20k":
         return S.icosphere_scene()
+    if name == "imaging_400":
+        return S.imaging_scene()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -103,7 +105,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="clutter_50k", choices=["clutter_50k", "icosphere_20k"])
+    ap.add_argument("--workload", default="clutter_50k", choices=["clutter_50k", "icosphere_20k", "imaging_400"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-latency measurement")
     ap.add_argument("--serving-requests", type=int, default=128)

@@ -214,6 +214,23 @@ int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_a
                    int32_t window, int32_t direction, float *out, void *scratch,
                    size_t scratch_bytes, void *stream);
 
+/* The same map T for a planar array (Sec. 4's 20 TX x 20 RX class of radar):
+ * the virtual antennas form a Vy x Vx grid, v = vy * Vx + vx (for example TX
+ * t along one axis and RX m along the other: vy = t, vx = m).  Range and
+ * Doppler as above; the angle stage is the 2D DFT over (vy, vx) zero-padded
+ * to (n_ay, n_ax), output angle index a = ay * n_ax + ax.
+ * direction 0: in [Vy*Vx][C][S][2] -> out [n_ay*n_ax][C][S][2]; direction 1
+ * applies the conjugate transpose.  Needs n_ax >= Vx, n_ay >= Vy and fewer
+ * than 2^31 cells per cube; scratch: sbr_radar_cube_2d_bytes(...) bytes.
+ * With Vy = n_ay = 1 it equals sbr_radar_cube. */
+int sbr_radar_cube_2d(const float *in, int32_t Vx, int32_t Vy, int32_t C, int32_t S,
+                      int32_t n_ax, int32_t n_ay, int32_t window, int32_t direction,
+                      float *out, void *scratch, size_t scratch_bytes, void *stream);
+
+/* Scratch bytes of sbr_radar_cube_2d; 0 for invalid sizes. */
+size_t sbr_radar_cube_2d_bytes(int32_t Vx, int32_t Vy, int32_t C, int32_t S, int32_t n_ax,
+                               int32_t n_ay);
+
 /* Radar point cloud from the cube: square-law cell-averaging CFAR on
  * P[d][r] = sum_a |X[a][d][r]|^2 with a (2(guard+train)+1)^2 window minus the
  * (2 guard+1)^2 guard cells, Doppler axis circular, range axis truncated,
@@ -266,9 +283,12 @@ int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
  *   grad = 4 (|a|^2 - H) a / n
  * grad: device float [n][2] = dL/dRe a + i dL/dIm a (overwritten; may be NULL);
  * loss: device float[1] (overwritten; may be NULL).  The sum is reduced in a
- * fixed order (deterministic). */
+ * fixed order (deterministic): per-block partials in double, then one block.
+ * scratch: device buffer of SBR_LOSS_SCRATCH_BYTES for those partials
+ * (needed only when loss is not NULL). */
+#define SBR_LOSS_SCRATCH_BYTES 8192
 int sbr_loss_grad(int32_t mode, const float *a, const float *b, int64_t n, float *grad,
-                  float *loss, void *stream);
+                  float *loss, void *scratch, size_t scratch_bytes, void *stream);
 
 /* Kernel timing for benchmarks.  sbr_profile(1) starts bracketing every launch
  * of the IF synthesis kernel (id 0), the synthesis-adjoint kernel (id 1) and

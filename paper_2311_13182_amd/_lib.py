@@ -21,11 +21,12 @@ SBR_DROP_FLAGGED = 1
 SBR_ATTACHED = 2
 SBR_EXIT_ONLY = 4
 SBR_OP_BUILD_BVH, SBR_OP_SYNTH, SBR_OP_BACKWARD, SBR_OP_RADAR_CUBE, SBR_OP_CFAR = 0, 1, 2, 3, 4
+SBR_LOSS_SCRATCH_BYTES = 8192
 
 # every function declared in include/sbr.h
 EXPORTS = ("sbr_bvh_bytes", "sbr_scratch_bytes", "sbr_build_bvh", "sbr_trace", "sbr_synth_if",
            "sbr_radar_cube", "sbr_cfar", "sbr_backward", "sbr_last_error", "sbr_loss_grad", "sbr_profile",
-           "sbr_profile_read")
+           "sbr_profile_read", "sbr_radar_cube_2d", "sbr_radar_cube_2d_bytes")
 PROF_SYNTH, PROF_SYNTH_ADJ, PROF_TRACE = 0, 1, 2
 
 
@@ -102,13 +103,17 @@ def load(path: str = LIB_PATH):
                                P(sbr_chirp), i32, vp, vp, sz, vp]
     L.sbr_radar_cube.restype = ct.c_int
     L.sbr_radar_cube.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.sbr_radar_cube_2d.restype = ct.c_int
+    L.sbr_radar_cube_2d.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.sbr_radar_cube_2d_bytes.restype = sz
+    L.sbr_radar_cube_2d_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
     L.sbr_cfar.restype = ct.c_int
     L.sbr_cfar.argtypes = [vp, i32, i32, i32, i32, i32, ct.c_double, vp, vp, i32, vp, vp, sz, vp]
     L.sbr_backward.restype = ct.c_int
     L.sbr_backward.argtypes = [P(sbr_mesh), P(sbr_material), i32, P(sbr_radar), P(sbr_rays), P(sbr_hits),
                                P(sbr_chirp), i32, vp, vp, P(sbr_param_grads), vp, sz, vp]
     L.sbr_loss_grad.restype = ct.c_int
-    L.sbr_loss_grad.argtypes = [i32, vp, vp, ct.c_int64, vp, vp, vp]
+    L.sbr_loss_grad.argtypes = [i32, vp, vp, ct.c_int64, vp, vp, vp, sz, vp]
     L.sbr_profile.restype = ct.c_int
     L.sbr_profile.argtypes = [i32]
     L.sbr_profile_read.restype = ct.c_int

@@ -36,6 +36,9 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
                     const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
                     int32_t flags, hipStream_t s);
 size_t cube_scratch_bytes(int V, int C, int S, int Na);
+size_t cube2_scratch_bytes(int Vx, int Vy, int C, int S, int Nax, int Nay);
+int radar_cube2_launch(const float2 *in, int Vx, int Vy, int C, int S, int Nax, int Nay, int window, int dir,
+                       float2 *out, void *scratch, hipStream_t s);
 size_t cfar_scratch_bytes(int C, int S);
 int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
                       void *scratch, hipStream_t s);
@@ -292,6 +295,45 @@ int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_a
     }
     return radar_cube_launch(reinterpret_cast<const float2 *>(in), V, C, S, n_angle, window, direction,
                              reinterpret_cast<float2 *>(out), scratch, (hipStream_t)stream);
+}
+
+static int check_cube2(int32_t Vx, int32_t Vy, int32_t C, int32_t S, int32_t n_ax, int32_t n_ay) {
+    SBR_CHECK_ARG(Vx >= 1 && Vy >= 1 && C >= 1 && S >= 1, "sizes must be >= 1 (Vx=%d Vy=%d C=%d S=%d)", Vx, Vy,
+                  C, S);
+    SBR_CHECK_ARG(Vx <= 4096 && Vy <= 4096 && C <= 4096 && S <= 4096 && n_ax <= 4096 && n_ay <= 4096,
+                  "sizes must be <= 4096");
+    SBR_CHECK_ARG(n_ax >= Vx && n_ay >= Vy, "n_ax=%d < Vx=%d or n_ay=%d < Vy=%d", n_ax, Vx, n_ay, Vy);
+    SBR_CHECK_ARG((long long)n_ax * n_ay * C * S < (1LL << 31) && (long long)Vx * Vy * C * S < (1LL << 31),
+                  "cube too large (more than 2^31 cells)");
+    const size_t lds_c = (size_t)C * 32 * 8 + (size_t)C * 8;
+    const size_t lds_a = (size_t)std::max(std::max(Vx, n_ax), std::max(Vy, n_ay)) * 32 * 8 +
+                         (size_t)std::max(n_ax, n_ay) * 8;
+    SBR_CHECK_ARG(lds_c <= 60000 && lds_a <= 60000, "C or the angle sizes too large for the LDS tiles");
+    return SBR_OK;
+}
+
+size_t sbr_radar_cube_2d_bytes(int32_t Vx, int32_t Vy, int32_t C, int32_t S, int32_t n_ax, int32_t n_ay) {
+    clear_error();
+    if (check_cube2(Vx, Vy, C, S, n_ax, n_ay)) return 0;
+    return cube2_scratch_bytes(Vx, Vy, C, S, n_ax, n_ay);
+}
+
+int sbr_radar_cube_2d(const float *in, int32_t Vx, int32_t Vy, int32_t C, int32_t S, int32_t n_ax, int32_t n_ay,
+                      int32_t window, int32_t direction, float *out, void *scratch, size_t scratch_bytes,
+                      void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(in && out, "in/out is NULL");
+    int rc;
+    if ((rc = check_cube2(Vx, Vy, C, S, n_ax, n_ay))) return rc;
+    SBR_CHECK_ARG(window == 0 || window == 1, "window must be 0 or 1");
+    SBR_CHECK_ARG(direction == 0 || direction == 1, "direction must be 0 or 1");
+    size_t need = cube2_scratch_bytes(Vx, Vy, C, S, n_ax, n_ay);
+    if (!scratch || scratch_bytes < need) {
+        set_error("radar cube scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    return radar_cube2_launch(reinterpret_cast<const float2 *>(in), Vx, Vy, C, S, n_ax, n_ay, window, direction,
+                              reinterpret_cast<float2 *>(out), scratch, (hipStream_t)stream);
 }
 
 int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard, int32_t train, double pfa,

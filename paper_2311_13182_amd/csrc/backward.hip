@@ -547,12 +547,15 @@ struct BackPlan {
     int nvs, v_per;
 };
 
+// One antenna per block row (grid.y) unless the per-row partial sums of Abar
+// and taudot_bar (12 bytes per path and row) would pass 4 GiB: the number of
+// live paths is only known on the device, and splitting over antennas keeps
+// the launch full when few of the `cap` slots hold paths.
 static BackPlan back_plan(long long cap, int V) {
-    long long blocks = (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL);
-    long long want = (4096 + blocks - 1) / std::max(1LL, blocks);
-    int nvs = (int)std::max(1LL, std::min((long long)V, want));
-    int v_per = (V + nvs - 1) / nvs;
-    nvs = (V + v_per - 1) / v_per;
+    const long long budget = 4LL << 30;
+    int v_per = 1;
+    while (v_per < V && (long long)((V + v_per - 1) / v_per) * cap * 12 > budget) v_per++;
+    const int nvs = (V + v_per - 1) / v_per;
     return {nvs, v_per};
 }
 

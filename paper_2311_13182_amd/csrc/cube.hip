@@ -95,22 +95,70 @@ __global__ __launch_bounds__(256) void k_dft_mid(const float2 *in, float2 *out, 
 }
 
 // ---- CFAR ------------------------------------------------------------------
-__global__ void k_power(const float2 *X, int Na, int plane, float *P, int *am) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= plane) return;
+// Power map P[e] = sum_a |X[a][e]|^2 and its argmax over a (lowest index on
+// ties).  The angle range is split over kPowSplit block rows and 4 lanes per
+// cell, so a cube with thousands of angle bins (planar arrays) still fills
+// the chip; partials are combined in a fixed order.
+constexpr int kPowSplit = 16;
+
+__global__ __launch_bounds__(256) void k_power_part(const float2 *X, int Na, int plane, float *psum, float *pmax,
+                                                    int *parg) {
+    __shared__ float ss[4][64], sm[4][64];
+    __shared__ int sa[4][64];
+    const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + cl;
+    const int per = (Na + kPowSplit - 1) / kPowSplit;
+    const int a0 = blockIdx.y * per, a1 = min(Na, a0 + per);
     float acc = 0.0f, best = -1.0f;
-    int ba = 0;
-    for (int a = 0; a < Na; a++) {
-        float2 x = X[(size_t)a * plane + e];
-        float q = x.x * x.x + x.y * x.y;
-        acc += q;
-        if (q > best) {
-            best = q;
-            ba = a;
+    int ba = a0;
+    if (e < plane) {
+        for (int a = a0 + g; a < a1; a += 4) {
+            const float2 x = X[(size_t)a * plane + e];
+            const float q = x.x * x.x + x.y * x.y;
+            acc += q;
+            if (q > best) {
+                best = q;
+                ba = a;
+            }
         }
     }
-    P[e] = acc;
-    am[e] = ba;
+    ss[g][cl] = acc;
+    sm[g][cl] = best;
+    sa[g][cl] = ba;
+    __syncthreads();
+    if (g == 0 && e < plane) {
+        float sum = ss[0][cl], m = sm[0][cl];
+        int am = sa[0][cl];
+        for (int k = 1; k < 4; k++) {
+            sum += ss[k][cl];
+            if (sm[k][cl] > m || (sm[k][cl] == m && sa[k][cl] < am)) {
+                m = sm[k][cl];
+                am = sa[k][cl];
+            }
+        }
+        psum[(size_t)blockIdx.y * plane + e] = sum;
+        pmax[(size_t)blockIdx.y * plane + e] = m;
+        parg[(size_t)blockIdx.y * plane + e] = am;
+    }
+}
+
+__global__ void k_power_final(int plane, const float *psum, const float *pmax, const int *parg, float *P,
+                              int *am) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= plane) return;
+    float sum = 0.0f, m = -1.0f;
+    int a = 0;
+    for (int k = 0; k < kPowSplit; k++) {
+        sum += psum[(size_t)k * plane + e];
+        const float mk = pmax[(size_t)k * plane + e];
+        const int ak = parg[(size_t)k * plane + e];
+        if (mk > m || (mk == m && ak < a)) {
+            m = mk;
+            a = ak;
+        }
+    }
+    P[e] = sum;
+    am[e] = a;
 }
 
 __global__ void k_cfar_cells(const float *P, int C, int S, int guard, int train, double pfa, float *ratio) {
@@ -177,19 +225,30 @@ __global__ __launch_bounds__(1024) void k_cfar_compact(const float *ratio, const
 
 }  // namespace
 
-size_t cube_scratch_bytes(int V, int C, int S, int Na) {
+// two staging buffers, each large enough for any intermediate of the chain
+static size_t cube_stage_elems(int Vx, int Vy, int C, int S, int Nax) {
+    return (size_t)std::max(Vx * Vy, Vy * Nax) * C * S;
+}
+
+size_t cube2_scratch_bytes(int Vx, int Vy, int C, int S, int Nax, int Nay) {
+    (void)Nay;
     Carver cv(nullptr);
-    size_t big = (size_t)std::max(V, Na) * C * S;
+    size_t big = cube_stage_elems(Vx, Vy, C, S, Nax);
     cv.take<float2>(big);
     cv.take<float2>(big);
     return align_up(cv.off, 256);
 }
+
+size_t cube_scratch_bytes(int V, int C, int S, int Na) { return cube2_scratch_bytes(V, 1, C, S, Na, 1); }
 
 size_t cfar_scratch_bytes(int C, int S) {
     Carver cv(nullptr);
     cv.take<float>((size_t)C * S);
     cv.take<int>((size_t)C * S);
     cv.take<float>((size_t)C * S);
+    cv.take<float>((size_t)kPowSplit * C * S);
+    cv.take<float>((size_t)kPowSplit * C * S);
+    cv.take<int>((size_t)kPowSplit * C * S);
     return align_up(cv.off, 256);
 }
 
@@ -213,24 +272,39 @@ static int launch_mid(const float2 *in, float2 *out, int outer, int N, int M, in
     return SBR_OK;
 }
 
-int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
-                      void *scratch, hipStream_t s) {
+// Planar array: virtual antenna v = vy * Vx + vx; angle index a = ay * Nax + ax.
+// Range and Doppler as for the linear array, then the angle DFT along vx
+// (zero-padded to Nax) and along vy (to Nay): separable, each a middle-axis
+// transform.  Vy = Nay = 1 is the linear array (one angle stage).
+int radar_cube2_launch(const float2 *in, int Vx, int Vy, int C, int S, int Nax, int Nay, int window, int dir,
+                       float2 *out, void *scratch, hipStream_t s) {
     Carver cv(scratch);
-    size_t big = (size_t)std::max(V, Na) * C * S;
+    const size_t big = cube_stage_elems(Vx, Vy, C, S, Nax);
     float2 *y1 = cv.take<float2>(big);
     float2 *y2 = cv.take<float2>(big);
+    const int V = Vx * Vy, CS = C * S;
+    const bool planar = Vy > 1 || Nay > 1;
     int rc;
     if (dir == 0) {
-        // range (inner), Doppler (middle), angle (outer, zero-padded V -> Na)
         if ((rc = launch_inner(in, y1, V * C, S, -1, window, 0, s))) return rc;
         if ((rc = launch_mid(y1, y2, V, C, C, C, S, -1, window, 0, s))) return rc;
-        if ((rc = launch_mid(y2, out, 1, V, Na, Na, C * S, -1, 0, 0, s))) return rc;
-    } else {
-        if ((rc = launch_mid(in, y2, 1, Na, V, Na, C * S, +1, 0, 0, s))) return rc;
-        if ((rc = launch_mid(y2, y1, V, C, C, C, S, +1, window, 1, s))) return rc;
-        if ((rc = launch_inner(y1, out, V * C, S, +1, window, 1, s))) return rc;
+        if (!planar) return launch_mid(y2, out, 1, Vx, Nax, Nax, CS, -1, 0, 0, s);
+        if ((rc = launch_mid(y2, y1, Vy, Vx, Nax, Nax, CS, -1, 0, 0, s))) return rc;   // [Vy][Nax][CS]
+        return launch_mid(y1, out, 1, Vy, Nay, Nay, Nax * CS, -1, 0, 0, s);          // [Nay][Nax][CS]
     }
-    return SBR_OK;
+    if (!planar) {
+        if ((rc = launch_mid(in, y2, 1, Nax, Vx, Nax, CS, +1, 0, 0, s))) return rc;
+    } else {
+        if ((rc = launch_mid(in, y1, 1, Nay, Vy, Nay, Nax * CS, +1, 0, 0, s))) return rc;   // [Vy][Nax][CS]
+        if ((rc = launch_mid(y1, y2, Vy, Nax, Vx, Nax, CS, +1, 0, 0, s))) return rc;        // [Vy][Vx][CS]
+    }
+    if ((rc = launch_mid(y2, y1, V, C, C, C, S, +1, window, 1, s))) return rc;
+    return launch_inner(y1, out, V * C, S, +1, window, 1, s);
+}
+
+int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
+                      void *scratch, hipStream_t s) {
+    return radar_cube2_launch(in, V, 1, C, S, Na, 1, window, dir, out, scratch, s);
 }
 
 int cfar_launch(const float2 *cube, int Na, int C, int S, int guard, int train, double pfa, int32_t *points,
@@ -240,7 +314,12 @@ int cfar_launch(const float2 *cube, int Na, int C, int S, int guard, int train, 
     float *P = cv.take<float>(plane);
     int *am = cv.take<int>(plane);
     float *ratio = cv.take<float>(plane);
-    hipLaunchKernelGGL(k_power, dim3((plane + 255) / 256), dim3(256), 0, s, cube, Na, plane, P, am);
+    float *psum = cv.take<float>((size_t)kPowSplit * plane);
+    float *pmax = cv.take<float>((size_t)kPowSplit * plane);
+    int *parg = cv.take<int>((size_t)kPowSplit * plane);
+    hipLaunchKernelGGL(k_power_part, dim3((plane + 63) / 64, kPowSplit), dim3(256), 0, s, cube, Na, plane, psum,
+                       pmax, parg);
+    hipLaunchKernelGGL(k_power_final, dim3((plane + 255) / 256), dim3(256), 0, s, plane, psum, pmax, parg, P, am);
     hipLaunchKernelGGL(k_cfar_cells, dim3((plane + 255) / 256), dim3(256), 0, s, P, C, S, guard, train, pfa,
                        ratio);
     hipLaunchKernelGGL(k_cfar_compact, dim3(1), dim3(1024), 0, s, ratio, am, plane, S, points, ratio_out, maxp,

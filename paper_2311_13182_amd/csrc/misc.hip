@@ -2,51 +2,62 @@
 #include <mutex>
 #include <vector>
 
+#include <algorithm>
+
 #include "sbr_internal.h"
 
 namespace sbr {
 
 namespace {
 
-__global__ void k_loss_grad(int mode, const float2 *a, const float *b, long long n, float2 *grad) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float2 x = a[i];
-    if (mode == 0) {
-        float2 y = reinterpret_cast<const float2 *>(b)[i];
-        grad[i] = make_float2(2.0f * (x.x - y.x), 2.0f * (x.y - y.y));
-    } else {
-        float e = x.x * x.x + x.y * x.y - b[i];
-        float s = 4.0f * e / (float)n;
-        grad[i] = make_float2(s * x.x, s * x.y);
-    }
-}
+constexpr int kLossBlocks = 1024;   // stage-1 blocks at most (partials in scratch)
 
-// fixed-order reduction in one block, double accumulation
-__global__ __launch_bounds__(1024) void k_loss(int mode, const float2 *a, const float *b, long long n,
-                                               float *loss) {
-    __shared__ double part[1024];
+// Stage 1: elementwise gradient and per-block partial sums of the loss, each
+// block reducing its strided share in a fixed order, in double.
+__global__ __launch_bounds__(256) void k_loss_part(int mode, const float2 *a, const float *b, long long n,
+                                                   float2 *grad, double *part) {
+    __shared__ double sh[256];
+    const long long stride = (long long)gridDim.x * 256;
     double s = 0.0;
-    for (long long i = threadIdx.x; i < n; i += 1024) {
-        float2 x = a[i];
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const float2 x = a[i];
         double e;
         if (mode == 0) {
-            float2 y = reinterpret_cast<const float2 *>(b)[i];
-            double dr = (double)x.x - y.x, di = (double)x.y - y.y;
+            const float2 y = reinterpret_cast<const float2 *>(b)[i];
+            if (grad) grad[i] = make_float2(2.0f * (x.x - y.x), 2.0f * (x.y - y.y));
+            const double dr = (double)x.x - y.x, di = (double)x.y - y.y;
             e = dr * dr + di * di;
         } else {
-            double q = (double)x.x * x.x + (double)x.y * x.y - b[i];
-            e = q * q;
+            const float q = x.x * x.x + x.y * x.y - b[i];
+            if (grad) {
+                const float g = 4.0f * q / (float)n;
+                grad[i] = make_float2(g * x.x, g * x.y);
+            }
+            const double qd = (double)x.x * x.x + (double)x.y * x.y - b[i];
+            e = qd * qd;
         }
         s += e;
     }
-    part[threadIdx.x] = s;
+    sh[threadIdx.x] = s;
     __syncthreads();
-    for (int off = 512; off >= 1; off >>= 1) {
-        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    for (int off = 128; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *loss = (float)(mode == 0 ? part[0] : part[0] / (double)n);
+    if (threadIdx.x == 0 && part) part[blockIdx.x] = sh[0];
+}
+
+// Stage 2: the partials in a fixed order (one block).
+__global__ __launch_bounds__(1024) void k_loss_final(const double *part, int nb, int mode, long long n,
+                                                     float *loss) {
+    __shared__ double sh[1024];
+    sh[threadIdx.x] = (int)threadIdx.x < nb ? part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int off = 512; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(mode == 0 ? sh[0] : sh[0] / (double)n);
 }
 
 struct ProfRec {
@@ -85,21 +96,27 @@ using namespace sbr;
 extern "C" {
 
 int sbr_loss_grad(int32_t mode, const float *a, const float *b, int64_t n, float *grad, float *loss,
-                  void *stream) {
+                  void *scratch, size_t scratch_bytes, void *stream) {
     clear_error();
     SBR_CHECK_ARG(mode == 0 || mode == 1, "mode must be 0 (IF) or 1 (heatmap)");
     SBR_CHECK_ARG(n >= 0, "n must be >= 0");
     SBR_CHECK_ARG(n == 0 || (a && b), "a/b is NULL");
+    if (loss && (!scratch || scratch_bytes < SBR_LOSS_SCRATCH_BYTES)) {
+        set_error("loss scratch too small: %zu bytes given, %d needed", scratch_bytes, SBR_LOSS_SCRATCH_BYTES);
+        return SBR_E_SCRATCH;
+    }
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) {
         if (loss) return fill_zero_f32(loss, 1, s);
         return SBR_OK;
     }
+    if (!grad && !loss) return SBR_OK;
     const float2 *a2 = reinterpret_cast<const float2 *>(a);
-    if (grad)
-        hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int)mode, a2, b,
-                           (long long)n, reinterpret_cast<float2 *>(grad));
-    if (loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, (int)mode, a2, b, (long long)n, loss);
+    const int nb = (int)std::min<long long>(kLossBlocks, (n + 1023) / 1024);
+    double *part = loss ? reinterpret_cast<double *>(scratch) : nullptr;
+    hipLaunchKernelGGL(k_loss_part, dim3((unsigned)nb), dim3(256), 0, s, (int)mode, a2, b, (long long)n,
+                       reinterpret_cast<float2 *>(grad), part);
+    if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, s, part, nb, (int)mode, (long long)n, loss);
     SBR_LAUNCHED();
     return SBR_OK;
 }

@@ -178,6 +178,16 @@ def sbr_synth_if(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chi
                                 _stream()))
 
 
+def sbr_radar_cube_2d_bytes(vx: int, vy: int, C: int, Sn: int, n_ax: int, n_ay: int) -> int:
+    return int(_lib().sbr_radar_cube_2d_bytes(vx, vy, C, Sn, n_ax, n_ay))
+
+
+def sbr_radar_cube_2d(x: torch.Tensor, vx: int, vy: int, C: int, Sn: int, n_ax: int, n_ay: int, window: int,
+                      direction: int, out: torch.Tensor, scratch: torch.Tensor):
+    L.check(_lib().sbr_radar_cube_2d(_p(x), vx, vy, C, Sn, n_ax, n_ay, window, direction, _p(out), _p(scratch),
+                                     scratch.numel() * scratch.element_size(), _stream()))
+
+
 def sbr_radar_cube(x: torch.Tensor, V: int, C: int, Sn: int, n_angle: int, window: int, direction: int,
                    out: torch.Tensor, scratch: torch.Tensor):
     L.check(_lib().sbr_radar_cube(_p(x), V, C, Sn, n_angle, window, direction, _p(out), _p(scratch),
@@ -210,8 +220,12 @@ def sbr_backward(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chi
 
 
 def sbr_loss_grad(mode: int, a: torch.Tensor, b: torch.Tensor, n: int, grad: Optional[torch.Tensor],
-                  loss: Optional[torch.Tensor]):
-    L.check(_lib().sbr_loss_grad(int(mode), _p(a), _p(b), int(n), _p(grad), _p(loss), _stream()))
+                  loss: Optional[torch.Tensor], scratch: Optional[torch.Tensor] = None):
+    if loss is not None and scratch is None:
+        scratch = torch.empty(L.SBR_LOSS_SCRATCH_BYTES, dtype=torch.uint8, device=a.device)
+    nbytes = scratch.numel() * scratch.element_size() if scratch is not None else 0
+    L.check(_lib().sbr_loss_grad(int(mode), _p(a), _p(b), int(n), _p(grad), _p(loss), _p(scratch), nbytes,
+                                 _stream()))
 
 
 def sbr_profile(op: int):
@@ -243,19 +257,26 @@ class Simulator:
         g, rd, ch = scene.grid, scene.radar, scene.chirp
         self.K, self.R = g.max_bounces, g.nx * g.ny
         self.V, self.C, self.S = rd.n_virtual, ch.n_chirps, ch.n_samples
-        self.n_angle = max(n_angle, self.V)
+        self.planar = bool(getattr(rd, "planar", False))
+        if self.planar:   # angle grid n_ay x n_ax over the (TX, RX) = (vy, vx) virtual grid
+            self.n_ax, self.n_ay = max(n_angle, rd.n_rx), max(n_angle, rd.n_tx)
+            self.n_angle = self.n_ax * self.n_ay
+        else:
+            self.n_angle = max(n_angle, self.V)
         need = max(sbr_scratch_bytes(L.SBR_OP_BUILD_BVH, self.mesh),
                    sbr_scratch_bytes(L.SBR_OP_SYNTH, self.mesh, g, rd, ch),
                    sbr_scratch_bytes(L.SBR_OP_BACKWARD, self.mesh, g, rd, ch),
                    sbr_scratch_bytes(L.SBR_OP_RADAR_CUBE, None, g, rd, dataclasses.replace(ch)),
                    sbr_scratch_bytes(L.SBR_OP_CFAR, None, g, rd, ch))
         # the cube stage needs room for max(V, n_angle) planes
-        need = max(need, 2 * 8 * self.n_angle * self.C * self.S + 1024)
+        need = max(need, 2 * 8 * self.n_angle * self.C * self.S + 1024) if not self.planar else \
+            max(need, sbr_radar_cube_2d_bytes(rd.n_rx, rd.n_tx, self.C, self.S, self.n_ax, self.n_ay))
         self.scratch = torch.empty(need, dtype=torch.uint8, device=self.device)
         self.bvh = bvh if bvh is not None else torch.empty(max(1, sbr_bvh_bytes(self.mesh.nf)), dtype=torch.uint8,
                                                            device=self.device)
         self.hits = Hits.empty(self.K, self.R, self.device)
         self.counters = torch.zeros(3, dtype=torch.int64, device=self.device)
+        self.loss_scratch = torch.empty(L.SBR_LOSS_SCRATCH_BYTES, dtype=torch.uint8, device=self.device)
         self.built = bvh is not None
 
     # ---- geometry
@@ -294,7 +315,12 @@ class Simulator:
             out = torch.empty((self.n_angle, self.C, self.S, 2), dtype=torch.float32, device=self.device)
         else:
             out = torch.empty((self.V, self.C, self.S, 2), dtype=torch.float32, device=self.device)
-        sbr_radar_cube(xf, self.V, self.C, self.S, self.n_angle, window, direction, out, self.scratch)
+        if self.planar:
+            rd = self.scene.radar
+            sbr_radar_cube_2d(xf, rd.n_rx, rd.n_tx, self.C, self.S, self.n_ax, self.n_ay, window, direction, out,
+                              self.scratch)
+        else:
+            sbr_radar_cube(xf, self.V, self.C, self.S, self.n_angle, window, direction, out, self.scratch)
         return torch.view_as_complex(out)
 
     def cfar(self, X: torch.Tensor, guard=2, train=8, pfa=1e-4, max_points=65536):
@@ -331,7 +357,7 @@ class Simulator:
             grad = torch.empty_like(a)
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=self.device)
-        sbr_loss_grad(mode, a, b, n, grad, loss)
+        sbr_loss_grad(mode, a, b, n, grad, loss, self.loss_scratch)
         return grad, loss
 
     def n_paths(self) -> int:

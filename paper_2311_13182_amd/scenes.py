@@ -56,6 +56,7 @@ class Radar:
     tx: np.ndarray                           # (n_tx, 3) radar frame
     rx: np.ndarray                           # (n_rx, 3) radar frame
     vel: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))  # scene velocity, world
+    planar: bool = False                     # virtual antennas form an n_tx x n_rx grid (vy = t, vx = m)
 
     @property
     def n_tx(self) -> int:
@@ -120,6 +121,23 @@ def default_radar(n_tx: int = 1, n_rx: int = 4, fc: float = 77e9,
                   vel=(0.0, 0.0, 0.0)) -> Radar:
     tx, rx = ula_array(n_tx, n_rx, fc)
     return Radar(origin=np.zeros(3), rot=np.eye(3), tx=tx, rx=rx, vel=np.asarray(vel, float))
+
+
+def planar_array(n_tx: int, n_rx: int, fc: float) -> Tuple[np.ndarray, np.ndarray]:
+    """TX along the radar y axis and RX along x, both lambda/2 apart: the
+    virtual array is an n_tx x n_rx lambda/2 grid centred at the origin (the
+    20 TX x 20 RX imaging class of Sec. 4)."""
+    lam = wavelength(fc)
+    tx = np.zeros((n_tx, 3))
+    rx = np.zeros((n_rx, 3))
+    tx[:, 1] = (np.arange(n_tx) - (n_tx - 1) / 2.0) * (lam / 2.0)
+    rx[:, 0] = (np.arange(n_rx) - (n_rx - 1) / 2.0) * (lam / 2.0)
+    return tx, rx
+
+
+def planar_radar(n_tx: int = 20, n_rx: int = 20, fc: float = 62e9, vel=(0.0, 0.0, 0.0)) -> Radar:
+    tx, rx = planar_array(n_tx, n_rx, fc)
+    return Radar(origin=np.zeros(3), rot=np.eye(3), tx=tx, rx=rx, vel=np.asarray(vel, float), planar=True)
 
 
 def fov_tan(radius: float, distance: float, margin: float = 1.02) -> float:
@@ -440,6 +458,26 @@ def clutter_scene(seed: int = 3, n_rays: int = 2048, n_chirps: int = 128,
     return Scene("clutter_50k", v.astype(np.float32), f.astype(np.int32),
                  default_radar(3, 4, vel=(0.0, 0.0, 1.0)), Chirp(n_chirps=n_chirps),
                  Grid(n_rays, n_rays, th, th, bounces))
+
+
+def imaging_scene(n_rays: int = 512, n_chirps: int = 16, n_samples: int = 256, seed: int = 5,
+                  n_tx: int = 20, n_rx: int = 20, bounces: int = 2) -> Scene:
+    """Planar-array imaging workload: 20 TX x 20 RX (400 virtual antennas,
+    lambda/2 grid) at 62 GHz with a 7 GHz sweep in the ADC window (256 samples
+    at 10 MHz, 2.1 cm range bins, 5.5 m unambiguous), 16 chirps; two
+    superquadrics (~10k triangles each) and a corner reflector 1-2 m out,
+    +-25 deg, 2 bounces, scene velocity 0.5 m/s."""
+    a, fa = superquadric_object(seed, 100, 51, (0.15, 0.2, 0.12), (-0.35, 0.1, 1.4))
+    b, fb = superquadric_object(seed + 1, 100, 51, (0.2, 0.12, 0.18), (0.4, -0.15, 1.9))
+    tv, tf = trihedral(0.12)
+    apex = np.array([0.05, 0.35, 1.2])
+    R = _rot_from_to(np.ones(3) / math.sqrt(3.0), -apex / np.linalg.norm(apex))
+    v, f = _concat([(a, fa), (b, fb), (tv @ R.T + apex, tf)])
+    th = math.tan(math.radians(25.0))
+    ch = Chirp(fc=62e9, slope=7e9 / (n_samples / 10e6), fs=10e6, t_chirp=40e-6, n_samples=n_samples,
+               n_chirps=n_chirps)
+    return Scene("imaging_400", v.astype(np.float32), f.astype(np.int32),
+                 planar_radar(n_tx, n_rx, 62e9, vel=(0.0, 0.0, 0.5)), ch, Grid(n_rays, n_rays, th, th, bounces))
 
 
 def recon_scenes(seed: int = 4, n_rays: int = 1024, n_chirps: int = 64):

@@ -647,3 +647,93 @@ def test_backward_shadow_and_exit_only(torch_cuda, orc, mode):
     log(f"backward {mode}: rel L2 {e:.3e} over {len(coords)} coordinates")
     assert e <= GRAD_TOL
 
+
+
+# ----------------------------------------------------------------- planar arrays (400 virtual antennas)
+@pytest.mark.parametrize("shape,window", [((5, 4, 6, 10, 8, 7), 1), ((20, 20, 8, 32, 32, 32), 0)])
+def test_radar_cube_2d_vs_oracle(torch_cuda, orc, shape, window):
+    """Planar-array T: 2D angle DFT over the (TX, RX) virtual grid, forward and
+    conjugate transpose, against the oracle's direct sums."""
+    import torch
+    from paper_2311_13182_amd.sbr import sbr_radar_cube_2d, sbr_radar_cube_2d_bytes
+    Vx, Vy, C, Sn, Nax, Nay = shape
+    rng = np.random.default_rng(4)
+    x = (rng.normal(size=(Vy * Vx, C, Sn)) + 1j * rng.normal(size=(Vy * Vx, C, Sn))).astype(np.complex64)
+    scratch = torch.empty(sbr_radar_cube_2d_bytes(Vx, Vy, C, Sn, Nax, Nay), dtype=torch.uint8, device="cuda")
+    out = torch.empty((Nay * Nax, C, Sn, 2), dtype=torch.float32, device="cuda")
+    sbr_radar_cube_2d(torch.view_as_real(torch.as_tensor(x, device="cuda")).contiguous(), Vx, Vy, C, Sn, Nax, Nay,
+                      window, 0, out, scratch)
+    X = torch.view_as_complex(out).cpu().numpy()
+    ref = orc.radar_cube2(x.astype(np.complex128), Vx, Vy, Nax, Nay, window=window)
+    e = rel_l2(X, ref)
+    y = (rng.normal(size=ref.shape) + 1j * rng.normal(size=ref.shape)).astype(np.complex64)
+    back = torch.empty((Vy * Vx, C, Sn, 2), dtype=torch.float32, device="cuda")
+    sbr_radar_cube_2d(torch.view_as_real(torch.as_tensor(y, device="cuda")).contiguous(), Vx, Vy, C, Sn, Nax, Nay,
+                      window, 1, back, scratch)
+    Y = torch.view_as_complex(back).cpu().numpy()
+    ea = rel_l2(Y, orc.radar_cube2(y.astype(np.complex128), Vx, Vy, Nax, Nay, window=window, direction=1))
+    log(f"cube 2d {shape} w={window}: rel L2 {e:.3e} / adjoint {ea:.3e}")
+    assert e <= CUBE_TOL and ea <= CUBE_TOL
+
+
+def _imaging_small():
+    return S.imaging_scene(n_rays=40, n_chirps=2, n_samples=32)
+
+
+def test_synth_planar_400_antennas(torch_cuda, orc):
+    sc = _imaging_small()
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    want = orc.synth(sc, p)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    got = _cube_np(sim.synth())
+    e = rel_l2(got, want)
+    log(f"synth 400 antennas: {len(p['amp'])} paths, V={sc.radar.n_virtual}, rel L2 {e:.3e}")
+    assert sc.radar.n_virtual == 400 and e <= 1e-4
+
+
+def test_backward_planar_400_antennas(torch_cuda, orc):
+    import torch
+    sc = _imaging_small()
+    o = orc.trace(sc)
+    tgt, _, _ = orc.forward(S.jitter(sc, 1e-3, 16))
+    p = orc.paths(sc, o["tri"], o["flags"])
+    G = 2.0 * (orc.synth(sc, p) - tgt)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    gr = torch.zeros(6, dtype=torch.float32, device="cuda")
+    got = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda"), grad_radar=gr)
+    got = got.cpu().numpy().astype(np.float64).reshape(-1)
+    hit_v = np.unique(sc.faces[np.unique(o["tri"][o["tri"] >= 0])].reshape(-1))
+    rng = np.random.default_rng(9)
+    coords = (rng.choice(hit_v, 3, replace=False)[:, None] * 3 + np.arange(3)[None, :]).reshape(-1)
+    fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, coords=coords, h=1e-9)
+    e = rel_l2(got[coords], fd)
+    log(f"backward 400 antennas: rel L2 {e:.3e} over {len(coords)} coordinates")
+    assert e <= GRAD_TOL
+
+
+def test_planar_cube_peak_at_target_direction(torch_cuda):
+    """A small plate seen off boresight peaks in the (azimuth, elevation) bins
+    its direction predicts for a lambda/2 grid: phase step pi sin(angle) per
+    element, so bin = -N u / 2 mod N along each axis."""
+    v, f = S.plate(0.04, 0.0)
+    c = np.array([0.35, -0.25, 1.6])
+    u = c / np.linalg.norm(c)
+    R = S._rot_from_to(np.array([0.0, 0.0, -1.0]), -u)      # plate faces the radar
+    sc = S.Scene("plate_off_axis", (v @ R.T + c).astype(np.float32), f.astype(np.int32),
+                 S.planar_radar(20, 20, 62e9), S.Chirp(fc=62e9, slope=7e9 / 25.6e-6, fs=10e6, n_samples=256,
+                                                        n_chirps=2),
+                 S.Grid(96, 96, 0.35, 0.35, 1))
+    sim = _sim(sc)
+    X = sim.radar_cube(sim.forward())
+    P = (X.abs() ** 2).sum(dim=1).cpu().numpy()             # [Na][S]
+    a = int(np.argmax(P.max(axis=1)))
+    ax, ay = a % sim.n_ax, a // sim.n_ax
+    want_x = int(round(-sim.n_ax * u[0] / 2)) % sim.n_ax
+    want_y = int(round(-sim.n_ay * u[1] / 2)) % sim.n_ay
+    log(f"planar peak ({ax}, {ay}) want ({want_x}, {want_y})")
+    dx = min((ax - want_x) % sim.n_ax, (want_x - ax) % sim.n_ax)
+    dy = min((ay - want_y) % sim.n_ay, (want_y - ay) % sim.n_ay)
+    assert dx <= 1 and dy <= 1

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     txt = open(os.path.join(ROOT, "include", "sbr.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(sbr_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(sbr_[a-z0-9_]+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +28,7 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     from paper_2311_13182_amd import _lib as L
     decl = _declared()
-    assert len(decl) == 12
+    assert len(decl) == 14
     assert sorted(L.EXPORTS) == decl
     for name in decl:
         assert hasattr(lib, name), name
@@ -82,6 +82,10 @@ def test_argument_errors_are_reported(lib):
     assert lib.sbr_radar_cube(fake, 12, 8, 16, 8, 0, 0, fake, fake, 1 << 30, None) == L.SBR_E_ARG
     assert lib.sbr_radar_cube(fake, 12, 8, 16, 64, 2, 0, fake, fake, 1 << 30, None) == L.SBR_E_ARG
     assert lib.sbr_radar_cube(fake, 12, 8, 16, 64, 0, 5, fake, fake, 1 << 30, None) == L.SBR_E_ARG
+    # planar cube: angle grid smaller than the array, size query
+    assert lib.sbr_radar_cube_2d(fake, 20, 20, 8, 16, 16, 64, 0, 0, fake, fake, 1 << 30, None) == L.SBR_E_ARG
+    assert lib.sbr_radar_cube_2d_bytes(20, 20, 8, 16, 8, 64) == 0
+    assert lib.sbr_radar_cube_2d_bytes(20, 20, 8, 16, 64, 64) >= 2 * 8 * 20 * 64 * 8 * 16
     # too many antennas
     rr = sbr.radar_struct(sc.radar)
     rr.n_tx, rr.n_rx = L.SBR_MAX_TX + 1, 4
