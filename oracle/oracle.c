@@ -588,6 +588,34 @@ void orc_radar_cube2(const double *in, int Vx, int Vy, int C, int S, int Nax, in
     }
 }
 
+/* ---------- detections -> 3D points (Sec. 4: radars output point clouds) ----------
+ * Range bin r of an S-sample chirp: beat frequency r f_s / S = mu tau, R = c tau / 2.
+ * Doppler bin d of C chirps: d / C cycles per chirp = f_c T_c taudot, v = c taudot / 2.
+ * Angle bin a of the zero-padded array DFT (sign -1) over lambda/2 spacing:
+ * the element phase step is -pi u, so u = -2 a_s / N with a_s the signed bin. */
+static double signed_bin(int a, int N) { return (a >= (N + 1) / 2) ? (double)(a - N) : (double)a; }
+
+void orc_cloud(const int *points, int n, const orc_radar *rd, const orc_chirp *ch, int Nax, int Nay,
+               double *out) {
+    const int S = ch->n_samples, C = ch->n_chirps;
+    for (int i = 0; i < n; i++) {
+        int rb = points[4 * i], db = points[4 * i + 1], a = points[4 * i + 2];
+        double R = C0 * (rb * ch->fs / ((double)S * ch->slope)) / 2.0;
+        double ax = a % Nax, ay = a / Nax;
+        double ux = -2.0 * signed_bin((int)ax, Nax) / Nax;
+        double uy = Nay > 1 ? -2.0 * signed_bin((int)ay, Nay) / Nay : 0.0;
+        double uz2 = 1.0 - ux * ux - uy * uy;
+        double u[3] = {ux, uy, uz2 > 0.0 ? sqrt(uz2) : 0.0};
+        double p[3] = {R * u[0], R * u[1], R * u[2]}, w[3];
+        to_world(rd, p, w);
+        double tdot = signed_bin(db, C) / ((double)C * ch->fc * ch->t_chirp);
+        out[4 * i] = w[0];
+        out[4 * i + 1] = w[1];
+        out[4 * i + 2] = w[2];
+        out[4 * i + 3] = C0 * tdot / 2.0;
+    }
+}
+
 /* ---------- textbook square-law cell-averaging CFAR ---------- */
 int orc_cfar(const double *cube, int Na, int C, int S, int guard, int train, double pfa,
              unsigned char *status, int *argmax, double *power) {

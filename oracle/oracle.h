@@ -34,6 +34,8 @@
  *   orc_radar_cube     numpy.fft, dot-product (adjoint) identity (1D and 2D
  *                      arrays)
  *   orc_cfar           injected targets, brute force on tiny maps
+ *   orc_cloud          bins of a synthesised point target map back to its
+ *                      position and velocity within one resolution cell
  */
 #ifndef SBR_ORACLE_H
 #define SBR_ORACLE_H
@@ -178,6 +180,14 @@ void orc_radar_cube2(const double *in, int Vx, int Vy, int C, int S, int Nax, in
  * Returns the number of detections. */
 int orc_cfar(const double *cube, int Na, int C, int S, int guard, int train,
              double pfa, unsigned char *status, int *argmax, double *power);
+
+/* Detections -> points.  points: [n][4] (range bin, Doppler bin, angle index
+ * a = ay * Nax + ax, unused) as orc_cfar's cells give them; Nay = 1 for a
+ * linear array along the radar x axis (elevation unknown: points in the
+ * radar's x-z plane), else a planar lambda/2 grid (vy along y).  out [n][4]:
+ * world x, y, z and radial velocity (m/s, positive = receding). */
+void orc_cloud(const int *points, int n, const orc_radar *rd, const orc_chirp *ch, int Nax,
+               int Nay, double *out);
 
 #ifdef __cplusplus
 }

@@ -88,6 +88,7 @@ def lib():
                                      ct.c_int, dp]
         L.orc_radar_cube2.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
                                       ct.c_int, ct.c_int, dp]
+        L.orc_cloud.argtypes = [ip, ct.c_int, ct.POINTER(_Radar), ct.POINTER(_Chirp), ct.c_int, ct.c_int, dp]
         L.orc_cfar.restype = ct.c_int
         L.orc_cfar.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_double,
                                bp, ip, dp]
@@ -298,6 +299,16 @@ def cfar(X, guard=2, train=8, pfa=1e-4):
     n = lib().orc_cfar(_p(inp, ct.c_double), Na, C, S, guard, train, pfa, _p(st, ct.c_ubyte),
                        _p(am, ct.c_int), _p(pw, ct.c_double))
     return {"count": n, "status": st, "argmax": am, "power": pw}
+
+
+def cloud(scene, points, n_ax, n_ay=1):
+    """[n][4] detections (range bin, Doppler bin, angle index, 0) -> [n][4]
+    world x, y, z, radial velocity."""
+    pts = np.ascontiguousarray(points, dtype=np.int32).reshape(-1, 4)
+    out = np.empty((len(pts), 4))
+    lib().orc_cloud(_p(pts, ct.c_int), len(pts), ct.byref(_radar(scene.radar)), ct.byref(_chirp(scene.chirp)),
+                    n_ax, n_ay, _p(out, ct.c_double))
+    return out
 
 
 def fresnel(mode, eps_r, sigma, fc, cos_i):

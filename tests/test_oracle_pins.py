@@ -425,3 +425,44 @@ def test_cfar_injected_targets_and_bruteforce(orc):
     mask = (out["status"] & 2) == 0
     assert np.array_equal((out["status"] & 1)[mask], ref[mask])
     assert out["count"] <= len(targets) + 3
+
+
+# ------------------------------------------------------------------------------ point cloud
+def _point_target_scene(c, radar, chirp):
+    v, f = S.plate(0.03, 0.0)
+    u = np.asarray(c, float) / np.linalg.norm(c)
+    R = S._rot_from_to(np.array([0.0, 0.0, -1.0]), -u)
+    return S.Scene("point", (v @ R.T + np.asarray(c, float)).astype(np.float32), f.astype(np.int32), radar, chirp,
+                   S.Grid(48, 48, 0.45, 0.45, 1))
+
+
+@pytest.mark.parametrize("planar", [False, True])
+def test_cloud_maps_peak_back_to_target(orc, planar):
+    """A small plate moving with the scene: the strongest cell of the oracle's
+    own radar cube, mapped by orc_cloud, lands within one resolution cell of
+    the plate's centre and radial velocity."""
+    c = np.array([0.3, 0.22 if planar else 0.0, 1.5])
+    vel = np.array([0.4, 0.0, 1.2])
+    if planar:
+        radar = S.planar_radar(8, 8, 62e9, vel=vel)
+        ch = S.Chirp(fc=62e9, slope=7e9 / 25.6e-6, fs=10e6, n_samples=128, n_chirps=16)
+        n_ax = n_ay = 32
+    else:
+        radar = S.default_radar(3, 4, vel=vel)
+        ch = S.Chirp(n_samples=128, n_chirps=16)
+        n_ax, n_ay = 64, 1
+    sc = _point_target_scene(c, radar, ch)
+    cube, _, _ = orc.forward(sc)
+    X = orc.radar_cube2(cube, radar.n_rx if planar else radar.n_virtual, radar.n_tx if planar else 1, n_ax, n_ay)
+    P = np.abs(X) ** 2
+    a, d, r = np.unravel_index(np.argmax(P), P.shape)
+    xyzv = orc.cloud(sc, [[r, d, a, 0]], n_ax, n_ay)[0]
+    dR = C0 * ch.fs / (2.0 * ch.slope * ch.n_samples)          # range bin
+    du = 2.0 / n_ax                                             # direction-cosine bin
+    Rt = np.linalg.norm(c)
+    assert abs(np.linalg.norm(xyzv[:3]) - Rt) <= dR
+    ut = c / Rt
+    ue = xyzv[:3] / np.linalg.norm(xyzv[:3])
+    assert abs(ue[0] - ut[0]) <= du and (not planar or abs(ue[1] - ut[1]) <= 2.0 / n_ay)
+    dv = C0 / (2.0 * ch.n_chirps * ch.fc * ch.t_chirp)         # Doppler bin in m/s
+    assert abs(xyzv[3] - float(vel @ ut)) <= dv
