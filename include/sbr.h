@@ -243,6 +243,21 @@ int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard,
              int32_t train, double pfa, int32_t *points, float *ratio, int32_t max_points,
              int32_t *n_points, void *scratch, size_t scratch_bytes, void *stream);
 
+/* Radar point cloud: CFAR detections to world points (Sec. 4: the radars
+ * output point clouds; Fig. 1 initialises the scene from them).  points:
+ * device int32 [max_points][4] as sbr_cfar writes them; n_points: device
+ * int32 count (entries past min(count, max_points) are written as NaN).
+ * Range bin r -> R = c r f_s / (2 mu S) from the array centre; Doppler bin d
+ * -> radial velocity c d_s / (2 C f_c t_chirp) (positive = receding); angle
+ * index a = ay * n_ax + ax of the cube over a lambda/2 array -> direction
+ * cosines u_x = -2 ax_s / n_ax and, for n_ay > 1 (planar array,
+ * sbr_radar_cube_2d), u_y = -2 ay_s / n_ay, else u_y = 0 (a linear array
+ * along x measures no elevation); a_s is the signed bin.  out: device float
+ * [max_points][4] = world x, y, z, radial velocity. */
+int sbr_cloud(const int32_t *points, const int32_t *n_points, int32_t max_points,
+              const sbr_radar *radar, const sbr_chirp *chirp, int32_t n_ax, int32_t n_ay,
+              float *out, void *stream);
+
 /* Gradients with respect to scene parameters other than the vertices (the
  * material, pose and dynamics entries of Theta, Sec. 3.2).  Device arrays,
  * accumulated (+=); either pointer may be NULL. */

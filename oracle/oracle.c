@@ -616,6 +616,53 @@ void orc_cloud(const int *points, int n, const orc_radar *rd, const orc_chirp *c
     }
 }
 
+/* ---------- angle peaks of detected range-Doppler cells ----------
+ * A cell's angle spectrum q[a] = |X[a][d][r]|^2 over the (circular) angle grid
+ * (ring for a linear array, torus of Nay x Nax for a planar one): a is a peak
+ * when q[a] >= rel * max_a q, q[a] > q[n] for every neighbour n with a lower
+ * index and q[a] >= q[n] for the others (plateaus give their first cell). */
+static double cell_q(const double *cube, size_t plane, size_t e, int a) {
+    size_t ix = ((size_t)a * plane + e) * 2;
+    return cube[ix] * cube[ix] + cube[ix + 1] * cube[ix + 1];
+}
+
+int orc_angle_peaks(const double *cube, int Nax, int Nay, int C, int S, const int *det, int n, double rel,
+                    int *out, int max_out) {
+    const size_t plane = (size_t)C * S;
+    const int Na = Nax * Nay;
+    int cnt = 0;
+    for (int i = 0; i < n; i++) {
+        const int r = det[4 * i], d = det[4 * i + 1];
+        const size_t e = (size_t)d * S + r;
+        double qmax = 0.0;
+        for (int a = 0; a < Na; a++) {
+            double q = cell_q(cube, plane, e, a);
+            if (q > qmax) qmax = q;
+        }
+        for (int a = 0; a < Na; a++) {
+            const double q = cell_q(cube, plane, e, a);
+            if (!(q >= rel * qmax) || q <= 0.0) continue;
+            const int ax = a % Nax, ay = a / Nax;
+            int peak = 1;
+            for (int dy = (Nay > 1 ? -1 : 0); dy <= (Nay > 1 ? 1 : 0) && peak; dy++)
+                for (int dx = -1; dx <= 1 && peak; dx++) {
+                    if (dx == 0 && dy == 0) continue;
+                    const int bx = (ax + dx + Nax) % Nax, by = (ay + dy + Nay) % Nay;
+                    const int b = by * Nax + bx;
+                    if (b == a) continue;
+                    const double qb = cell_q(cube, plane, e, b);
+                    if (b < a ? !(q > qb) : !(q >= qb)) peak = 0;
+                }
+            if (!peak) continue;
+            if (cnt < max_out) {
+                out[4 * cnt] = r; out[4 * cnt + 1] = d; out[4 * cnt + 2] = a; out[4 * cnt + 3] = 0;
+            }
+            cnt++;
+        }
+    }
+    return cnt;
+}
+
 /* ---------- textbook square-law cell-averaging CFAR ---------- */
 int orc_cfar(const double *cube, int Na, int C, int S, int guard, int train, double pfa,
              unsigned char *status, int *argmax, double *power) {

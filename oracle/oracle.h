@@ -34,6 +34,7 @@
  *   orc_radar_cube     numpy.fft, dot-product (adjoint) identity (1D and 2D
  *                      arrays)
  *   orc_cfar           injected targets, brute force on tiny maps
+ *   orc_angle_peaks    independent NumPy local-maximum search, planted peaks
  *   orc_cloud          bins of a synthesised point target map back to its
  *                      position and velocity within one resolution cell
  */
@@ -180,6 +181,17 @@ void orc_radar_cube2(const double *in, int Vx, int Vy, int C, int S, int Nax, in
  * Returns the number of detections. */
 int orc_cfar(const double *cube, int Na, int C, int S, int guard, int train,
              double pfa, unsigned char *status, int *argmax, double *power);
+
+/* Angle peaks of detected range-Doppler cells (several scatterers per cell,
+ * as a radar's angle search reports them).  cube [Nay*Nax][C][S][2]; det
+ * [n][4] (range bin, Doppler bin, ...); rel: a peak holds at least rel of the
+ * cell's largest angle power.  Peaks are local maxima over the circular angle
+ * grid (ring if Nay = 1, else the 8-neighbourhood on the Nay x Nax torus);
+ * equal neighbours keep the lower index.  out [max_out][4] = (range bin,
+ * Doppler bin, angle index, 0), detection-major then angle ascending.
+ * Returns the number of peaks (may exceed max_out). */
+int orc_angle_peaks(const double *cube, int Nax, int Nay, int C, int S, const int *det, int n,
+                    double rel, int *out, int max_out);
 
 /* Detections -> points.  points: [n][4] (range bin, Doppler bin, angle index
  * a = ay * Nax + ax, unused) as orc_cfar's cells give them; Nay = 1 for a

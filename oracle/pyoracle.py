@@ -88,6 +88,9 @@ def lib():
                                      ct.c_int, dp]
         L.orc_radar_cube2.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
                                       ct.c_int, ct.c_int, dp]
+        L.orc_angle_peaks.restype = ct.c_int
+        L.orc_angle_peaks.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ip, ct.c_int, ct.c_double, ip,
+                                      ct.c_int]
         L.orc_cloud.argtypes = [ip, ct.c_int, ct.POINTER(_Radar), ct.POINTER(_Chirp), ct.c_int, ct.c_int, dp]
         L.orc_cfar.restype = ct.c_int
         L.orc_cfar.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_double,
@@ -299,6 +302,18 @@ def cfar(X, guard=2, train=8, pfa=1e-4):
     n = lib().orc_cfar(_p(inp, ct.c_double), Na, C, S, guard, train, pfa, _p(st, ct.c_ubyte),
                        _p(am, ct.c_int), _p(pw, ct.c_double))
     return {"count": n, "status": st, "argmax": am, "power": pw}
+
+
+def angle_peaks(X, n_ax, n_ay, det, rel, max_out=1 << 20):
+    """Angle peaks of the detected cells of cube X [Nay*Nax][C][S]."""
+    X = np.asarray(X, np.complex128)
+    _, C, S = X.shape
+    inp = np.ascontiguousarray(np.stack([X.real, X.imag], -1))
+    d = np.ascontiguousarray(det, dtype=np.int32).reshape(-1, 4)
+    out = np.empty((max_out, 4), np.int32)
+    n = lib().orc_angle_peaks(_p(inp, ct.c_double), n_ax, n_ay, C, S, _p(d, ct.c_int), len(d), float(rel),
+                              _p(out, ct.c_int), max_out)
+    return out[:min(n, max_out)].copy()
 
 
 def cloud(scene, points, n_ax, n_ay=1):

@@ -26,7 +26,7 @@ SBR_LOSS_SCRATCH_BYTES = 8192
 # every function declared in include/sbr.h
 EXPORTS = ("sbr_bvh_bytes", "sbr_scratch_bytes", "sbr_build_bvh", "sbr_trace", "sbr_synth_if",
            "sbr_radar_cube", "sbr_cfar", "sbr_backward", "sbr_last_error", "sbr_loss_grad", "sbr_profile",
-           "sbr_profile_read", "sbr_radar_cube_2d", "sbr_radar_cube_2d_bytes")
+           "sbr_profile_read", "sbr_radar_cube_2d", "sbr_radar_cube_2d_bytes", "sbr_cloud")
 PROF_SYNTH, PROF_SYNTH_ADJ, PROF_TRACE = 0, 1, 2
 
 
@@ -105,6 +105,8 @@ def load(path: str = LIB_PATH):
     L.sbr_radar_cube.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
     L.sbr_radar_cube_2d.restype = ct.c_int
     L.sbr_radar_cube_2d.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.sbr_cloud.restype = ct.c_int
+    L.sbr_cloud.argtypes = [vp, vp, i32, P(sbr_radar), P(sbr_chirp), i32, i32, vp, vp]
     L.sbr_radar_cube_2d_bytes.restype = sz
     L.sbr_radar_cube_2d_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
     L.sbr_cfar.restype = ct.c_int

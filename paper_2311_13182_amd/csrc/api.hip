@@ -37,6 +37,8 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
                     int32_t flags, hipStream_t s);
 size_t cube_scratch_bytes(int V, int C, int S, int Na);
 size_t cube2_scratch_bytes(int Vx, int Vy, int C, int S, int Nax, int Nay);
+int cloud_launch(const int32_t *points, const int32_t *n_points, int32_t max_points, const RadarDev &rd,
+                 const ChirpDev &cd, int32_t n_ax, int32_t n_ay, float *out, hipStream_t s);
 int radar_cube2_launch(const float2 *in, int Vx, int Vy, int C, int S, int Nax, int Nay, int window, int dir,
                        float2 *out, void *scratch, hipStream_t s);
 size_t cfar_scratch_bytes(int C, int S);
@@ -334,6 +336,19 @@ int sbr_radar_cube_2d(const float *in, int32_t Vx, int32_t Vy, int32_t C, int32_
     }
     return radar_cube2_launch(reinterpret_cast<const float2 *>(in), Vx, Vy, C, S, n_ax, n_ay, window, direction,
                               reinterpret_cast<float2 *>(out), scratch, (hipStream_t)stream);
+}
+
+int sbr_cloud(const int32_t *points, const int32_t *n_points, int32_t max_points, const sbr_radar *radar,
+              const sbr_chirp *chirp, int32_t n_ax, int32_t n_ay, float *out, void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(radar && chirp && n_points, "radar/chirp/n_points is NULL");
+    SBR_CHECK_ARG(max_points >= 0 && (max_points == 0 || (points && out)), "points/out is NULL");
+    SBR_CHECK_ARG(n_ax >= 1 && n_ay >= 1 && n_ax <= 4096 && n_ay <= 4096, "n_ax/n_ay out of [1, 4096]");
+    SBR_CHECK_ARG(chirp->n_samples >= 1 && chirp->n_chirps >= 1 && chirp->fs > 0.0 && chirp->slope > 0.0 &&
+                      chirp->fc > 0.0 && chirp->t_chirp > 0.0,
+                  "chirp parameters must be positive");
+    return cloud_launch(points, n_points, max_points, make_radar(radar), make_chirp(chirp), n_ax, n_ay, out,
+                        (hipStream_t)stream);
 }
 
 int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard, int32_t train, double pfa,

@@ -223,7 +223,67 @@ __global__ __launch_bounds__(1024) void k_cfar_compact(const float *ratio, const
     if (t == 0) *npts = base;
 }
 
+// Detections -> world points.  Range bin r: beat frequency r f_s / S = mu tau,
+// R = c tau / 2; Doppler bin d: d / C cycles per chirp = f_c T_c taudot,
+// v = c taudot / 2; angle bins over a lambda/2 array with DFT sign -1: the
+// element phase step is -pi u, so u = -2 a_s / N with a_s the signed bin.
+struct CloudArgs {
+    const int32_t *points;
+    const int32_t *n_points;
+    int32_t max_points;
+    int32_t n_ax, n_ay;
+    double o[3], rot[9];
+    double fc, slope, fs, tc;
+    int32_t S, C;
+    float4 *out;
+};
+
+__device__ __forceinline__ double signed_bin(int a, int N) { return a >= (N + 1) / 2 ? (double)(a - N) : (double)a; }
+
+__global__ void k_cloud(CloudArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.max_points) return;
+    if (i >= min(a.n_points[0], a.max_points)) {
+        a.out[i] = make_float4(NAN, NAN, NAN, NAN);
+        return;
+    }
+    const int rb = a.points[4 * i], db = a.points[4 * i + 1], ang = a.points[4 * i + 2];
+    const double R = kC0 * (rb * a.fs / ((double)a.S * a.slope)) / 2.0;
+    const int ax = ang % a.n_ax, ay = ang / a.n_ax;
+    const double ux = -2.0 * signed_bin(ax, a.n_ax) / a.n_ax;
+    const double uy = a.n_ay > 1 ? -2.0 * signed_bin(ay, a.n_ay) / a.n_ay : 0.0;
+    const double uz2 = 1.0 - ux * ux - uy * uy;
+    const double p[3] = {R * ux, R * uy, uz2 > 0.0 ? R * sqrt(uz2) : 0.0};
+    double w[3];
+    for (int k = 0; k < 3; k++) w[k] = a.o[k] + a.rot[3 * k] * p[0] + a.rot[3 * k + 1] * p[1] + a.rot[3 * k + 2] * p[2];
+    const double tdot = signed_bin(db, a.C) / ((double)a.C * a.fc * a.tc);
+    a.out[i] = make_float4((float)w[0], (float)w[1], (float)w[2], (float)(kC0 * tdot / 2.0));
+}
+
 }  // namespace
+
+int cloud_launch(const int32_t *points, const int32_t *n_points, int32_t max_points, const RadarDev &rd,
+                 const ChirpDev &cd, int32_t n_ax, int32_t n_ay, float *out, hipStream_t s) {
+    if (max_points == 0) return SBR_OK;
+    CloudArgs a;
+    a.points = points;
+    a.n_points = n_points;
+    a.max_points = max_points;
+    a.n_ax = n_ax;
+    a.n_ay = n_ay;
+    for (int k = 0; k < 3; k++) a.o[k] = rd.o[k];
+    for (int k = 0; k < 9; k++) a.rot[k] = rd.rot[k];
+    a.fc = cd.fc;
+    a.slope = cd.slope;
+    a.fs = cd.fs;
+    a.tc = cd.tc;
+    a.S = cd.S;
+    a.C = cd.C;
+    a.out = reinterpret_cast<float4 *>(out);
+    hipLaunchKernelGGL(k_cloud, dim3((max_points + 255) / 256), dim3(256), 0, s, a);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
 
 // two staging buffers, each large enough for any intermediate of the chain
 static size_t cube_stage_elems(int Vx, int Vy, int C, int S, int Nax) {

@@ -196,6 +196,91 @@ def fit_pose(scene: S.Scene, target_cube: torch.Tensor, steps: int = 100, lr: fl
     return PoseResult(losses, omega.detach().cpu().numpy(), trans.detach().cpu().numpy(), times)
 
 
+# --------------------------------------------------------------------------- point clouds (Fig. 1)
+def chamfer_points(a: torch.Tensor, b: torch.Tensor) -> float:
+    """Symmetric Chamfer distance between two point sets [n, 3] and [m, 3]:
+    mean squared nearest-neighbour distance, both directions, summed."""
+    if len(a) == 0 or len(b) == 0:
+        return float("inf")
+    d = torch.cdist(a.double(), b.double())
+    return float((d.min(dim=1).values ** 2).mean() + (d.min(dim=0).values ** 2).mean())
+
+
+def _kabsch(p: torch.Tensor, q: torch.Tensor):
+    """Rotation R and translation t minimising sum |R p_i + t - q_i|^2."""
+    pc, qc = p.mean(0), q.mean(0)
+    H = (p - pc).T @ (q - qc)
+    U, _, Vt = torch.linalg.svd(H)
+    d = torch.sign(torch.linalg.det(Vt.T @ U.T))
+    D = torch.diag(torch.stack([torch.ones_like(d), torch.ones_like(d), d]))
+    R = Vt.T @ D @ U.T
+    return R, qc - R @ pc
+
+
+def register_rigid(src: torch.Tensor, dst: torch.Tensor, iters: int = 30, rotate: bool = True):
+    """Rigid registration of point set src onto dst: centroid alignment, then
+    point-to-point ICP (nearest neighbours + Kabsch).  Returns R [3,3], t [3]
+    with dst ~ R src + t."""
+    src, dst = src.double(), dst.double()
+    R = torch.eye(3, dtype=torch.float64, device=src.device)
+    t = dst.mean(0) - src.mean(0)
+    if rotate:
+        for _ in range(iters):
+            cur = src @ R.T + t
+            nn = torch.cdist(cur, dst).argmin(dim=1)
+            R, t = _kabsch(src, dst[nn])
+    return R, t
+
+
+def rotation_to_axis_angle(R: torch.Tensor) -> torch.Tensor:
+    c = ((torch.trace(R) - 1.0) / 2.0).clamp(-1.0, 1.0)
+    th = torch.arccos(c)
+    w = torch.stack([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    s = torch.sin(th)
+    return w * (0.5 if float(th) < 1e-6 else float(th / (2.0 * s)))
+
+
+@dataclasses.dataclass
+class CloudFitResult:
+    omega_init: np.ndarray
+    trans_init: np.ndarray
+    pose: PoseResult
+    chamfer_cloud_start: float     # template cloud vs target cloud, before registration
+    chamfer_cloud_init: float      # after point-cloud registration
+    chamfer_cloud_final: float     # after the signal-domain fit
+    n_target_points: int
+
+
+def fit_from_point_cloud(template: S.Scene, target_cube: torch.Tensor, steps: int = 60, lr: float = 2e-3,
+                         objective: str = "heatmap", device="cuda", pfa: float = 1e-4) -> CloudFitResult:
+    """Fig. 1's loop from a radar measurement: the target signal is turned
+    into a point cloud (radar cube, CA-CFAR, detections to points); the
+    template mesh is registered to it (centroid + ICP of the template's own
+    simulated cloud) to initialise its pose (Sec. 3.1, initialisation from
+    point clouds by registration), and the pose is then refined by gradient
+    descent on the signal loss (`fit_pose`)."""
+    dev = torch.device(device)
+    sim = Simulator(template, dev)
+    tgt = sim.point_cloud(target_cube, pfa=pfa)[:, :3]
+    src = sim.point_cloud(sim.forward().clone(), pfa=pfa)[:, :3]
+    c0 = chamfer_points(src, tgt)
+    R, t = register_rigid(src, tgt)
+    # the pose acts about the template's vertex centroid: x' = R (x - c) + c + trans
+    base = torch.as_tensor(template.verts, dtype=torch.float64, device=dev)
+    c = base.mean(0)
+    omega0 = rotation_to_axis_angle(R)
+    trans0 = R @ c + t - c
+    init_pts = rigid_pose(base.float(), omega0.float(), trans0.float())
+    isim = Simulator(dataclasses.replace(template, verts=init_pts.cpu().numpy()), dev)
+    c1 = chamfer_points(isim.point_cloud(isim.forward().clone(), pfa=pfa)[:, :3], tgt)
+    res = fit_pose(template, target_cube, steps=steps, lr=lr, omega0=tuple(omega0.tolist()),
+                   trans0=tuple(trans0.tolist()), objective=objective, device=device)
+    fin = rigid_pose(base.float(), torch.as_tensor(res.omega, device=dev), torch.as_tensor(res.trans, device=dev))
+    fsim = Simulator(dataclasses.replace(template, verts=fin.cpu().numpy()), dev)
+    c2 = chamfer_points(fsim.point_cloud(fsim.forward().clone(), pfa=pfa)[:, :3], tgt)
+    return CloudFitResult(omega0.cpu().numpy(), trans0.cpu().numpy(), res, c0, c1, c2, int(len(tgt)))
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="mesh reconstruction from a simulated IF cube")

@@ -188,6 +188,13 @@ def sbr_radar_cube_2d(x: torch.Tensor, vx: int, vy: int, C: int, Sn: int, n_ax: 
                                      scratch.numel() * scratch.element_size(), _stream()))
 
 
+def sbr_cloud(points: torch.Tensor, n_points: torch.Tensor, radar: S.Radar, chirp: S.Chirp, n_ax: int, n_ay: int,
+              out: torch.Tensor):
+    r, c = radar_struct(radar), chirp_struct(chirp)
+    L.check(_lib().sbr_cloud(_p(points), _p(n_points), int(points.shape[0]), ct.byref(r), ct.byref(c), n_ax, n_ay,
+                             _p(out), _stream()))
+
+
 def sbr_radar_cube(x: torch.Tensor, V: int, C: int, Sn: int, n_angle: int, window: int, direction: int,
                    out: torch.Tensor, scratch: torch.Tensor):
     L.check(_lib().sbr_radar_cube(_p(x), V, C, Sn, n_angle, window, direction, _p(out), _p(scratch),
@@ -330,6 +337,24 @@ class Simulator:
         n = torch.zeros(1, dtype=torch.int32, device=self.device)
         sbr_cfar(xf, int(xf.shape[0]), self.C, self.S, guard, train, pfa, pts, ratio, n, self.scratch)
         return pts, ratio, n
+
+    def cloud(self, points: torch.Tensor, n_points: torch.Tensor) -> torch.Tensor:
+        """CFAR detections ([max_points, 4] int32 + device count) of this
+        simulator's radar cube -> world points [max_points, 4] (x, y, z,
+        radial velocity); rows past the count are NaN."""
+        out = torch.empty((points.shape[0], 4), dtype=torch.float32, device=self.device)
+        n_ax, n_ay = (self.n_ax, self.n_ay) if self.planar else (self.n_angle, 1)
+        sbr_cloud(points, n_points, self.scene.radar, self.scene.chirp, n_ax, n_ay, out)
+        return out
+
+    def point_cloud(self, cube: torch.Tensor, guard: int = 2, train: int = 8, pfa: float = 1e-4,
+                    max_points: int = 65536, window: int = 0) -> torch.Tensor:
+        """IF cube -> radar cube -> CA-CFAR -> world points [n, 4] (the
+        point cloud a radar reports)."""
+        X = self.radar_cube(cube, window=window)
+        pts, _, n = self.cfar(X, guard, train, pfa, max_points)
+        xyz = self.cloud(pts, n)
+        return xyz[: min(int(n.item()), max_points)]
 
     def backward(self, grad_if: torch.Tensor, grad_verts: Optional[torch.Tensor] = None,
                  grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,

@@ -466,3 +466,47 @@ def test_cloud_maps_peak_back_to_target(orc, planar):
     assert abs(ue[0] - ut[0]) <= du and (not planar or abs(ue[1] - ut[1]) <= 2.0 / n_ay)
     dv = C0 / (2.0 * ch.n_chirps * ch.fc * ch.t_chirp)         # Doppler bin in m/s
     assert abs(xyzv[3] - float(vel @ ut)) <= dv
+
+
+def _np_angle_peaks(X, n_ax, n_ay, det, rel):
+    out = []
+    for r, d, _, _ in det:
+        q = np.abs(X[:, d, r]) ** 2
+        qm = q.max()
+        for a in range(n_ax * n_ay):
+            if not (q[a] >= rel * qm) or q[a] <= 0:
+                continue
+            ax, ay = a % n_ax, a // n_ax
+            ok = True
+            for dy in ((-1, 0, 1) if n_ay > 1 else (0,)):
+                for dx in (-1, 0, 1):
+                    b = ((ay + dy) % n_ay) * n_ax + (ax + dx) % n_ax
+                    if b == a:
+                        continue
+                    ok &= (q[a] > q[b]) if b < a else (q[a] >= q[b])
+            if ok:
+                out.append((r, d, a, 0))
+    return np.array(out, np.int32).reshape(-1, 4)
+
+
+@pytest.mark.parametrize("n_ax,n_ay", [(16, 1), (8, 6)])
+def test_angle_peaks_vs_numpy_and_planted(orc, n_ax, n_ay):
+    rng = np.random.default_rng(5)
+    C, S_ = 4, 12
+    X = rng.normal(size=(n_ax * n_ay, C, S_)) + 1j * rng.normal(size=(n_ax * n_ay, C, S_))
+    det = np.array([[r, d, 0, 0] for d in range(C) for r in range(0, S_, 3)], np.int32)
+    for rel in (0.0, 0.3):
+        got = orc.angle_peaks(X, n_ax, n_ay, det, rel)
+        assert np.array_equal(got, _np_angle_peaks(X, n_ax, n_ay, det, rel))
+    # planted: two Gaussian bumps in one cell's angle spectrum (smooth, so no
+    # other local maxima), the weaker at 40 % power
+    Y = np.zeros_like(X)
+    ax = np.arange(n_ax)[None, :]
+    ay = np.arange(n_ay)[:, None]
+    bump = lambda cx, cy, w: np.exp(-0.5 * (((ax - cx) / 1.2) ** 2 + ((ay - cy) / 1.2) ** 2)) * w
+    img = bump(3, min(2, n_ay - 1), 1.0) + bump(11 if n_ay == 1 else 6, n_ay - 1 if n_ay > 1 else 0, np.sqrt(0.4))
+    Y[:, 1, 5] = img.reshape(-1)
+    got = orc.angle_peaks(Y, n_ax, n_ay, [[5, 1, 0, 0]], 0.3)
+    want = sorted([min(2, n_ay - 1) * n_ax + 3, (n_ay - 1) * n_ax + (11 if n_ay == 1 else 6)])
+    assert got[:, 2].tolist() == want
+    assert len(orc.angle_peaks(Y, n_ax, n_ay, [[5, 1, 0, 0]], 0.5)) == 1
