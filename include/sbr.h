@@ -243,6 +243,24 @@ int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard,
              int32_t train, double pfa, int32_t *points, float *ratio, int32_t max_points,
              int32_t *n_points, void *scratch, size_t scratch_bytes, void *stream);
 
+/* Angle peaks of detected range-Doppler cells, the several scatterers per
+ * cell a radar's angle search reports.  For each detection i < min(*n_det,
+ * max_det) (det: device int32 [max_det][4] as sbr_cfar writes them) its angle
+ * spectrum q[a] = |X[a][d][r]|^2 (cube [n_ay*n_ax][C][S][2]) is searched for
+ * local maxima over the circular angle grid (ring if n_ay = 1, else the
+ * 8-neighbourhood on the n_ay x n_ax torus; among equal neighbours the lower
+ * index wins) holding at least rel (0..1) of the cell's largest q.  points:
+ * device int32 [max_points][4] = (range bin, Doppler bin, angle index, 0),
+ * detection-major, angle ascending; n_points: device int32 total (may exceed
+ * max_points).  scratch: sbr_angle_peaks_bytes(max_det, n_ax, n_ay). */
+int sbr_angle_peaks(const float *cube, int32_t n_ax, int32_t n_ay, int32_t C, int32_t S,
+                    const int32_t *det, const int32_t *n_det, int32_t max_det, float rel,
+                    int32_t *points, int32_t max_points, int32_t *n_points, void *scratch,
+                    size_t scratch_bytes, void *stream);
+
+/* Scratch bytes of sbr_angle_peaks; 0 for invalid sizes. */
+size_t sbr_angle_peaks_bytes(int32_t max_det, int32_t n_ax, int32_t n_ay);
+
 /* Radar point cloud: CFAR detections to world points (Sec. 4: the radars
  * output point clouds; Fig. 1 initialises the scene from them).  points:
  * device int32 [max_points][4] as sbr_cfar writes them; n_points: device

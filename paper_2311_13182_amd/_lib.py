@@ -26,7 +26,8 @@ SBR_LOSS_SCRATCH_BYTES = 8192
 # every function declared in include/sbr.h
 EXPORTS = ("sbr_bvh_bytes", "sbr_scratch_bytes", "sbr_build_bvh", "sbr_trace", "sbr_synth_if",
            "sbr_radar_cube", "sbr_cfar", "sbr_backward", "sbr_last_error", "sbr_loss_grad", "sbr_profile",
-           "sbr_profile_read", "sbr_radar_cube_2d", "sbr_radar_cube_2d_bytes", "sbr_cloud")
+           "sbr_profile_read", "sbr_radar_cube_2d", "sbr_radar_cube_2d_bytes", "sbr_cloud",
+           "sbr_angle_peaks", "sbr_angle_peaks_bytes")
 PROF_SYNTH, PROF_SYNTH_ADJ, PROF_TRACE = 0, 1, 2
 
 
@@ -105,6 +106,10 @@ def load(path: str = LIB_PATH):
     L.sbr_radar_cube.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
     L.sbr_radar_cube_2d.restype = ct.c_int
     L.sbr_radar_cube_2d.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.sbr_angle_peaks.restype = ct.c_int
+    L.sbr_angle_peaks.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, ct.c_float, vp, i32, vp, vp, sz, vp]
+    L.sbr_angle_peaks_bytes.restype = sz
+    L.sbr_angle_peaks_bytes.argtypes = [i32, i32, i32]
     L.sbr_cloud.restype = ct.c_int
     L.sbr_cloud.argtypes = [vp, vp, i32, P(sbr_radar), P(sbr_chirp), i32, i32, vp, vp]
     L.sbr_radar_cube_2d_bytes.restype = sz

