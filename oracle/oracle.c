@@ -53,11 +53,37 @@ static void to_world(const orc_radar *rd, const double p[3], double o[3]) {
         o[i] = rd->origin[i] + rd->rot[3 * i] * p[0] + rd->rot[3 * i + 1] * p[1] + rd->rot[3 * i + 2] * p[2];
 }
 
-/* ---------- ray launch (Eq. 3 estimator on a uniform tangent grid) ---------- */
+/* ---------- Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) ----------
+ * Counter-based generator: ten rounds of two 32x32->64 multiplications with
+ * the published constants, the key bumped by the Weyl constants each round. */
+void orc_philox4x32_10(const unsigned int ctr[4], const unsigned int key[2], unsigned int out[4]) {
+    unsigned int x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; r++) {
+        unsigned long long p0 = 0xD2511F53ull * x0, p1 = 0xCD9E8D57ull * x2;
+        unsigned int n0 = (unsigned int)(p1 >> 32) ^ x1 ^ k0, n1 = (unsigned int)p1;
+        unsigned int n2 = (unsigned int)(p0 >> 32) ^ x3 ^ k1, n3 = (unsigned int)p0;
+        x0 = n0; x1 = n1; x2 = n2; x3 = n3;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ---------- ray launch (Eq. 3 / Eq. 4 estimator on the tangent grid) ----------
+ * Without jitter the sample of cell (ix, iy) is its centre.  With jitter it is
+ * uniform in the cell (stratified Monte Carlo, Eq. 4): offsets u1 - 1/2 and
+ * u2 - 1/2 of the cell size from Philox-4x32-10 with counter (r, 0, 0, 0) and
+ * key (seed_lo, seed_hi), u = (word >> 8) / 2^24 for the first two words. */
 void orc_ray(const orc_radar *rd, const orc_grid *g, int r, double o[3], double d[3], double *domega) {
     int ix = r % g->nx, iy = r / g->nx;
-    double u = g->tan_hx * (2.0 * (ix + 0.5) / g->nx - 1.0);
-    double v = g->tan_hy * (2.0 * (iy + 0.5) / g->ny - 1.0);
+    double jx = 0.5, jy = 0.5;
+    if (g->jitter) {
+        unsigned int ctr[4] = {(unsigned int)r, 0u, 0u, 0u}, key[2] = {g->seed_lo, g->seed_hi}, w[4];
+        orc_philox4x32_10(ctr, key, w);
+        jx = (double)(w[0] >> 8) / 16777216.0;
+        jy = (double)(w[1] >> 8) / 16777216.0;
+    }
+    double u = g->tan_hx * (2.0 * (ix + jx) / g->nx - 1.0);
+    double v = g->tan_hy * (2.0 * (iy + jy) / g->ny - 1.0);
     double q = 1.0 + u * u + v * v;
     double s = 1.0 / sqrt(q);
     double dr[3] = {u * s, v * s, s};
@@ -65,7 +91,7 @@ void orc_ray(const orc_radar *rd, const orc_grid *g, int r, double o[3], double 
         o[i] = rd->origin[i];
         d[i] = rd->rot[3 * i] * dr[0] + rd->rot[3 * i + 1] * dr[1] + rd->rot[3 * i + 2] * dr[2];
     }
-    /* solid angle of one grid cell: (cell area on the z=1 plane) * cos / dist^2 */
+    /* solid angle of one grid cell at its sample: (cell area on the z=1 plane) * cos / dist^2 */
     if (domega) *domega = (2.0 * g->tan_hx / g->nx) * (2.0 * g->tan_hy / g->ny) / (q * sqrt(q));
 }
 

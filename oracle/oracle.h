@@ -15,7 +15,8 @@
  * z = boresight.  Virtual antenna index v = t * n_rx + m.
  *
  * Parity status (what pins each function; the tests under tests/ hold them):
- *   orc_ray            closed-form solid angle of the grid, boresight symmetry
+ *   orc_ray            closed-form solid angle of the grid, boresight symmetry;
+ *                      jitter: Philox known-answer vectors, unbiased solid angle
  *   orc_trace          independent NumPy brute force, trihedral and plate
  *                      closed forms, energy invariant; shadow test: no
  *                      occlusion inside a convex room, independent NumPy
@@ -85,6 +86,8 @@ typedef struct {
     int shadow;              /* 1: test the return segment of every hit after
                                 the first for occlusion (any hit strictly
                                 between it and the array centre)              */
+    int jitter;              /* 1: stratified Monte Carlo sample per cell      */
+    unsigned int seed_lo, seed_hi;   /* Philox key of the jitter              */
 } orc_grid;
 
 /* hit flags, one byte per (bounce, ray) */
@@ -99,7 +102,11 @@ typedef struct {
 #define ORC_DROP_FLAGGED 1 /* skip records with any flag other than OCCLUDED     */
 #define ORC_EXIT_ONLY    2 /* only the last hit of each ray returns              */
 
-/* Ray r = iy * nx + ix of the grid: origin, unit direction, solid-angle weight. */
+/* Philox-4x32-10 counter-based generator (Salmon et al., SC 2011). */
+void orc_philox4x32_10(const unsigned int ctr[4], const unsigned int key[2], unsigned int out[4]);
+
+/* Ray r = iy * nx + ix of the grid: origin, unit direction, solid-angle weight
+ * (cell centre, or with g->jitter a Philox-drawn point of the cell). */
 void orc_ray(const orc_radar *rd, const orc_grid *g, int r,
              double o[3], double d[3], double *domega);
 

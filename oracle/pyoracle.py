@@ -58,7 +58,7 @@ class _Chirp(ct.Structure):
 class _Grid(ct.Structure):
     _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("tan_hx", ct.c_double),
                 ("tan_hy", ct.c_double), ("max_bounces", ct.c_int), ("t_min", ct.c_double),
-                ("shadow", ct.c_int)]
+                ("shadow", ct.c_int), ("jitter", ct.c_int), ("seed_lo", ct.c_uint), ("seed_hi", ct.c_uint)]
 
 
 _lib = None
@@ -70,6 +70,7 @@ def lib():
         build()
         L = ct.CDLL(LIB_PATH)
         dp, ip, bp = ct.POINTER(ct.c_double), ct.POINTER(ct.c_int), ct.POINTER(ct.c_ubyte)
+        L.orc_philox4x32_10.argtypes = [ct.POINTER(ct.c_uint), ct.POINTER(ct.c_uint), ct.POINTER(ct.c_uint)]
         L.orc_ray.argtypes = [ct.POINTER(_Radar), ct.POINTER(_Grid), ct.c_int, dp, dp, dp]
         L.orc_trace.restype = ct.c_longlong
         L.orc_trace.argtypes = [ct.POINTER(_Mesh), ct.POINTER(_Radar), ct.POINTER(_Grid), ip,
@@ -157,7 +158,17 @@ def _chirp(ch):
 
 
 def _grid(g):
-    return _Grid(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces, g.t_min, int(getattr(g, "shadow", False)))
+    seed = getattr(g, "jitter_seed", None)
+    return _Grid(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces, g.t_min, int(getattr(g, "shadow", False)),
+                 int(seed is not None), (seed or 0) & 0xFFFFFFFF, ((seed or 0) >> 32) & 0xFFFFFFFF)
+
+
+def philox4x32_10(ctr, key):
+    c = (ct.c_uint * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ct.c_uint * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ct.c_uint * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
 
 
 def ray(scene, r):

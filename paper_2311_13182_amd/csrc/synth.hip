@@ -1,5 +1,10 @@
 // Path stage (FP64 refinement of every hit into I^t / I^s, compacted in
 // ray-major order) and the IF synthesis of Eq. (8).
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "sbr_internal.h"
 #include "sbr_device.h"
 
@@ -363,16 +368,56 @@ int fill_zero_f32(float *p, size_t n, hipStream_t s) {
 
 constexpr int kSynthL = 64;   // samples per lane (128 measured slower: occupancy 1)
 
+// Blocks of 256 threads of k_synth<L> the device holds at once: CUs times the
+// occupancy of the compiled kernel, queried once per (device, L); 256 CUs x 3
+// where the runtime cannot answer (no device in this process).
+static int resident_synth_blocks(int L) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 256 * 3;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({dev, L});
+    if (it != cache.end()) return it->second;
+    int cus = 0, nb = 0;
+    hipError_t e1 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e2;
+    if (L == 128)
+        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth<128>, 256, 0);
+    else if (L == 64)
+        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth<64>, 256, 0);
+    else if (L == 32)
+        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth<32>, 256, 0);
+    else
+        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth<16>, 256, 0);
+    int res = 256 * 3;
+    if (e1 == hipSuccess && e2 == hipSuccess && cus > 0 && nb > 0) res = cus * nb;
+    else (void)hipGetLastError();
+    cache[{dev, L}] = res;
+    return res;
+}
+
+// Paths are split into n_chunks chunks (grid.y).  Every wave of the grid does
+// the same work, so the chunk count is chosen to make the grid a whole number
+// of device-fulls of resident blocks (about 16k waves in all): a partly filled
+// last round leaves most of the chip idle for one wave's run time.
 SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
     SynthPlan p;
     p.L = S >= kSynthL ? kSynthL : (S >= 64 ? 64 : (S >= 32 ? 32 : 16));
     p.SB = (S + p.L - 1) / p.L;
     p.tiles_per_v = (C * p.SB + 63) / 64;
     long long waves = (long long)V * p.tiles_per_v;
+    long long grid_x = (waves + 3) / 4;
     long long cap = (long long)R * K;
     long long want = (16384 + waves - 1) / waves;
     long long maxc = (cap + 63) / 64;
-    p.n_chunks = (int32_t)std::max(1LL, std::min(std::min(want, maxc), 1024LL));
+    const long long res = resident_synth_blocks(p.L);
+    long long rounds = std::max(1LL, (long long)std::llround((double)want * grid_x / res));
+    long long nch = (rounds * res + grid_x - 1) / grid_x;
+    p.n_chunks = (int32_t)std::max(1LL, std::min(std::min(nch, maxc), 1024LL));
     return p;
 }
 

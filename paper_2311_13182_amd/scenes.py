@@ -43,6 +43,7 @@ class Grid:
     max_bounces: int = 3
     t_min: float = 1e-5
     shadow: bool = False          # occlusion test of every return after the first bounce
+    jitter_seed: Optional[int] = None   # stratified Monte Carlo sample per cell (Eq. 4), 64-bit Philox key
 
     @property
     def n_rays(self) -> int:

@@ -510,3 +510,40 @@ def test_angle_peaks_vs_numpy_and_planted(orc, n_ax, n_ay):
     want = sorted([min(2, n_ay - 1) * n_ax + 3, (n_ay - 1) * n_ax + (11 if n_ay == 1 else 6)])
     assert got[:, 2].tolist() == want
     assert len(orc.angle_peaks(Y, n_ax, n_ay, [[5, 1, 0, 0]], 0.5)) == 1
+
+
+# ------------------------------------------------------------------------------ Monte Carlo jitter (Eq. 4)
+def test_philox_known_answers(orc):
+    """Philox-4x32-10 against the published known-answer vectors."""
+    assert orc.philox4x32_10([0, 0, 0, 0], [0, 0]) == [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]
+    f = 0xFFFFFFFF
+    assert orc.philox4x32_10([f, f, f, f], [f, f]) == [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]
+    assert orc.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0]) == \
+        [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+
+
+def test_jittered_grid_is_an_unbiased_solid_angle_estimator(orc):
+    """With a jittered sample per cell, the summed weights estimate the
+    pyramid's solid angle without bias: the mean over seeds matches the closed
+    form, single seeds scatter, samples stay inside their cells."""
+    a = math.radians(15.0)
+    exact = 4.0 * math.asin(math.sin(a) * math.sin(a))
+    n = 8
+    base = S.trihedral_plate().with_grid(nx=n, ny=n)
+    tots = []
+    for seed in range(200):
+        sc = base.with_grid(jitter_seed=seed * 7919 + 1)
+        tots.append(sum(orc.ray(sc, r)[2] for r in range(n * n)))
+    tots = np.array(tots)
+    assert tots.std() > 1e-5
+    assert abs(tots.mean() - exact) <= 4.0 * tots.std() / math.sqrt(len(tots))
+    # the same seed reproduces; the sample lies in its cell
+    sc = base.with_grid(jitter_seed=12345)
+    r1, r2 = orc.ray(sc, 9), orc.ray(sc, 9)
+    assert all(np.array_equal(x, y) for x, y in zip(r1, r2))
+    assert not np.array_equal(r1[1], orc.ray(base, 9)[1])
+    _, d, _ = orc.ray(sc, 9)
+    tx, ty = d[0] / d[2], d[1] / d[2]
+    cell = 2 * math.tan(a) / n
+    assert -math.tan(a) + 1 * cell <= tx <= -math.tan(a) + 2 * cell
+    assert -math.tan(a) + 1 * cell <= ty <= -math.tan(a) + 2 * cell
