@@ -104,6 +104,7 @@ typedef struct {
     int32_t max_bounces;     /* K, 1..8                                          */
     int32_t options;         /* SBR_RAYS_* bits (0 = none)                       */
     double t_min;            /* hits closer than this are ignored, metres        */
+    uint32_t seed_lo, seed_hi;   /* Philox key of SBR_RAYS_JITTER                */
 } sbr_rays;
 
 /* sbr_rays.options */
@@ -113,6 +114,15 @@ typedef struct {
                                 t in (t_min, D - t_min) along the segment of length D
                                 from the hit point to the array centre sets
                                 SBR_HIT_OCCLUDED.  Any-hit traversal, early exit. */
+#define SBR_RAYS_JITTER 2    /* stratified Monte Carlo sampling (Sec. 3.2.1, Eq. 4):
+                                the sample of cell (ix, iy) is uniform in the cell
+                                instead of its centre, offsets (u1 - 1/2, u2 - 1/2)
+                                cells with u = (w >> 8) / 2^24 of the first two words
+                                of Philox-4x32-10 (Salmon et al., SC 2011) at counter
+                                (iy * nx + ix, 0, 0, 0), key (seed_lo, seed_hi); the
+                                weight is the cell's solid-angle density at the
+                                sample.  Every entry point given the same sbr_rays
+                                draws the same samples. */
 
 /* Closest-hit records, structure of arrays, each [K][nx*ny] (device). */
 typedef struct {

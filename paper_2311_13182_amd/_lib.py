@@ -16,7 +16,7 @@ SBR_OK, SBR_E_ARG, SBR_E_HIP, SBR_E_SCRATCH, SBR_E_UNSUPPORTED = 0, -1, -2, -3, 
 SBR_MAX_BOUNCES, SBR_MAX_TX, SBR_MAX_RX, SBR_MAX_VIRTUAL, SBR_MAX_MATERIALS = 8, 20, 20, 400, 64
 SBR_HIT_EDGE, SBR_HIT_TIE, SBR_HIT_GRAZE, SBR_HIT_TMIN, SBR_HIT_PARENT = 1, 2, 4, 8, 16
 SBR_HIT_OCCLUDED = 32
-SBR_RAYS_SHADOW = 1
+SBR_RAYS_SHADOW, SBR_RAYS_JITTER = 1, 2
 SBR_DROP_FLAGGED = 1
 SBR_ATTACHED = 2
 SBR_EXIT_ONLY = 4
@@ -60,7 +60,7 @@ class sbr_chirp(ct.Structure):
 class sbr_rays(ct.Structure):
     _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("tan_half_x", ct.c_double),
                 ("tan_half_y", ct.c_double), ("max_bounces", ct.c_int32), ("options", ct.c_int32),
-                ("t_min", ct.c_double)]
+                ("t_min", ct.c_double), ("seed_lo", ct.c_uint32), ("seed_hi", ct.c_uint32)]
 
 
 class sbr_param_grads(ct.Structure):

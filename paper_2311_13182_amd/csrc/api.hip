@@ -75,7 +75,8 @@ static int check_rays(const sbr_rays *g) {
     SBR_CHECK_ARG((long long)g->nx * g->ny <= (1LL << 26), "grid too large (%d x %d)", g->nx, g->ny);
     SBR_CHECK_ARG(g->max_bounces >= 1 && g->max_bounces <= SBR_MAX_BOUNCES, "max_bounces=%d out of [1,%d]",
                   g->max_bounces, SBR_MAX_BOUNCES);
-    SBR_CHECK_ARG((g->options & ~SBR_RAYS_SHADOW) == 0, "unknown sbr_rays.options bits 0x%x", g->options);
+    SBR_CHECK_ARG((g->options & ~(SBR_RAYS_SHADOW | SBR_RAYS_JITTER)) == 0, "unknown sbr_rays.options bits 0x%x",
+                  g->options);
     SBR_CHECK_ARG(g->tan_half_x > 0 && g->tan_half_y > 0, "grid half-widths must be positive");
     SBR_CHECK_ARG(g->t_min >= 0, "t_min must be >= 0");
     return SBR_OK;
@@ -155,6 +156,8 @@ GridDev make_grid(const sbr_rays *g) {
     d.ny = g->ny;
     d.K = g->max_bounces;
     d.options = g->options;
+    d.seed_lo = g->seed_lo;
+    d.seed_hi = g->seed_hi;
     d.thx = g->tan_half_x;
     d.thy = g->tan_half_y;
     d.t_min = g->t_min;

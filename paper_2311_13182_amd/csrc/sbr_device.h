@@ -87,10 +87,39 @@ __device__ inline cd reflect_deps(const MatTable &mt, int mi, double fc, double 
     return cdivz(num, cmul(den, den));
 }
 
-// Unit direction of grid cell (ix, iy) in the radar frame and its solid angle.
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
+// 32 x 32 -> 64-bit products with the published multipliers, the key bumped by
+// the Weyl constants after each round.  Words 0 and 1 of the output.
+__device__ __forceinline__ void philox2(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                                        uint32_t *w0, uint32_t *w1) {
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        const uint32_t h0 = __umulhi(0xD2511F53u, c0), l0 = 0xD2511F53u * c0;
+        const uint32_t h1 = __umulhi(0xCD9E8D57u, c2), l1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = l1;
+        c2 = n2;
+        c3 = l0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    *w0 = c0;
+    *w1 = c1;
+}
+
+// Unit direction of grid cell (ix, iy) in the radar frame and its solid angle:
+// at the cell centre, or with SBR_RAYS_JITTER at a Philox-drawn point of it.
 __device__ __forceinline__ void grid_dir_local(const GridDev &g, int ix, int iy, double dr[3], double *dw) {
-    double u = g.thx * (2.0 * (ix + 0.5) / g.nx - 1.0);
-    double v = g.thy * (2.0 * (iy + 0.5) / g.ny - 1.0);
+    double jx = 0.5, jy = 0.5;
+    if (g.options & SBR_RAYS_JITTER) {
+        uint32_t w0, w1;
+        philox2((uint32_t)(iy * g.nx + ix), 0u, 0u, 0u, g.seed_lo, g.seed_hi, &w0, &w1);
+        jx = (double)(w0 >> 8) * (1.0 / 16777216.0);
+        jy = (double)(w1 >> 8) * (1.0 / 16777216.0);
+    }
+    double u = g.thx * (2.0 * (ix + jx) / g.nx - 1.0);
+    double v = g.thy * (2.0 * (iy + jy) / g.ny - 1.0);
     double q = 1.0 + u * u + v * v;
     double s = 1.0 / sqrt(q);
     dr[0] = u * s;

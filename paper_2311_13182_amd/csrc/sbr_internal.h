@@ -116,6 +116,7 @@ struct RadarDev {
 struct GridDev {
     int32_t nx, ny, K, options;
     double thx, thy, t_min;
+    uint32_t seed_lo, seed_hi;
 };
 
 struct ChirpDev {

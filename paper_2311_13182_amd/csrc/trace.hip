@@ -1,6 +1,7 @@
 // Ray launch + stackless BVH traversal + watertight ray-triangle test +
 // specular multi-bounce, one lane per ray, 8x8 ray tiles per wavefront.
 #include "sbr_internal.h"
+#include "sbr_device.h"
 
 namespace sbr {
 
@@ -132,10 +133,8 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         const size_t R = (size_t)a.g.nx * a.g.ny;
         const size_t r = (size_t)iy * a.g.nx + ix;
         // ray of the grid, formed in double and rounded once
-        double u = a.g.thx * (2.0 * (ix + 0.5) / a.g.nx - 1.0);
-        double w = a.g.thy * (2.0 * (iy + 0.5) / a.g.ny - 1.0);
-        double s = 1.0 / sqrt(1.0 + u * u + w * w);
-        double dr[3] = {u * s, w * s, s};
+        double dr[3], dw_unused;
+        grid_dir_local(a.g, ix, iy, dr, &dw_unused);
         float3 d, o;
         d.x = (float)(a.rot[0] * dr[0] + a.rot[1] * dr[1] + a.rot[2] * dr[2]);
         d.y = (float)(a.rot[3] * dr[0] + a.rot[4] * dr[1] + a.rot[5] * dr[2]);

@@ -85,7 +85,7 @@ class ReconResult:
 def reconstruct(start: S.Scene, target: S.Scene, steps: int = 200, lr: float = 1e-3,
                 rebuild_every: int = 20, device="cuda", log_every: int = 0, objective: str = "heatmap",
                 lam_scale: float = 0.1, checkpoint: Optional[str] = None, resume: Optional[str] = None,
-                attached: bool = False) -> ReconResult:
+                attached: bool = False, mc_seed: Optional[int] = None) -> ReconResult:
     dev = torch.device(device)
     sim = Simulator(start, dev)
     # target signal (untimed)
@@ -131,6 +131,8 @@ def reconstruct(start: S.Scene, target: S.Scene, steps: int = 200, lr: float = 1
         t0 = time.perf_counter()
         verts = base + offsets
         refit = (it % rebuild_every) != 0
+        if mc_seed is not None:   # fresh stratified Monte Carlo samples each step (Eq. 4)
+            sim.scene = sim.scene.with_grid(jitter_seed=(mc_seed << 20) + it)
         cube = SBRFunction.apply(verts, sim, refit, attached)
         data = data_term(cube)
         total = data + lam * uniform_laplacian(offsets, edges, degt)
@@ -160,7 +162,8 @@ class PoseResult:
 
 def fit_pose(scene: S.Scene, target_cube: torch.Tensor, steps: int = 100, lr: float = 2e-3,
              omega0=(0.0, 0.0, 0.0), trans0=(0.0, 0.0, 0.0), objective: str = "heatmap",
-             device="cuda", rebuild_every: int = 20, attached: bool = False) -> PoseResult:
+             device="cuda", rebuild_every: int = 20, attached: bool = False,
+             mc_seed: Optional[int] = None) -> PoseResult:
     """Object pose from a radar IF cube (the object-transform parameterisation
     of Sec. 3.1 (i) driven by the loss of Eqs. 14/16): the mesh of `scene` is
     posed by exp([omega]x) about its centroid plus a translation, and Adam
@@ -182,6 +185,8 @@ def fit_pose(scene: S.Scene, target_cube: torch.Tensor, steps: int = 100, lr: fl
     losses, times = [], []
     for it in range(steps):
         t0 = time.perf_counter()
+        if mc_seed is not None:   # fresh stratified Monte Carlo samples each step (Eq. 4)
+            sim.scene = sim.scene.with_grid(jitter_seed=(mc_seed << 20) + it)
         cube = SBRFunction.apply(rigid_pose(base, omega, trans), sim, (it % rebuild_every) != 0, attached)
         if objective == "heatmap":
             loss = HeatmapLoss.apply(RadarCubeFunction.apply(cube, sim, 0), tgt, sim, 1.0 / tnorm)

@@ -59,8 +59,10 @@ def chirp_struct(c: S.Chirp) -> L.sbr_chirp:
 
 
 def rays_struct(g: S.Grid) -> L.sbr_rays:
-    return L.sbr_rays(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces,
-                      L.SBR_RAYS_SHADOW if getattr(g, "shadow", False) else 0, g.t_min)
+    seed = getattr(g, "jitter_seed", None)
+    opts = (L.SBR_RAYS_SHADOW if getattr(g, "shadow", False) else 0) | (L.SBR_RAYS_JITTER if seed is not None else 0)
+    return L.sbr_rays(g.nx, g.ny, g.tan_hx, g.tan_hy, g.max_bounces, opts, g.t_min, (seed or 0) & 0xFFFFFFFF,
+                      ((seed or 0) >> 32) & 0xFFFFFFFF)
 
 
 def materials_struct(mats: Sequence[Tuple[int, float, float]]):

@@ -737,3 +737,31 @@ def test_planar_cube_peak_at_target_direction(torch_cuda):
     dx = min((ax - want_x) % sim.n_ax, (want_x - ax) % sim.n_ax)
     dy = min((ay - want_y) % sim.n_ay, (want_y - ay) % sim.n_ay)
     assert dx <= 1 and dy <= 1
+
+
+# ----------------------------------------------------------------- Monte Carlo jitter (Eq. 4)
+def test_jittered_grid_trace_synth_backward(torch_cuda, orc):
+    """SBR_RAYS_JITTER: the GPU draws the same Philox samples as the oracle
+    (trace ids and distances, IF cube, vertex gradient vs central
+    differences)."""
+    import torch
+    sc = S.trihedral_plate().with_grid(jitter_seed=0x1234_5678_9ABC)
+    sim = _sim(sc)
+    sim.build()
+    sim.trace()
+    torch.cuda.synchronize()
+    o = orc.trace(sc)
+    n_ok, n_fl = compare_trace(_gpu_hits_np(sim), o)
+    o0 = orc.trace(S.trihedral_plate())
+    assert not np.array_equal(o["t"], o0["t"])                  # the samples moved
+    p = orc.paths(sc, o["tri"], o["flags"])
+    want = orc.synth(sc, p)
+    sim.hits = device_hits_from_oracle(o)
+    e = rel_l2(_cube_np(sim.synth()), want)
+    tgt = _target(orc, sc, 1e-3, 17)
+    G = 2.0 * (orc.synth(sc, p) - tgt)
+    got = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda")).cpu().numpy().astype(np.float64)
+    fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, h=1e-9).reshape(-1, 3)
+    eg = rel_l2(got, fd)
+    log(f"jitter: {n_ok} hits checked, synth rel L2 {e:.3e}, backward rel L2 {eg:.3e}")
+    assert n_ok > 0.9 * (o["tri"] >= 0).sum() and e <= 1e-4 and eg <= GRAD_TOL
