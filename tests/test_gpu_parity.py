@@ -765,3 +765,30 @@ def test_jittered_grid_trace_synth_backward(torch_cuda, orc):
     eg = rel_l2(got, fd)
     log(f"jitter: {n_ok} hits checked, synth rel L2 {e:.3e}, backward rel L2 {eg:.3e}")
     assert n_ok > 0.9 * (o["tri"] >= 0).sum() and e <= 1e-4 and eg <= GRAD_TOL
+
+
+def test_maximum_grid_size(torch_cuda, orc):
+    """The largest grid the library accepts (2^26 rays = 8192^2, two bounces):
+    every 97th ray's hits against the oracle, then the IF cube of all paths
+    on the oracle's hit records against the oracle's direct sum."""
+    import torch
+    v, f = S.plate(0.08, 1.0)
+    sc = S.Scene("plate_max_grid", v.astype(np.float32), f.astype(np.int32), S.default_radar(3, 4),
+                 S.Chirp(n_samples=32, n_chirps=2), S.Grid(8192, 8192, 0.35, 0.35, 2))
+    log(f"max grid: {sc.grid.n_rays} rays, K=2")
+    sim = _sim(sc)
+    sim.build()
+    sim.trace()
+    torch.cuda.synchronize()
+    rays = np.arange(0, sc.grid.n_rays, 97, dtype=np.int32)
+    o_s = orc.trace(sc, rays=rays)
+    n_ok, n_fl = compare_trace(_gpu_hits_np(sim), o_s, rays=rays)
+    log(f"  sampled trace: {n_ok} hits checked, {n_fl} flagged")
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    want = orc.synth(sc, p)
+    sim.hits = device_hits_from_oracle(o)
+    got = _cube_np(sim.synth())
+    e = rel_l2(got, want)
+    log(f"  {len(p['amp'])} paths (gpu {sim.n_paths()}), synth rel L2 {e:.3e}")
+    assert n_ok > 100 and sim.n_paths() == len(p["amp"]) > 100000 and e <= 1e-4
