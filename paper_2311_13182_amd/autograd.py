@@ -109,6 +109,16 @@ def skew(w: torch.Tensor) -> torch.Tensor:
                         torch.stack([-w[1], w[0], z])])
 
 
+def box_pose(base: torch.Tensor, log_scale: torch.Tensor, omega: torch.Tensor, trans: torch.Tensor,
+             center: torch.Tensor = None) -> torch.Tensor:
+    """3D bounding-box parameterisation (Sec. 3.1 (i), the object's
+    transformation matrix): verts = exp([omega]x) diag(exp(log_scale))
+    (base - c) + c + trans about the vertex centroid c."""
+    c = base.mean(dim=0) if center is None else center
+    R = torch.linalg.matrix_exp(skew(omega))
+    return ((base - c) * torch.exp(log_scale)) @ R.T + c + trans
+
+
 def rigid_pose(base: torch.Tensor, omega: torch.Tensor, trans: torch.Tensor,
                center: torch.Tensor = None) -> torch.Tensor:
     """Object-transform parameterisation of the geometry (Sec. 3.1 (i)):
