@@ -792,3 +792,29 @@ def test_maximum_grid_size(torch_cuda, orc):
     e = rel_l2(got, want)
     log(f"  {len(p['amp'])} paths (gpu {sim.n_paths()}), synth rel L2 {e:.3e}")
     assert n_ok > 100 and sim.n_paths() == len(p["amp"]) > 100000 and e <= 1e-4
+
+
+def test_backward_attached_exit_only_and_shadow(torch_cuda, orc):
+    """The reparameterised gradient combined with exit-only returns (the
+    first hit is attached even when it does not return itself) and with
+    occlusion-tested returns, vs the oracle's attached central differences."""
+    import torch
+    from paper_2311_13182_amd.sbr import Simulator
+    for name, sc, exit_only in (("trihedral_plate exit-only", S.trihedral_plate(), True),
+                                ("room shadow", S.room_scene(n_rays=24, n_samples=32), False)):
+        o = orc.trace(sc)
+        att = orc.attach(sc, o["tri"])
+        tgt, _, _ = orc.forward(S.jitter(sc, 1e-3, 18), exit_only=exit_only)
+        p = orc.paths(sc, o["tri"], o["flags"], exit_only=exit_only)
+        G = 2.0 * (orc.synth(sc, p) - tgt)
+        sim = Simulator(sc, "cuda", exit_only=exit_only)
+        sim.hits = device_hits_from_oracle(o)
+        got = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda"), attached=True)
+        got = got.cpu().numpy().astype(np.float64).reshape(-1)
+        hit_v = np.unique(sc.faces[np.unique(o["tri"][o["tri"] >= 0])].reshape(-1))
+        rng = np.random.default_rng(21)
+        coords = (rng.choice(hit_v, min(12, len(hit_v)), replace=False)[:, None] * 3 + np.arange(3)[None, :]).reshape(-1)
+        fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, coords=coords, h=1e-9, att=att, exit_only=exit_only)
+        e = rel_l2(got[coords], fd)
+        log(f"attached backward, {name}: rel L2 {e:.3e} over {len(coords)} coordinates")
+        assert e <= GRAD_TOL
