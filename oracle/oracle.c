@@ -397,8 +397,9 @@ int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const o
             if ((options & ORC_DROP_FLAGGED) && flags && (flags[slot] & ~ORC_F_OCCLUDED)) keep = 0;
             if ((options & ORC_EXIT_ONLY) && k + 1 < K && tri[slot + n] >= 0) keep = 0;
             if (keep) {
-                /* I^s = d_omega * prod r_j * cos(theta_k) / (L_k R_k) */
-                double s = dw * cos_i / (Lk * Rk);
+                /* I^s = d_omega * prod r_j * cos(theta_k) / (L_k R_k), times the
+                 * medium's attenuation exp(-a (L_k + R_k)) */
+                double s = dw * cos_i / (Lk * Rk) * exp(-rd->atten * (Lk + Rk));
                 amp[2 * P] = pr_re * s;
                 amp[2 * P + 1] = pr_im * s;
                 /* I^t per virtual antenna: TX -> x_1 -> ... -> x_k -> RX */

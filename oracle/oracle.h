@@ -68,6 +68,8 @@ typedef struct {
     double tx[ORC_MAXTX][3];  /* radar frame                                   */
     double rx[ORC_MAXRX][3];  /* radar frame                                   */
     double vel[3];      /* rigid scene velocity, world frame, m/s              */
+    double atten;       /* amplitude attenuation of the medium, 1/m: each path's
+                           I^s carries exp(-atten (L_k + R_k)) (Eq. 5's A)      */
 } orc_radar;
 
 typedef struct {

@@ -58,6 +58,7 @@ class Radar:
     rx: np.ndarray                           # (n_rx, 3) radar frame
     vel: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))  # scene velocity, world
     planar: bool = False                     # virtual antennas form an n_tx x n_rx grid (vy = t, vx = m)
+    atten: float = 0.0                       # amplitude attenuation of the medium, 1/m (Eq. 5's A)
 
     @property
     def n_tx(self) -> int:

@@ -162,6 +162,12 @@ def test_plate_normal_incidence(orc):
     # conductor: I^s = -d_omega * cos / (L R) with cos = 1, L = R = 1.5
     _, _, dw = orc.ray(sc, rc)
     assert abs(p["amp"][0] - (-dw / 2.25)) < 1e-15
+    # a lossy medium (Eq. 5's attenuation A): the same path times exp(-a (L + R)) = exp(-3 a)
+    import dataclasses as dc
+    sa = dc.replace(sc, radar=dc.replace(sc.radar, atten=0.3))
+    pa = orc.paths(sa, tr["tri"], tr["flags"], rays=[rc], drop=False)
+    assert abs(pa["amp"][0] - (-dw / 2.25) * math.exp(-0.9)) < 1e-15
+    assert np.array_equal(pa["tau"], p["tau"])
 
 
 def test_frozen_fd_of_plate_translation(orc):
