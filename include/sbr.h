@@ -84,6 +84,9 @@ typedef struct {
     double tx[SBR_MAX_TX][3];/* radar frame                                      */
     double rx[SBR_MAX_RX][3];/* radar frame                                      */
     double velocity[3];      /* rigid scene velocity, world frame, m/s (Doppler) */
+    double attenuation;      /* amplitude attenuation of the medium, 1/m (>= 0): each
+                                path's I^s carries exp(-attenuation (L_k + R_k)), the
+                                attenuation function A of Sec. 3.2.1, Eqs. 4-5      */
 } sbr_radar;
 
 /* FMCW chirp (Eq. 8: fc, mu = B / T).  Sample s is taken at t = s / fs from
@@ -295,6 +298,7 @@ typedef struct {
     float *rot;              /* [9]: dL/d rot, row-major like sbr_radar.rot (the full
                                 3x3 matrix; project onto a rotation parameterisation
                                 outside, e.g. dL/d omega = axial part of G R^T) */
+    float *attenuation;      /* [1]: dL/d sbr_radar.attenuation (Eq. 5)          */
 } sbr_param_grads;
 
 /* Backpropagation (Sec. 3.2.2 Eqs. 11-12, Sec. 3.3 Eq. 13): given

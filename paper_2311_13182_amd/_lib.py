@@ -49,7 +49,8 @@ class sbr_material(ct.Structure):
 class sbr_radar(ct.Structure):
     _fields_ = [("origin", ct.c_double * 3), ("rot", ct.c_double * 9), ("n_tx", ct.c_int32),
                 ("n_rx", ct.c_int32), ("tx", (ct.c_double * 3) * SBR_MAX_TX),
-                ("rx", (ct.c_double * 3) * SBR_MAX_RX), ("velocity", ct.c_double * 3)]
+                ("rx", (ct.c_double * 3) * SBR_MAX_RX), ("velocity", ct.c_double * 3),
+                ("attenuation", ct.c_double)]
 
 
 class sbr_chirp(ct.Structure):
@@ -64,7 +65,8 @@ class sbr_rays(ct.Structure):
 
 
 class sbr_param_grads(ct.Structure):
-    _fields_ = [("materials", ct.c_void_p), ("radar", ct.c_void_p), ("rot", ct.c_void_p)]
+    _fields_ = [("materials", ct.c_void_p), ("radar", ct.c_void_p), ("rot", ct.c_void_p),
+                ("attenuation", ct.c_void_p)]
 
 
 class sbr_hits(ct.Structure):

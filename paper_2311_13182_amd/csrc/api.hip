@@ -66,6 +66,7 @@ static int check_radar(const sbr_radar *r) {
     SBR_CHECK_ARG(r->n_rx >= 1 && r->n_rx <= SBR_MAX_RX, "n_rx=%d out of [1,%d]", r->n_rx, SBR_MAX_RX);
     SBR_CHECK_ARG(r->n_tx * r->n_rx <= SBR_MAX_VIRTUAL, "n_tx*n_rx=%d > %d", r->n_tx * r->n_rx,
                   SBR_MAX_VIRTUAL);
+    SBR_CHECK_ARG(r->attenuation >= 0.0 && r->attenuation < 1e6, "attenuation must be in [0, 1e6) per metre");
     return SBR_OK;
 }
 
@@ -133,6 +134,7 @@ RadarDev make_radar(const sbr_radar *r) {
         d.vel[i] = r->velocity[i];
     }
     for (int i = 0; i < 9; i++) d.rot[i] = r->rot[i];
+    d.atten = r->attenuation;
     d.n_tx = r->n_tx;
     d.n_rx = r->n_rx;
     auto world = [&](const double *p, double *o) {

@@ -185,6 +185,7 @@ struct GeomArgs {
     float *g_mats;          // [n_mats][2] or NULL
     float *g_radar;         // [6] or NULL
     float *g_rot;           // [9] or NULL
+    float *g_atten;         // [1] or NULL
     int32_t attached;       // 1: first hits follow their triangle (Eqs. 6-7)
     float txl[SBR_MAX_TX][3];   // antenna positions in the radar frame
     float rxl[SBR_MAX_RX][3];
@@ -302,6 +303,8 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     for (int q = 0; q < 9; q++) gR[q] = 0.0f;
     const bool want_rot = a.g_rot != nullptr;
     float wJ = 0.0f;                        // sum over the ray's paths of Re(conj(Abar) A)
+    const float atn = (float)a.rd.atten;
+    float ga_atn = 0.0f;                    // dL/d attenuation
     const float3 U = f3((float)a.rd.vel[0], (float)a.rd.vel[1], (float)a.rd.vel[2]);
 #pragma unroll
     for (int k = 0; k < K; k++) {
@@ -322,13 +325,14 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
             for (int j = 0; j <= k; j++)
                 prod = make_float2(prod.x * RC[j].x - prod.y * RC[j].y, prod.x * RC[j].y + prod.y * RC[j].x);
             const float Rk = len3(X[k] - O);
-            // A = dw prod ci_k / (L R);  u = Re(conj(Abar) dw prod / (L R))
-            const float sc = dw / (LC[k] * Rk);
+            // A = dw prod ci_k exp(-a (L + R)) / (L R);  u = Re(conj(Abar) A / ci_k)
+            const float sc = dw / (LC[k] * Rk) * __expf(-atn * (LC[k] + Rk));
             const float u = sc * (ab.x * prod.x + ab.y * prod.y);
             const float gk = u * CI[k];
             wJ += gk;                               // Re(conj(Abar) A): dL/d log(cell weight)
             cib[k] += u;
-            const float Lb = -gk / LC[k], Rb = -gk / Rk;
+            const float Lb = -gk / LC[k] - atn * gk, Rb = -gk / Rk - atn * gk;
+            ga_atn -= gk * (LC[k] + Rk);            // d A / d a = -(L + R) A
             if (a.any_fresnel) {
 #pragma unroll
                 for (int j = 0; j <= k; j++) {
@@ -525,6 +529,11 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
             if (lane == 0) atomicAdd(&a.g_radar[q], v6[q]);
         }
     }
+    if (a.g_atten) {
+        float v = ga_atn;
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) atomicAdd(a.g_atten, v);
+    }
     if (want_rot) {
         // d_0 = rot d_local: dL/drot += (dL/dd_0) d_local^T, where dL/dd_0 is
         // what the reverse sweep left for the first segment plus the Doppler part
@@ -635,6 +644,7 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     g.g_mats = params ? params->materials : nullptr;
     g.g_radar = params ? params->radar : nullptr;
     g.g_rot = params ? params->rot : nullptr;
+    g.g_atten = params ? params->attenuation : nullptr;
     g.attached = attached ? 1 : 0;
     for (int t = 0; t < SBR_MAX_TX; t++)
         for (int c = 0; c < 3; c++) g.txl[t][c] = t < radar->n_tx ? (float)radar->tx[t][c] : 0.0f;

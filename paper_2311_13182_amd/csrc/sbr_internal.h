@@ -111,6 +111,7 @@ struct RadarDev {
     double tx[SBR_MAX_TX][3];   // world frame
     double rx[SBR_MAX_RX][3];   // world frame
     double vel[3];
+    double atten;               // amplitude attenuation of the medium, 1/m
 };
 
 struct GridDev {

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
         }
         double Rk = sqrt((x[0] - a.rd.o[0]) * (x[0] - a.rd.o[0]) + (x[1] - a.rd.o[1]) * (x[1] - a.rd.o[1]) +
                          (x[2] - a.rd.o[2]) * (x[2] - a.rd.o[2]));
-        double sc = dw * ci / (L * Rk);
+        double sc = dw * ci / (L * Rk) * exp(-a.rd.atten * (L + Rk));
         a.st.rec.amp[p] = make_float2((float)(pr.re * sc), (float)(pr.im * sc));
         a.st.rec.beta[p] = (float)beta;
         a.st.rec.epsd[p] = (float)epsd;

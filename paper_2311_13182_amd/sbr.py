@@ -41,6 +41,7 @@ def radar_struct(r: S.Radar) -> L.sbr_radar:
     for i in range(3):
         s.origin[i] = float(r.origin[i])
         s.velocity[i] = float(r.vel[i])
+    s.attenuation = float(getattr(r, "atten", 0.0))
     rot = np.asarray(r.rot, dtype=np.float64).reshape(-1)
     for i in range(9):
         s.rot[i] = float(rot[i])
@@ -227,16 +228,16 @@ def sbr_cfar(cube: torch.Tensor, Na: int, C: int, Sn: int, guard: int, train: in
 def sbr_backward(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: S.Chirp, flags: int,
                  grad_if: torch.Tensor, grad_verts: torch.Tensor, scratch: torch.Tensor,
                  grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,
-                 grad_rot: Optional[torch.Tensor] = None):
+                 grad_rot: Optional[torch.Tensor] = None, grad_atten: Optional[torch.Tensor] = None):
     m, r, g, h, c = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct(), chirp_struct(chirp)
     mats, nm = materials_struct(mesh.materials)
     pg = None
-    if grad_materials is not None or grad_radar is not None or grad_rot is not None:
-        for t, n in ((grad_materials, 2 * len(mesh.materials or [])), (grad_radar, 6), (grad_rot, 9)):
+    bufs = (grad_materials, grad_radar, grad_rot, grad_atten)
+    if any(t is not None for t in bufs):
+        for t, n in zip(bufs, (2 * len(mesh.materials or []), 6, 9, 1)):
             if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n):
                 raise ValueError(f"parameter gradient buffer must be contiguous float32 with {n} elements")
-        pg = L.sbr_param_grads(*[t.data_ptr() if t is not None else None
-                                 for t in (grad_materials, grad_radar, grad_rot)])
+        pg = L.sbr_param_grads(*[t.data_ptr() if t is not None else None for t in bufs])
     L.check(_lib().sbr_backward(ct.byref(m), mats, nm, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c),
                                 int(flags), _p(grad_if), _p(grad_verts), ct.byref(pg) if pg is not None else None,
                                 _p(scratch), scratch.numel() * scratch.element_size(), _stream()))
@@ -396,10 +397,11 @@ class Simulator:
 
     def backward(self, grad_if: torch.Tensor, grad_verts: Optional[torch.Tensor] = None,
                  grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,
-                 grad_rot: Optional[torch.Tensor] = None, attached: bool = False) -> torch.Tensor:
+                 grad_rot: Optional[torch.Tensor] = None, attached: bool = False,
+                 grad_atten: Optional[torch.Tensor] = None) -> torch.Tensor:
         """dL/dverts (accumulated into grad_verts); optionally also accumulates
         dL/d(eps_r, sigma) per material [n_mats,2], dL/d(origin, velocity) [6]
-        and dL/d rot [3,3] (radar -> world, row-major).  attached=True
+        dL/d rot [3,3] (radar -> world, row-major) and dL/d attenuation [1].  attached=True
         differentiates the reparameterised estimator (samples follow their
         first hit, Eqs. 6-7), so that moving silhouettes contribute."""
         gf = (torch.view_as_real(grad_if) if grad_if.is_complex() else grad_if).contiguous().to(torch.float32)
@@ -407,7 +409,7 @@ class Simulator:
             grad_verts = torch.zeros((self.mesh.nv, 3), dtype=torch.float32, device=self.device)
         flags = self.flags | (L.SBR_ATTACHED if attached else 0)
         sbr_backward(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, flags, gf,
-                     grad_verts, self.scratch, grad_materials, grad_radar, grad_rot)
+                     grad_verts, self.scratch, grad_materials, grad_radar, grad_rot, grad_atten)
         return grad_verts
 
     def loss_grad(self, cube: torch.Tensor, target: torch.Tensor, grad: Optional[torch.Tensor] = None,

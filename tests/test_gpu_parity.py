@@ -818,3 +818,35 @@ def test_backward_attached_exit_only_and_shadow(torch_cuda, orc):
         e = rel_l2(got[coords], fd)
         log(f"attached backward, {name}: rel L2 {e:.3e} over {len(coords)} coordinates")
         assert e <= GRAD_TOL
+
+
+def test_attenuation_forward_and_gradients(torch_cuda, orc):
+    """A lossy medium (Sec. 3.2.1, Eqs. 4-5: I^s times exp(-a (L + R))): IF
+    cube, vertex gradient and dL/da against the oracle."""
+    import torch
+    sc = _synth_case("fresnel_mixed").with_grid(nx=32, ny=32)
+    sc = dataclasses.replace(sc, radar=dataclasses.replace(sc.radar, atten=0.35))
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    want = orc.synth(sc, p)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    e = rel_l2(_cube_np(sim.synth()), want)
+    tgt = _target(orc, sc, 1e-3, 19)
+    G = 2.0 * (want - tgt)
+    ga = torch.zeros(1, dtype=torch.float32, device="cuda")
+    got = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda"), grad_atten=ga)
+    got = got.cpu().numpy().astype(np.float64).reshape(-1)
+    hit_v = np.unique(sc.faces[np.unique(o["tri"][o["tri"] >= 0])].reshape(-1))
+    coords = (hit_v[:12, None] * 3 + np.arange(3)[None, :]).reshape(-1)
+    fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, coords=coords, h=1e-9)
+    ev = rel_l2(got[coords], fd)
+    fa = orc.fd_scene(sc, o["tri"], o["flags"], tgt,
+                      lambda s, d: dataclasses.replace(s, radar=dataclasses.replace(s.radar, atten=s.radar.atten + d)),
+                      1e-6)
+    ea = abs(float(ga.item()) - fa) / abs(fa)
+    log(f"attenuation: synth {e:.3e}, vertex grad {ev:.3e}, dL/da gpu {float(ga.item()):.6e} fd {fa:.6e} ({ea:.2e})")
+    assert e <= 1e-4 and ev <= GRAD_TOL and ea <= GRAD_TOL
+    # the medium weakens every path: the cube's power falls
+    sc0 = dataclasses.replace(sc, radar=dataclasses.replace(sc.radar, atten=0.0))
+    assert np.linalg.norm(want) < np.linalg.norm(orc.synth(sc0, orc.paths(sc0, o["tri"], o["flags"])))
