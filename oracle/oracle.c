@@ -365,6 +365,7 @@ int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const o
         /* Doppler of the path: rate of change of the round trip for a rigidly
          * moving scene, 2 (u . d_1) / c */
         double tdot = 2.0 * dot3(rd->vel, d) / C0;
+        double d0[3] = {d[0], d[1], d[2]};
         double x1[3] = {0, 0, 0}, xprev[3] = {O[0], O[1], O[2]};
         double Lk = 0.0, Lmid = 0.0;
         double pr_re = 1.0, pr_im = 0.0;   /* product of reflection coefficients */
@@ -400,6 +401,13 @@ int orc_paths(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const o
                 /* I^s = d_omega * prod r_j * cos(theta_k) / (L_k R_k), times the
                  * medium's attenuation exp(-a (L_k + R_k)) */
                 double s = dw * cos_i / (Lk * Rk) * exp(-rd->atten * (Lk + Rk));
+                if (rd->n_tx_gain != 0.0 || rd->n_rx_gain != 0.0) {
+                    /* F G of Eq. 1: cos^n to boresight (third column of rot) */
+                    double zb[3] = {rd->rot[2], rd->rot[5], rd->rot[8]}, q[3];
+                    sub3(x, O, q);
+                    double ct = dot3(d0, zb), cr = dot3(q, zb) / norm3(q);
+                    s *= pow(ct > 0.0 ? ct : 0.0, rd->n_tx_gain) * pow(cr > 0.0 ? cr : 0.0, rd->n_rx_gain);
+                }
                 amp[2 * P] = pr_re * s;
                 amp[2 * P + 1] = pr_im * s;
                 /* I^t per virtual antenna: TX -> x_1 -> ... -> x_k -> RX */

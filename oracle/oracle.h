@@ -70,6 +70,9 @@ typedef struct {
     double vel[3];      /* rigid scene velocity, world frame, m/s              */
     double atten;       /* amplitude attenuation of the medium, 1/m: each path's
                            I^s carries exp(-atten (L_k + R_k)) (Eq. 5's A)      */
+    double n_tx_gain, n_rx_gain;  /* directional gains F, G of Eq. 1: cos^n of
+                           the angle to boresight of the outgoing ray (F) and of
+                           the return from the last hit (G); 0 = isotropic      */
 } orc_radar;
 
 typedef struct {

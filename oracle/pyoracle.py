@@ -47,7 +47,8 @@ class _Mesh(ct.Structure):
 class _Radar(ct.Structure):
     _fields_ = [("origin", ct.c_double * 3), ("rot", ct.c_double * 9), ("n_tx", ct.c_int),
                 ("n_rx", ct.c_int), ("tx", (ct.c_double * 3) * 20), ("rx", (ct.c_double * 3) * 20),
-                ("vel", ct.c_double * 3), ("atten", ct.c_double)]
+                ("vel", ct.c_double * 3), ("atten", ct.c_double), ("n_tx_gain", ct.c_double),
+                ("n_rx_gain", ct.c_double)]
 
 
 class _Chirp(ct.Structure):
@@ -145,6 +146,8 @@ def _radar(rd):
         r.rot[i] = float(np.asarray(rd.rot).reshape(-1)[i])
     r.n_tx, r.n_rx = rd.n_tx, rd.n_rx
     r.atten = float(getattr(rd, "atten", 0.0))
+    r.n_tx_gain = float(getattr(rd, "n_tx_gain", 0.0))
+    r.n_rx_gain = float(getattr(rd, "n_rx_gain", 0.0))
     for t in range(rd.n_tx):
         for j in range(3):
             r.tx[t][j] = float(rd.tx[t][j])

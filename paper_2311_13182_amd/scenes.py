@@ -59,6 +59,8 @@ class Radar:
     vel: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))  # scene velocity, world
     planar: bool = False                     # virtual antennas form an n_tx x n_rx grid (vy = t, vx = m)
     atten: float = 0.0                       # amplitude attenuation of the medium, 1/m (Eq. 5's A)
+    n_tx_gain: float = 0.0                   # TX gain F = cos^n(angle to boresight), 0 = isotropic (Eq. 1)
+    n_rx_gain: float = 0.0                   # RX gain G = cos^n(angle to boresight) of the return
 
     @property
     def n_tx(self) -> int:

@@ -553,3 +553,32 @@ def test_jittered_grid_is_an_unbiased_solid_angle_estimator(orc):
     cell = 2 * math.tan(a) / n
     assert -math.tan(a) + 1 * cell <= tx <= -math.tan(a) + 2 * cell
     assert -math.tan(a) + 1 * cell <= ty <= -math.tan(a) + 2 * cell
+
+
+def test_directional_gains(orc):
+    """F and G of Eq. 1 as cos^n patterns about boresight: for a first-bounce
+    path the return retraces the ray, so the amplitude scales by
+    cos^(n_tx + n_rx) of the ray's angle to boresight; for later bounces G
+    follows the direction of the last hit."""
+    import dataclasses as dc
+    sc = S.trihedral_plate()
+    tr = orc.trace(sc)
+    p0 = orc.paths(sc, tr["tri"], tr["flags"])
+    sg = dc.replace(sc, radar=dc.replace(sc.radar, n_tx_gain=2.0, n_rx_gain=1.5))
+    pg = orc.paths(sg, tr["tri"], tr["flags"])
+    assert np.array_equal(pg["ray"], p0["ray"]) and np.array_equal(pg["tau"], p0["tau"])
+    one = p0["k"] == 1
+    cz = np.array([orc.ray(sc, r)[1][2] for r in p0["ray"]])     # boresight = +z, rot = I
+    assert np.allclose(pg["amp"][one], p0["amp"][one] * cz[one] ** 3.5, rtol=1e-12, atol=0)
+    # later bounces: G from the last hit's direction (recomputed here from the hit record)
+    k = np.nonzero(~one)[0]
+    assert len(k) > 10
+    v = sc.verts.astype(np.float64)
+    f = sc.faces
+    for j in k[:50]:
+        r, kk = p0["ray"][j], p0["k"][j] - 1
+        fid = tr["tri"][kk, r]
+        a, b, c = v[f[fid, 0]], v[f[fid, 1]], v[f[fid, 2]]
+        x = a + tr["b1"][kk, r] * (b - a) + tr["b2"][kk, r] * (c - a)
+        want = p0["amp"][j] * cz[j] ** 2.0 * (x[2] / np.linalg.norm(x)) ** 1.5
+        assert abs(pg["amp"][j] - want) <= 1e-9 * abs(want)
