@@ -87,6 +87,10 @@ typedef struct {
     double attenuation;      /* amplitude attenuation of the medium, 1/m (>= 0): each
                                 path's I^s carries exp(-attenuation (L_k + R_k)), the
                                 attenuation function A of Sec. 3.2.1, Eqs. 4-5      */
+    double tx_gain_exp;      /* F of Eq. 1: TX gain cos^n of the outgoing ray's angle
+                                to boresight (third column of rot); 0 = isotropic   */
+    double rx_gain_exp;      /* G of Eq. 1: RX gain cos^n of the angle to boresight of
+                                the direction from the array centre to the last hit */
 } sbr_radar;
 
 /* FMCW chirp (Eq. 8: fc, mu = B / T).  Sample s is taken at t = s / fs from

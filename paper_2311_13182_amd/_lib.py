@@ -50,7 +50,7 @@ class sbr_radar(ct.Structure):
     _fields_ = [("origin", ct.c_double * 3), ("rot", ct.c_double * 9), ("n_tx", ct.c_int32),
                 ("n_rx", ct.c_int32), ("tx", (ct.c_double * 3) * SBR_MAX_TX),
                 ("rx", (ct.c_double * 3) * SBR_MAX_RX), ("velocity", ct.c_double * 3),
-                ("attenuation", ct.c_double)]
+                ("attenuation", ct.c_double), ("tx_gain_exp", ct.c_double), ("rx_gain_exp", ct.c_double)]
 
 
 class sbr_chirp(ct.Structure):

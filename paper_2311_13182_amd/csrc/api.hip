@@ -67,6 +67,9 @@ static int check_radar(const sbr_radar *r) {
     SBR_CHECK_ARG(r->n_tx * r->n_rx <= SBR_MAX_VIRTUAL, "n_tx*n_rx=%d > %d", r->n_tx * r->n_rx,
                   SBR_MAX_VIRTUAL);
     SBR_CHECK_ARG(r->attenuation >= 0.0 && r->attenuation < 1e6, "attenuation must be in [0, 1e6) per metre");
+    SBR_CHECK_ARG(r->tx_gain_exp >= 0.0 && r->tx_gain_exp <= 1000.0 && r->rx_gain_exp >= 0.0 &&
+                      r->rx_gain_exp <= 1000.0,
+                  "gain exponents must be in [0, 1000]");
     return SBR_OK;
 }
 
@@ -135,6 +138,8 @@ RadarDev make_radar(const sbr_radar *r) {
     }
     for (int i = 0; i < 9; i++) d.rot[i] = r->rot[i];
     d.atten = r->attenuation;
+    d.n_tg = r->tx_gain_exp;
+    d.n_rg = r->rx_gain_exp;
     d.n_tx = r->n_tx;
     d.n_rx = r->n_rx;
     auto world = [&](const double *p, double *o) {

@@ -305,6 +305,13 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     float wJ = 0.0f;                        // sum over the ray's paths of Re(conj(Abar) A)
     const float atn = (float)a.rd.atten;
     float ga_atn = 0.0f;                    // dL/d attenuation
+    // directional gains F(d_0) G(x_k - o) of Eq. 1, cos^n about the boresight zb
+    const float ntg = (float)a.rd.n_tg, nrg = (float)a.rd.n_rg;
+    const float3 ZB = f3((float)a.rd.rot[2], (float)a.rd.rot[5], (float)a.rd.rot[8]);
+    const float3 D0 = f3((float)d0[0], (float)d0[1], (float)d0[2]);
+    const float ctx = dot3(D0, ZB);
+    const float Fg = ntg == 0.0f ? 1.0f : (ctx > 0.0f ? __powf(ctx, ntg) : 0.0f);
+    float3 gZ = f3(0.f, 0.f, 0.f);          // dL/d boresight vector (world)
     const float3 U = f3((float)a.rd.vel[0], (float)a.rd.vel[1], (float)a.rd.vel[2]);
 #pragma unroll
     for (int k = 0; k < K; k++) {
@@ -324,15 +331,28 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
 #pragma unroll
             for (int j = 0; j <= k; j++)
                 prod = make_float2(prod.x * RC[j].x - prod.y * RC[j].y, prod.x * RC[j].y + prod.y * RC[j].x);
-            const float Rk = len3(X[k] - O);
-            // A = dw prod ci_k exp(-a (L + R)) / (L R);  u = Re(conj(Abar) A / ci_k)
-            const float sc = dw / (LC[k] * Rk) * __expf(-atn * (LC[k] + Rk));
+            const float3 qk = X[k] - O;
+            const float Rk = len3(qk);
+            const float qz = dot3(qk, ZB);
+            const float Gg = nrg == 0.0f ? 1.0f : (qz > 0.0f ? __powf(qz / Rk, nrg) : 0.0f);
+            // A = dw prod ci_k exp(-a (L + R)) F G / (L R);  u = Re(conj(Abar) A / ci_k)
+            const float sc = dw / (LC[k] * Rk) * __expf(-atn * (LC[k] + Rk)) * (Fg * Gg);
             const float u = sc * (ab.x * prod.x + ab.y * prod.y);
             const float gk = u * CI[k];
             wJ += gk;                               // Re(conj(Abar) A): dL/d log(cell weight)
             cib[k] += u;
             const float Lb = -gk / LC[k] - atn * gk, Rb = -gk / Rk - atn * gk;
             ga_atn -= gk * (LC[k] + Rk);            // d A / d a = -(L + R) A
+            if (nrg != 0.0f && qz > 0.0f) {         // log G = n (log(q.zb) - log |q|)
+                const float3 t = nrg * ((1.0f / qz) * ZB - (1.0f / (Rk * Rk)) * qk);
+                xb[k] = xb[k] + gk * t;
+                go = go - gk * t;
+                gZ = gZ + (gk * nrg / qz) * qk;
+            }
+            if (ntg != 0.0f && ctx > 0.0f) {        // log F = n log(d_0.zb)
+                gd0 = gd0 + (gk * ntg / ctx) * ZB;
+                gZ = gZ + (gk * ntg / ctx) * D0;
+            }
             if (a.any_fresnel) {
 #pragma unroll
                 for (int j = 0; j <= k; j++) {
@@ -539,9 +559,10 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
         // what the reverse sweep left for the first segment plus the Doppler part
         const float3 g0 = dnext + gd0;
         const float l0 = (float)dl[0], l1 = (float)dl[1], l2 = (float)dl[2];
-        float v9[9] = {gR[0] + g0.x * l0, gR[1] + g0.x * l1, gR[2] + g0.x * l2,
-                       gR[3] + g0.y * l0, gR[4] + g0.y * l1, gR[5] + g0.y * l2,
-                       gR[6] + g0.z * l0, gR[7] + g0.z * l1, gR[8] + g0.z * l2};
+        // zb = rot e_z: the gains add dL/dzb to the third column
+        float v9[9] = {gR[0] + g0.x * l0, gR[1] + g0.x * l1, gR[2] + g0.x * l2 + gZ.x,
+                       gR[3] + g0.y * l0, gR[4] + g0.y * l1, gR[5] + g0.y * l2 + gZ.y,
+                       gR[6] + g0.z * l0, gR[7] + g0.z * l1, gR[8] + g0.z * l2 + gZ.z};
 #pragma unroll
         for (int q = 0; q < 9; q++) {
             for (int off = 32; off >= 1; off >>= 1) v9[q] += __shfl_xor(v9[q], off);

@@ -112,6 +112,7 @@ struct RadarDev {
     double rx[SBR_MAX_RX][3];   // world frame
     double vel[3];
     double atten;               // amplitude attenuation of the medium, 1/m
+    double n_tg, n_rg;          // TX / RX gain exponents (cos^n about boresight)
 };
 
 struct GridDev {

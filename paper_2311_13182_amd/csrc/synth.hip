@@ -111,6 +111,7 @@ __global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
     const int ix = (int)(r % a.g.nx), iy = (int)(r / a.g.nx);
     double d[3], dw;
     grid_ray(a.g, a.rd, ix, iy, d, &dw);
+    const double d0[3] = {d[0], d[1], d[2]};
     double o[3] = {a.rd.o[0], a.rd.o[1], a.rd.o[2]};
     const double taudot = 2.0 * (a.rd.vel[0] * d[0] + a.rd.vel[1] * d[1] + a.rd.vel[2] * d[2]) / kC0;
     const double beta = frac_d(a.ch.fc * a.ch.tc * taudot);
@@ -161,6 +162,12 @@ __global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
         double Rk = sqrt((x[0] - a.rd.o[0]) * (x[0] - a.rd.o[0]) + (x[1] - a.rd.o[1]) * (x[1] - a.rd.o[1]) +
                          (x[2] - a.rd.o[2]) * (x[2] - a.rd.o[2]));
         double sc = dw * ci / (L * Rk) * exp(-a.rd.atten * (L + Rk));
+        if (a.rd.n_tg != 0.0 || a.rd.n_rg != 0.0) {   // F G of Eq. 1 about boresight
+            const double zb[3] = {a.rd.rot[2], a.rd.rot[5], a.rd.rot[8]};
+            const double ct = d0[0] * zb[0] + d0[1] * zb[1] + d0[2] * zb[2];
+            const double cr = ((x[0] - a.rd.o[0]) * zb[0] + (x[1] - a.rd.o[1]) * zb[1] + (x[2] - a.rd.o[2]) * zb[2]) / Rk;
+            sc *= pow(ct > 0.0 ? ct : 0.0, a.rd.n_tg) * pow(cr > 0.0 ? cr : 0.0, a.rd.n_rg);
+        }
         a.st.rec.amp[p] = make_float2((float)(pr.re * sc), (float)(pr.im * sc));
         a.st.rec.beta[p] = (float)beta;
         a.st.rec.epsd[p] = (float)epsd;

@@ -42,6 +42,8 @@ def radar_struct(r: S.Radar) -> L.sbr_radar:
         s.origin[i] = float(r.origin[i])
         s.velocity[i] = float(r.vel[i])
     s.attenuation = float(getattr(r, "atten", 0.0))
+    s.tx_gain_exp = float(getattr(r, "n_tx_gain", 0.0))
+    s.rx_gain_exp = float(getattr(r, "n_rx_gain", 0.0))
     rot = np.asarray(r.rot, dtype=np.float64).reshape(-1)
     for i in range(9):
         s.rot[i] = float(rot[i])

@@ -850,3 +850,51 @@ def test_attenuation_forward_and_gradients(torch_cuda, orc):
     # the medium weakens every path: the cube's power falls
     sc0 = dataclasses.replace(sc, radar=dataclasses.replace(sc.radar, atten=0.0))
     assert np.linalg.norm(want) < np.linalg.norm(orc.synth(sc0, orc.paths(sc0, o["tri"], o["flags"])))
+
+
+def test_directional_gains_forward_and_gradients(torch_cuda, orc):
+    """F and G of Eq. 1 (cos^n patterns about boresight, radar turned off the
+    scene axis): IF cube, vertex gradient (fixed and attached), radar origin
+    and rotation gradients against the oracle."""
+    import torch
+    sc = _synth_case("fresnel_mixed").with_grid(nx=32, ny=32)
+    c, s_ = math.cos(0.08), math.sin(0.08)
+    rd = dataclasses.replace(sc.radar, n_tx_gain=3.0, n_rx_gain=2.0,
+                             rot=np.array([[c, 0.0, s_], [0.0, 1.0, 0.0], [-s_, 0.0, c]]))
+    sc = dataclasses.replace(sc, radar=rd)
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    want = orc.synth(sc, p)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    e = rel_l2(_cube_np(sim.synth()), want)
+    tgt = _target(orc, sc, 1e-3, 20)
+    G = torch.as_tensor((2.0 * (want - tgt)).astype(np.complex64), device="cuda")
+    gr = torch.zeros(6, dtype=torch.float32, device="cuda")
+    gR = torch.zeros(9, dtype=torch.float32, device="cuda")
+    got = sim.backward(G, grad_radar=gr, grad_rot=gR).cpu().numpy().astype(np.float64).reshape(-1)
+    hit_v = np.unique(sc.faces[np.unique(o["tri"][o["tri"] >= 0])].reshape(-1))
+    coords = (hit_v[:12, None] * 3 + np.arange(3)[None, :]).reshape(-1)
+    ev = rel_l2(got[coords], orc.fd_grad(sc, o["tri"], o["flags"], tgt, coords=coords, h=1e-9))
+    gr = gr.cpu().numpy().astype(np.float64)
+    gR = gR.cpu().numpy().astype(np.float64).reshape(3, 3)
+    fo = np.array([orc.fd_scene(sc, o["tri"], o["flags"], tgt, lambda s, d, k=k: dataclasses.replace(
+        s, radar=dataclasses.replace(s.radar, origin=s.radar.origin + d * np.eye(3)[k])), 1e-9) for k in range(3)])
+    an, fr = [], []
+    for k in range(3):
+        K = np.zeros((3, 3))
+        i, j = (k + 1) % 3, (k + 2) % 3
+        K[i, j], K[j, i] = -1.0, 1.0
+
+        def rotk(s, d, K=K):
+            Rk = np.eye(3) + math.sin(d) * K + (1.0 - math.cos(d)) * (K @ K)
+            return dataclasses.replace(s, radar=dataclasses.replace(s.radar, rot=Rk @ np.asarray(s.radar.rot)))
+        an.append((gR * (K @ np.asarray(sc.radar.rot))).sum())
+        fr.append(orc.fd_scene(sc, o["tri"], o["flags"], tgt, rotk, 1e-7))
+    att = orc.attach(sc, o["tri"])
+    ga = sim.backward(G, attached=True).cpu().numpy().astype(np.float64).reshape(-1)
+    eat = rel_l2(ga[coords], orc.fd_grad(sc, o["tri"], o["flags"], tgt, coords=coords, h=1e-9, att=att))
+    log(f"gains: synth {e:.3e}, vertex {ev:.3e}, attached {eat:.3e}, origin {rel_l2(gr[:3], fo):.3e}, "
+        f"rotation {an} vs {fr}")
+    assert e <= 1e-4 and ev <= GRAD_TOL and eat <= GRAD_TOL
+    assert rel_l2(gr[:3], fo) <= GRAD_TOL and rel_l2(np.array(an), np.array(fr)) <= GRAD_TOL
