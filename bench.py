@@ -103,8 +103,8 @@ def cpu_baseline(scene, queries_full: int, budget_rows: int = 16, chirp_stride: 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clutter_50k", choices=["clutter_50k", "icosphere_20k", "imaging_400"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-latency measurement")
@@ -173,16 +173,17 @@ def main():
     torch.cuda.synchronize()
     sbr_profile(2)
     sbr_profile(1)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
+    ev[0].record()
+    for i in range(args.steps):
         step()
-    e1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     w1 = time.perf_counter()
+    e0, e1 = ev[0], ev[-1]
+    per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     sbr_profile(0)
     ms_total = e0.elapsed_time(e1)
     ms_step = ms_total / args.steps
@@ -210,6 +211,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_p10_p50_p90": [round(float(np.percentile(per_step, q)), 3) for q in (10, 50, 90)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -234,7 +236,7 @@ def main():
         del sim, cube, grad, gv, target
         torch.cuda.empty_cache()
         from paper_2311_13182_amd.serve import serving_benchmark
-        sv = serving_benchmark(n=args.serving_requests, phases=(("main", 1.25),), quiet=True)
+        sv = serving_benchmark(n=args.serving_requests, phases=(("main", 1.25), ("low", 0.5)), quiet=True)
         m = sv["main"]
         out["serving"] = {"requests": args.serving_requests, "qps": round(m["qps"], 2),
                           "throughput_rps": round(m["server"]["throughput_rps"], 2),
@@ -243,6 +245,12 @@ def main():
                           "sequential_throughput_rps": round(m["sequential"]["throughput_rps"], 2),
                           "sequential_p50_latency_ms": round(m["sequential"]["p50_latency_ms"], 1),
                           "sequential_p99_latency_ms": round(m["sequential"]["p99_latency_ms"], 1)}
+        lo = sv["low"]
+        out["serving"]["low_load"] = {"qps": round(lo["qps"], 2),
+                                      "p50_latency_ms": round(lo["server"]["p50_latency_ms"], 1),
+                                      "p99_latency_ms": round(lo["server"]["p99_latency_ms"], 1),
+                                      "sequential_p50_latency_ms": round(lo["sequential"]["p50_latency_ms"], 1),
+                                      "sequential_p99_latency_ms": round(lo["sequential"]["p99_latency_ms"], 1)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, queries)
     print(json.dumps(out), flush=True)
