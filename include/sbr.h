@@ -18,6 +18,9 @@
  *     u = tan_half_x * (2 (ix + 0.5) / nx - 1), v likewise in y; its Monte
  *     Carlo weight (Eq. 3) is the cell solid angle
  *     (2 tan_half_x / nx)(2 tan_half_y / ny) / (1 + u^2 + v^2)^(3/2).
+ *     With SBR_RAYS_JITTER in sbr_rays.options the offset 0.5 becomes a
+ *     per-ray uniform draw from Philox-4x32-10 (key seed_lo, seed_hi); the
+ *     weight stays the cell's, evaluated at the drawn (u, v).
  *   - Virtual antenna v = t * n_rx + m (TX t, RX m).
  *   - Complex arrays are interleaved float pairs (re, im), C-contiguous.
  *   - Memory: every pointer inside the structs below and every array argument
