@@ -302,8 +302,6 @@ int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_a
     SBR_CHECK_ARG(n_angle >= V, "n_angle=%d < V=%d", n_angle, V);
     SBR_CHECK_ARG(window == 0 || window == 1, "window must be 0 or 1");
     SBR_CHECK_ARG(direction == 0 || direction == 1, "direction must be 0 or 1");
-    SBR_CHECK_ARG((size_t)C * 32 * 8 + (size_t)C * 8 <= 60000 && (size_t)std::max(V, n_angle) * 32 * 8 +
-                      (size_t)n_angle * 8 <= 60000, "C or n_angle too large for the LDS tiles");
     size_t need = cube_scratch_bytes(V, C, S, n_angle);
     if (!scratch || scratch_bytes < need) {
         set_error("radar cube scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
@@ -319,12 +317,8 @@ static int check_cube2(int32_t Vx, int32_t Vy, int32_t C, int32_t S, int32_t n_a
     SBR_CHECK_ARG(Vx <= 4096 && Vy <= 4096 && C <= 4096 && S <= 4096 && n_ax <= 4096 && n_ay <= 4096,
                   "sizes must be <= 4096");
     SBR_CHECK_ARG(n_ax >= Vx && n_ay >= Vy, "n_ax=%d < Vx=%d or n_ay=%d < Vy=%d", n_ax, Vx, n_ay, Vy);
-    SBR_CHECK_ARG((long long)n_ax * n_ay * C * S < (1LL << 31) && (long long)Vx * Vy * C * S < (1LL << 31),
-                  "cube too large (more than 2^31 cells)");
-    const size_t lds_c = (size_t)C * 32 * 8 + (size_t)C * 8;
-    const size_t lds_a = (size_t)std::max(std::max(Vx, n_ax), std::max(Vy, n_ay)) * 32 * 8 +
-                         (size_t)std::max(n_ax, n_ay) * 8;
-    SBR_CHECK_ARG(lds_c <= 60000 && lds_a <= 60000, "C or the angle sizes too large for the LDS tiles");
+    SBR_CHECK_ARG((long long)n_ax * n_ay * C * S < (1LL << 31) - 64 && (long long)Vx * Vy * C * S < (1LL << 31) - 64,
+                  "cube too large (2^31 cells or more)");
     return SBR_OK;
 }
 

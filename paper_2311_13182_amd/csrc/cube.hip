@@ -1,7 +1,7 @@
 // The signal-to-image map T of the spatial loss (Eq. 16): range, Doppler and
 // angle DFTs and their conjugate transpose; and the CA-CFAR point extraction.
-// Direct DFTs with exact twiddle indices (k n mod N) held in LDS; the stage
-// moves a few MiB and is bound by memory traffic, not arithmetic.
+// Each DFT is a dense FP32 contraction with the DFT matrix on the matrix cores
+// (MFMA), twiddles by exact index (k n mod N) from an LDS table.
 #include "sbr_internal.h"
 
 namespace sbr {
@@ -22,74 +22,156 @@ __device__ __forceinline__ float window_at(int window, int i, int N) {
     return 1.0f;
 }
 
-// Transform along the innermost axis: rows of length N -> rows of length N.
-// pre-window on the input (forward) or post-window on the output (adjoint).
-__global__ __launch_bounds__(256) void k_dft_inner(const float2 *in, float2 *out, int rows, int N, int sign,
-                                                    int window, int post) {
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// D += A B for complex A, B on four real 16x16x4 FP32 MFMAs.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; D[4 (l / 16) + j][l % 16] is
+// element j of the lane's accumulators.
+__device__ __forceinline__ void cmfma(float ar, float ai, float br, float bi, f32x4 &dr, f32x4 &di) {
+    dr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, dr, 0, 0, 0);
+    di = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, di, 0, 0, 0);
+    dr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, dr, 0, 0, 0);
+    di = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, di, 0, 0, 0);
+}
+
+// LDS tables shared by both transforms: Nt twiddles, then the window over the
+// pre-windowed input axis (length N) or the post-windowed output axis (M).
+__device__ void dft_tables(float2 *tw, float *wt, int Nt, int sign, int window, int Lw) {
+    make_twiddles(tw, Nt, sign);
+    for (int k = threadIdx.x; k < Lw; k += blockDim.x) wt[k] = window_at(window, k, Lw);
+    __syncthreads();
+}
+
+// DFT along the innermost axis as a dense FP32 contraction on the matrix
+// cores: [rows][N] -> [rows][M],
+//   out[row][m] = w_post(m) sum_n w_pre(n) in[row][n] e^{sign 2 pi j (n m mod Nt) / Nt}.
+// A wavefront owns 16 rows x 16 outputs.  Per step of 4 input columns: A = the
+// 16 x 4 input block (global loads, lane l reads row r0 + l%16, column
+// n0 + l/16), B = the 4 x 16 twiddle block from LDS (exact index n m mod Nt,
+// advanced incrementally).  Waves of one block share the rows (m tiles
+// fastest), so the input is read from HBM once and reused from cache.
+__global__ __launch_bounds__(256) void k_dft_inner(const float2 *in, float2 *out, int rows, int N, int M, int Nt,
+                                                    int sign, int window, int post) {
     extern __shared__ float2 sm[];
-    float2 *tw = sm, *x = sm + N;
-    make_twiddles(tw, N, sign);
-    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            float2 v = in[(size_t)row * N + i];
-            float w = post ? 1.0f : window_at(window, i, N);
-            x[i] = make_float2(v.x * w, v.y * w);
+    float2 *tw = sm;
+    float *wt = reinterpret_cast<float *>(sm + Nt);
+    dft_tables(tw, wt, Nt, sign, window, post ? M : N);
+    const int mt = (M + 15) / 16;
+    const long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= (long long)mt * ((rows + 15) / 16)) return;   // wave-uniform; no barrier follows
+    const int m_t = (int)(tile % mt), r_t = (int)(tile / mt);
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int row = r_t * 16 + r;   // A row of this lane
+    const int m = m_t * 16 + r;     // B column of this lane
+    const float2 *src = in + (size_t)(row < rows ? row : 0) * N;
+    const int step = (int)((4LL * m) % Nt);
+    int idx = (int)(((long long)q * m) % Nt);
+    // 16 input columns per stage, two register buffers in turn: the loads of
+    // one stage are in flight while the MFMAs of the previous one run (no
+    // copy between buffers, so no wait on loads still in flight).  Loads are
+    // unconditional (clamped addresses; weight zero outside the matrix).
+    // Alternate steps go to two accumulator pairs.
+    const int N1 = N - 1;
+    f32x4 dr0 = {0.f, 0.f, 0.f, 0.f}, di0 = dr0, dr1 = dr0, di1 = dr0;
+    auto load = [&](float2 *buf, int n0) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) buf[u] = src[min(n0 + 4 * u + q, N1)];
+    };
+    auto stage = [&](const float2 *buf, int n0) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int n = n0 + 4 * u + q;
+            const float w = (row < rows && n < N) ? (post ? 1.0f : wt[min(n, N1)]) : 0.0f;
+            const float2 t = tw[idx];
+            idx += step;
+            if (idx >= Nt) idx -= Nt;
+            if (u & 1) cmfma(buf[u].x * w, buf[u].y * w, t.x, t.y, dr1, di1);
+            else cmfma(buf[u].x * w, buf[u].y * w, t.x, t.y, dr0, di0);
         }
-        __syncthreads();
-        for (int k = threadIdx.x; k < N; k += blockDim.x) {
-            float re = 0.0f, im = 0.0f;
-            int idx = 0;
-            for (int n = 0; n < N; n++) {
-                float2 t = tw[idx];
-                float2 v = x[n];
-                re = fmaf(v.x, t.x, fmaf(-v.y, t.y, re));
-                im = fmaf(v.x, t.y, fmaf(v.y, t.x, im));
-                idx += k;
-                if (idx >= N) idx -= N;
-            }
-            float w = post ? window_at(window, k, N) : 1.0f;
-            out[(size_t)row * N + k] = make_float2(re * w, im * w);
-        }
+    };
+    float2 ba[4], bb[4];
+    load(ba, 0);
+    for (int n0 = 0; n0 < N; n0 += 32) {
+        load(bb, n0 + 16);
+        stage(ba, n0);
+        load(ba, n0 + 32);
+        if (n0 + 16 < N) stage(bb, n0 + 16);
+    }
+    const f32x4 dr = dr0 + dr1, di = di0 + di1;
+    const int mo = m_t * 16 + r;
+    if (mo >= M) return;
+    const float w = post ? wt[mo] : 1.0f;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int ro = r_t * 16 + 4 * q + j;
+        if (ro < rows) out[(size_t)ro * M + mo] = make_float2(dr[j] * w, di[j] * w);
     }
 }
 
-// Transform along a middle axis of [outer][N][inner] -> [outer][M][inner]
-// (output index k < M, input index n < N, twiddle index (k n) mod Nt).
-// A block owns one outer index and 32 inner columns, staged in LDS.
-__global__ __launch_bounds__(256) void k_dft_mid(const float2 *in, float2 *out, int outer, int N, int M,
-                                                  int Nt, int inner, int sign, int window, int post) {
+// DFT along a middle axis as a dense FP32 contraction on the matrix cores:
+// [outer][N][inner] -> [outer][M][inner],
+//   out[o][m][i] = w_post(m) sum_n e^{sign 2 pi j (m n mod Nt) / Nt} w_pre(n) in[o][n][i].
+// A wavefront owns 16 (m) x 16 (i) outputs.  Per step of 4 input rows: A = the
+// 16 x 4 twiddle block from LDS (window folded in), B = the 4 x 16 input block
+// (four 128-byte row segments).
+__global__ __launch_bounds__(256) void k_dft_mid(const float2 *in, float2 *out, int outer, int N, int M, int Nt,
+                                                  int inner, int sign, int window, int post) {
     extern __shared__ float2 sm[];
-    float2 *tw = sm, *x = sm + Nt;
-    make_twiddles(tw, Nt, sign);
-    const int cols = 32;
-    const int nct = (inner + cols - 1) / cols;
-    for (int job = blockIdx.x; job < outer * nct; job += gridDim.x) {
-        const int o = job / nct, j0 = (job % nct) * cols;
-        __syncthreads();
-        for (int i = threadIdx.x; i < N * cols; i += blockDim.x) {
-            int n = i / cols, j = i % cols;
-            float2 v = make_float2(0.0f, 0.0f);
-            if (j0 + j < inner) v = in[((size_t)o * N + n) * inner + j0 + j];
-            float w = post ? 1.0f : window_at(window, n, N);
-            x[i] = make_float2(v.x * w, v.y * w);
+    float2 *tw = sm;
+    float *wt = reinterpret_cast<float *>(sm + Nt);
+    dft_tables(tw, wt, Nt, sign, window, post ? M : N);
+    const int mt = (M + 15) / 16, it = (inner + 15) / 16;
+    const long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= (long long)outer * mt * it) return;   // wave-uniform; no barrier follows
+    const int i_t = (int)(tile % it);
+    const long long rest = tile / it;
+    const int m_t = (int)(rest % mt), o = (int)(rest / mt);
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int m = m_t * 16 + r;   // A row of this lane
+    const int i = i_t * 16 + r;   // B column of this lane
+    const float2 *src = in + (size_t)o * N * inner + (i < inner ? i : 0);
+    const int step = (int)((4LL * m) % Nt);
+    int idx = (int)(((long long)q * m) % Nt);
+    // 16 input rows per stage, two register buffers in turn (as in
+    // k_dft_inner).  A (row m, column n) and B (row n, column i) are
+    // different elements: the window and the bounds of each are taken on its
+    // own indices.
+    const int N1 = N - 1;
+    const float bi_ok = i < inner ? 1.0f : 0.0f;
+    f32x4 dr0 = {0.f, 0.f, 0.f, 0.f}, di0 = dr0, dr1 = dr0, di1 = dr0;
+    auto load = [&](float2 *buf, int n0) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) buf[u] = src[(size_t)min(n0 + 4 * u + q, N1) * inner];
+    };
+    auto stage = [&](const float2 *buf, int n0) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int n = n0 + 4 * u + q;
+            const float w = n < N ? (post ? 1.0f : wt[min(n, N1)]) : 0.0f;
+            const float bw = n < N ? bi_ok : 0.0f;
+            const float2 t = tw[idx];
+            idx += step;
+            if (idx >= Nt) idx -= Nt;
+            if (u & 1) cmfma(t.x * w, t.y * w, buf[u].x * bw, buf[u].y * bw, dr1, di1);
+            else cmfma(t.x * w, t.y * w, buf[u].x * bw, buf[u].y * bw, dr0, di0);
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < M * cols; i += blockDim.x) {
-            int k = i / cols, j = i % cols;
-            if (j0 + j >= inner) continue;
-            float re = 0.0f, im = 0.0f;
-            int idx = 0;
-            for (int n = 0; n < N; n++) {
-                float2 t = tw[idx];
-                float2 v = x[n * cols + j];
-                re = fmaf(v.x, t.x, fmaf(-v.y, t.y, re));
-                im = fmaf(v.x, t.y, fmaf(v.y, t.x, im));
-                idx += k;
-                while (idx >= Nt) idx -= Nt;
-            }
-            float w = post ? window_at(window, k, M) : 1.0f;
-            out[((size_t)o * M + k) * inner + j0 + j] = make_float2(re * w, im * w);
+    };
+    float2 ba[4], bb[4];
+    load(ba, 0);
+    for (int n0 = 0; n0 < N; n0 += 32) {
+        load(bb, n0 + 16);
+        stage(ba, n0);
+        load(ba, n0 + 32);
+        if (n0 + 16 < N) stage(bb, n0 + 16);
+    }
+    const f32x4 dr = dr0 + dr1, di = di0 + di1;
+    if (i >= inner) return;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int mo = m_t * 16 + 4 * q + j;
+        if (mo < M) {
+            const float w = post ? wt[mo] : 1.0f;
+            out[((size_t)o * M + mo) * inner + i] = make_float2(dr[j] * w, di[j] * w);
         }
     }
 }
@@ -476,22 +558,24 @@ size_t cfar_scratch_bytes(int C, int S) {
     return align_up(cv.off, 256);
 }
 
+static size_t dft_lds_bytes(int N, int M, int Nt) {
+    return sizeof(float2) * (size_t)Nt + sizeof(float) * (size_t)std::max(N, M);
+}
+
 static int launch_inner(const float2 *in, float2 *out, int rows, int N, int sign, int window, int post,
                         hipStream_t s) {
-    int blocks = std::min(rows, 4096);
-    size_t lds = sizeof(float2) * 2 * N;
-    hipLaunchKernelGGL(k_dft_inner, dim3(blocks), dim3(256), lds, s, in, out, rows, N, sign, window, post);
+    const long long tiles = (long long)((N + 15) / 16) * ((rows + 15) / 16);
+    hipLaunchKernelGGL(k_dft_inner, dim3((unsigned)((tiles + 3) / 4)), dim3(256), dft_lds_bytes(N, N, N), s, in,
+                       out, rows, N, N, N, sign, window, post);
     SBR_LAUNCHED();
     return SBR_OK;
 }
 
 static int launch_mid(const float2 *in, float2 *out, int outer, int N, int M, int Nt, int inner, int sign,
                       int window, int post, hipStream_t s) {
-    int jobs = outer * ((inner + 31) / 32);
-    int blocks = std::min(jobs, 4096);
-    size_t lds = sizeof(float2) * (Nt + (size_t)N * 32);
-    hipLaunchKernelGGL(k_dft_mid, dim3(blocks), dim3(256), lds, s, in, out, outer, N, M, Nt, inner, sign,
-                       window, post);
+    const long long tiles = (long long)outer * ((M + 15) / 16) * ((inner + 15) / 16);
+    hipLaunchKernelGGL(k_dft_mid, dim3((unsigned)((tiles + 3) / 4)), dim3(256), dft_lds_bytes(N, M, Nt), s, in,
+                       out, outer, N, M, Nt, inner, sign, window, post);
     SBR_LAUNCHED();
     return SBR_OK;
 }
