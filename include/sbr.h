@@ -262,7 +262,9 @@ size_t sbr_radar_cube_2d_bytes(int32_t Vx, int32_t Vy, int32_t C, int32_t S, int
  * cube: device [Na][C][S][2].  points: device int32 [max_points][4] =
  * (range bin, Doppler bin, argmax_a |X|^2 (lowest on ties), 0) in row-major
  * (d, r) order; ratio: device float [max_points] = P / threshold, or NULL;
- * n_points: device int32, total detections (may exceed max_points). */
+ * n_points: device int32, total detections (may exceed max_points).
+ * Sizes: Na <= 65536, C and S <= 4096, guard + train < 4096; scratch:
+ * sbr_scratch_bytes(SBR_OP_CFAR, ...). */
 int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard,
              int32_t train, double pfa, int32_t *points, float *ratio, int32_t max_points,
              int32_t *n_points, void *scratch, size_t scratch_bytes, void *stream);

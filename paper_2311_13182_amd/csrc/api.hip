@@ -392,7 +392,8 @@ int sbr_cfar(const float *cube, int32_t Na, int32_t C, int32_t S, int32_t guard,
     SBR_CHECK_ARG(cube && n_points, "cube/n_points is NULL");
     SBR_CHECK_ARG(max_points >= 0 && (max_points == 0 || points), "points is NULL");
     SBR_CHECK_ARG(Na >= 1 && C >= 1 && S >= 1, "sizes must be >= 1");
-    SBR_CHECK_ARG(guard >= 0 && train >= 1, "guard >= 0 and train >= 1 required");
+    SBR_CHECK_ARG(Na <= 65536 && C <= 4096 && S <= 4096, "sizes out of range (Na <= 65536, C and S <= 4096)");
+    SBR_CHECK_ARG(guard >= 0 && train >= 1 && guard + train < 4096, "guard >= 0, train >= 1, guard + train < 4096");
     SBR_CHECK_ARG(pfa > 0.0 && pfa < 1.0, "pfa must be in (0, 1)");
     size_t need = cfar_scratch_bytes(C, S);
     if (!scratch || scratch_bytes < need) {

@@ -1,6 +1,9 @@
 // Backpropagation: adjoint of the IF synthesis (Eqs. 11-12) per path, then
 // the reverse sweep through the ray geometry of every ray (Eq. 13 chain rule)
 // with per-bounce recomputation, scattering dL/dverts.
+#include <map>
+#include <mutex>
+
 #include "sbr_internal.h"
 #include "sbr_device.h"
 
@@ -21,6 +24,7 @@ struct AdjArgs {
     float *tau_bar;        // [V][cap]
     float2 *abar_part;     // [nvs][cap]
     float *tdb_part;       // [nvs][cap] dL/d taudot partials
+    uint32_t *queue;       // work counter, zero at launch
 };
 
 constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time (at most 64 KiB)
@@ -34,12 +38,14 @@ constexpr int kAdjPPL = 2;       // paths per lane
 //   dL/dtau  += -2 pi Im(A (fc z0 P + (slope/fs) z0 x P'))       (Eq. 11)
 // Each lane carries PPL paths (256 apart) so every G sample read from LDS
 // feeds 8 * PPL fused multiply-adds.
+//
+// Work items are (antenna group, tile of 256 * PPL paths) pairs, antenna group
+// major; the number of live paths is only known on the device, so a grid of
+// about one device-full of blocks takes items from an atomic counter until
+// they run out (no blocks are launched for the empty path slots).
 template <int PPL>
-__global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
-    extern __shared__ float2 gsh[];   // [rows][Sp]
-    const int P = a.count[0];
-    const int blk_p0 = blockIdx.x * 256 * PPL;
-    if (blk_p0 >= P) return;   // uniform over the block
+__device__ __forceinline__ void adj_item(const AdjArgs &a, float2 *gsh, const int P, const int grp,
+                                         const int blk_p0) {
     int pp[PPL];
     bool act[PPL];
     float2 A[PPL];
@@ -57,7 +63,7 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
         tdb[i] = 0.0f;
         pp[i] = pc;
     }
-    const int v0 = blockIdx.y * a.v_per, v1 = min(a.V, v0 + a.v_per);
+    const int v0 = grp * a.v_per, v1 = min(a.V, v0 + a.v_per);
     const int S = a.S;
     for (int v = v0; v < v1; v++) {
         float alpha[PPL], gamma[PPL], tb[PPL];
@@ -143,9 +149,28 @@ __global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
 #pragma unroll
     for (int i = 0; i < PPL; i++)
         if (act[i]) {
-            a.abar_part[(size_t)blockIdx.y * a.rec.cap + pp[i]] = make_float2(abr[i], abi[i]);
-            a.tdb_part[(size_t)blockIdx.y * a.rec.cap + pp[i]] = tdb[i];
+            a.abar_part[(size_t)grp * a.rec.cap + pp[i]] = make_float2(abr[i], abi[i]);
+            a.tdb_part[(size_t)grp * a.rec.cap + pp[i]] = tdb[i];
         }
+}
+
+template <int PPL>
+__global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
+    // [rows][Sp] G rows, then the current work item.  No static LDS: it would
+    // shift the dynamic area off the 16-byte alignment of the row reads.
+    extern __shared__ float2 gsh[];
+    uint32_t &s_item = *reinterpret_cast<uint32_t *>(gsh + a.rows * a.Sp);
+    const int P = a.count[0];
+    const uint32_t tiles = (uint32_t)((P + 256 * PPL - 1) / (256 * PPL));
+    const uint32_t total = tiles * (uint32_t)a.nvs;
+    for (;;) {
+        __syncthreads();   // the previous item is done with s_item and gsh
+        if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= total) break;   // uniform over the block
+        adj_item<PPL>(a, gsh, P, (int)(item / tiles), (int)(item % tiles) * 256 * PPL);
+    }
 }
 
 __global__ void k_reduce_abar(const int32_t *count, const float2 *part, const float *tpart, int nvs, int cap,
@@ -598,7 +623,32 @@ size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V) {
     cv.take<float2>(cap);
     cv.take<float>((size_t)bp.nvs * cap);
     cv.take<float>(cap);
+    cv.take<uint32_t>(64);
     return align_up(cv.off, 256);
+}
+
+// Blocks of k_synth_adj the device holds at once (CUs times the occupancy of
+// the compiled kernel with its LDS), queried once per (device, LDS size);
+// 256 CUs x 2 where the runtime cannot answer.
+static int resident_adj_blocks(size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<int, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 256 * 2;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({dev, lds});
+    if (it != cache.end()) return it->second;
+    int cus = 0, nb = 0;
+    hipError_t e1 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth_adj<kAdjPPL>, 256, lds);
+    int res = 256 * 2;
+    if (e1 == hipSuccess && e2 == hipSuccess && cus > 0 && nb > 0) res = cus * nb;
+    else (void)hipGetLastError();
+    cache[{dev, lds}] = res;
+    return res;
 }
 
 int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
@@ -614,6 +664,9 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     float2 *abar = cv.take<float2>(cap);
     float *tpart = cv.take<float>((size_t)bp.nvs * cap);
     float *tdbar = cv.take<float>(cap);
+    uint32_t *queue = cv.take<uint32_t>(64);
+    int rc = fill_zero_f32(reinterpret_cast<float *>(queue), 1, s);   // all-zero bits
+    if (rc) return rc;
     AdjArgs a;
     a.count = st.count;
     a.rec = st.rec;
@@ -629,10 +682,13 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     a.tau_bar = tau_bar;
     a.abar_part = part;
     a.tdb_part = tpart;
-    dim3 grid((unsigned)((cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL)), (unsigned)bp.nvs);
+    a.queue = queue;
     a.Sp = (cd.S + 7) / 8 * 8;
     a.rows = std::max(1, std::min(kAdjRowsMax, 8192 / a.Sp));
-    size_t lds = sizeof(float2) * a.rows * a.Sp;
+    size_t lds = sizeof(float2) * a.rows * a.Sp + 16;
+    // one device-full of blocks, or fewer if the path slots cannot fill it
+    const long long items_max = (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL) * bp.nvs;
+    dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_max, resident_adj_blocks(lds))));
     {
         ProfScope ps(kProfSynthAdj, s);
         hipLaunchKernelGGL(k_synth_adj<kAdjPPL>, grid, dim3(256), lds, s, a);

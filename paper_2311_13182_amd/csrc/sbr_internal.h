@@ -180,6 +180,10 @@ class ProfScope {
 };
 enum { kProfSynth = 0, kProfSynthAdj = 1, kProfTrace = 2 };
 
+// zero n floats with a fill kernel on stream s (no memset node, so the call
+// can sit in a captured graph)
+int fill_zero_f32(float *p, size_t n, hipStream_t s);
+
 // enqueue path compaction + FP64 refinement; records go to st.rec
 int launch_paths(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                  const ChirpDev &cd, const sbr_hits *h, int32_t flags, const PathStage &st,

@@ -99,6 +99,9 @@ def test_argument_errors_are_reported(lib):
     # CFAR: bad pfa
     assert lib.sbr_cfar(fake, 4, 8, 16, 2, 8, ct.c_double(2.0), fake, None, 10, fake, fake, 1 << 30,
                         None) == L.SBR_E_ARG
+    # CFAR: sizes beyond the documented limits
+    assert lib.sbr_cfar(fake, 4, 8192, 16, 2, 8, ct.c_double(1e-4), fake, None, 10, fake, fake, 1 << 30,
+                        None) == L.SBR_E_ARG
     # BVH: empty mesh
     m0 = L.sbr_mesh(None, 0, None, 0, None)
     assert lib.sbr_build_bvh(ct.byref(m0), fake, 1 << 20, 0, fake, 1 << 20, None) == L.SBR_E_ARG
