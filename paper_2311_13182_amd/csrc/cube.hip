@@ -34,6 +34,16 @@ __device__ __forceinline__ void cmfma(float ar, float ai, float br, float bi, f3
     di = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, di, 0, 0, 0);
 }
 
+// Workgroups are dealt to the 8 XCDs round robin.  Renumber them so that each
+// XCD runs a contiguous range of logical blocks: neighbouring tiles, which
+// read the same input rows, then share one L2.  The ragged tail (gridDim.x
+// mod 8 blocks) keeps its index.
+__device__ __forceinline__ long long xcd_logical_block() {
+    const unsigned b = blockIdx.x, per = gridDim.x / 8;
+    if (b >= per * 8) return b;
+    return (long long)(b % 8) * per + b / 8;
+}
+
 // LDS tables shared by both transforms: Nt twiddles, then the window over the
 // pre-windowed input axis (length N) or the post-windowed output axis (M).
 __device__ void dft_tables(float2 *tw, float *wt, int Nt, int sign, int window, int Lw) {
@@ -57,7 +67,7 @@ __global__ __launch_bounds__(256) void k_dft_inner(const float2 *in, float2 *out
     float *wt = reinterpret_cast<float *>(sm + Nt);
     dft_tables(tw, wt, Nt, sign, window, post ? M : N);
     const int mt = (M + 15) / 16;
-    const long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long long tile = xcd_logical_block() * 4 + (threadIdx.x >> 6);
     if (tile >= (long long)mt * ((rows + 15) / 16)) return;   // wave-uniform; no barrier follows
     const int m_t = (int)(tile % mt), r_t = (int)(tile / mt);
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
@@ -121,11 +131,13 @@ __global__ __launch_bounds__(256) void k_dft_mid(const float2 *in, float2 *out, 
     float *wt = reinterpret_cast<float *>(sm + Nt);
     dft_tables(tw, wt, Nt, sign, window, post ? M : N);
     const int mt = (M + 15) / 16, it = (inner + 15) / 16;
-    const long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // m tiles fastest: the waves of a block, and neighbouring blocks, share
+    // their input columns
+    const long long tile = xcd_logical_block() * 4 + (threadIdx.x >> 6);
     if (tile >= (long long)outer * mt * it) return;   // wave-uniform; no barrier follows
-    const int i_t = (int)(tile % it);
-    const long long rest = tile / it;
-    const int m_t = (int)(rest % mt), o = (int)(rest / mt);
+    const int m_t = (int)(tile % mt);
+    const long long rest = tile / mt;
+    const int i_t = (int)(rest % it), o = (int)(rest / it);
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     const int m = m_t * 16 + r;   // A row of this lane
     const int i = i_t * 16 + r;   // B column of this lane
