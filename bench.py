@@ -63,7 +63,7 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(scene, queries_full: int, budget_rows: int = 16, chirp_stride: int = 16):
+def cpu_baseline(scene, queries_full: int, budget_rows: int = 8, chirp_stride: int = 16):
     """The FP64 oracle (trace + paths + synthesis + synthesis adjoint) on a
     bounded sample: every `budget_rows`-th ray row and column, every
     `chirp_stride`-th chirp; scaled linearly to the full workload."""
