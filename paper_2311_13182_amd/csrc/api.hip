@@ -2,7 +2,10 @@
 #include <stdarg.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 
 #include "sbr_internal.h"
 
@@ -51,6 +54,28 @@ int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window,
 int cfar_launch(const float2 *cube, int Na, int C, int S, int guard, int train, double pfa, int32_t *points,
                 float *ratio_out, int maxp, int32_t *npts, void *scratch, hipStream_t s);
 int fill_zero_f32(float *p, size_t n, hipStream_t s);
+
+int resident_blocks(const void *kernel, int threads, size_t lds, int fallback) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, int, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fallback;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_tuple(dev, kernel, threads, lds);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int cus = 0, nb = 0;
+    hipError_t e1 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds);
+    int res = fallback;
+    if (e1 == hipSuccess && e2 == hipSuccess && cus > 0 && nb > 0) res = cus * nb;
+    else (void)hipGetLastError();
+    cache[key] = res;
+    return res;
+}
 
 int check_mesh(const sbr_mesh *m) {
     SBR_CHECK_ARG(m, "mesh is NULL");

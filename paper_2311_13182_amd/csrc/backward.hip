@@ -1,9 +1,6 @@
 // Backpropagation: adjoint of the IF synthesis (Eqs. 11-12) per path, then
 // the reverse sweep through the ray geometry of every ray (Eq. 13 chain rule)
 // with per-bounce recomputation, scattering dL/dverts.
-#include <map>
-#include <mutex>
-
 #include "sbr_internal.h"
 #include "sbr_device.h"
 
@@ -627,30 +624,6 @@ size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V) {
     return align_up(cv.off, 256);
 }
 
-// Blocks of k_synth_adj the device holds at once (CUs times the occupancy of
-// the compiled kernel with its LDS), queried once per (device, LDS size);
-// 256 CUs x 2 where the runtime cannot answer.
-static int resident_adj_blocks(size_t lds) {
-    static std::mutex mu;
-    static std::map<std::pair<int, size_t>, int> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
-        (void)hipGetLastError();
-        return 256 * 2;
-    }
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find({dev, lds});
-    if (it != cache.end()) return it->second;
-    int cus = 0, nb = 0;
-    hipError_t e1 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipError_t e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth_adj<kAdjPPL>, 256, lds);
-    int res = 256 * 2;
-    if (e1 == hipSuccess && e2 == hipSuccess && cus > 0 && nb > 0) res = cus * nb;
-    else (void)hipGetLastError();
-    cache[{dev, lds}] = res;
-    return res;
-}
-
 int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
                     const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
                     const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
@@ -688,7 +661,7 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     size_t lds = sizeof(float2) * a.rows * a.Sp + 16;
     // one device-full of blocks, or fewer if the path slots cannot fill it
     const long long items_max = (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL) * bp.nvs;
-    dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_max, resident_adj_blocks(lds))));
+    dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_max, resident_blocks((const void *)k_synth_adj<kAdjPPL>, 256, lds, 256 * 2))));
     {
         ProfScope ps(kProfSynthAdj, s);
         hipLaunchKernelGGL(k_synth_adj<kAdjPPL>, grid, dim3(256), lds, s, a);

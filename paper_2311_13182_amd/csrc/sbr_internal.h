@@ -180,6 +180,12 @@ class ProfScope {
 };
 enum { kProfSynth = 0, kProfSynthAdj = 1, kProfTrace = 2 };
 
+// Blocks of `kernel` (launched with `threads` threads and `lds` bytes of
+// dynamic LDS) the current device holds at once: CUs times the occupancy the
+// runtime reports for the compiled kernel, cached per (device, kernel,
+// threads, lds); `fallback` where the runtime cannot answer.
+int resident_blocks(const void *kernel, int threads, size_t lds, int fallback);
+
 // zero n floats with a fill kernel on stream s (no memset node, so the call
 // can sit in a captured graph)
 int fill_zero_f32(float *p, size_t n, hipStream_t s);

@@ -1,8 +1,6 @@
 // Path stage (FP64 refinement of every hit into I^t / I^s, compacted in
 // ray-major order) and the IF synthesis of Eq. (8).
 #include <cmath>
-#include <map>
-#include <mutex>
 #include <utility>
 
 #include "sbr_internal.h"
@@ -375,36 +373,14 @@ int fill_zero_f32(float *p, size_t n, hipStream_t s) {
 
 constexpr int kSynthL = 64;   // samples per lane (128 measured slower: occupancy 1)
 
-// Blocks of 256 threads of k_synth<L> the device holds at once: CUs times the
-// occupancy of the compiled kernel, queried once per (device, L); 256 CUs x 3
-// where the runtime cannot answer (no device in this process).
+// Blocks of 256 threads of k_synth<L> the device holds at once (256 CUs x 3
+// where the runtime cannot answer).
 static int resident_synth_blocks(int L) {
-    static std::mutex mu;
-    static std::map<std::pair<int, int>, int> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
-        (void)hipGetLastError();
-        return 256 * 3;
-    }
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find({dev, L});
-    if (it != cache.end()) return it->second;
-    int cus = 0, nb = 0;
-    hipError_t e1 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipError_t e2;
-    if (L == 128)
-        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth<128>, 256, 0);
-    else if (L == 64)
-        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth<64>, 256, 0);
-    else if (L == 32)
-        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth<32>, 256, 0);
-    else
-        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_synth<16>, 256, 0);
-    int res = 256 * 3;
-    if (e1 == hipSuccess && e2 == hipSuccess && cus > 0 && nb > 0) res = cus * nb;
-    else (void)hipGetLastError();
-    cache[{dev, L}] = res;
-    return res;
+    const void *k = L == 128 ? (const void *)k_synth<128>
+                    : L == 64 ? (const void *)k_synth<64>
+                    : L == 32 ? (const void *)k_synth<32>
+                              : (const void *)k_synth<16>;
+    return resident_blocks(k, 256, 0, 256 * 3);
 }
 
 // Paths are split into n_chunks chunks (grid.y).  Every wave of the grid does
