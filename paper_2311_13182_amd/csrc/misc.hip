@@ -77,14 +77,24 @@ ProfScope::ProfScope(int id, hipStream_t s) : id_(id), s_(s), active_(false) {
         (void)hipEventDestroy(a_);
         return;
     }
-    if (hipEventRecord(a_, s_) != hipSuccess) return;
+    if (hipEventRecord(a_, s_) != hipSuccess) {
+        (void)hipEventDestroy(a_);
+        (void)hipEventDestroy(b_);
+        return;
+    }
     active_ = true;
 }
 
 ProfScope::~ProfScope() {
     if (!active_) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    if (hipEventRecord(b_, s_) == hipSuccess) g_rec[id_].push_back({a_, b_});
+    if (hipEventRecord(b_, s_) == hipSuccess) {
+        g_rec[id_].push_back({a_, b_});
+    } else {
+        (void)hipEventSynchronize(a_);
+        (void)hipEventDestroy(a_);
+        (void)hipEventDestroy(b_);
+    }
 }
 
 int fill_zero_f32(float *p, size_t n, hipStream_t s);
