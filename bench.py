@@ -8,7 +8,7 @@ IF-loss gradient, backward (synthesis adjoint, Eqs. 11-12, and geometry
 adjoint to the vertices, Eq. 13).  Inputs are resident in device memory before
 the timed region.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -113,7 +113,7 @@ def main():
                     help="run one plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the ray-sharded multi-GPU split is a design "
+        print("bench.py: the library runs on one GPU only (the ray-sharded multi-GPU split is a design "
               "note, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
