@@ -259,16 +259,79 @@ __device__ __forceinline__ float frac_mul(float n, float f) {
     return fmaf(n, f, -rintf(p));
 }
 
+// A path's beat frequency delta (cycles per sample) is within 0.0403 of 0 or
+// 1/2 -- |sin(2 pi delta)| < 1/4 -- on some lane of the wavefront.  Its lanes
+// differ only in chirp, so in delta only by the tiny Doppler drift, and the
+// choice is made once per wavefront.
+__device__ __forceinline__ bool near_dc_or_nyquist(float dph) {
+    const float m = fabsf(dph);
+    return __any(m < 0.0403f || m > 0.4597f);
+}
+
+constexpr int kRotList = 512;   // paths per wavefront remembered for the rotation pass
+
+// Accumulate one path into the lane's L samples.  ROT = false advances the
+// phase with the real three-term recurrence z[s+1] = 2 cos(2 pi delta) z[s] -
+// z[s-1] (2 FMA per sample), which loses about cot(2 pi delta) <= 4 ulps of
+// frequency per step on the paths it is used for.  ROT = true advances by
+// complex rotation z[s+1] = z[s] w (4 per sample), accurate at every
+// frequency, for the paths near 0 or 1/2 cycle per sample.  Both restart the
+// phase exactly (hardware sin/cos in revolutions).
+template <int L, bool ROT>
+__device__ __forceinline__ void add_path(float alpha, float delta, float dph, float beta, float2 A, float cf,
+                                         float s0, float (&ar)[L], float (&ai)[L]) {
+    float ph = alpha + frac_mul(cf, beta) + frac_mul(s0, delta);
+    ph = ph - rintf(ph);
+    const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+    const float ws = __builtin_amdgcn_sinf(dph), wc = __builtin_amdgcn_cosf(dph);
+    float zr = A.x * cs - A.y * sn, zi = A.x * sn + A.y * cs;   // z[s0]
+    float yr = zr * wc - zi * ws, yi = zr * ws + zi * wc;       // z[s0 + 1]
+    ar[0] += zr;
+    ai[0] += zi;
+    if (L > 1) {
+        ar[1] += yr;
+        ai[1] += yi;
+    }
+    if (!ROT) {
+        const float k2 = 2.0f * wc;
+#pragma unroll
+        for (int i = 2; i < L; i++) {
+            float nr = fmaf(k2, yr, -zr);
+            float ni = fmaf(k2, yi, -zi);
+            zr = yr;
+            zi = yi;
+            yr = nr;
+            yi = ni;
+            ar[i] += nr;
+            ai[i] += ni;
+        }
+    } else {
+#pragma unroll
+        for (int i = 2; i < L; i++) {
+            float nr = fmaf(yr, wc, -yi * ws);
+            float ni = fmaf(yr, ws, yi * wc);
+            yr = nr;
+            yi = ni;
+            ar[i] += nr;
+            ai[i] += ni;
+        }
+    }
+}
+
 // One wavefront owns 64 (chirp, sample-block) lanes of one antenna; each lane
-// accumulates L consecutive samples over a chunk of paths.  Per path the lane
-// restarts the phase exactly (hardware sin/cos in revolutions) and advances it
-// with the real three-term recurrence z[s+1] = 2 cos(2 pi delta) z[s] - z[s-1].
+// accumulates L consecutive samples over a chunk of paths.  The main pass
+// takes the paths whose beat frequency is well away from 0 and 1/2 cycle per
+// sample on every lane (recurrence) and remembers the others in LDS; a second
+// pass adds those by rotation (it rescans the chunk if more than kRotList of
+// them came up).  Path records are wavefront-uniform (scalar loads); the next
+// one is fetched while the current one is accumulated.
 template <int L>
 __global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
+    __shared__ int rot_list[4][kRotList];
     const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int v = __builtin_amdgcn_readfirstlane(wv / a.tiles_per_v);
-    if (v >= a.V) return;
+    if (v >= a.V) return;   // wave-uniform; the kernel has no block barrier
     const int e = (wv % a.tiles_per_v) * 64 + lane;
     const int c = e / a.SB, b = e % a.SB;
     const int chunk = blockIdx.y;
@@ -286,55 +349,50 @@ __global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
     }
     const float *al = a.rec.alpha + (size_t)v * a.rec.cap;
     const float *ga = a.rec.gamma + (size_t)v * a.rec.cap;
-    // path records are wavefront-uniform (scalar loads); the next path's
-    // record is fetched while the current one is accumulated
-    float n_al = 0.f, n_ga = 0.f, n_be = 0.f, n_ep = 0.f;
-    float2 n_A = make_float2(0.f, 0.f);
-    if (p0 < p1) {
-        n_al = al[p0];
-        n_ga = ga[p0];
-        n_A = a.rec.amp[p0];
-        n_be = a.rec.beta[p0];
-        n_ep = a.rec.epsd[p0];
-    }
-    for (int p = p0; p < p1; p++) {
-        const float alpha = n_al, gamma = n_ga, beta = n_be, epsd = n_ep;
-        const float2 A = n_A;
-        if (p + 1 < p1) {
-            n_al = al[p + 1];
-            n_ga = ga[p + 1];
-            n_A = a.rec.amp[p + 1];
-            n_be = a.rec.beta[p + 1];
-            n_ep = a.rec.epsd[p + 1];
+    int n_rot = 0;   // wave-uniform
+    {
+        float n_al = 0.f, n_ga = 0.f, n_be = 0.f, n_ep = 0.f;
+        float2 n_A = make_float2(0.f, 0.f);
+        if (p0 < p1) {
+            n_al = al[p0];
+            n_ga = ga[p0];
+            n_A = a.rec.amp[p0];
+            n_be = a.rec.beta[p0];
+            n_ep = a.rec.epsd[p0];
         }
-        const float delta = fmaf(cf, epsd, gamma);            // cycles per sample
-        float ph = alpha + frac_mul(cf, beta) + frac_mul(s0, delta);
-        ph = ph - rintf(ph);
-        float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        float dph = delta - rintf(delta);
-        float ws = __builtin_amdgcn_sinf(dph), wc = __builtin_amdgcn_cosf(dph);
-        float zr = A.x * cs - A.y * sn, zi = A.x * sn + A.y * cs;   // z[s0]
-        float yr = zr * wc - zi * ws, yi = zr * ws + zi * wc;       // z[s0 + 1]
-        ar[0] += zr;
-        ai[0] += zi;
-        if (L > 1) {
-            ar[1] += yr;
-            ai[1] += yi;
-        }
-        {
-            const float k2 = 2.0f * wc;
-#pragma unroll
-            for (int i = 2; i < L; i++) {
-                float nr = fmaf(k2, yr, -zr);
-                float ni = fmaf(k2, yi, -zi);
-                zr = yr;
-                zi = yi;
-                yr = nr;
-                yi = ni;
-                ar[i] += nr;
-                ai[i] += ni;
+        for (int p = p0; p < p1; p++) {
+            const float alpha = n_al, gamma = n_ga, beta = n_be, epsd = n_ep;
+            const float2 A = n_A;
+            if (p + 1 < p1) {
+                n_al = al[p + 1];
+                n_ga = ga[p + 1];
+                n_A = a.rec.amp[p + 1];
+                n_be = a.rec.beta[p + 1];
+                n_ep = a.rec.epsd[p + 1];
             }
+            const float delta = fmaf(cf, epsd, gamma);   // cycles per sample
+            const float dph = delta - rintf(delta);
+            if (near_dc_or_nyquist(dph)) {
+                if (n_rot < kRotList && lane == 0) rot_list[wl][n_rot] = p;
+                n_rot++;
+                continue;
+            }
+            add_path<L, false>(alpha, delta, dph, beta, A, cf, s0, ar, ai);
         }
+    }
+    // rotation pass: over the remembered paths, or the whole chunk again if
+    // they did not fit (one loop body, so the accumulators are not doubled)
+    const bool listed = n_rot <= kRotList;
+    const int n_iter = n_rot == 0 ? 0 : (listed ? n_rot : p1 - p0);
+    // the list was written by lane 0 of this wavefront; LDS operations of one
+    // wavefront complete in order
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int i = 0; i < n_iter; i++) {
+        const int p = listed ? __builtin_amdgcn_readfirstlane(rot_list[wl][i]) : p0 + i;
+        const float delta = fmaf(cf, a.rec.epsd[p], ga[p]);
+        const float dph = delta - rintf(delta);
+        if (!listed && !near_dc_or_nyquist(dph)) continue;
+        add_path<L, true>(al[p], delta, dph, a.rec.beta[p], a.rec.amp[p], cf, s0, ar, ai);
     }
     if (c < a.C) {
         float2 *out = a.partial + ((size_t)chunk * a.V + v) * (size_t)a.C * a.S + (size_t)c * a.S;

@@ -144,6 +144,23 @@ def planar_radar(n_tx: int = 20, n_rx: int = 20, fc: float = 62e9, vel=(0.0, 0.0
     return Radar(origin=np.zeros(3), rot=np.eye(3), tx=tx, rx=rx, vel=np.asarray(vel, float), planar=True)
 
 
+def platform(name: str) -> Tuple[Radar, Chirp]:
+    """Radar and chirp of the three FMCW platform classes of Sec. 4.  The paper
+    gives each one's band and antenna counts only; the chirps here are
+    choices that fit those bands (256 samples at 10 MHz in every case):
+      "ranging_24g"    1 TX, 2 RX at 24 GHz, 200 MHz swept over the ADC window
+      "automotive_77g" 3 TX, 4 RX lambda/2 ULA at 77 GHz, 60 MHz/us
+      "imaging_62g"    20 TX x 20 RX planar grid at 62 GHz, 7 GHz swept"""
+    window = 256 / 10e6
+    if name == "ranging_24g":
+        return default_radar(1, 2, 24.0e9), Chirp(fc=24.0e9, slope=200e6 / window)
+    if name == "automotive_77g":
+        return default_radar(3, 4, 77e9), Chirp(fc=77e9, slope=60e12)
+    if name == "imaging_62g":
+        return planar_radar(20, 20, 62e9), Chirp(fc=62e9, slope=7e9 / window, t_chirp=40e-6)
+    raise ValueError(f"unknown platform {name!r}")
+
+
 def fov_tan(radius: float, distance: float, margin: float = 1.02) -> float:
     """Half-width of the tangent grid that covers a bounding sphere."""
     return math.tan(math.asin(min(radius / distance, 0.999))) * margin

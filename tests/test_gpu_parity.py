@@ -1012,3 +1012,78 @@ def test_backward_several_antennas_per_work_item(torch_cuda, orc):
         errs.append(abs(float((got * w).sum()) - fd) / abs(fd))
     log(f"  directional rel errors {errs}")
     assert max(errs) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name", ["ranging_24g", "automotive_77g"])
+def test_platform_presets_synth_and_backward(torch_cuda, orc, name):
+    """The trihedral + plate scene seen by the platform classes of Sec. 4
+    (24 GHz 1 TX / 2 RX ranging radar; 77 GHz 3 TX / 4 RX automotive radar):
+    IF cube vs the oracle and the vertex gradient vs its central differences
+    on every coordinate."""
+    import torch
+    radar, chirp = S.platform(name)
+    sc = dataclasses.replace(S.trihedral_plate(), radar=radar, chirp=dataclasses.replace(chirp, n_chirps=2))
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    want = orc.synth(sc, p)
+    tgt = _target(orc, sc, 1e-3, 13)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    got = _cube_np(sim.synth())
+    e = rel_l2(got, want)
+    G = 2.0 * (want - tgt)
+    g = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda")).cpu().numpy().astype(np.float64)
+    fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, h=1e-9).reshape(-1, 3)
+    eg = rel_l2(g, fd)
+    log(f"platform {name}: V={sc.radar.n_virtual}, {len(p['amp'])} paths, synth rel L2 {e:.3e}, backward {eg:.3e}")
+    assert e <= 1e-4 and eg <= GRAD_TOL
+
+
+@pytest.mark.parametrize("case", ["near_dc_24g", "near_nyquist_77g"])
+def test_synth_low_and_high_beat_frequency(torch_cuda, orc, case):
+    """Beat frequencies near 0 and near f_s / 2 per sample, where a real
+    three-term recurrence cos-coefficient is ill-conditioned: a plate at 0.5 m
+    seen by the 24 GHz ranging radar (0.0026 cycles per sample), and one at
+    12.4 m seen by the 77 GHz radar (0.496 cycles per sample)."""
+    if case == "near_dc_24g":
+        radar, chirp = S.platform("ranging_24g")
+        dist, size = 0.5, 0.05
+    else:
+        radar, chirp = S.platform("automotive_77g")
+        dist, size = 12.4, 1.0
+    v, f = S.plate(size, dist)
+    th = 0.6 * size / dist
+    sc = S.Scene(case, v.astype(np.float32), f.astype(np.int32), radar, dataclasses.replace(chirp, n_chirps=2),
+                 S.Grid(40, 40, th, th, 1))
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    want = orc.synth(sc, p)
+    delta = chirp.slope * p["tau"].mean() / chirp.fs
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    got = _cube_np(sim.synth())
+    e = rel_l2(got, want)
+    log(f"{case}: {len(p['amp'])} paths, {delta:.4f} cycles per sample, synth rel L2 {e:.3e}")
+    assert len(p["amp"]) > 100 and e <= 1e-4
+
+
+def test_synth_many_near_dc_paths_per_wavefront(torch_cuda, orc):
+    """A million paths, all near 0 cycles per sample (a plate filling the
+    1024^2 grid at 0.5 m, 24 GHz ranging radar): each wavefront meets more
+    near-DC paths than it can remember, so the rotation pass rescans its chunk.
+    Sampled cube rows vs the oracle."""
+    radar, chirp = S.platform("ranging_24g")
+    v, f = S.plate(0.6, 0.5)
+    sc = S.Scene("plate_near_dc", v.astype(np.float32), f.astype(np.int32), radar,
+                 dataclasses.replace(chirp, n_chirps=2), S.Grid(1024, 1024, 0.5, 0.5, 1))
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    assert len(p["amp"]) > 600 * 1024   # more than 512 per wavefront at the 1024-chunk cap
+    rows = np.array([0, 3], np.int32)
+    want = orc.synth(sc, p, rows=rows)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    got = _cube_np(sim.synth()).reshape(-1, sc.chirp.n_samples)[rows]
+    e = rel_l2(got, want)
+    log(f"many near-DC paths: {len(p['amp'])} paths, rows {list(rows)}: rel L2 {e:.3e}")
+    assert e <= 1e-4

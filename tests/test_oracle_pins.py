@@ -283,6 +283,26 @@ def test_range_peaks_of_plate_and_trihedral(orc):
         assert prof[j] >= prof[j - 1] and prof[j] >= prof[j + 1]
 
 
+def test_ranging_platform_plate_peak(orc):
+    """The 24 GHz 1 TX / 2 RX ranging class of Sec. 4 with a 200 MHz sweep:
+    a plate at 3 m on boresight beats at 2 R mu / c = 156.4 kHz, range bin
+    4.00 of 256 samples at 10 MHz, and reaches both receivers (lambda/2 apart,
+    target on boresight) with equal strength."""
+    radar, chirp = S.platform("ranging_24g")
+    assert radar.n_virtual == 2 and chirp.fc == 24e9
+    v, f = S.plate(0.3, 3.0)
+    sc = S.Scene("plate_24g", v.astype(np.float32), f.astype(np.int32), radar, chirp,
+                 S.Grid(48, 48, 0.06, 0.06, 1))
+    cube, _, _ = orc.forward(sc)
+    want = 2 * 3.0 * chirp.slope / C0 * chirp.n_samples / chirp.fs
+    assert abs(want - 4.0) < 0.01
+    X = orc.radar_cube(cube, n_angle=2)
+    prof = np.abs(X).sum(axis=(0, 1))
+    assert int(np.argmax(prof)) == 4
+    e = np.abs(cube).sum(axis=(1, 2))
+    assert abs(e[0] - e[1]) <= 1e-9 * e.max()
+
+
 def test_doppler_and_angle_peaks(orc):
     C = 64
     sc = S.icosphere_scene(level=1, n_rays=8, n_chirps=C)
