@@ -1087,3 +1087,34 @@ def test_synth_many_near_dc_paths_per_wavefront(torch_cuda, orc):
     e = rel_l2(got, want)
     log(f"many near-DC paths: {len(p['amp'])} paths, rows {list(rows)}: rel L2 {e:.3e}")
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("case", ["near_dc_24g", "near_nyquist_77g"])
+def test_backward_low_and_high_beat_frequency(torch_cuda, orc, case):
+    """The synthesis adjoint's Horner sums at beat frequencies near 0 and 1/2
+    cycle per sample: vertex gradient vs the oracle's central differences."""
+    import torch
+    if case == "near_dc_24g":
+        radar, chirp = S.platform("ranging_24g")
+        dist, size = 0.5, 0.05
+    else:
+        radar, chirp = S.platform("automotive_77g")
+        dist, size = 12.4, 1.0
+    v, f = S.plate(size, dist)
+    v = v + np.random.default_rng(41).normal(scale=1e-3 * size, size=v.shape)
+    th = 0.6 * size / dist
+    sc = S.Scene(case, v.astype(np.float32), f.astype(np.int32), radar, dataclasses.replace(chirp, n_chirps=2),
+                 S.Grid(40, 40, th, th, 1))
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    Sx = orc.synth(sc, p)
+    rng = np.random.default_rng(42)
+    tgt = 0.8 * Sx + 0.05 * np.abs(Sx).max() * (rng.normal(size=Sx.shape) + 1j * rng.normal(size=Sx.shape))
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    g = sim.backward(torch.as_tensor((2.0 * (Sx - tgt)).astype(np.complex64), device="cuda"))
+    got = g.cpu().numpy().astype(np.float64)
+    fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, h=1e-9).reshape(-1, 3)
+    e = rel_l2(got, fd)
+    log(f"backward {case}: {len(p['amp'])} paths, rel L2 {e:.3e}")
+    assert e <= GRAD_TOL
