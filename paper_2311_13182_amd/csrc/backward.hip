@@ -24,7 +24,7 @@ struct AdjArgs {
     uint32_t *queue;       // work counter, zero at launch
 };
 
-constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time (at most 64 KiB)
+constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time
 constexpr int kAdjPPL = 2;       // paths per lane
 
 // Path-stationary adjoint of Eq. (8).  For each (path, v, c) the sums
@@ -657,7 +657,9 @@ int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, c
     a.tdb_part = tpart;
     a.queue = queue;
     a.Sp = (cd.S + 7) / 8 * 8;
-    a.rows = std::max(1, std::min(kAdjRowsMax, 8192 / a.Sp));
+    // G rows per LDS stage, with the 16-byte work-item slot after them, within
+    // 64 KiB of LDS per block
+    a.rows = std::max(1, std::min<int>(kAdjRowsMax, (65536 - 16) / (int)(sizeof(float2) * a.Sp)));
     size_t lds = sizeof(float2) * a.rows * a.Sp + 16;
     // one device-full of blocks, or fewer if the path slots cannot fill it
     const long long items_max = (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL) * bp.nvs;

@@ -1118,3 +1118,41 @@ def test_backward_low_and_high_beat_frequency(torch_cuda, orc, case):
     e = rel_l2(got, fd)
     log(f"backward {case}: {len(p['amp'])} paths, rel L2 {e:.3e}")
     assert e <= GRAD_TOL
+
+
+def test_max_samples_and_chirps(torch_cuda, orc):
+    """The largest chirp the library accepts, 4096 samples x 4096 chirps (one
+    antenna pair), on the trihedral + plate scene with a coarse grid: IF cube
+    vs the oracle on sampled chirp rows, and the synthesis adjoint (one G row
+    per LDS stage at this length) along a random direction vs central
+    differences."""
+    import torch
+    sc = S.trihedral_plate()
+    sc = dataclasses.replace(sc, radar=S.default_radar(1, 1),
+                             chirp=dataclasses.replace(sc.chirp, n_samples=4096, n_chirps=4096, slope=60e12 / 16))
+    sc = sc.with_grid(nx=10, ny=10)
+    o = orc.trace(sc)
+    p = orc.paths(sc, o["tri"], o["flags"])
+    rows = np.array([0, 1777, 4095], np.int32)
+    want = orc.synth(sc, p, rows=rows)
+    sim = _sim(sc)
+    sim.hits = device_hits_from_oracle(o)
+    cube = sim.synth()
+    got = _cube_np(cube).reshape(-1, 4096)[rows]
+    e = rel_l2(got, want)
+    # backward: a loss on one chirp row keeps the oracle's sums small
+    sc1 = sc.with_chirp(n_chirps=1)
+    S1 = orc.synth(sc1, orc.paths(sc1, o["tri"], o["flags"]))
+    rng = np.random.default_rng(51)
+    tgt1 = 0.5 * S1 + 0.1 * np.abs(S1).max() * (rng.normal(size=S1.shape) + 1j * rng.normal(size=S1.shape))
+    G = torch.zeros((1, 4096, 4096), dtype=torch.complex64, device="cuda")
+    G[:, :1, :] = torch.as_tensor((2.0 * (S1 - tgt1)).astype(np.complex64), device="cuda")
+    g = sim.backward(G).cpu().numpy().astype(np.float64)
+    hit_v = np.unique(sc.faces[np.unique(o["tri"][o["tri"] >= 0])].reshape(-1))
+    w = np.zeros((sc.nv, 3))
+    w[hit_v] = rng.normal(size=(len(hit_v), 3))
+    w /= np.linalg.norm(w)
+    fd = orc.fd_directional(sc1, o["tri"], o["flags"], tgt1, w, h=1e-9)
+    eg = abs(float((g * w).sum()) - fd) / abs(fd)
+    log(f"max chirp 4096 x 4096: {len(p['amp'])} paths, synth rows rel L2 {e:.3e}, directional gradient {eg:.3e}")
+    assert e <= 1e-4 and eg <= GRAD_TOL
