@@ -29,6 +29,32 @@ def _p(t: Optional[torch.Tensor]):
     return ct.c_void_p(t.data_ptr())
 
 
+def _buf(t: Optional[torch.Tensor], dtype, n: int, name: str, optional: bool = False):
+    """Pointer to a buffer the C ABI writes or reads without knowing its size,
+    after the checks it cannot make itself: dtype, contiguity, at least `n`
+    elements, device memory.  Raises ValueError instead of letting a kernel
+    run past the end of a buffer."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, {n} needed")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be in device memory")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _check_hits(h: "Hits", K: int, R: int):
+    for f, dt in (("tri", torch.int32), ("t", torch.float32), ("u", torch.float32), ("v", torch.float32),
+                  ("flags", torch.uint8)):
+        _buf(getattr(h, f), dt, K * R, f"hits.{f}")
+
+
 def _stream():
     return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -169,18 +195,21 @@ def sbr_build_bvh(mesh: DeviceMesh, bvh: torch.Tensor, mode: int = 0, scratch: O
 
 def sbr_trace(mesh: DeviceMesh, bvh: Optional[torch.Tensor], radar: S.Radar, rays: S.Grid, hits: Hits,
               counters: Optional[torch.Tensor] = None):
+    _check_hits(hits, rays.max_bounces, rays.nx * rays.ny)
+    cnt = _buf(counters, torch.int64, 3, "counters", optional=True)
     m, r, g, h = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct()
-    L.check(_lib().sbr_trace(ct.byref(m), _p(bvh), ct.byref(r), ct.byref(g), ct.byref(h), _p(counters),
-                             _stream()))
+    L.check(_lib().sbr_trace(ct.byref(m), _p(bvh), ct.byref(r), ct.byref(g), ct.byref(h), cnt, _stream()))
 
 
 def sbr_synth_if(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: S.Chirp, flags: int,
                  if_cube: torch.Tensor, scratch: torch.Tensor):
+    out = _buf(if_cube, torch.float32, 2 * radar.n_virtual * chirp.n_chirps * chirp.n_samples, "if_cube")
+    _check_hits(hits, rays.max_bounces, rays.nx * rays.ny)
+    sp = _buf(scratch, torch.uint8, 0, "scratch")
     m, r, g, h, c = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct(), chirp_struct(chirp)
     mats, nm = materials_struct(mesh.materials)
     L.check(_lib().sbr_synth_if(ct.byref(m), mats, nm, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c),
-                                int(flags), _p(if_cube), _p(scratch), scratch.numel() * scratch.element_size(),
-                                _stream()))
+                                int(flags), out, sp, scratch.numel() * scratch.element_size(), _stream()))
 
 
 def sbr_radar_cube_2d_bytes(vx: int, vy: int, C: int, Sn: int, n_ax: int, n_ay: int) -> int:
@@ -189,7 +218,11 @@ def sbr_radar_cube_2d_bytes(vx: int, vy: int, C: int, Sn: int, n_ax: int, n_ay: 
 
 def sbr_radar_cube_2d(x: torch.Tensor, vx: int, vy: int, C: int, Sn: int, n_ax: int, n_ay: int, window: int,
                       direction: int, out: torch.Tensor, scratch: torch.Tensor):
-    L.check(_lib().sbr_radar_cube_2d(_p(x), vx, vy, C, Sn, n_ax, n_ay, window, direction, _p(out), _p(scratch),
+    nv, na = vx * vy * C * Sn * 2, n_ax * n_ay * C * Sn * 2
+    xi = _buf(x, torch.float32, nv if direction == 0 else na, "x")
+    xo = _buf(out, torch.float32, na if direction == 0 else nv, "out")
+    L.check(_lib().sbr_radar_cube_2d(xi, vx, vy, C, Sn, n_ax, n_ay, window, direction, xo,
+                                     _buf(scratch, torch.uint8, 0, "scratch"),
                                      scratch.numel() * scratch.element_size(), _stream()))
 
 
@@ -202,28 +235,39 @@ def sbr_angle_peaks(X: torch.Tensor, n_ax: int, n_ay: int, C: int, Sn: int, det:
     scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=xf.device)
     pts = torch.empty((max_points, 4), dtype=torch.int32, device=xf.device)
     n = torch.zeros(1, dtype=torch.int32, device=xf.device)
-    L.check(_lib().sbr_angle_peaks(_p(xf), n_ax, n_ay, C, Sn, _p(det), _p(n_det), int(det.shape[0]), ct.c_float(rel),
-                                   _p(pts), max_points, _p(n), _p(scratch), need, _stream()))
+    xp = _buf(xf, torch.float32, 2 * n_ax * n_ay * C * Sn, "X")
+    dp = _buf(det, torch.int32, 4 * int(det.shape[0]), "det")
+    L.check(_lib().sbr_angle_peaks(xp, n_ax, n_ay, C, Sn, dp, _buf(n_det, torch.int32, 1, "n_det"),
+                                   int(det.shape[0]), ct.c_float(rel), _p(pts), max_points, _p(n), _p(scratch), need,
+                                   _stream()))
     return pts, n
 
 
 def sbr_cloud(points: torch.Tensor, n_points: torch.Tensor, radar: S.Radar, chirp: S.Chirp, n_ax: int, n_ay: int,
               out: torch.Tensor):
     r, c = radar_struct(radar), chirp_struct(chirp)
-    L.check(_lib().sbr_cloud(_p(points), _p(n_points), int(points.shape[0]), ct.byref(r), ct.byref(c), n_ax, n_ay,
-                             _p(out), _stream()))
+    mp = int(points.shape[0])
+    L.check(_lib().sbr_cloud(_buf(points, torch.int32, 4 * mp, "points"), _buf(n_points, torch.int32, 1, "n_points"),
+                             mp, ct.byref(r), ct.byref(c), n_ax, n_ay, _buf(out, torch.float32, 4 * mp, "out"),
+                             _stream()))
 
 
 def sbr_radar_cube(x: torch.Tensor, V: int, C: int, Sn: int, n_angle: int, window: int, direction: int,
                    out: torch.Tensor, scratch: torch.Tensor):
-    L.check(_lib().sbr_radar_cube(_p(x), V, C, Sn, n_angle, window, direction, _p(out), _p(scratch),
+    nv, na = V * C * Sn * 2, n_angle * C * Sn * 2
+    xi = _buf(x, torch.float32, nv if direction == 0 else na, "x")
+    xo = _buf(out, torch.float32, na if direction == 0 else nv, "out")
+    L.check(_lib().sbr_radar_cube(xi, V, C, Sn, n_angle, window, direction, xo, _buf(scratch, torch.uint8, 0, "scratch"),
                                   scratch.numel() * scratch.element_size(), _stream()))
 
 
 def sbr_cfar(cube: torch.Tensor, Na: int, C: int, Sn: int, guard: int, train: int, pfa: float,
              points: torch.Tensor, ratio: Optional[torch.Tensor], n_points: torch.Tensor, scratch: torch.Tensor):
-    L.check(_lib().sbr_cfar(_p(cube), Na, C, Sn, guard, train, float(pfa), _p(points), _p(ratio),
-                            int(points.shape[0]), _p(n_points), _p(scratch),
+    mp = int(points.shape[0])
+    L.check(_lib().sbr_cfar(_buf(cube, torch.float32, 2 * Na * C * Sn, "cube"), Na, C, Sn, guard, train, float(pfa),
+                            _buf(points, torch.int32, 4 * mp, "points"),
+                            _buf(ratio, torch.float32, mp, "ratio", optional=True), mp,
+                            _buf(n_points, torch.int32, 1, "n_points"), _buf(scratch, torch.uint8, 0, "scratch"),
                             scratch.numel() * scratch.element_size(), _stream()))
 
 
@@ -240,9 +284,13 @@ def sbr_backward(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chi
             if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n):
                 raise ValueError(f"parameter gradient buffer must be contiguous float32 with {n} elements")
         pg = L.sbr_param_grads(*[t.data_ptr() if t is not None else None for t in bufs])
+    _check_hits(hits, rays.max_bounces, rays.nx * rays.ny)
+    gi = _buf(grad_if, torch.float32, 2 * radar.n_virtual * chirp.n_chirps * chirp.n_samples, "grad_if")
+    gv = _buf(grad_verts, torch.float32, 3 * mesh.nv, "grad_verts")
     L.check(_lib().sbr_backward(ct.byref(m), mats, nm, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c),
-                                int(flags), _p(grad_if), _p(grad_verts), ct.byref(pg) if pg is not None else None,
-                                _p(scratch), scratch.numel() * scratch.element_size(), _stream()))
+                                int(flags), gi, gv, ct.byref(pg) if pg is not None else None,
+                                _buf(scratch, torch.uint8, 0, "scratch"), scratch.numel() * scratch.element_size(),
+                                _stream()))
 
 
 def sbr_loss_grad(mode: int, a: torch.Tensor, b: torch.Tensor, n: int, grad: Optional[torch.Tensor],
@@ -250,7 +298,10 @@ def sbr_loss_grad(mode: int, a: torch.Tensor, b: torch.Tensor, n: int, grad: Opt
     if loss is not None and scratch is None:
         scratch = torch.empty(L.SBR_LOSS_SCRATCH_BYTES, dtype=torch.uint8, device=a.device)
     nbytes = scratch.numel() * scratch.element_size() if scratch is not None else 0
-    L.check(_lib().sbr_loss_grad(int(mode), _p(a), _p(b), int(n), _p(grad), _p(loss), _p(scratch), nbytes,
+    ap = _buf(a, torch.float32, 2 * n, "a")
+    bp = _buf(b, torch.float32, (2 if mode == 0 else 1) * n, "b")
+    L.check(_lib().sbr_loss_grad(int(mode), ap, bp, int(n), _buf(grad, torch.float32, 2 * n, "grad", optional=True),
+                                 _buf(loss, torch.float32, 1, "loss", optional=True), _p(scratch), nbytes,
                                  _stream()))
 
 

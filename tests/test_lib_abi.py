@@ -116,3 +116,30 @@ def test_product_path_fails_loudly_without_library(tmp_path):
             L.load(str(tmp_path / "missing.so"))
         finally:
             L._lib = L._lib_backup
+
+
+def test_binding_checks_buffers_before_the_call():
+    """The binding refuses buffers the C ABI would overrun or misread (it
+    cannot see their sizes): wrong dtype, too few elements, non-contiguous,
+    host memory."""
+    import torch
+    from paper_2311_13182_amd import sbr
+    f32 = torch.zeros(8, dtype=torch.float32)
+    with pytest.raises(ValueError, match="float32"):
+        sbr._buf(torch.zeros(8, dtype=torch.float64), torch.float32, 8, "x")
+    with pytest.raises(ValueError, match="needed"):
+        sbr._buf(f32, torch.float32, 9, "x")
+    with pytest.raises(ValueError, match="contiguous"):
+        sbr._buf(torch.zeros(4, 4)[:, 1], torch.float32, 4, "x")
+    with pytest.raises(ValueError, match="device memory"):
+        sbr._buf(f32, torch.float32, 8, "x")
+    assert sbr._buf(None, torch.float32, 8, "x", optional=True) is None
+    with pytest.raises(ValueError, match="required"):
+        sbr._buf(None, torch.float32, 8, "x")
+    # an IF cube one sample short is refused before anything reaches the library
+    from paper_2311_13182_amd import scenes as S
+    sc = S.trihedral_plate()
+    h = sbr.Hits.empty(sc.grid.max_bounces, sc.grid.n_rays, "cpu")
+    short = torch.zeros(2 * sc.radar.n_virtual * sc.chirp.n_chirps * sc.chirp.n_samples - 1)
+    with pytest.raises(ValueError, match="if_cube"):
+        sbr.sbr_synth_if(None, sc.radar, sc.grid, h, sc.chirp, 0, short, torch.zeros(16, dtype=torch.uint8))
