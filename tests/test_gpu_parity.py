@@ -763,8 +763,15 @@ def test_jittered_grid_trace_synth_backward(torch_cuda, orc):
     got = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda")).cpu().numpy().astype(np.float64)
     fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, h=1e-9).reshape(-1, 3)
     eg = rel_l2(got, fd)
-    log(f"jitter: {n_ok} hits checked, synth rel L2 {e:.3e}, backward rel L2 {eg:.3e}")
-    assert n_ok > 0.9 * (o["tri"] >= 0).sum() and e <= 1e-4 and eg <= GRAD_TOL
+    # the reparameterised estimator on the jittered samples (the cell weight's
+    # |det J_T| taken at the drawn direction)
+    att = orc.attach(sc, o["tri"])
+    ga = sim.backward(torch.as_tensor(G.astype(np.complex64), device="cuda"), attached=True)
+    ga = ga.cpu().numpy().astype(np.float64)
+    fda = orc.fd_grad(sc, o["tri"], o["flags"], tgt, h=1e-9, att=att).reshape(-1, 3)
+    ea = rel_l2(ga, fda)
+    log(f"jitter: {n_ok} hits checked, synth rel L2 {e:.3e}, backward rel L2 {eg:.3e}, attached {ea:.3e}")
+    assert n_ok > 0.9 * (o["tri"] >= 0).sum() and e <= 1e-4 and eg <= GRAD_TOL and ea <= GRAD_TOL
 
 
 def test_maximum_grid_size(torch_cuda, orc):
