@@ -30,7 +30,8 @@
  *                      dense re-traced grid (loose)
  *   orc_fresnel        normal incidence, grazing, passivity, conductor limit
  *   orc_synth          single-path geometric sequence and Dirichlet kernel,
- *                      range / Doppler / angle peak bins
+ *                      range / Doppler / angle peak bins, 24 GHz ranging
+ *                      radar's plate at its 2R mu / c bin
  *   orc_synth_adjoint  central differences of orc_synth
  *   orc_radar_cube     numpy.fft, dot-product (adjoint) identity (1D and 2D
  *                      arrays)
