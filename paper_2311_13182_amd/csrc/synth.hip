@@ -169,22 +169,22 @@ __global__ __launch_bounds__(kPathBlock) void k_path_refine(PathArgs a) {
         a.st.rec.amp[p] = make_float2((float)(pr.re * sc), (float)(pr.im * sc));
         a.st.rec.beta[p] = (float)beta;
         a.st.rec.epsd[p] = (float)epsd;
-        double dtx[SBR_MAX_TX], drx[SBR_MAX_RX];
-        for (int t = 0; t < ntx; t++)
-            dtx[t] = sqrt((x1[0] - a.rd.tx[t][0]) * (x1[0] - a.rd.tx[t][0]) +
-                          (x1[1] - a.rd.tx[t][1]) * (x1[1] - a.rd.tx[t][1]) +
-                          (x1[2] - a.rd.tx[t][2]) * (x1[2] - a.rd.tx[t][2]));
-        for (int m = 0; m < nrx; m++)
-            drx[m] = sqrt((x[0] - a.rd.rx[m][0]) * (x[0] - a.rd.rx[m][0]) +
-                          (x[1] - a.rd.rx[m][1]) * (x[1] - a.rd.rx[m][1]) +
-                          (x[2] - a.rd.rx[m][2]) * (x[2] - a.rd.rx[m][2]));
-        for (int t = 0; t < ntx; t++)
+        // one square root per (TX, RX) pair instead of per-antenna distance
+        // arrays: a runtime-indexed array would live in per-thread stack memory
+        for (int t = 0; t < ntx; t++) {
+            const double dtx = sqrt((x1[0] - a.rd.tx[t][0]) * (x1[0] - a.rd.tx[t][0]) +
+                                    (x1[1] - a.rd.tx[t][1]) * (x1[1] - a.rd.tx[t][1]) +
+                                    (x1[2] - a.rd.tx[t][2]) * (x1[2] - a.rd.tx[t][2]));
             for (int m = 0; m < nrx; m++) {
-                double tau = (dtx[t] + Lmid + drx[m]) / kC0;
-                int v = t * nrx + m;
+                const double drx = sqrt((x[0] - a.rd.rx[m][0]) * (x[0] - a.rd.rx[m][0]) +
+                                        (x[1] - a.rd.rx[m][1]) * (x[1] - a.rd.rx[m][1]) +
+                                        (x[2] - a.rd.rx[m][2]) * (x[2] - a.rd.rx[m][2]));
+                const double tau = (dtx + Lmid + drx) / kC0;
+                const int v = t * nrx + m;
                 a.st.rec.alpha[(size_t)v * cap + p] = (float)frac_d(a.ch.fc * tau);
                 a.st.rec.gamma[(size_t)v * cap + p] = (float)(a.ch.slope * tau / a.ch.fs);
             }
+        }
         p++;
         for (int i = 0; i < 3; i++) {
             o[i] = x[i];
