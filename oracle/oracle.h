@@ -23,7 +23,11 @@
  *                      segment test with occluders, no inheritance
  *   orc_paths (exit)   exit-only == last record of each ray of the full model
  *   orc_paths          plate normal incidence (tau = 2R/c), trihedral
- *                      point-reflection identity, Fresnel special cases
+ *                      point-reflection identity, Fresnel special cases;
+ *                      per-antenna legs of k >= 2 paths: the angle DFT of
+ *                      a two-plate double bounce peaks at the first hit's
+ *                      azimuth for a TX line and at the last hit's for an
+ *                      RX line (a TX<->RX leg swap moves both peaks)
  *   orc_attach         summed attached weights vs the closed-form solid angle
  *                      of a triangle (Van Oosterom-Strackee) and its
  *                      derivative; attached estimator == fixed one at theta_0;

@@ -332,6 +332,99 @@ def test_doppler_and_angle_peaks(orc):
     assert abs(int(np.argmax(ang)) - want) <= 1
 
 
+def _oriented_plate(size, centre, normal):
+    """Square plate of side `size` centred at `centre` with unit normal `normal`."""
+    v, f = S.plate(size, 0.0)
+    v = v @ S._rot_from_to(np.array([0.0, 0.0, -1.0]), normal).T + centre
+    return v, f
+
+
+def _bistatic_two_plates(n_tx, n_rx, th1, th2):
+    """Plate A at azimuth th1 (1.0 m) turned so that the radar's rays mirror
+    onto plate B at azimuth th2 (1.3 m); a lambda/2 line array of n_tx TX and
+    n_rx RX along x, both centred on the origin."""
+    lam = S.wavelength(77e9)
+    pa = 1.0 * np.array([math.sin(th1), 0.0, math.cos(th1)])
+    pb = 1.3 * np.array([math.sin(th2), 0.0, math.cos(th2)])
+    to_r, to_b = -pa / np.linalg.norm(pa), (pb - pa) / np.linalg.norm(pb - pa)
+    na = (to_r + to_b) / np.linalg.norm(to_r + to_b)
+    va, fa = _oriented_plate(0.05, pa, na)
+    vb, fb = _oriented_plate(0.30, pb, (pa - pb) / np.linalg.norm(pa - pb))
+    v = np.concatenate([va, vb]).astype(np.float32)
+    f = np.concatenate([fa, fb + len(va)]).astype(np.int32)
+    line = lambda n: np.array([[(i - (n - 1) / 2.0) * lam / 2.0, 0.0, 0.0] for i in range(n)])
+    rd = S.Radar(np.zeros(3), np.eye(3), line(n_tx), line(n_rx))
+    g = S.Grid(400, 16, math.tan(math.radians(25.0)), math.tan(math.radians(3.0)), 2)
+    return S.Scene("bistatic_two_plates", v, f, rd, S.Chirp(n_chirps=1), g)
+
+
+def _double_bounce_geometry(orc, sc, tr, pth, sel):
+    """Hit points x_1, x_2 of the selected paths, rebuilt from the traced
+    distances and the plate normal (test-side geometry, for the control)."""
+    x1s, x2s = [], []
+    for p in sel:
+        r = int(pth["ray"][p])
+        o, d, _ = orc.ray(sc, r)
+        f0 = sc.faces[tr["tri"][0, r]].astype(np.int64)
+        a, b, c = (sc.verts[f0[i]].astype(np.float64) for i in range(3))
+        n = np.cross(b - a, c - a)
+        n /= np.linalg.norm(n)
+        x1 = o + tr["t"][0, r] * d
+        d2 = d - 2.0 * np.dot(d, n) * n
+        x2 = x1 + tr["t"][1, r] * d2
+        x1s.append(x1)
+        x2s.append(x2)
+    return np.array(x1s), np.array(x2s)
+
+
+def test_double_bounce_departure_and_arrival_angles(orc):
+    """Sec. 3.2.2 / Eq. 8: a k = 2 path leaves the TX array towards its first
+    hit and reaches the RX array from its last hit.  With N TX x 1 RX on a
+    lambda/2 line the angle DFT of the double-bounce returns peaks at the
+    first hit's azimuth, with 1 TX x N RX at the last hit's (far field: the
+    per-element phase step is -sin(theta)/2 cycles, so the peak bin is
+    -Na sin(theta)/2).  A TX<->RX leg swap (first leg to the RX, last leg from
+    the TX) moves both peaks; the control below shows that."""
+    th1, th2, Na, N = math.radians(-20.0), math.radians(16.0), 64, 8
+    bin_of = lambda th: round(-Na * math.sin(th) / 2.0) % Na
+    b1, b2 = bin_of(th1), bin_of(th2)
+    assert abs(b1 - b2) >= 10
+
+    def peak(sc, pth):
+        X = orc.radar_cube(orc.synth(sc, pth), n_angle=Na)
+        return int(np.argmax((np.abs(X) ** 2).sum(axis=(1, 2))))
+
+    def circ(a, b):
+        return min((a - b) % Na, (b - a) % Na)
+
+    for n_tx, n_rx, want, other in ((N, 1, b1, b2), (1, N, b2, b1)):
+        sc = _bistatic_two_plates(n_tx, n_rx, th1, th2)
+        tr = orc.trace(sc)
+        pth = orc.paths(sc, tr["tri"], tr["flags"])
+        # double-bounce paths A -> B only (faces 0-1 are plate A, 2-3 plate B)
+        ray, k = pth["ray"], pth["k"]
+        kk = k - k.min()   # bounce index from 0, whatever the oracle's base
+        sel = np.flatnonzero((kk == 1) & (tr["tri"][0, ray] <= 1) & (tr["tri"][1, ray] >= 2))
+        assert len(sel) >= 50, len(sel)
+        sub = {"amp": pth["amp"][sel], "tau": pth["tau"][sel], "taudot": pth["taudot"][sel]}
+        assert circ(peak(sc, sub), want) <= 1
+        # control: the same paths with the legs swapped peak at the other angle
+        x1, x2 = _double_bounce_geometry(orc, sc, tr, pth, sel)
+        tx = sc.radar.tx.astype(np.float64)
+        rx = sc.radar.rx.astype(np.float64)
+        mid = np.linalg.norm(x2 - x1, axis=1)
+        good = np.empty_like(sub["tau"])
+        swap = np.empty_like(sub["tau"])
+        for t in range(n_tx):
+            for m in range(n_rx):
+                v = t * n_rx + m
+                good[:, v] = (np.linalg.norm(x1 - tx[t], axis=1) + mid + np.linalg.norm(x2 - rx[m], axis=1)) / C0
+                swap[:, v] = (np.linalg.norm(x1 - rx[m], axis=1) + mid + np.linalg.norm(x2 - tx[t], axis=1)) / C0
+        # the control is built on the oracle's own paths (same hit points)
+        assert np.max(np.abs(good - sub["tau"]) / sub["tau"]) < 1e-12
+        assert circ(peak(sc, dict(sub, tau=swap)), other) <= 1
+
+
 def test_synth_adjoint_matches_central_differences(orc):
     sc = S.icosphere_scene(level=1, n_rays=8, n_chirps=4)
     ch = sc.chirp
