@@ -173,7 +173,7 @@ static int occluded(const orc_mesh *m, const double x[3], const double O[3], int
 
 long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, const int *rays, int n,
                     int *tri, double *t_out, double *b1_out, double *b2_out, unsigned char *flags,
-                    unsigned char *shadow_edge) {
+                    unsigned char *shadow_edge, double *cos_out) {
     const int K = g->max_bounces;
     long long queries = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : queries)
@@ -193,6 +193,7 @@ long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, c
             if (b2_out) b2_out[slot] = 0.0;
             if (flags) flags[slot] = 0;
             if (shadow_edge) shadow_edge[slot] = 0;
+            if (cos_out) cos_out[slot] = 0.0;
             if (!alive) continue;
             queries++;
             /* closest hit = lexicographic minimum of (t, triangle id) */
@@ -233,6 +234,7 @@ long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g, c
             if (t_out) t_out[slot] = bt;
             if (b1_out) b1_out[slot] = bu;
             if (b2_out) b2_out[slot] = bv;
+            if (cos_out) cos_out[slot] = fabs(dn);
             anc |= fl;
             if (g->shadow && k > 0) {
                 int edge;

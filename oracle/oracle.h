@@ -131,10 +131,13 @@ void orc_ray(const orc_radar *rd, const orc_grid *g, int r,
  * shadow_edge ([K][n], NULL-able): 1 where that decision is borderline -- some
  * other triangle meets the segment's line within delta_k of its boundary, or
  * a hit lies within delta_k of the segment's ends.
+ * cos_i ([K][n], NULL-able): |d . n| of each hit, the cosine of its incidence
+ * angle (0 where there is none).
  * Returns the number of closest-hit queries issued (a ray's final miss counts). */
 long long orc_trace(const orc_mesh *m, const orc_radar *rd, const orc_grid *g,
                     const int *rays, int n, int *tri, double *t, double *b1,
-                    double *b2, unsigned char *flags, unsigned char *shadow_edge);
+                    double *b2, unsigned char *flags, unsigned char *shadow_edge,
+                    double *cos_i);
 
 /* Reflection coefficient of material `mi` at incidence cosine cos_i (in [0,1]).
  * out[0] = real part, out[1] = imaginary part. */

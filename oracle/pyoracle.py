@@ -75,7 +75,7 @@ def lib():
         L.orc_ray.argtypes = [ct.POINTER(_Radar), ct.POINTER(_Grid), ct.c_int, dp, dp, dp]
         L.orc_trace.restype = ct.c_longlong
         L.orc_trace.argtypes = [ct.POINTER(_Mesh), ct.POINTER(_Radar), ct.POINTER(_Grid), ip,
-                                ct.c_int, ip, dp, dp, dp, bp, bp]
+                                ct.c_int, ip, dp, dp, dp, bp, bp, dp]
         L.orc_fresnel.argtypes = [ct.POINTER(_Mesh), ct.c_int, ct.c_double, ct.c_double, dp]
         L.orc_paths.restype = ct.c_int
         L.orc_paths.argtypes = [ct.POINTER(_Mesh), ct.POINTER(_Radar), ct.POINTER(_Grid),
@@ -193,11 +193,13 @@ def trace(scene, rays=None, verts64=None):
     b2 = np.empty((K, n))
     fl = np.empty((K, n), np.uint8)
     se = np.empty((K, n), np.uint8)
+    cs = np.empty((K, n))
     m, keep = _mesh(scene, verts64)
     q = lib().orc_trace(ct.byref(m), ct.byref(_radar(scene.radar)), ct.byref(_grid(g)),
                         _p(ids, ct.c_int), n, _p(tri, ct.c_int), _p(t, ct.c_double),
-                        _p(b1, ct.c_double), _p(b2, ct.c_double), _p(fl, ct.c_ubyte), _p(se, ct.c_ubyte))
-    return {"tri": tri, "t": t, "b1": b1, "b2": b2, "flags": fl, "shadow_edge": se, "queries": int(q)}
+                        _p(b1, ct.c_double), _p(b2, ct.c_double), _p(fl, ct.c_ubyte), _p(se, ct.c_ubyte),
+                        _p(cs, ct.c_double))
+    return {"tri": tri, "t": t, "b1": b1, "b2": b2, "flags": fl, "shadow_edge": se, "cos": cs, "queries": int(q)}
 
 
 def attach(scene, tri, rays=None, verts64=None):
