@@ -63,7 +63,7 @@ typedef enum {
 typedef struct {
     const float *verts;      /* [nv][3] world frame, metres                      */
     int32_t nv;
-    const int32_t *faces;    /* [nf][3] vertex indices                            */
+    const int32_t *faces;    /* [nf][3] vertex indices, each in [0, nv)           */
     int32_t nf;
     const uint16_t *mat_id;  /* [nf] material table index (>= n_mats: conductor), or NULL */
 } sbr_mesh;
@@ -189,7 +189,10 @@ size_t sbr_scratch_bytes(int32_t op, const sbr_mesh *mesh, const sbr_rays *rays,
  * binary radix tree (Karras, HPG 2012), computes boxes bottom-up and lays
  * nodes out in depth-first order with escape links for stackless traversal.
  * REFIT keeps the tree of the last BUILD of this buffer (same faces, new
- * vertex positions) and recomputes boxes and triangle data.
+ * vertex positions) and recomputes boxes and triangle data.  A BUILD seals
+ * the buffer with its face count; a REFIT of a buffer that no BUILD for
+ * mesh->nf faces has sealed changes nothing but sets the buffer's int32
+ * word 2 to 1, and sbr_trace reports every ray of such a buffer as a miss.
  * bvh: device buffer of at least sbr_bvh_bytes(nf).  The BVH is not part of
  * the paper's method; it accelerates the closest-hit queries of Sec. 3.2.1. */
 int sbr_build_bvh(const sbr_mesh *mesh, void *bvh, size_t bvh_bytes, int32_t mode,
@@ -216,7 +219,8 @@ int sbr_trace(const sbr_mesh *mesh, const void *bvh, const sbr_radar *radar,
  * angle at the last hit and r_j the material reflection coefficients.
  *   if_cube[v][c][s] = sum_paths I^s exp(2 pi j (slope s / fs + fc) I^t_v(c))
  * if_cube: device float [V][C][S][2], overwritten.  mats: host array of
- * n_mats (<= 64) entries, or NULL / 0 for all-conductor. */
+ * n_mats (<= 64) entries, or NULL / 0 for all-conductor.  A hit id outside
+ * [0, nf) ends its ray like a miss (no face outside the mesh is read). */
 int sbr_synth_if(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
                  const sbr_radar *radar, const sbr_rays *rays, const sbr_hits *hits,
                  const sbr_chirp *chirp, int32_t flags, float *if_cube,
@@ -334,6 +338,56 @@ int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
 
 /* Number of paths the last sbr_synth_if / sbr_backward found is left in the
  * first int32 of their scratch buffer (device) once the stream reaches it. */
+
+/* ---- Batched entry points (serving many simulations on one device) ------
+ * Not part of the paper's method: they run several independent requests'
+ * Eq. 8 synthesis, or Eqs. 11-13 adjoints, as one launch, so small requests
+ * fill the device together.  Each request carries exactly the arguments of
+ * sbr_synth_if (if_cube) or sbr_backward (grad_if, grad_verts, params), with
+ * its own scratch of the size those calls need; requests must not share
+ * scratch, outputs or (for the backward) grad_verts.  A request's launch
+ * shapes depend only on its own sizes, so its IF cube is bit-identical to
+ * sbr_synth_if's and its gradients equal sbr_backward's up to the order of
+ * floating-point atomics. */
+#define SBR_MAX_BATCH 1024
+
+typedef struct {
+    const sbr_mesh *mesh;
+    const sbr_material *mats;       /* host, n_mats entries, or NULL          */
+    int32_t n_mats;
+    int32_t flags;                  /* as for sbr_synth_if / sbr_backward     */
+    const sbr_radar *radar;
+    const sbr_rays *rays;
+    const sbr_hits *hits;
+    const sbr_chirp *chirp;
+    float *if_cube;                 /* synthesis: [V][C][S][2], overwritten   */
+    const float *grad_if;           /* backward: dL/dRe S + i dL/dIm S        */
+    float *grad_verts;              /* backward: [nv][3], accumulated (+=)     */
+    const sbr_param_grads *params;  /* backward: NULL or where to add them    */
+    void *scratch;                  /* device, >= sbr_scratch_bytes of the op */
+    size_t scratch_bytes;
+} sbr_request;
+
+/* Bytes of the device table a batched call of n (1..SBR_MAX_BATCH) requests
+ * needs; 0 for other n. */
+size_t sbr_batch_table_bytes(int32_t n_requests);
+
+/* sbr_synth_if for each of reqs[0..n) (host array), enqueued on `stream`:
+ * every request's path stage, then ONE launch per sample-run length over the
+ * synthesis blocks of all requests -- a device table (written by the call
+ * into `table`, device memory of sbr_batch_table_bytes(n) bytes, not to be
+ * reused until the stream has passed this call) gives each block its request
+ * -- then each request's fixed-order reduction into its if_cube.  Every
+ * request is checked before anything is enqueued; the error message names
+ * the first bad one. */
+int sbr_synth_if_batched(const sbr_request *reqs, int32_t n, void *table, size_t table_bytes, void *stream);
+
+/* sbr_backward for each of reqs[0..n): every request's path stage, ONE
+ * work-queue launch of the synthesis adjoint (Eqs. 11-12) whose items --
+ * (antenna group, path tile) of every request, counted on the device -- are
+ * mapped to their request through the device table, then each request's
+ * geometry adjoint (Eq. 13).  Table and checks as sbr_synth_if_batched. */
+int sbr_backward_batched(const sbr_request *reqs, int32_t n, void *table, size_t table_bytes, void *stream);
 
 /* Loss of the inverse problem (Sec. 3.4.1, Eq. 14) and its gradient, the
  * entry point of the backward pass.  n complex elements, device arrays.

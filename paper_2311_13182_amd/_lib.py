@@ -22,12 +22,14 @@ SBR_ATTACHED = 2
 SBR_EXIT_ONLY = 4
 SBR_OP_BUILD_BVH, SBR_OP_SYNTH, SBR_OP_BACKWARD, SBR_OP_RADAR_CUBE, SBR_OP_CFAR = 0, 1, 2, 3, 4
 SBR_LOSS_SCRATCH_BYTES = 8192
+SBR_MAX_BATCH = 1024
 
 # every function declared in include/sbr.h
 EXPORTS = ("sbr_bvh_bytes", "sbr_scratch_bytes", "sbr_build_bvh", "sbr_trace", "sbr_synth_if",
            "sbr_radar_cube", "sbr_cfar", "sbr_backward", "sbr_last_error", "sbr_loss_grad", "sbr_profile",
            "sbr_profile_read", "sbr_radar_cube_2d", "sbr_radar_cube_2d_bytes", "sbr_cloud",
-           "sbr_angle_peaks", "sbr_angle_peaks_bytes")
+           "sbr_angle_peaks", "sbr_angle_peaks_bytes", "sbr_batch_table_bytes", "sbr_synth_if_batched",
+           "sbr_backward_batched")
 PROF_SYNTH, PROF_SYNTH_ADJ, PROF_TRACE = 0, 1, 2
 
 
@@ -72,6 +74,14 @@ class sbr_param_grads(ct.Structure):
 class sbr_hits(ct.Structure):
     _fields_ = [("tri", ct.c_void_p), ("t", ct.c_void_p), ("u", ct.c_void_p), ("v", ct.c_void_p),
                 ("flags", ct.c_void_p)]
+
+
+class sbr_request(ct.Structure):
+    _fields_ = [("mesh", ct.POINTER(sbr_mesh)), ("mats", ct.POINTER(sbr_material)), ("n_mats", ct.c_int32),
+                ("flags", ct.c_int32), ("radar", ct.POINTER(sbr_radar)), ("rays", ct.POINTER(sbr_rays)),
+                ("hits", ct.POINTER(sbr_hits)), ("chirp", ct.POINTER(sbr_chirp)), ("if_cube", ct.c_void_p),
+                ("grad_if", ct.c_void_p), ("grad_verts", ct.c_void_p), ("params", ct.POINTER(sbr_param_grads)),
+                ("scratch", ct.c_void_p), ("scratch_bytes", ct.c_size_t)]
 
 
 _lib = None
@@ -127,6 +137,12 @@ def load(path: str = LIB_PATH):
     L.sbr_profile.argtypes = [i32]
     L.sbr_profile_read.restype = ct.c_int
     L.sbr_profile_read.argtypes = [i32, P(ct.c_double), P(ct.c_int64)]
+    L.sbr_batch_table_bytes.restype = sz
+    L.sbr_batch_table_bytes.argtypes = [i32]
+    L.sbr_synth_if_batched.restype = ct.c_int
+    L.sbr_synth_if_batched.argtypes = [P(sbr_request), i32, vp, sz, vp]
+    L.sbr_backward_batched.restype = ct.c_int
+    L.sbr_backward_batched.argtypes = [P(sbr_request), i32, vp, sz, vp]
     _lib = L
     return L
 

@@ -6,6 +6,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "sbr_internal.h"
 
@@ -29,15 +30,6 @@ int bvh_build(const sbr_mesh *m, void *bvh, size_t bvh_bytes, int32_t mode, void
 size_t build_scratch_bytes(int32_t nf);
 int trace_launch(const sbr_mesh *m, const void *bvh, const RadarDev &rd, const GridDev &gd,
                  const sbr_hits *h, uint64_t *counters, hipStream_t st);
-SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S);
-size_t synth_partial_elems(const SynthPlan &p, int32_t V, int32_t C, int32_t S);
-int launch_synth(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial,
-                 float2 *out, hipStream_t s);
-size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V);
-int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
-                    const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
-                    const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
-                    int32_t flags, hipStream_t s);
 size_t cube_scratch_bytes(int V, int C, int S, int Na);
 size_t cube2_scratch_bytes(int Vx, int Vy, int C, int S, int Nax, int Nay);
 int cloud_launch(const int32_t *points, const int32_t *n_points, int32_t max_points, const RadarDev &rd,
@@ -207,18 +199,139 @@ ChirpDev make_chirp(const sbr_chirp *c) {
     return d;
 }
 
-static size_t synth_bytes(int R, int K, int V, int C, int S) {
-    Carver cv(nullptr);
-    carve_path_stage(cv, R, K, V);
-    SynthPlan p = synth_plan(R, K, V, C, S);
-    cv.take<float2>(synth_partial_elems(p, V, C, S));
-    return align_up(cv.off, 256);
+// Scratch of one synthesis: path stage, chunk partials, a one-request table.
+struct SynthCarve {
+    PathStage st;
+    SynthPlan p;
+    float2 *partial;
+    void *table;
+    size_t bytes;
+};
+
+static SynthCarve synth_carve(void *scratch, int R, int K, int V, int C, int S) {
+    SynthCarve c;
+    Carver cv(scratch);
+    c.st = carve_path_stage(cv, R, K, V);
+    c.p = synth_plan(R, K, V, C, S);
+    c.partial = cv.take<float2>(synth_partial_elems(c.p, V, C, S));
+    c.table = cv.take<char>(synth_table_bytes(1));
+    c.bytes = align_up(cv.off, 256);
+    return c;
 }
 
-static size_t backward_bytes(int R, int K, int V) {
-    Carver cv(nullptr);
-    carve_path_stage(cv, R, K, V);
-    return align_up(cv.off, 256) + backward_extra_bytes(R, K, V) + 256;
+static size_t synth_bytes(int R, int K, int V, int C, int S) {
+    return synth_carve(nullptr, R, K, V, C, S).bytes;
+}
+
+// Scratch of one backward pass: path stage, adjoint buffers, a one-request table.
+struct BackCarve {
+    PathStage st;
+    void *extra;
+    void *table;
+    size_t bytes;
+};
+
+static BackCarve back_carve(void *scratch, int R, int K, int V) {
+    BackCarve c;
+    Carver cv(scratch);
+    c.st = carve_path_stage(cv, R, K, V);
+    c.extra = cv.take<char>(backward_extra_bytes(R, K, V));
+    c.table = cv.take<char>(adj_table_bytes(1));
+    c.bytes = align_up(cv.off, 256);
+    return c;
+}
+
+static size_t backward_bytes(int R, int K, int V) { return back_carve(nullptr, R, K, V).bytes; }
+
+// Checks of one sbr_synth_if request; 0 if it may be enqueued.
+static int check_synth(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats, const sbr_radar *radar,
+                       const sbr_rays *rays, const sbr_hits *hits, const sbr_chirp *chirp, int32_t flags,
+                       const float *if_cube, const void *scratch, size_t scratch_bytes) {
+    int rc;
+    if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
+    SBR_CHECK_ARG(if_cube, "if_cube is NULL");
+    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_EXIT_ONLY)) == 0, "unknown flags 0x%x", flags);
+    const size_t need = synth_bytes(rays->nx * rays->ny, rays->max_bounces, radar->n_tx * radar->n_rx,
+                                    chirp->n_chirps, chirp->n_samples);
+    if (!scratch || scratch_bytes < need) {
+        set_error("synth scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    return SBR_OK;
+}
+
+// Checks of one sbr_backward request; 0 if it may be enqueued.
+static int check_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats, const sbr_radar *radar,
+                          const sbr_rays *rays, const sbr_hits *hits, const sbr_chirp *chirp, int32_t flags,
+                          const float *grad_if, const float *grad_verts, const sbr_param_grads *params,
+                          const void *scratch, size_t scratch_bytes) {
+    int rc;
+    if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
+    SBR_CHECK_ARG(grad_if && grad_verts, "grad_if/grad_verts is NULL");
+    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY)) == 0, "unknown flags 0x%x", flags);
+    SBR_CHECK_ARG(!params || !params->materials || (mats && n_mats > 0),
+                  "material gradients requested without a material table");
+    const size_t need = backward_bytes(rays->nx * rays->ny, rays->max_bounces, radar->n_tx * radar->n_rx);
+    if (!scratch || scratch_bytes < need) {
+        set_error("backward scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    return SBR_OK;
+}
+
+// Enqueue the path stage of a synthesis request and fill its batch entry;
+// *skip = 1 when its cube is all zero (empty grid: zero-filled here).
+static int enqueue_synth(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats, const sbr_radar *radar,
+                         const sbr_rays *rays, const sbr_hits *hits, const sbr_chirp *chirp, int32_t flags,
+                         float *if_cube, void *scratch, hipStream_t s, SynthArgs *args, int *L, void **table,
+                         int *skip) {
+    const int R = rays->nx * rays->ny, K = rays->max_bounces;
+    const int V = radar->n_tx * radar->n_rx, C = chirp->n_chirps, S = chirp->n_samples;
+    *skip = 0;
+    if (R == 0) {
+        *skip = 1;
+        return fill_zero_f32(if_cube, (size_t)2 * V * C * S, s);
+    }
+    SynthCarve c = synth_carve(scratch, R, K, V, C, S);
+    int rc;
+    if ((rc = launch_paths(mesh, make_mats(mats, n_mats), make_radar(radar), make_grid(rays), make_chirp(chirp),
+                           hits, flags, c.st, s)))
+        return rc;
+    *args = synth_args(c.st, c.p, V, C, S, c.partial);
+    *L = c.p.L;
+    if (table) *table = c.table;
+    return SBR_OK;
+}
+
+// Enqueue the path stage of a backward request and fill its batch entry;
+// *skip = 1 when it adds nothing (empty grid or mesh).
+static int enqueue_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats, const sbr_radar *radar,
+                            const sbr_rays *rays, const sbr_hits *hits, const sbr_chirp *chirp, int32_t flags,
+                            const float *grad_if, float *grad_verts, const sbr_param_grads *params, void *scratch,
+                            hipStream_t s, BackwardReq *q, void **table, int *skip) {
+    const int R = rays->nx * rays->ny, K = rays->max_bounces;
+    const int V = radar->n_tx * radar->n_rx;
+    *skip = 0;
+    if (R == 0 || mesh->nf == 0) {
+        *skip = 1;
+        return SBR_OK;
+    }
+    BackCarve c = back_carve(scratch, R, K, V);
+    q->mesh = mesh;
+    q->mt = make_mats(mats, n_mats);
+    q->rd = make_radar(radar);
+    q->gd = make_grid(rays);
+    q->cd = make_chirp(chirp);
+    q->hits = hits;
+    q->st = c.st;
+    q->extra = c.extra;
+    q->G = reinterpret_cast<const float2 *>(grad_if);
+    q->grad = grad_verts;
+    q->radar = radar;
+    q->params = params;
+    q->flags = flags;
+    if (table) *table = c.table;
+    return launch_paths(mesh, q->mt, q->rd, q->gd, q->cd, hits, flags, q->st, s);
 }
 
 }  // namespace sbr
@@ -296,26 +409,96 @@ int sbr_synth_if(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
                  float *if_cube, void *scratch, size_t scratch_bytes, void *stream) {
     clear_error();
     int rc;
-    if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
-    SBR_CHECK_ARG(if_cube, "if_cube is NULL");
-    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_EXIT_ONLY)) == 0, "unknown flags 0x%x", flags);
-    const int R = rays->nx * rays->ny, K = rays->max_bounces;
-    const int V = radar->n_tx * radar->n_rx, C = chirp->n_chirps, S = chirp->n_samples;
+    if ((rc = check_synth(mesh, mats, n_mats, radar, rays, hits, chirp, flags, if_cube, scratch, scratch_bytes)))
+        return rc;
     hipStream_t s = (hipStream_t)stream;
-    size_t need = synth_bytes(R, K, V, C, S);
-    if (!scratch || scratch_bytes < need) {
-        set_error("synth scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
+    SynthArgs a;
+    int L = 0, skip = 0;
+    void *table = nullptr;
+    if ((rc = enqueue_synth(mesh, mats, n_mats, radar, rays, hits, chirp, flags, if_cube, scratch, s, &a, &L, &table,
+                            &skip)))
+        return rc;
+    if (skip) return SBR_OK;
+    float2 *out = reinterpret_cast<float2 *>(if_cube);
+    return launch_synth_batch(&a, &L, 1, table, &out, s);
+}
+
+size_t sbr_batch_table_bytes(int32_t n_requests) {
+    if (n_requests < 1 || n_requests > SBR_MAX_BATCH) return 0;
+    return std::max(synth_table_bytes(n_requests), adj_table_bytes(n_requests));
+}
+
+int sbr_synth_if_batched(const sbr_request *reqs, int32_t n, void *table, size_t table_bytes, void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(n >= 0 && n <= SBR_MAX_BATCH, "n=%d out of [0, %d]", n, SBR_MAX_BATCH);
+    SBR_CHECK_ARG(n == 0 || reqs, "reqs is NULL");
+    if (n == 0) return SBR_OK;
+    const size_t need = sbr_batch_table_bytes(n);
+    if (!table || table_bytes < need) {
+        set_error("batch table too small: %zu bytes given, %zu needed", table_bytes, need);
         return SBR_E_SCRATCH;
     }
-    if (R == 0) return fill_zero_f32(if_cube, (size_t)2 * V * C * S, s);
-    Carver cv(scratch);
-    PathStage st = carve_path_stage(cv, R, K, V);
-    SynthPlan p = synth_plan(R, K, V, C, S);
-    float2 *partial = cv.take<float2>(synth_partial_elems(p, V, C, S));
-    if ((rc = launch_paths(mesh, make_mats(mats, n_mats), make_radar(radar), make_grid(rays), make_chirp(chirp),
-                           hits, flags, st, s)))
-        return rc;
-    return launch_synth(st, p, V, C, S, partial, reinterpret_cast<float2 *>(if_cube), s);
+    int rc;
+    for (int i = 0; i < n; i++) {
+        const sbr_request &q = reqs[i];
+        if ((rc = check_synth(q.mesh, q.mats, q.n_mats, q.radar, q.rays, q.hits, q.chirp, q.flags, q.if_cube,
+                              q.scratch, q.scratch_bytes))) {
+            const std::string msg = sbr_last_error();
+            set_error("request %d: %s", i, msg.c_str());
+            return rc;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<SynthArgs> args;
+    std::vector<int> Ls;
+    std::vector<float2 *> outs;
+    for (int i = 0; i < n; i++) {
+        const sbr_request &q = reqs[i];
+        SynthArgs a;
+        int L = 0, skip = 0;
+        if ((rc = enqueue_synth(q.mesh, q.mats, q.n_mats, q.radar, q.rays, q.hits, q.chirp, q.flags, q.if_cube,
+                                q.scratch, s, &a, &L, nullptr, &skip)))
+            return rc;
+        if (skip) continue;
+        args.push_back(a);
+        Ls.push_back(L);
+        outs.push_back(reinterpret_cast<float2 *>(q.if_cube));
+    }
+    return launch_synth_batch(args.data(), Ls.data(), (int)args.size(), table, outs.data(), s);
+}
+
+int sbr_backward_batched(const sbr_request *reqs, int32_t n, void *table, size_t table_bytes, void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(n >= 0 && n <= SBR_MAX_BATCH, "n=%d out of [0, %d]", n, SBR_MAX_BATCH);
+    SBR_CHECK_ARG(n == 0 || reqs, "reqs is NULL");
+    if (n == 0) return SBR_OK;
+    const size_t need = sbr_batch_table_bytes(n);
+    if (!table || table_bytes < need) {
+        set_error("batch table too small: %zu bytes given, %zu needed", table_bytes, need);
+        return SBR_E_SCRATCH;
+    }
+    int rc;
+    for (int i = 0; i < n; i++) {
+        const sbr_request &q = reqs[i];
+        if ((rc = check_backward(q.mesh, q.mats, q.n_mats, q.radar, q.rays, q.hits, q.chirp, q.flags, q.grad_if,
+                                 q.grad_verts, q.params, q.scratch, q.scratch_bytes))) {
+            const std::string msg = sbr_last_error();
+            set_error("request %d: %s", i, msg.c_str());
+            return rc;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<BackwardReq> qs;
+    for (int i = 0; i < n; i++) {
+        const sbr_request &q = reqs[i];
+        BackwardReq b;
+        int skip = 0;
+        if ((rc = enqueue_backward(q.mesh, q.mats, q.n_mats, q.radar, q.rays, q.hits, q.chirp, q.flags, q.grad_if,
+                                   q.grad_verts, q.params, q.scratch, s, &b, nullptr, &skip)))
+            return rc;
+        if (!skip) qs.push_back(b);
+    }
+    return launch_backward_batch(qs.data(), (int)qs.size(), table, s);
 }
 
 int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_angle, int32_t window,
@@ -435,29 +618,18 @@ int sbr_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
                  size_t scratch_bytes, void *stream) {
     clear_error();
     int rc;
-    if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
-    SBR_CHECK_ARG(grad_if && grad_verts, "grad_if/grad_verts is NULL");
-    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY)) == 0, "unknown flags 0x%x", flags);
-    SBR_CHECK_ARG(!params || !params->materials || (mats && n_mats > 0),
-                  "material gradients requested without a material table");
-    const int R = rays->nx * rays->ny, K = rays->max_bounces;
-    const int V = radar->n_tx * radar->n_rx;
-    size_t need = backward_bytes(R, K, V);
-    if (!scratch || scratch_bytes < need) {
-        set_error("backward scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
-        return SBR_E_SCRATCH;
-    }
-    if (R == 0 || mesh->nf == 0) return SBR_OK;
+    if ((rc = check_backward(mesh, mats, n_mats, radar, rays, hits, chirp, flags, grad_if, grad_verts, params,
+                             scratch, scratch_bytes)))
+        return rc;
     hipStream_t s = (hipStream_t)stream;
-    Carver cv(scratch);
-    PathStage st = carve_path_stage(cv, R, K, V);
-    MatTable mt = make_mats(mats, n_mats);
-    RadarDev rd = make_radar(radar);
-    GridDev gd = make_grid(rays);
-    ChirpDev cd = make_chirp(chirp);
-    if ((rc = launch_paths(mesh, mt, rd, gd, cd, hits, flags, st, s))) return rc;
-    return launch_backward(mesh, mt, rd, gd, cd, hits, st, cv, reinterpret_cast<const float2 *>(grad_if),
-                           grad_verts, radar, params, flags, s);
+    BackwardReq q;
+    void *table = nullptr;
+    int skip = 0;
+    if ((rc = enqueue_backward(mesh, mats, n_mats, radar, rays, hits, chirp, flags, grad_if, grad_verts, params,
+                               scratch, s, &q, &table, &skip)))
+        return rc;
+    if (skip) return SBR_OK;
+    return launch_backward_batch(&q, 1, table, s);
 }
 
 }  // extern "C"

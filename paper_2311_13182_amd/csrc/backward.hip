@@ -1,6 +1,8 @@
 // Backpropagation: adjoint of the IF synthesis (Eqs. 11-12) per path, then
 // the reverse sweep through the ray geometry of every ray (Eq. 13 chain rule)
 // with per-bounce recomputation, scattering dL/dverts.
+#include <vector>
+
 #include "sbr_internal.h"
 #include "sbr_device.h"
 
@@ -21,7 +23,6 @@ struct AdjArgs {
     float *tau_bar;        // [V][cap]
     float2 *abar_part;     // [nvs][cap]
     float *tdb_part;       // [nvs][cap] dL/d taudot partials
-    uint32_t *queue;       // work counter, zero at launch
 };
 
 constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time
@@ -43,6 +44,12 @@ constexpr int kAdjPPL = 2;       // paths per lane
 template <int PPL>
 __device__ __forceinline__ void adj_item(const AdjArgs &a, float2 *gsh, const int P, const int grp,
                                          const int blk_p0) {
+    const auto amp = gmem(a.rec.amp);
+    const auto bet = gmem(a.rec.beta);
+    const auto eps = gmem(a.rec.epsd);
+    const auto alp = gmem(a.rec.alpha);
+    const auto gam = gmem(a.rec.gamma);
+    const auto tbar = gmem(a.tau_bar);
     int pp[PPL];
     bool act[PPL];
     float2 A[PPL];
@@ -52,9 +59,9 @@ __device__ __forceinline__ void adj_item(const AdjArgs &a, float2 *gsh, const in
         pp[i] = blk_p0 + i * 256 + threadIdx.x;
         act[i] = pp[i] < P;
         const int pc = act[i] ? pp[i] : blk_p0;
-        A[i] = a.rec.amp[pc];
-        beta[i] = a.rec.beta[pc];
-        epsd[i] = a.rec.epsd[pc];
+        A[i] = make_float2(amp[pc].x, amp[pc].y);
+        beta[i] = bet[pc];
+        epsd[i] = eps[pc];
         abr[i] = 0.0f;
         abi[i] = 0.0f;
         tdb[i] = 0.0f;
@@ -66,8 +73,8 @@ __device__ __forceinline__ void adj_item(const AdjArgs &a, float2 *gsh, const in
         float alpha[PPL], gamma[PPL], tb[PPL];
 #pragma unroll
         for (int i = 0; i < PPL; i++) {
-            alpha[i] = a.rec.alpha[(size_t)v * a.rec.cap + pp[i]];
-            gamma[i] = a.rec.gamma[(size_t)v * a.rec.cap + pp[i]];
+            alpha[i] = alp[(size_t)v * a.rec.cap + pp[i]];
+            gamma[i] = gam[(size_t)v * a.rec.cap + pp[i]];
             tb[i] = 0.0f;
         }
         for (int c0 = 0; c0 < a.C; c0 += a.rows) {
@@ -75,10 +82,15 @@ __device__ __forceinline__ void adj_item(const AdjArgs &a, float2 *gsh, const in
             __syncthreads();
             // rows padded with zeros to Sp = S rounded up to 8: leading zero
             // coefficients leave Horner's recurrences unchanged
-            const float2 *src = a.G + ((size_t)v * a.C + c0) * S;
+            const auto src = gmem(a.G) + ((size_t)v * a.C + c0) * S;
             for (int i = threadIdx.x; i < nr * a.Sp; i += 256) {
                 const int rr = i / a.Sp, ss = i - rr * a.Sp;
-                gsh[i] = ss < S ? src[(size_t)rr * S + ss] : make_float2(0.0f, 0.0f);
+                if (ss < S) {
+                    const F2 g = src[(size_t)rr * S + ss];
+                    gsh[i] = make_float2(g.x, g.y);
+                } else {
+                    gsh[i] = make_float2(0.0f, 0.0f);
+                }
             }
             __syncthreads();
             for (int cc = 0; cc < nr; cc++) {
@@ -141,32 +153,79 @@ __device__ __forceinline__ void adj_item(const AdjArgs &a, float2 *gsh, const in
         }
 #pragma unroll
         for (int i = 0; i < PPL; i++)
-            if (act[i]) a.tau_bar[(size_t)v * a.rec.cap + pp[i]] = tb[i];
+            if (act[i]) tbar[(size_t)v * a.rec.cap + pp[i]] = tb[i];
     }
 #pragma unroll
     for (int i = 0; i < PPL; i++)
         if (act[i]) {
-            a.abar_part[(size_t)grp * a.rec.cap + pp[i]] = make_float2(abr[i], abi[i]);
-            a.tdb_part[(size_t)grp * a.rec.cap + pp[i]] = tdb[i];
+            gmem(a.abar_part)[(size_t)grp * a.rec.cap + pp[i]] = F2{abr[i], abi[i]};
+            gmem(a.tdb_part)[(size_t)grp * a.rec.cap + pp[i]] = tdb[i];
         }
 }
 
+// Work items of each request of a batch: (antenna groups) x (path tiles) for
+// its device-side path count; item_first[i] = first item of request i,
+// item_first[n] = total.  Also clears the work counter.  One block.
+__global__ __launch_bounds__(1024) void k_adj_items(const AdjArgs *args, int n, int ppl, uint32_t *item_first,
+                                                    uint32_t *queue) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = t * chunk, e = min(n, b + chunk);
+    uint32_t sum = 0;
+    for (int i = b; i < e; i++) {
+        const uint32_t P = (uint32_t)args[i].count[0];
+        sum += (P + 256u * ppl - 1u) / (256u * ppl) * (uint32_t)args[i].nvs;
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int i = b; i < e; i++) {
+        item_first[i] = run;
+        const uint32_t P = (uint32_t)args[i].count[0];
+        run += (P + 256u * ppl - 1u) / (256u * ppl) * (uint32_t)args[i].nvs;
+    }
+    if (t == 1023) item_first[n] = part[1023];
+    if (t == 0) queue[0] = 0u;
+}
+
+// Work items of all requests of a batch (one request for sbr_backward) are
+// taken from one atomic counter by about one device-full of blocks; an item
+// is mapped to its request by binary search over item_first, then to (antenna
+// group, path tile) exactly as in a launch of its own.  `slot` is the LDS
+// float2 offset of the work-item word (after the largest G-row stage).
 template <int PPL>
-__global__ __launch_bounds__(256) void k_synth_adj(AdjArgs a) {
+__global__ __launch_bounds__(256) void k_synth_adj(const AdjArgs *__restrict__ args,
+                                                   const uint32_t *__restrict__ item_first, int n,
+                                                   uint32_t *queue, int slot) {
     // [rows][Sp] G rows, then the current work item.  No static LDS: it would
     // shift the dynamic area off the 16-byte alignment of the row reads.
     extern __shared__ float2 gsh[];
-    uint32_t &s_item = *reinterpret_cast<uint32_t *>(gsh + a.rows * a.Sp);
-    const int P = a.count[0];
-    const uint32_t tiles = (uint32_t)((P + 256 * PPL - 1) / (256 * PPL));
-    const uint32_t total = tiles * (uint32_t)a.nvs;
+    uint32_t &s_item = *reinterpret_cast<uint32_t *>(gsh + slot);
+    const uint32_t total = item_first[n];
     for (;;) {
         __syncthreads();   // the previous item is done with s_item and gsh
-        if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1u);
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
         __syncthreads();
-        const uint32_t item = s_item;
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= total) break;   // uniform over the block
-        adj_item<PPL>(a, gsh, P, (int)(item / tiles), (int)(item % tiles) * 256 * PPL);
+        int lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (item_first[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const AdjArgs &a = args[lo];
+        const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
+        const uint32_t tiles = (uint32_t)((P + 256 * PPL - 1) / (256 * PPL));
+        const uint32_t local = item - item_first[lo];
+        adj_item<PPL>(a, gsh, P, (int)(local / tiles), (int)(local % tiles) * 256 * PPL);
     }
 }
 
@@ -191,6 +250,7 @@ struct GeomArgs {
     const uint16_t *mat_id;
     const int32_t *tri;
     int32_t R;
+    int32_t nf;
     MatTable mt;
     int32_t any_fresnel;
     RadarDev rd;
@@ -256,7 +316,7 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
     uint32_t mask = 0;                  // bounces that return a path
     if (r < a.R) {
         first = a.ray_first[r];
-        mask = ray_path_mask(a.tri, a.flags, (size_t)a.R, (size_t)r, a.g.K, a.drop != 0, a.exit_only != 0, &n);
+        mask = ray_path_mask(a.tri, a.flags, (size_t)a.R, (size_t)r, a.g.K, a.nf, a.drop != 0, a.exit_only != 0, &n);
     }
     if (__ballot(n > 0) == 0) return;   // uniform over the wavefront
     const int ix = r % a.g.nx, iy = r / a.g.nx;
@@ -405,19 +465,17 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
                 prv = X[j];
             }
             xb[k] = xb[k] + (Rb / Rk) * (X[k] - O);
-            float TS[SBR_MAX_TX], RS[SBR_MAX_RX], Tt = 0.0f;
-            for (int t = 0; t < ntx; t++) TS[t] = 0.0f;
-            for (int m = 0; m < nrx; m++) RS[m] = 0.0f;
-            for (int t = 0; t < ntx; t++)
-                for (int m = 0; m < nrx; m++) {
-                    const float tb = a.tau_bar[(size_t)(t * nrx + m) * a.cap + p];
-                    TS[t] += tb;
-                    RS[m] += tb;
-                    Tt += tb;
-                }
+            // the TX leg of antenna (t, m) moves with the sum over m of its
+            // delay adjoints, the RX leg with the sum over t; both sums are
+            // formed inside their loops (no runtime-indexed arrays)
+            const float *tbp = a.tau_bar + p;
+            float Tt = 0.0f;
             for (int t = 0; t < ntx; t++) {
+                float ts = 0.0f;
+                for (int m = 0; m < nrx; m++) ts += tbp[(size_t)(t * nrx + m) * a.cap];
+                Tt += ts;
                 const float3 q = X[0] - f3((float)a.rd.tx[t][0], (float)a.rd.tx[t][1], (float)a.rd.tx[t][2]);
-                const float3 gq = (TS[t] * ic0 / len3(q)) * q;
+                const float3 gq = (ts * ic0 / len3(q)) * q;
                 xb[0] = xb[0] + gq;
                 go = go - gq;                       // TX positions move with the origin
                 if (want_rot) {                     // tx_world = origin + rot tx_local
@@ -430,8 +488,10 @@ __global__ __launch_bounds__(256) void k_geom_adj(GeomArgs a) {
                 }
             }
             for (int m = 0; m < nrx; m++) {
+                float rs = 0.0f;
+                for (int t = 0; t < ntx; t++) rs += tbp[(size_t)(t * nrx + m) * a.cap];
                 const float3 q = X[k] - f3((float)a.rd.rx[m][0], (float)a.rd.rx[m][1], (float)a.rd.rx[m][2]);
-                const float3 gq = (RS[m] * ic0 / len3(q)) * q;
+                const float3 gq = (rs * ic0 / len3(q)) * q;
                 xb[k] = xb[k] + gq;
                 go = go - gq;                       // RX positions move with the origin
                 if (want_rot) {
@@ -620,100 +680,143 @@ size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V) {
     cv.take<float2>(cap);
     cv.take<float>((size_t)bp.nvs * cap);
     cv.take<float>(cap);
-    cv.take<uint32_t>(64);
     return align_up(cv.off, 256);
 }
 
-int launch_backward(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, const GridDev &gd,
-                    const ChirpDev &cd, const sbr_hits *h, const PathStage &st, Carver &cv,
-                    const float2 *G, float *grad, const sbr_radar *radar, const sbr_param_grads *params,
-                    int32_t flags, hipStream_t s) {
-    const bool attached = (flags & SBR_ATTACHED) != 0;
-    const int V = rd.n_tx * rd.n_rx;
-    const long long cap = st.rec.cap;
-    BackPlan bp = back_plan(cap, V);
-    float *tau_bar = cv.take<float>((size_t)V * cap);
-    float2 *part = cv.take<float2>((size_t)bp.nvs * cap);
-    float2 *abar = cv.take<float2>(cap);
-    float *tpart = cv.take<float>((size_t)bp.nvs * cap);
-    float *tdbar = cv.take<float>(cap);
-    uint32_t *queue = cv.take<uint32_t>(64);
-    int rc = fill_zero_f32(reinterpret_cast<float *>(queue), 1, s);   // all-zero bits
+// Device table of a batched adjoint: the requests' arguments, their first
+// work items and the work counter.
+struct AdjTable {
+    AdjArgs *args;
+    uint32_t *item_first;
+    uint32_t *queue;
+};
+
+static AdjTable adj_table(void *buf, int n, size_t *bytes) {
+    Carver cv(buf);
+    AdjTable t;
+    t.args = cv.take<AdjArgs>(n);
+    t.item_first = cv.take<uint32_t>((size_t)n + 1);
+    t.queue = cv.take<uint32_t>(64);
+    if (bytes) *bytes = align_up(cv.off, 256);
+    return t;
+}
+
+size_t adj_table_bytes(int n) {
+    size_t b = 0;
+    adj_table(nullptr, n, &b);
+    return b;
+}
+
+// G rows per LDS stage of a request with S samples, with the 16-byte
+// work-item slot after them, within 64 KiB of LDS per block.
+static int adj_rows(int Sp) { return std::max(1, std::min<int>(kAdjRowsMax, (65536 - 16) / (int)(sizeof(float2) * Sp))); }
+
+int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream_t s) {
+    if (n <= 0) return SBR_OK;
+    std::vector<AdjArgs> aa(n);
+    std::vector<GeomArgs> gg(n);
+    size_t lds_f2 = 0;   // float2 words of the largest G-row stage
+    long long items_max = 0;
+    for (int r = 0; r < n; r++) {
+        const BackwardReq &q = reqs[r];
+        const RadarDev &rd = q.rd;
+        const int V = rd.n_tx * rd.n_rx;
+        const long long cap = q.st.rec.cap;
+        BackPlan bp = back_plan(cap, V);
+        Carver cv(q.extra);
+        float *tau_bar = cv.take<float>((size_t)V * cap);
+        float2 *part = cv.take<float2>((size_t)bp.nvs * cap);
+        float2 *abar = cv.take<float2>(cap);
+        float *tpart = cv.take<float>((size_t)bp.nvs * cap);
+        float *tdbar = cv.take<float>(cap);
+        AdjArgs &a = aa[r];
+        a.count = q.st.count;
+        a.rec = q.st.rec;
+        a.G = q.G;
+        a.V = V;
+        a.C = q.cd.C;
+        a.S = q.cd.S;
+        a.v_per = bp.v_per;
+        a.nvs = bp.nvs;
+        a.fcf = (float)q.cd.fc;
+        a.sl_fs = (float)(q.cd.slope / q.cd.fs);
+        a.tc = (float)q.cd.tc;
+        a.tau_bar = tau_bar;
+        a.abar_part = part;
+        a.tdb_part = tpart;
+        a.Sp = (q.cd.S + 7) / 8 * 8;
+        a.rows = adj_rows(a.Sp);
+        lds_f2 = std::max(lds_f2, (size_t)a.rows * a.Sp);
+        items_max += (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL) * bp.nvs;
+        GeomArgs &g = gg[r];
+        const sbr_mesh *m = q.mesh;
+        g.verts = m->verts;
+        g.faces = m->faces;
+        g.mat_id = m->mat_id;
+        g.tri = q.hits->tri;
+        g.R = q.gd.nx * q.gd.ny;
+        g.nf = m->nf;
+        g.mt = q.mt;
+        g.any_fresnel = 0;
+        for (int i = 0; i < q.mt.n; i++)
+            if (q.mt.mode[i] != 0) g.any_fresnel = 1;
+        g.rd = rd;
+        g.g = q.gd;
+        g.ch = q.cd;
+        g.ray_first = q.st.ray_first;
+        g.flags = q.hits->flags;
+        g.drop = (q.flags & SBR_DROP_FLAGGED) ? 1 : 0;
+        g.exit_only = (q.flags & SBR_EXIT_ONLY) ? 1 : 0;
+        g.abar = abar;
+        g.tau_bar = tau_bar;
+        g.tdbar = tdbar;
+        g.cap = (int32_t)cap;
+        g.grad = q.grad;
+        g.g_mats = q.params ? q.params->materials : nullptr;
+        g.g_radar = q.params ? q.params->radar : nullptr;
+        g.g_rot = q.params ? q.params->rot : nullptr;
+        g.g_atten = q.params ? q.params->attenuation : nullptr;
+        g.attached = (q.flags & SBR_ATTACHED) ? 1 : 0;
+        for (int t = 0; t < SBR_MAX_TX; t++)
+            for (int c = 0; c < 3; c++) g.txl[t][c] = t < q.radar->n_tx ? (float)q.radar->tx[t][c] : 0.0f;
+        for (int k = 0; k < SBR_MAX_RX; k++)
+            for (int c = 0; c < 3; c++) g.rxl[k][c] = k < q.radar->n_rx ? (float)q.radar->rx[k][c] : 0.0f;
+    }
+    AdjTable t = adj_table(table, n, nullptr);
+    int rc = put_table(t.args, aa.data(), sizeof(AdjArgs) * n, s);
     if (rc) return rc;
-    AdjArgs a;
-    a.count = st.count;
-    a.rec = st.rec;
-    a.G = G;
-    a.V = V;
-    a.C = cd.C;
-    a.S = cd.S;
-    a.v_per = bp.v_per;
-    a.nvs = bp.nvs;
-    a.fcf = (float)cd.fc;
-    a.sl_fs = (float)(cd.slope / cd.fs);
-    a.tc = (float)cd.tc;
-    a.tau_bar = tau_bar;
-    a.abar_part = part;
-    a.tdb_part = tpart;
-    a.queue = queue;
-    a.Sp = (cd.S + 7) / 8 * 8;
-    // G rows per LDS stage, with the 16-byte work-item slot after them, within
-    // 64 KiB of LDS per block
-    a.rows = std::max(1, std::min<int>(kAdjRowsMax, (65536 - 16) / (int)(sizeof(float2) * a.Sp)));
-    size_t lds = sizeof(float2) * a.rows * a.Sp + 16;
+    hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, s, t.args, n, kAdjPPL, t.item_first, t.queue);
+    const size_t lds = sizeof(float2) * lds_f2 + 16;
     // one device-full of blocks, or fewer if the path slots cannot fill it
-    const long long items_max = (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL) * bp.nvs;
-    dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_max, resident_blocks((const void *)k_synth_adj<kAdjPPL>, 256, lds, 256 * 2))));
+    dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_max, resident_blocks((const void *)k_synth_adj<kAdjPPL>,
+                                                                                      256, lds, 256 * 2))));
     {
         ProfScope ps(kProfSynthAdj, s);
-        hipLaunchKernelGGL(k_synth_adj<kAdjPPL>, grid, dim3(256), lds, s, a);
-    }
-    hipLaunchKernelGGL(k_reduce_abar, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st.count, part, tpart,
-                       bp.nvs, (int)cap, abar, tdbar);
-    SBR_LAUNCHED();
-    GeomArgs g;
-    g.verts = m->verts;
-    g.faces = m->faces;
-    g.mat_id = m->mat_id;
-    g.tri = h->tri;
-    g.R = gd.nx * gd.ny;
-    g.mt = mt;
-    g.any_fresnel = 0;
-    for (int i = 0; i < mt.n; i++)
-        if (mt.mode[i] != 0) g.any_fresnel = 1;
-    g.rd = rd;
-    g.g = gd;
-    g.ch = cd;
-    g.ray_first = st.ray_first;
-    g.flags = h->flags;
-    g.drop = (flags & SBR_DROP_FLAGGED) ? 1 : 0;
-    g.exit_only = (flags & SBR_EXIT_ONLY) ? 1 : 0;
-    g.abar = abar;
-    g.tau_bar = tau_bar;
-    g.tdbar = tdbar;
-    g.cap = (int32_t)cap;
-    g.grad = grad;
-    g.g_mats = params ? params->materials : nullptr;
-    g.g_radar = params ? params->radar : nullptr;
-    g.g_rot = params ? params->rot : nullptr;
-    g.g_atten = params ? params->attenuation : nullptr;
-    g.attached = attached ? 1 : 0;
-    for (int t = 0; t < SBR_MAX_TX; t++)
-        for (int c = 0; c < 3; c++) g.txl[t][c] = t < radar->n_tx ? (float)radar->tx[t][c] : 0.0f;
-    for (int q = 0; q < SBR_MAX_RX; q++)
-        for (int c = 0; c < 3; c++) g.rxl[q][c] = q < radar->n_rx ? (float)radar->rx[q][c] : 0.0f;
-    dim3 gg((unsigned)((g.R + 255) / 256));
-    switch (gd.K) {
-    case 1: hipLaunchKernelGGL(k_geom_adj<1>, gg, dim3(256), 0, s, g); break;
-    case 2: hipLaunchKernelGGL(k_geom_adj<2>, gg, dim3(256), 0, s, g); break;
-    case 3: hipLaunchKernelGGL(k_geom_adj<3>, gg, dim3(256), 0, s, g); break;
-    case 4: hipLaunchKernelGGL(k_geom_adj<4>, gg, dim3(256), 0, s, g); break;
-    case 5: hipLaunchKernelGGL(k_geom_adj<5>, gg, dim3(256), 0, s, g); break;
-    case 6: hipLaunchKernelGGL(k_geom_adj<6>, gg, dim3(256), 0, s, g); break;
-    case 7: hipLaunchKernelGGL(k_geom_adj<7>, gg, dim3(256), 0, s, g); break;
-    default: hipLaunchKernelGGL(k_geom_adj<8>, gg, dim3(256), 0, s, g); break;
+        hipLaunchKernelGGL(k_synth_adj<kAdjPPL>, grid, dim3(256), lds, s, t.args, t.item_first, n, t.queue,
+                           (int)lds_f2);
     }
     SBR_LAUNCHED();
+    for (int r = 0; r < n; r++) {
+        const AdjArgs &a = aa[r];
+        const GeomArgs &g = gg[r];
+        const long long cap = a.rec.cap;
+        hipLaunchKernelGGL(k_reduce_abar, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, a.count, a.abar_part,
+                           a.tdb_part, a.nvs, (int)cap, const_cast<float2 *>(g.abar), const_cast<float *>(g.tdbar));
+        SBR_LAUNCHED();
+        if (g.R == 0 || g.nf == 0) continue;
+        dim3 gb((unsigned)((g.R + 255) / 256));
+        switch (g.g.K) {
+        case 1: hipLaunchKernelGGL(k_geom_adj<1>, gb, dim3(256), 0, s, g); break;
+        case 2: hipLaunchKernelGGL(k_geom_adj<2>, gb, dim3(256), 0, s, g); break;
+        case 3: hipLaunchKernelGGL(k_geom_adj<3>, gb, dim3(256), 0, s, g); break;
+        case 4: hipLaunchKernelGGL(k_geom_adj<4>, gb, dim3(256), 0, s, g); break;
+        case 5: hipLaunchKernelGGL(k_geom_adj<5>, gb, dim3(256), 0, s, g); break;
+        case 6: hipLaunchKernelGGL(k_geom_adj<6>, gb, dim3(256), 0, s, g); break;
+        case 7: hipLaunchKernelGGL(k_geom_adj<7>, gb, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL(k_geom_adj<8>, gb, dim3(256), 0, s, g); break;
+        }
+        SBR_LAUNCHED();
+    }
     return SBR_OK;
 }
 

@@ -251,10 +251,34 @@ __device__ __forceinline__ float ld_coherent(const float *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// leaf triangles + boxes, then bottom-up unions (second arrival continues)
+// header of a finished BUILD: face count and seal
+__global__ void k_bvh_seal(int32_t *header, int n) {
+    if (threadIdx.x == 0) {
+        header[0] = n;
+        header[1] = kBvhMagic;
+        header[2] = 0;
+    }
+}
+
+// bottom-up arrival counters cleared for a refit, only in a buffer sealed
+// for this face count (its layout is then the one bvh_view computes)
+__global__ void k_zero_visits(const int32_t *header, int n, uint32_t *visits) {
+    if (header[1] != kBvhMagic || header[0] != n) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n - 1) visits[i] = 0u;
+}
+
+// leaf triangles + boxes, then bottom-up unions (second arrival continues).
+// The stored order, parent, child and depth-first maps are followed only in a
+// buffer sealed by a BUILD for this face count; otherwise nothing is written
+// but the header's refit-rejected word.
 __global__ void k_leaves(const float *verts, const int32_t *faces, BvhView bv) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int n = bv.n;
+    if (bv.header[1] != kBvhMagic || bv.header[0] != n) {
+        if (i == 0) bv.header[2] = 1;
+        return;
+    }
     if (i >= n) return;
     int f = bv.order[i];
     float3 a = load_vert(verts, faces[3 * f]);
@@ -395,11 +419,12 @@ int bvh_build(const sbr_mesh *m, void *bvh, size_t bvh_bytes, int32_t mode, void
                            2 * nf - 1);
         hipLaunchKernelGGL(k_dfs, dim3(nblocks(2 * nf - 1, kThreads)), dim3(kThreads), 0, st, nf,
                            bv.parent, bv.child, s.range, bv.dfs_of, bv.nodes);
+        hipLaunchKernelGGL(k_bvh_seal, dim3(1), dim3(64), 0, st, bv.header, nf);
         SBR_LAUNCHED();
     }
     if (nf > 1)
-        hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(nf - 1, kThreads)), dim3(kThreads), 0, st,
-                           bv.visits, 0u, nf - 1);
+        hipLaunchKernelGGL(k_zero_visits, dim3(nblocks(nf - 1, kThreads)), dim3(kThreads), 0, st, bv.header, nf,
+                           bv.visits);
     hipLaunchKernelGGL(k_leaves, dim3(nblocks(nf, kThreads)), dim3(kThreads), 0, st, m->verts,
                        m->faces, bv);
     SBR_LAUNCHED();

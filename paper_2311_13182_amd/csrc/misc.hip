@@ -4,6 +4,8 @@
 
 #include <algorithm>
 
+#include <cstring>
+
 #include "sbr_internal.h"
 
 namespace sbr {
@@ -98,6 +100,34 @@ ProfScope::~ProfScope() {
 }
 
 int fill_zero_f32(float *p, size_t n, hipStream_t s);
+
+namespace {
+constexpr int kPutWords = 448;   // 1792 bytes of data per launch, within the kernel-argument limit
+struct PutChunk {
+    uint32_t w[kPutWords];
+};
+__global__ void k_put_words(PutChunk c, uint32_t *dst, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = c.w[i];
+}
+}  // namespace
+
+int put_table(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes % 4 != 0) {
+        set_error("put_table: %zu bytes is not a multiple of 4", bytes);
+        return SBR_E_ARG;
+    }
+    const uint32_t *w = static_cast<const uint32_t *>(src);
+    uint32_t *d = static_cast<uint32_t *>(dst);
+    const size_t nw = bytes / 4;
+    for (size_t off = 0; off < nw; off += kPutWords) {
+        PutChunk c;
+        const int n = (int)std::min<size_t>(kPutWords, nw - off);
+        memcpy(c.w, w + off, sizeof(uint32_t) * n);
+        hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s, c, d + off, n);
+    }
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
 
 }  // namespace sbr
 

@@ -139,15 +139,16 @@ __device__ __forceinline__ void grid_ray(const GridDev &g, const RadarDev &rd, i
 // Bounces of ray r that return a path: a hit that is not occluded, not cut
 // by SBR_DROP_FLAGGED (a flag other than SBR_HIT_OCCLUDED ends the ray's
 // paths), and with SBR_EXIT_ONLY only the ray's last hit.  Bit k = bounce k;
-// *nb = highest returning bounce + 1 (0 when none).
+// *nb = highest returning bounce + 1 (0 when none).  A face id outside
+// [0, nf) ends the ray like a miss, so no face outside the mesh is read.
 __device__ __forceinline__ uint32_t ray_path_mask(const int32_t *tri, const uint8_t *flags, size_t R, size_t r,
-                                                  int K, bool drop, bool exit_only, int *nb) {
+                                                  int K, int nf, bool drop, bool exit_only, int *nb) {
     uint32_t mask = 0;
     int nh = 0;
     bool cut = false;
     for (int k = 0; k < K; k++) {
         const size_t slot = (size_t)k * R + r;
-        if (tri[slot] < 0) break;
+        if ((unsigned)tri[slot] >= (unsigned)nf) break;
         nh = k + 1;
         const uint8_t fl = flags[slot];
         if (drop && (fl & ~SBR_HIT_OCCLUDED)) cut = true;

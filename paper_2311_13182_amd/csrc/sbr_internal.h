@@ -86,8 +86,13 @@ struct BvhView {
     int2 *child;        // [n-1] radix-tree children
     int32_t *dfs_of;    // [n_nodes] radix-tree index -> depth-first index
     uint32_t *visits;   // [n-1] bottom-up arrival counters
-    int32_t *header;    // [16] n, built flag
+    int32_t *header;    // [16] [0] n, [1] kBvhMagic once a BUILD of n faces has
+                        // finished, [2] set to 1 by a REFIT that found no such BUILD
 };
+
+// Seal of a built BVH buffer (header[1]); refit and traversal check it
+// together with header[0] == face count before they follow any stored index.
+constexpr int32_t kBvhMagic = 0x48564253;
 
 BvhView bvh_view(void *buf, int32_t nf, size_t *bytes_out);
 
@@ -154,7 +159,78 @@ struct SynthPlan {
     int32_t L, SB, tiles_per_v, n_chunks;
 };
 
+// A pointer read from a device table is generic; marking it global lets the
+// compiler use scalar or global (not flat) loads through it.  The qualifier
+// exists in the device pass only (the host pass merely parses these bodies).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SBR_GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define SBR_GLOBAL_AS
+#endif
+template <class T>
+__device__ __forceinline__ SBR_GLOBAL_AS T *gmem(T *p) {
+    return (SBR_GLOBAL_AS T *)p;
+}
+// plain pair of floats with float2's layout, for address-space-qualified access
+struct F2 {
+    float x, y;
+};
+__device__ __forceinline__ SBR_GLOBAL_AS const F2 *gmem(const float2 *p) { return (SBR_GLOBAL_AS const F2 *)p; }
+__device__ __forceinline__ SBR_GLOBAL_AS F2 *gmem(float2 *p) { return (SBR_GLOBAL_AS F2 *)p; }
+
+// Arguments of one request's IF synthesis (device-table entry of a batch).
+struct SynthArgs {
+    const int32_t *count;
+    PathSoA rec;
+    int32_t V, C, S;
+    int32_t SB;          // sample blocks per chirp row
+    int32_t tiles_per_v; // wavefront tiles per antenna
+    int32_t n_chunks;
+    int32_t gx;          // blocks per chunk (4 wavefronts each)
+    float2 *partial;     // [n_chunks][V][C][S]
+};
+
 PathStage carve_path_stage(Carver &cv, int32_t R, int32_t K, int32_t V);
+SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S);
+size_t synth_partial_elems(const SynthPlan &p, int32_t V, int32_t C, int32_t S);
+SynthArgs synth_args(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial);
+// Device-table bytes of a batch of n syntheses.
+size_t synth_table_bytes(int n);
+// IF synthesis of n requests whose path stages are enqueued: one launch per
+// sample-run length over all their blocks (args[i] and L[i] = synth_plan's L),
+// then each request's fixed-order chunk reduction into out[i].
+int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, float2 *const *out,
+                       hipStream_t s);
+
+// One request of a (batched) backward pass: validated arguments, path stage
+// enqueued into st, `extra` = its scratch after the path stage.
+struct BackwardReq {
+    const sbr_mesh *mesh;
+    MatTable mt;
+    RadarDev rd;
+    GridDev gd;
+    ChirpDev cd;
+    const sbr_hits *hits;
+    PathStage st;
+    void *extra;
+    const float2 *G;
+    float *grad;
+    const sbr_radar *radar;
+    const sbr_param_grads *params;
+    int32_t flags;
+};
+size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V);
+// Device-table bytes of a batch of n adjoints.
+size_t adj_table_bytes(int n);
+// Synthesis adjoint of n requests as one work-queue launch over all their
+// (antenna group, path tile) items, then each request's reduction and
+// geometry adjoint.
+int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream_t s);
+
+// Copy `bytes` (a multiple of 4) of host data into device memory on stream s
+// with fill kernels that carry the data as kernel arguments: no memcpy node,
+// and the host data need not outlive the call.
+int put_table(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 // host-side conversions / validation shared by the entry points
 int check_mesh(const sbr_mesh *m);

@@ -2,6 +2,7 @@
 // ray-major order) and the IF synthesis of Eq. (8).
 #include <cmath>
 #include <utility>
+#include <vector>
 
 #include "sbr_internal.h"
 #include "sbr_device.h"
@@ -19,6 +20,7 @@ struct PathArgs {
     int32_t drop;
     int32_t exit_only;
     int32_t R;
+    int32_t nf;
     MatTable mt;
     RadarDev rd;
     GridDev g;
@@ -27,7 +29,7 @@ struct PathArgs {
 };
 
 __device__ __forceinline__ uint32_t ray_mask(const PathArgs &a, size_t r, int *nb) {
-    return ray_path_mask(a.tri, a.flags, (size_t)a.R, r, a.g.K, a.drop != 0, a.exit_only != 0, nb);
+    return ray_path_mask(a.tri, a.flags, (size_t)a.R, r, a.g.K, a.nf, a.drop != 0, a.exit_only != 0, nb);
 }
 
 __device__ __forceinline__ int block_sum(int x, int *sh) {
@@ -225,6 +227,7 @@ int launch_paths(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, cons
     a.drop = (flags & SBR_DROP_FLAGGED) ? 1 : 0;
     a.exit_only = (flags & SBR_EXIT_ONLY) ? 1 : 0;
     a.R = gd.nx * gd.ny;
+    a.nf = m->nf;
     a.mt = mt;
     a.rd = rd;
     a.g = gd;
@@ -240,15 +243,6 @@ int launch_paths(const sbr_mesh *m, const MatTable &mt, const RadarDev &rd, cons
 // ------------------------------------------------------------------ Eq. (8)
 namespace {
 
-struct SynthArgs {
-    const int32_t *count;
-    PathSoA rec;
-    int32_t V, C, S;
-    int32_t SB;          // sample blocks per chirp row
-    int32_t tiles_per_v; // wavefront tiles per antenna
-    int32_t n_chunks;
-    float2 *partial;     // [n_chunks][V][C][S]
-};
 
 __device__ __forceinline__ float frac_f(float x) { return x - floorf(x); }
 
@@ -324,18 +318,18 @@ __device__ __forceinline__ void add_path(float alpha, float delta, float dph, fl
 // sample on every lane (recurrence) and remembers the others in LDS; a second
 // pass adds those by rotation (it rescans the chunk if more than kRotList of
 // them came up).  Path records are wavefront-uniform (scalar loads); the next
-// one is fetched while the current one is accumulated.
+// one is fetched while the current one is accumulated.  (bx, chunk) is the
+// block's place in the request's own (x, chunk) grid.
 template <int L>
-__global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
-    __shared__ int rot_list[4][kRotList];
-    const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+__device__ __forceinline__ void synth_block(const SynthArgs &a, const int bx, const int chunk,
+                                            int (&rot_list)[4][kRotList]) {
+    const int wv = __builtin_amdgcn_readfirstlane(bx * 4 + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int v = __builtin_amdgcn_readfirstlane(wv / a.tiles_per_v);
     if (v >= a.V) return;   // wave-uniform; the kernel has no block barrier
     const int e = (wv % a.tiles_per_v) * 64 + lane;
     const int c = e / a.SB, b = e % a.SB;
-    const int chunk = blockIdx.y;
-    const int P = __builtin_amdgcn_readfirstlane(a.count[0]);
+    const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
     const long long per = ((long long)P + a.n_chunks - 1) / a.n_chunks;
     const int p0 = (int)min((long long)P, per * chunk);
     const int p1 = (int)min((long long)P, per * (chunk + 1));
@@ -347,28 +341,31 @@ __global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
         ar[i] = 0.0f;
         ai[i] = 0.0f;
     }
-    const float *al = a.rec.alpha + (size_t)v * a.rec.cap;
-    const float *ga = a.rec.gamma + (size_t)v * a.rec.cap;
+    const auto al = gmem(a.rec.alpha + (size_t)v * a.rec.cap);
+    const auto ga = gmem(a.rec.gamma + (size_t)v * a.rec.cap);
+    const auto amp = gmem(a.rec.amp);
+    const auto bet = gmem(a.rec.beta);
+    const auto eps = gmem(a.rec.epsd);
     int n_rot = 0;   // wave-uniform
     {
         float n_al = 0.f, n_ga = 0.f, n_be = 0.f, n_ep = 0.f;
-        float2 n_A = make_float2(0.f, 0.f);
+        F2 n_A = {0.f, 0.f};
         if (p0 < p1) {
             n_al = al[p0];
             n_ga = ga[p0];
-            n_A = a.rec.amp[p0];
-            n_be = a.rec.beta[p0];
-            n_ep = a.rec.epsd[p0];
+            n_A = amp[p0];
+            n_be = bet[p0];
+            n_ep = eps[p0];
         }
         for (int p = p0; p < p1; p++) {
             const float alpha = n_al, gamma = n_ga, beta = n_be, epsd = n_ep;
-            const float2 A = n_A;
+            const float2 A = make_float2(n_A.x, n_A.y);
             if (p + 1 < p1) {
                 n_al = al[p + 1];
                 n_ga = ga[p + 1];
-                n_A = a.rec.amp[p + 1];
-                n_be = a.rec.beta[p + 1];
-                n_ep = a.rec.epsd[p + 1];
+                n_A = amp[p + 1];
+                n_be = bet[p + 1];
+                n_ep = eps[p + 1];
             }
             const float delta = fmaf(cf, epsd, gamma);   // cycles per sample
             const float dph = delta - rintf(delta);
@@ -389,18 +386,41 @@ __global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     for (int i = 0; i < n_iter; i++) {
         const int p = listed ? __builtin_amdgcn_readfirstlane(rot_list[wl][i]) : p0 + i;
-        const float delta = fmaf(cf, a.rec.epsd[p], ga[p]);
+        const float delta = fmaf(cf, eps[p], ga[p]);
         const float dph = delta - rintf(delta);
         if (!listed && !near_dc_or_nyquist(dph)) continue;
-        add_path<L, true>(al[p], delta, dph, a.rec.beta[p], a.rec.amp[p], cf, s0, ar, ai);
+        const F2 Ap = amp[p];
+        add_path<L, true>(al[p], delta, dph, bet[p], make_float2(Ap.x, Ap.y), cf, s0, ar, ai);
     }
     if (c < a.C) {
-        float2 *out = a.partial + ((size_t)chunk * a.V + v) * (size_t)a.C * a.S + (size_t)c * a.S;
+        const auto out = gmem(a.partial) + ((size_t)chunk * a.V + v) * (size_t)a.C * a.S + (size_t)c * a.S;
         int sb = b * L;
 #pragma unroll
         for (int i = 0; i < L; i++)
-            if (sb + i < a.S) out[sb + i] = make_float2(ar[i], ai[i]);
+            if (sb + i < a.S) out[sb + i] = F2{ar[i], ai[i]};
     }
+}
+
+// One launch covers the requests of a batch that share L (one request for
+// sbr_synth_if): request idx[i] owns blocks [first[i], first[i + 1]) of the
+// grid, its own (x, chunk) grid laid out x fastest.  A block finds its
+// request by binary search over `first` (uniform, scalar loads), so every
+// request's waves do exactly the work they do in a launch of their own.
+template <int L>
+__global__ __launch_bounds__(256) void k_synth(const SynthArgs *__restrict__ args,
+                                               const int32_t *__restrict__ first, const int32_t *__restrict__ idx,
+                                               int n) {
+    __shared__ int rot_list[4][kRotList];
+    const int blk = (int)blockIdx.x;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    const SynthArgs &a = args[idx[lo]];
+    const int local = blk - first[lo];
+    synth_block<L>(a, local % a.gx, local / a.gx, rot_list);
 }
 
 __global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, float2 *out) {
@@ -434,20 +454,20 @@ constexpr int kSynthL = 64;   // samples per lane (128 measured slower: occupanc
 // Blocks of 256 threads of k_synth<L> the device holds at once (256 CUs x 3
 // where the runtime cannot answer).
 static int resident_synth_blocks(int L) {
-    const void *k = L == 128 ? (const void *)k_synth<128>
-                    : L == 64 ? (const void *)k_synth<64>
-                    : L == 32 ? (const void *)k_synth<32>
-                              : (const void *)k_synth<16>;
+    const void *k = L == 64 ? (const void *)k_synth<64> : L == 32 ? (const void *)k_synth<32>
+                                                                  : (const void *)k_synth<16>;
     return resident_blocks(k, 256, 0, 256 * 3);
 }
 
-// Paths are split into n_chunks chunks (grid.y).  Every wave of the grid does
-// the same work, so the chunk count is chosen to make the grid a whole number
-// of device-fulls of resident blocks (about 16k waves in all): a partly filled
-// last round leaves most of the chip idle for one wave's run time.
+// Paths are split into n_chunks chunks.  Every wave of the grid does the same
+// work, so the chunk count is chosen to make the grid a whole number of
+// device-fulls of resident blocks (about 16k waves in all): a partly filled
+// last round leaves most of the chip idle for one wave's run time.  The plan
+// depends only on the request's own sizes (and the device), so a request
+// runs the same waves alone and in a batch.
 SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
     SynthPlan p;
-    p.L = S >= kSynthL ? kSynthL : (S >= 64 ? 64 : (S >= 32 ? 32 : 16));
+    p.L = S >= kSynthL ? kSynthL : (S >= 32 ? 32 : 16);
     p.SB = (S + p.L - 1) / p.L;
     p.tiles_per_v = (C * p.SB + 63) / 64;
     long long waves = (long long)V * p.tiles_per_v;
@@ -466,8 +486,7 @@ size_t synth_partial_elems(const SynthPlan &p, int32_t V, int32_t C, int32_t S) 
     return (size_t)p.n_chunks * V * C * S;
 }
 
-int launch_synth(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial,
-                 float2 *out, hipStream_t s) {
+SynthArgs synth_args(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial) {
     SynthArgs a;
     a.count = st.count;
     a.rec = st.rec;
@@ -477,23 +496,75 @@ int launch_synth(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, 
     a.SB = p.SB;
     a.tiles_per_v = p.tiles_per_v;
     a.n_chunks = p.n_chunks;
+    a.gx = (int32_t)(((long long)V * p.tiles_per_v + 3) / 4);
     a.partial = partial;
-    long long waves = (long long)V * p.tiles_per_v;
-    dim3 grid((unsigned)((waves + 3) / 4), (unsigned)p.n_chunks);
-    {
-        ProfScope ps(kProfSynth, s);
-        if (p.L == 128)
-            hipLaunchKernelGGL(k_synth<128>, grid, dim3(256), 0, s, a);
-        else if (p.L == 64)
-            hipLaunchKernelGGL(k_synth<64>, grid, dim3(256), 0, s, a);
-        else if (p.L == 32)
-            hipLaunchKernelGGL(k_synth<32>, grid, dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL(k_synth<16>, grid, dim3(256), 0, s, a);
+    return a;
+}
+
+// Device table of a batched synthesis: the requests' arguments, then per
+// sample-run length L (16, 32, 64) the requests using it and their first blocks.
+struct SynthTable {
+    SynthArgs *args;
+    int32_t *idx[3];
+    int32_t *first[3];
+};
+
+static SynthTable synth_table(void *buf, int n, size_t *bytes) {
+    Carver cv(buf);
+    SynthTable t;
+    t.args = cv.take<SynthArgs>(n);
+    for (int g = 0; g < 3; g++) {
+        t.idx[g] = cv.take<int32_t>(n);
+        t.first[g] = cv.take<int32_t>((size_t)n + 1);
     }
-    size_t n = (size_t)V * C * S;
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial,
-                       p.n_chunks, n, out);
+    if (bytes) *bytes = align_up(cv.off, 256);
+    return t;
+}
+
+size_t synth_table_bytes(int n) {
+    size_t b = 0;
+    synth_table(nullptr, n, &b);
+    return b;
+}
+
+int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, float2 *const *out,
+                       hipStream_t s) {
+    if (n <= 0) return SBR_OK;
+    SynthTable t = synth_table(table, n, nullptr);
+    int rc = put_table(t.args, args, sizeof(SynthArgs) * n, s);
+    if (rc) return rc;
+    static const int kLs[3] = {16, 32, 64};
+    for (int g = 0; g < 3; g++) {
+        std::vector<int32_t> idx, first(1, 0);
+        for (int i = 0; i < n; i++) {
+            if (L[i] != kLs[g]) continue;
+            const long long blocks = (long long)args[i].gx * args[i].n_chunks;
+            if (first.back() + blocks > 0x7fffffffLL) {
+                set_error("batched synthesis: more than 2^31 blocks in one launch");
+                return SBR_E_ARG;
+            }
+            idx.push_back(i);
+            first.push_back(first.back() + (int32_t)blocks);
+        }
+        if (idx.empty() || first.back() == 0) continue;
+        if ((rc = put_table(t.idx[g], idx.data(), sizeof(int32_t) * idx.size(), s))) return rc;
+        if ((rc = put_table(t.first[g], first.data(), sizeof(int32_t) * first.size(), s))) return rc;
+        const int m = (int)idx.size();
+        const dim3 grid((unsigned)first.back());
+        ProfScope ps(kProfSynth, s);
+        if (kLs[g] == 64)
+            hipLaunchKernelGGL(k_synth<64>, grid, dim3(256), 0, s, t.args, t.first[g], t.idx[g], m);
+        else if (kLs[g] == 32)
+            hipLaunchKernelGGL(k_synth<32>, grid, dim3(256), 0, s, t.args, t.first[g], t.idx[g], m);
+        else
+            hipLaunchKernelGGL(k_synth<16>, grid, dim3(256), 0, s, t.args, t.first[g], t.idx[g], m);
+    }
+    SBR_LAUNCHED();
+    for (int i = 0; i < n; i++) {
+        const size_t e = (size_t)args[i].V * args[i].C * args[i].S;
+        hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, args[i].partial,
+                           args[i].n_chunks, e, out[i]);
+    }
     SBR_LAUNCHED();
     return SBR_OK;
 }

@@ -8,6 +8,7 @@ namespace sbr {
 namespace {
 
 struct TraceArgs {
+    const int32_t *header;   // BVH header: [0] faces, [1] seal
     const BvhNode *nodes;
     const LeafTri *tris;
     int32_t n_nodes;
@@ -80,7 +81,7 @@ __device__ __forceinline__ Shear make_shear(float3 d) {
 // Any hit of a triangle other than `self` at t in (tmin, tmax) along the unit
 // direction s from x: the occlusion test of a return segment.  Same stackless
 // walk as the closest-hit query, leaving at the first accepted hit.
-__device__ bool any_hit(const TraceArgs &a, float3 x, float3 s, float tmin, float tmax, int self) {
+__device__ bool any_hit(const TraceArgs &a, int n_nodes, float3 x, float3 s, float tmin, float tmax, int self) {
     const Shear sh = make_shear(s);
     float3 id;
     id.x = 1.0f / (fabsf(s.x) > 1e-30f ? s.x : copysignf(1e-30f, s.x));
@@ -88,7 +89,7 @@ __device__ bool any_hit(const TraceArgs &a, float3 x, float3 s, float tmin, floa
     id.z = 1.0f / (fabsf(s.z) > 1e-30f ? s.z : copysignf(1e-30f, s.z));
     const float3 oid = make_float3(x.x * id.x, x.y * id.y, x.z * id.z);
     int i = 0;
-    while (i < a.n_nodes) {
+    while (i < n_nodes) {
         const BvhNode nd = a.nodes[i];
         float tx0 = fmaf(nd.lo[0], id.x, -oid.x), tx1 = fmaf(nd.hi[0], id.x, -oid.x);
         float ty0 = fmaf(nd.lo[1], id.y, -oid.y), ty1 = fmaf(nd.hi[1], id.y, -oid.y);
@@ -128,6 +129,9 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     const int ix = (tile % tiles_x) * 8 + (l & 7);
     const int iy = (tile / tiles_x) * 8 + (l >> 3);
     const bool active = ix < a.g.nx && iy < a.g.ny;
+    // a buffer that no BUILD for this face count has sealed is never walked:
+    // every ray misses
+    const int n_nodes = (a.n_nodes > 0 && a.header[1] == kBvhMagic && a.header[0] == a.n_tris) ? a.n_nodes : 0;
     unsigned long long n_q = 0, n_node = 0, n_tri = 0;
     if (active) {
         const size_t R = (size_t)a.g.nx * a.g.ny;
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
             float t1 = INFINITY, t2 = INFINITY, bb0 = 0.f, bb1 = 0.f, bb2 = 0.f;
             float tlim = INFINITY;   // box cull limit: best t plus the tie margin
             int i = 0;
-            while (i < a.n_nodes) {
+            while (i < n_nodes) {
                 const BvhNode nd = a.nodes[i];
                 if (COUNT) n_node++;
                 float tx0 = fmaf(nd.lo[0], id.x, -oid.x), tx1 = fmaf(nd.hi[0], id.x, -oid.x);
@@ -197,6 +201,10 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                 }
                 const LeafTri lt = a.tris[nd.leaf];
                 const int fid = __float_as_int(lt.a.w);
+                if ((unsigned)fid >= (unsigned)a.n_tris) {   // not a face of this mesh
+                    i = esc;
+                    continue;
+                }
                 if (COUNT) n_tri++;
                 float th, c0, c1, c2;
                 if (fid != prev &&
@@ -260,7 +268,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                 const float3 q = make_float3(o0.x - o.x, o0.y - o.y, o0.z - o.z);
                 const float D = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z);
                 const float3 sd = make_float3(q.x / D, q.y / D, q.z / D);
-                if (any_hit(a, o, sd, tmin, D - tmin, best)) fl |= SBR_HIT_OCCLUDED;
+                if (any_hit(a, n_nodes, o, sd, tmin, D - tmin, best)) fl |= SBR_HIT_OCCLUDED;
             }
             a.tri[slot] = best;
             a.t[slot] = t1;
@@ -297,6 +305,7 @@ int trace_launch(const sbr_mesh *m, const void *bvh, const RadarDev &rd, const G
                  const sbr_hits *h, uint64_t *counters, hipStream_t st) {
     BvhView bv = bvh_view(const_cast<void *>(bvh), m->nf, nullptr);
     TraceArgs a;
+    a.header = bv.header;
     a.nodes = bv.nodes;
     a.tris = bv.tris;
     a.n_nodes = m->nf > 0 ? bv.n_nodes : 0;

@@ -305,6 +305,56 @@ def sbr_loss_grad(mode: int, a: torch.Tensor, b: torch.Tensor, n: int, grad: Opt
                                  _stream()))
 
 
+def sbr_batch_table_bytes(n: int) -> int:
+    return int(_lib().sbr_batch_table_bytes(int(n)))
+
+
+def _request(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: S.Chirp, flags: int,
+             scratch: torch.Tensor, keep: list, if_cube: Optional[torch.Tensor] = None,
+             grad_if: Optional[torch.Tensor] = None, grad_verts: Optional[torch.Tensor] = None) -> L.sbr_request:
+    """One sbr_request after the buffer checks of the single-request calls;
+    `keep` holds the ctypes structs it points to for the duration of the call."""
+    V, C, Sn = radar.n_virtual, chirp.n_chirps, chirp.n_samples
+    _check_hits(hits, rays.max_bounces, rays.nx * rays.ny)
+    m, r, g, h, c = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct(), chirp_struct(chirp)
+    mats, nm = materials_struct(mesh.materials)
+    keep.extend([m, r, g, h, c, mats])
+    q = L.sbr_request()
+    q.mesh, q.radar, q.rays, q.hits, q.chirp = ct.pointer(m), ct.pointer(r), ct.pointer(g), ct.pointer(h), ct.pointer(c)
+    if mats is not None:
+        q.mats = ct.cast(mats, ct.POINTER(L.sbr_material))
+    q.n_mats, q.flags = nm, int(flags)
+    q.if_cube = _buf(if_cube, torch.float32, 2 * V * C * Sn, "if_cube") if if_cube is not None else None
+    q.grad_if = _buf(grad_if, torch.float32, 2 * V * C * Sn, "grad_if") if grad_if is not None else None
+    q.grad_verts = _buf(grad_verts, torch.float32, 3 * mesh.nv, "grad_verts") if grad_verts is not None else None
+    q.scratch = _buf(scratch, torch.uint8, 0, "scratch")
+    q.scratch_bytes = scratch.numel() * scratch.element_size()
+    return q
+
+
+def sbr_synth_if_batched(items: Sequence[tuple], table: torch.Tensor):
+    """items: (mesh, radar, rays, hits, chirp, flags, if_cube, scratch) per
+    request; one batched synthesis on the current stream."""
+    keep: list = []
+    arr = (L.sbr_request * max(1, len(items)))()
+    for i, (mesh, radar, rays, hits, chirp, flags, if_cube, scratch) in enumerate(items):
+        arr[i] = _request(mesh, radar, rays, hits, chirp, flags, scratch, keep, if_cube=if_cube)
+    L.check(_lib().sbr_synth_if_batched(arr, len(items), _buf(table, torch.uint8, 0, "table"),
+                                        table.numel() * table.element_size(), _stream()))
+
+
+def sbr_backward_batched(items: Sequence[tuple], table: torch.Tensor):
+    """items: (mesh, radar, rays, hits, chirp, flags, grad_if, grad_verts,
+    scratch) per request; one batched backward pass on the current stream."""
+    keep: list = []
+    arr = (L.sbr_request * max(1, len(items)))()
+    for i, (mesh, radar, rays, hits, chirp, flags, grad_if, grad_verts, scratch) in enumerate(items):
+        arr[i] = _request(mesh, radar, rays, hits, chirp, flags, scratch, keep, grad_if=grad_if,
+                          grad_verts=grad_verts)
+    L.check(_lib().sbr_backward_batched(arr, len(items), _buf(table, torch.uint8, 0, "table"),
+                                        table.numel() * table.element_size(), _stream()))
+
+
 def sbr_profile(op: int):
     L.check(_lib().sbr_profile(int(op)))
 
@@ -321,12 +371,54 @@ def last_error() -> str:
 
 
 # ----------------------------------------------------------------- convenience
+def _angle_grid(rd: S.Radar, n_angle: int):
+    """(n_ax, n_ay, n_angle) of the radar cube: a planar array's angle grid is
+    n_ay x n_ax over the (TX, RX) = (vy, vx) virtual grid."""
+    if getattr(rd, "planar", False):
+        n_ax, n_ay = max(n_angle, rd.n_rx), max(n_angle, rd.n_tx)
+        return n_ax, n_ay, n_ax * n_ay
+    n = max(n_angle, rd.n_virtual)
+    return n, 1, n
+
+
+def simulator_scratch_bytes(scene: S.Scene, nf: Optional[int] = None, backward: bool = True, cube: bool = True,
+                            n_angle: int = 64) -> int:
+    """Bytes of the one scratch buffer a Simulator allocates: the largest of
+    the stages it may run (BVH build and synthesis always; the backward pass
+    and the radar cube + CFAR when asked for)."""
+    g, rd, ch = scene.grid, scene.radar, scene.chirp
+    nf = scene.nf if nf is None else nf
+    m = L.sbr_mesh(None, scene.nv, None, nf, None)
+    lib = _lib()
+    rs, rr, cs = rays_struct(g), radar_struct(rd), chirp_struct(ch)
+    need = max(int(lib.sbr_scratch_bytes(L.SBR_OP_BUILD_BVH, ct.byref(m), None, None, None)),
+               int(lib.sbr_scratch_bytes(L.SBR_OP_SYNTH, ct.byref(m), ct.byref(rs), ct.byref(rr), ct.byref(cs))))
+    if backward:
+        need = max(need, int(lib.sbr_scratch_bytes(L.SBR_OP_BACKWARD, ct.byref(m), ct.byref(rs), ct.byref(rr),
+                                                   ct.byref(cs))))
+    if cube:
+        n_ax, n_ay, na = _angle_grid(rd, n_angle)
+        C, Sn = ch.n_chirps, ch.n_samples
+        need = max(need, int(lib.sbr_scratch_bytes(L.SBR_OP_RADAR_CUBE, None, ct.byref(rs), ct.byref(rr),
+                                                   ct.byref(cs))),
+                   int(lib.sbr_scratch_bytes(L.SBR_OP_CFAR, None, ct.byref(rs), ct.byref(rr), ct.byref(cs))))
+        # the cube stage needs room for max(V, n_angle) planes
+        if getattr(rd, "planar", False):
+            need = max(need, sbr_radar_cube_2d_bytes(rd.n_rx, rd.n_tx, C, Sn, n_ax, n_ay))
+        else:
+            need = max(need, 2 * 8 * na * C * Sn + 1024)
+    return need
+
+
 class Simulator:
     """One scene resident on the device: mesh, BVH, hit records, one scratch
-    buffer shared by all stages (stages on one stream run in order)."""
+    buffer shared by all stages (stages on one stream run in order).  The
+    scratch is sized for the stages asked for: `backward` (sbr_backward) and
+    `cube` (radar cube, CFAR, point clouds); BVH build and synthesis always."""
 
     def __init__(self, scene: S.Scene, device="cuda", drop_flagged: bool = True, n_angle: int = 64,
-                 mesh: Optional[DeviceMesh] = None, bvh: Optional[torch.Tensor] = None, exit_only: bool = False):
+                 mesh: Optional[DeviceMesh] = None, bvh: Optional[torch.Tensor] = None, exit_only: bool = False,
+                 backward: bool = True, cube: bool = True):
         self.scene = scene
         self.device = torch.device(device)
         self.mesh = mesh if mesh is not None else DeviceMesh.from_scene(scene, self.device)
@@ -335,19 +427,8 @@ class Simulator:
         self.K, self.R = g.max_bounces, g.nx * g.ny
         self.V, self.C, self.S = rd.n_virtual, ch.n_chirps, ch.n_samples
         self.planar = bool(getattr(rd, "planar", False))
-        if self.planar:   # angle grid n_ay x n_ax over the (TX, RX) = (vy, vx) virtual grid
-            self.n_ax, self.n_ay = max(n_angle, rd.n_rx), max(n_angle, rd.n_tx)
-            self.n_angle = self.n_ax * self.n_ay
-        else:
-            self.n_angle = max(n_angle, self.V)
-        need = max(sbr_scratch_bytes(L.SBR_OP_BUILD_BVH, self.mesh),
-                   sbr_scratch_bytes(L.SBR_OP_SYNTH, self.mesh, g, rd, ch),
-                   sbr_scratch_bytes(L.SBR_OP_BACKWARD, self.mesh, g, rd, ch),
-                   sbr_scratch_bytes(L.SBR_OP_RADAR_CUBE, None, g, rd, dataclasses.replace(ch)),
-                   sbr_scratch_bytes(L.SBR_OP_CFAR, None, g, rd, ch))
-        # the cube stage needs room for max(V, n_angle) planes
-        need = max(need, 2 * 8 * self.n_angle * self.C * self.S + 1024) if not self.planar else \
-            max(need, sbr_radar_cube_2d_bytes(rd.n_rx, rd.n_tx, self.C, self.S, self.n_ax, self.n_ay))
+        self.n_ax, self.n_ay, self.n_angle = _angle_grid(rd, n_angle)
+        need = simulator_scratch_bytes(scene, self.mesh.nf, backward, cube, n_angle)
         self.scratch = torch.empty(need, dtype=torch.uint8, device=self.device)
         self.bvh = bvh if bvh is not None else torch.empty(max(1, sbr_bvh_bytes(self.mesh.nf)), dtype=torch.uint8,
                                                            device=self.device)

@@ -2,22 +2,29 @@
 simulations of many requests on one GPU with continuous batching.
 
 * Admission by device-memory footprint: a request is admitted when its
-  estimated footprint fits the free part of the budget (FIFO order, a request
-  larger than the whole budget is rejected).
-* Continuous batching: an admitted request's whole pipeline (mesh upload, BVH
-  build, trace, synthesis, and for forward+backward the loss entry and the
-  adjoint) is enqueued at once on one of several HIP streams; requests that
-  arrive while others run are admitted as soon as memory and slots free up,
-  so their kernels overlap other requests' kernels on the device.
+  footprint (exactly the device buffers its pipeline allocates) fits the part
+  of the budget that active requests and idle cached meshes leave free (FIFO
+  order; idle cache entries are evicted to make room; a request larger than
+  the whole budget is rejected).
+* Continuous batching: at every scheduling tick the requests admitted since
+  the last one form a batch.  Their per-request stages (mesh upload, BVH
+  build, trace, path refinement) are enqueued on one HIP stream, then ONE
+  batched IF-synthesis launch covers the synthesis blocks of all of them
+  (sbr_synth_if_batched), and the forward+backward ones share ONE batched
+  adjoint launch (sbr_backward_batched).  Consecutive ticks go to different
+  streams, so a batch admitted while others run overlaps them on the device.
 * BVHs and meshes stay resident for the life of a request, and repeated
-  meshes reuse a cached device copy (LRU keyed by the mesh bytes).
+  meshes (same vertices, faces and materials) reuse a cached device copy: a
+  request that hits the cache waits (on the device) for the event that ends
+  the copy's upload and build on the stream that made it.
 * Each request's launch shapes depend only on its own sizes, so its forward
   result is bit-identical alone and in the mix (the backward differs only in
   the order of floating-point atomics).
 
 The scheduler is independent of the device: `Scheduler` drives any object
 with the executor interface (`footprint`, `launch`, `poll`, `collect`,
-`release`), which the tests replace with a CPU fake.
+`release`, optionally `launch_batch`, `resident_bytes` and `evict_idle`),
+which the tests replace with a CPU fake.
 """
 from __future__ import annotations
 
@@ -56,6 +63,7 @@ class Result:
     t_done: float = 0.0
     footprint: int = 0
     error: str = ""
+    hits: Optional[Dict[str, np.ndarray]] = None   # tri / flags when the executor returns them
 
     @property
     def latency(self) -> float:
@@ -114,6 +122,8 @@ class Scheduler:
                 still.append(item)
         self._active = still
         now = self.now()
+        admitted = []
+        n_active = len(self._active)
         while True:
             with self._lock:
                 if not self._pending or self._pending[0][0].arrival > now:
@@ -130,23 +140,59 @@ class Scheduler:
                     fut.set_result(res)
                     progressed = True
                     continue
-                if self._used + fp > self.budget or len(self._active) >= self.max_active:
+                if n_active + len(admitted) >= self.max_active:
                     break
+                if self._used + fp + self.resident_bytes() > self.budget:
+                    # idle cached meshes give way to requests
+                    self._evict(self._used + fp + self.resident_bytes() - self.budget)
+                    if self._used + fp + self.resident_bytes() > self.budget:
+                        break
                 self._pending.popleft()
-            t_admit = self.now()
+            self._used += fp
+            admitted.append((req, fut, fp))
+        if admitted:
+            self._launch(admitted)
+            progressed = True
+        return progressed
+
+    def resident_bytes(self) -> int:
+        """Device bytes the executor holds outside active requests (idle cache)."""
+        f = getattr(self.ex, "resident_bytes", None)
+        return int(f()) if f is not None else 0
+
+    def _evict(self, nbytes: int):
+        f = getattr(self.ex, "evict_idle", None)
+        if f is not None:
+            f(int(nbytes))
+
+    def _fail_launch(self, req, fut, fp, t_admit, e):
+        self._used -= fp
+        res = Result(req.rid, "failed", t_arrival=req.arrival, t_admit=t_admit, t_done=self.now(),
+                     footprint=fp, error=repr(e))
+        self.log.append(res)
+        fut.set_result(res)
+
+    def _launch(self, admitted):
+        """One batch for the executor (or one launch per request without
+        launch_batch, or when the batch as a whole fails: then each request
+        is launched alone so that a bad request fails only itself)."""
+        t_admit = self.now()
+        batch = getattr(self.ex, "launch_batch", None)
+        if batch is not None and len(admitted) > 1:
+            try:
+                hs = batch([a[0] for a in admitted])
+                for (req, fut, fp), h in zip(admitted, hs):
+                    self._active.append((req, fut, h, fp, t_admit))
+                return
+            except Exception:   # fall back to single launches below
+                pass
+        for req, fut, fp in admitted:
             try:
                 h = self.ex.launch(req)
             except Exception as e:
-                res = Result(req.rid, "failed", t_arrival=req.arrival, t_admit=t_admit, t_done=self.now(),
-                             footprint=fp, error=repr(e))
-                self.log.append(res)
-                fut.set_result(res)
-                progressed = True
+                self._fail_launch(req, fut, fp, t_admit, e)
                 continue
-            self._used += fp
             self._active.append((req, fut, h, fp, t_admit))
-            progressed = True
-        return progressed
 
     def _finish(self, req, fut, h, fp, t_admit, out, err):
         try:
@@ -155,7 +201,8 @@ class Scheduler:
             self._used -= fp
         if err is None:
             res = Result(req.rid, "ok", cube=out.get("cube"), grad=out.get("grad"), n_paths=out.get("n_paths", -1),
-                         t_arrival=req.arrival, t_admit=t_admit, t_done=self.now(), footprint=fp)
+                         t_arrival=req.arrival, t_admit=t_admit, t_done=self.now(), footprint=fp,
+                         hits={k: out[k] for k in ("tri", "flags") if k in out} or None)
         else:
             res = Result(req.rid, "failed", t_arrival=req.arrival, t_admit=t_admit, t_done=self.now(),
                          footprint=fp, error=repr(err))
@@ -201,90 +248,221 @@ class Scheduler:
 
 
 # --------------------------------------------------------------------------- GPU executor
-def request_footprint(scene: S.Scene, backward: bool) -> int:
-    """Device bytes a request holds while active: mesh, BVH, hit records,
-    scratch, IF cube (x3 for forward+backward: cube, target, gradient) and
-    vertex gradients."""
+def _dev_bytes(n: int) -> int:
+    """Bytes the caching allocator books for an n-byte tensor (512-byte blocks)."""
+    return (int(n) + 511) // 512 * 512
+
+
+def mesh_bytes(scene: S.Scene) -> int:
+    """Device bytes of a resident mesh and its BVH (the cached part of a request)."""
     from . import sbr as B
-    from . import _lib as L
+    b = _dev_bytes(scene.nv * 12) + _dev_bytes(scene.nf * 12)
+    if scene.mat_id is not None:
+        b += _dev_bytes(scene.nf * 2)
+    return b + _dev_bytes(max(1, B.sbr_bvh_bytes(scene.nf)))
+
+
+def request_footprint(scene: S.Scene, backward: bool) -> int:
+    """Device bytes a request's pipeline allocates while it is active: mesh
+    and BVH (counted even when a cached copy is reused), the Simulator's
+    scratch sized for the stages it runs, hit records, counters, the loss
+    partials, the IF cube and path count; for forward+backward also the
+    target cube, dL/dIF, the loss and dL/dverts; plus the request's share of
+    the batch table."""
+    from . import sbr as B
     g, rd, ch = scene.grid, scene.radar, scene.chirp
     V, C, Sn, R, K = rd.n_virtual, ch.n_chirps, ch.n_samples, g.n_rays, g.max_bounces
-    mesh = scene.nv * 12 + scene.nf * 12
-    bvh = B.sbr_bvh_bytes(scene.nf)
-    ops = [L.SBR_OP_SYNTH] + ([L.SBR_OP_BACKWARD] if backward else [])
-    scratch = max(B.sbr_scratch_bytes(op, None, g, rd, ch) for op in ops)
-    scratch = max(scratch, 64 * scene.nf + (1 << 20), 16 * 64 * C * Sn + 1024)   # BVH build, radar cube
-    hits = R * K * 17
-    cube = V * C * Sn * 8 * (3 if backward else 1)
-    grads = scene.nv * 12 if backward else 0
-    return int(mesh + bvh + scratch + hits + cube + grads + (1 << 20))
+    cube = _dev_bytes(V * C * Sn * 8)
+    b = mesh_bytes(scene)
+    b += _dev_bytes(B.simulator_scratch_bytes(scene, backward=backward, cube=False))
+    b += 4 * _dev_bytes(4 * R * K) + _dev_bytes(R * K)        # tri, t, u, v, flags
+    b += _dev_bytes(24) + _dev_bytes(8192)                    # counters, loss partials
+    b += cube + _dev_bytes(4)                                 # IF cube, path count
+    if backward:
+        b += 2 * cube + _dev_bytes(4) + _dev_bytes(scene.nv * 12)   # target, dL/dIF, loss, dL/dverts
+    return int(b + _dev_bytes(B.sbr_batch_table_bytes(1)))
 
 
 def _mesh_key(scene: S.Scene) -> str:
     h = hashlib.sha1()
     h.update(np.ascontiguousarray(scene.verts).tobytes())
     h.update(np.ascontiguousarray(scene.faces).tobytes())
+    if scene.mat_id is not None:
+        h.update(np.ascontiguousarray(scene.mat_id).astype(np.int64).tobytes())
+    h.update(repr([tuple(float(x) for x in m) for m in scene.materials]).encode())
     return h.hexdigest()
 
 
-class GPUExecutor:
-    """Runs each request's pipeline on one of `n_streams` HIP streams."""
+@dataclasses.dataclass
+class _MeshEntry:
+    mesh: Any            # DeviceMesh
+    bvh: Any             # uint8 tensor
+    ready: Any           # torch.cuda.Event recorded after upload + build
+    nbytes: int
+    refs: int = 0        # active requests using it
 
-    def __init__(self, device="cuda", n_streams: int = 4, cache_meshes: int = 8):
+
+class GPUExecutor:
+    """Runs batches of requests on `n_streams` HIP streams in turn (one stream
+    per batch); meshes and BVHs are cached by content, reference-counted."""
+
+    def __init__(self, device="cuda", n_streams: int = 4, cache_meshes: int = 8, extra_flags=None,
+                 return_hits: bool = False):
+        """extra_flags: None, or a callable request -> None or uint8 [K, R]
+        hit flags to OR into the request's traced flags before synthesis (rays
+        a caller wants dropped, e.g. those another implementation flags when
+        results are compared record by record).  return_hits: results also
+        carry the hit ids and flags the synthesis used ("tri", "flags")."""
         import torch
         self.torch = torch
+        self.extra_flags = extra_flags
+        self.return_hits = return_hits
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]  # default priority
         self.next = 0
-        self.cache: "collections.OrderedDict[str, Any]" = collections.OrderedDict()
+        self.cache: "collections.OrderedDict[str, _MeshEntry]" = collections.OrderedDict()
         self.cache_meshes = cache_meshes
 
     def footprint(self, req: Request) -> int:
         return request_footprint(req.scene, req.backward)
 
-    def launch(self, req: Request):
+    # ---- mesh cache
+    def resident_bytes(self) -> int:
+        """Bytes of cached meshes and BVHs that no active request uses."""
+        return sum(e.nbytes for e in self.cache.values() if e.refs == 0)
+
+    def evict_idle(self, nbytes: int) -> int:
+        """Drop idle cache entries, least recently used first, until `nbytes`
+        are freed (or none is idle); returns the bytes freed."""
+        freed = 0
+        for key in list(self.cache.keys()):
+            if freed >= nbytes:
+                break
+            e = self.cache[key]
+            if e.refs == 0:
+                del self.cache[key]
+                freed += e.nbytes
+        return freed
+
+    def _trim(self):
+        idle = [k for k, e in self.cache.items() if e.refs == 0]
+        while len(self.cache) > self.cache_meshes and idle:
+            del self.cache[idle.pop(0)]
+
+    def _mesh_for(self, req: Request, st):
+        """(key, entry) of the request's mesh on stream st: a cached copy (st
+        waits for its ready event) or a fresh upload + BVH build on st."""
+        from .sbr import DeviceMesh, sbr_build_bvh, sbr_bvh_bytes, sbr_scratch_bytes
+        from . import _lib as L
         torch = self.torch
-        from .sbr import DeviceMesh, Simulator
+        key = _mesh_key(req.scene)
+        e = self.cache.get(key)
+        if e is not None:
+            self.cache.move_to_end(key)
+            st.wait_event(e.ready)
+            for t in (e.mesh.verts, e.mesh.faces, e.bvh):
+                t.record_stream(st)
+            if e.mesh.mat_id is not None:
+                e.mesh.mat_id.record_stream(st)
+        else:
+            mesh = DeviceMesh.from_scene(req.scene, self.device, non_blocking=True)
+            bvh = torch.empty(max(1, sbr_bvh_bytes(mesh.nf)), dtype=torch.uint8, device=self.device)
+            if mesh.nf > 0:
+                bs = torch.empty(max(1, sbr_scratch_bytes(L.SBR_OP_BUILD_BVH, mesh)), dtype=torch.uint8,
+                                 device=self.device)
+                sbr_build_bvh(mesh, bvh, 0, bs)
+            ready = torch.cuda.Event()
+            ready.record(st)
+            e = _MeshEntry(mesh, bvh, ready, mesh_bytes(req.scene))
+            self.cache[key] = e
+        e.refs += 1
+        return key, e
+
+    # ---- launches
+    def launch(self, req: Request):
+        return self.launch_batch([req])[0]
+
+    def launch_batch(self, reqs: List[Request]):
+        """Enqueue the requests' pipelines on the next stream: per request
+        mesh (cached or uploaded + built) and trace, then one batched
+        synthesis over all of them and one batched adjoint over the
+        forward+backward ones; results are copied to pinned host buffers
+        behind one event.  Returns one handle per request."""
+        torch = self.torch
+        from .sbr import Simulator, sbr_backward_batched, sbr_batch_table_bytes, sbr_synth_if_batched
         st = self.streams[self.next % len(self.streams)]
         self.next += 1
-        out: Dict[str, Any] = {"stream": st}
-        with torch.cuda.stream(st):
-            key = _mesh_key(req.scene)
-            cached = self.cache.get(key)
-            if cached is not None:       # resident mesh + BVH of an identical mesh
-                self.cache.move_to_end(key)
-                mesh, bvh = cached
-                for t in (mesh.verts, mesh.faces, bvh):
-                    t.record_stream(st)
-                sim = Simulator(req.scene, self.device, mesh=mesh, bvh=bvh)
-            else:
-                mesh = DeviceMesh.from_scene(req.scene, self.device, non_blocking=True)
-                sim = Simulator(req.scene, self.device, mesh=mesh)
-                sim.build()
-                self.cache[key] = (sim.mesh, sim.bvh)
-                while len(self.cache) > self.cache_meshes:
-                    self.cache.popitem(last=False)
-            sim.trace()
-            cube = sim.synth()
-            out["sim"], out["cube"] = sim, cube
-            # the synthesis leaves the path count in the scratch buffer
-            out["n_paths_dev"] = sim.scratch[:4].view(torch.int32).clone()
-            if req.backward:
-                th = torch.from_numpy(np.ascontiguousarray(req.target, dtype=np.complex64)).pin_memory()
-                tgt = th.to(self.device, non_blocking=True)
-                out["target_staging"] = th
-                grad, _ = sim.loss_grad(cube, tgt)
-                out["grad"] = sim.backward(grad)
-                out["grad_host"] = torch.empty(out["grad"].shape, dtype=torch.float32, pin_memory=True)
-                out["grad_host"].copy_(out["grad"], non_blocking=True)
-            out["cube_host"] = torch.empty(cube.shape, dtype=torch.float32, pin_memory=True)
-            out["cube_host"].copy_(cube, non_blocking=True)
-            out["np_host"] = torch.empty(1, dtype=torch.int32, pin_memory=True)
-            out["np_host"].copy_(out["n_paths_dev"], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(st)
-            out["event"] = ev
-        return out
+        hs: List[Dict[str, Any]] = [dict(stream=st) for _ in reqs]
+        keys: List[str] = []
+        try:
+            with torch.cuda.stream(st):
+                sims = []
+                for req, h in zip(reqs, hs):
+                    key, e = self._mesh_for(req, st)
+                    keys.append(key)
+                    h["mesh_key"] = key
+                    sim = Simulator(req.scene, self.device, mesh=e.mesh, bvh=e.bvh, backward=req.backward,
+                                    cube=False)
+                    sim.trace()
+                    extra = self.extra_flags(req) if self.extra_flags is not None else None
+                    if extra is not None:
+                        fl = torch.from_numpy(np.ascontiguousarray(extra, dtype=np.uint8)).pin_memory()
+                        h["flag_staging"] = fl
+                        sim.hits.flags.bitwise_or_(fl.to(self.device, non_blocking=True).view_as(sim.hits.flags))
+                    sims.append(sim)
+                    h["sim"] = sim
+                table = torch.empty(max(1, sbr_batch_table_bytes(len(reqs))), dtype=torch.uint8,
+                                    device=self.device)
+                cubes = [torch.empty((s.V, s.C, s.S, 2), dtype=torch.float32, device=self.device) for s in sims]
+                sbr_synth_if_batched([(s.mesh, s.scene.radar, s.scene.grid, s.hits, s.scene.chirp, s.flags, c,
+                                       s.scratch) for s, c in zip(sims, cubes)], table)
+                for h, s, c in zip(hs, sims, cubes):
+                    h["cube"] = c
+                    # the synthesis leaves the path count in the scratch buffer
+                    h["n_paths_dev"] = s.scratch[:4].view(torch.int32).clone()
+                bw = [i for i, r in enumerate(reqs) if r.backward]
+                if bw:
+                    items = []
+                    for i in bw:
+                        s, h = sims[i], hs[i]
+                        th = torch.from_numpy(np.ascontiguousarray(reqs[i].target, dtype=np.complex64)).pin_memory()
+                        h["target_staging"] = th
+                        tgt = th.to(self.device, non_blocking=True)
+                        grad_if, _ = s.loss_grad(h["cube"], tgt)
+                        gv = torch.zeros((s.mesh.nv, 3), dtype=torch.float32, device=self.device)
+                        h["grad"] = gv
+                        items.append((s.mesh, s.scene.radar, s.scene.grid, s.hits, s.scene.chirp, s.flags, grad_if,
+                                      gv, s.scratch))
+                    sbr_backward_batched(items, table)
+                for h in hs:
+                    h["cube_host"] = torch.empty(h["cube"].shape, dtype=torch.float32, pin_memory=True)
+                    h["cube_host"].copy_(h["cube"], non_blocking=True)
+                    h["np_host"] = torch.empty(1, dtype=torch.int32, pin_memory=True)
+                    h["np_host"].copy_(h["n_paths_dev"], non_blocking=True)
+                    if "grad" in h:
+                        h["grad_host"] = torch.empty(h["grad"].shape, dtype=torch.float32, pin_memory=True)
+                        h["grad_host"].copy_(h["grad"], non_blocking=True)
+                    if self.return_hits:
+                        for name in ("tri", "flags"):
+                            src = getattr(h["sim"].hits, name)
+                            h[name + "_host"] = torch.empty(src.shape, dtype=src.dtype, pin_memory=True)
+                            h[name + "_host"].copy_(src, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(st)
+                for h in hs:
+                    h["event"] = ev
+                    h["table"] = table
+        except Exception:
+            for key in keys:
+                self._unref(key)
+            raise
+        self._trim()
+        return hs
+
+    def _unref(self, key):
+        e = self.cache.get(key)
+        if e is not None:
+            e.refs -= 1
 
     def poll(self, h) -> bool:
         return h["event"].query()
@@ -295,10 +473,17 @@ class GPUExecutor:
                "n_paths": int(h["np_host"][0])}
         if "grad_host" in h:
             res["grad"] = h["grad_host"].numpy().copy()
+        for name in ("tri", "flags"):
+            if name + "_host" in h:
+                res[name] = h[name + "_host"].numpy().copy()
         return res
 
     def release(self, h):
+        key = h.get("mesh_key")
+        if key is not None:
+            self._unref(key)
         h.clear()
+        self._trim()
 
 
 def run_sequential(executor, requests: List[Request]) -> List[Result]:
@@ -316,7 +501,8 @@ def run_sequential(executor, requests: List[Request]) -> List[Result]:
         r = executor.collect(h)
         executor.release(h)
         out.append(Result(req.rid, "ok", cube=r["cube"], grad=r.get("grad"), n_paths=r["n_paths"],
-                          t_arrival=req.arrival, t_admit=ta, t_done=time.perf_counter() - t0))
+                          t_arrival=req.arrival, t_admit=ta, t_done=time.perf_counter() - t0,
+                          hits={k: r[k] for k in ("tri", "flags") if k in r} or None))
     return out
 
 

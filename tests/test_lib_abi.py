@@ -28,7 +28,7 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     from paper_2311_13182_amd import _lib as L
     decl = _declared()
-    assert len(decl) == 17
+    assert len(decl) == 20
     assert sorted(L.EXPORTS) == decl
     for name in decl:
         assert hasattr(lib, name), name
@@ -53,6 +53,13 @@ def test_size_queries(lib):
     assert lib.sbr_scratch_bytes(L.SBR_OP_SYNTH, None, None, None, None) == 0
 
 
+def _gpu_visible() -> bool:
+    import torch
+    return torch.cuda.device_count() > 0
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="passes made-up device addresses; runs only where no GPU is visible, "
+                                           "so no kernel can ever receive them")
 def test_argument_errors_are_reported(lib):
     from paper_2311_13182_amd import _lib as L
     from paper_2311_13182_amd import scenes as S
@@ -105,6 +112,23 @@ def test_argument_errors_are_reported(lib):
     # BVH: empty mesh
     m0 = L.sbr_mesh(None, 0, None, 0, None)
     assert lib.sbr_build_bvh(ct.byref(m0), fake, 1 << 20, 0, fake, 1 << 20, None) == L.SBR_E_ARG
+    # batched calls: table size query, table too small, a bad request named
+    assert lib.sbr_batch_table_bytes(0) == 0 and lib.sbr_batch_table_bytes(L.SBR_MAX_BATCH + 1) == 0
+    assert 0 < lib.sbr_batch_table_bytes(1) < lib.sbr_batch_table_bytes(64)
+    reqs = (L.sbr_request * 2)()
+    for q in reqs:
+        q.mesh, q.radar, q.rays, q.hits, q.chirp = ct.pointer(m), ct.pointer(r), ct.pointer(g), ct.pointer(h), \
+            ct.pointer(c)
+        q.flags, q.if_cube, q.grad_if, q.grad_verts, q.scratch, q.scratch_bytes = 1, fake, fake, fake, fake, 1 << 40
+    assert lib.sbr_synth_if_batched(reqs, 2, fake, 16, None) == L.SBR_E_SCRATCH
+    reqs[1].scratch_bytes = 16
+    rc = lib.sbr_synth_if_batched(reqs, 2, fake, 1 << 20, None)
+    assert rc == L.SBR_E_SCRATCH and lib.sbr_last_error().startswith(b"request 1:")
+    reqs[1].scratch_bytes = 1 << 40
+    reqs[0].rays = ct.pointer(bad)
+    rc = lib.sbr_backward_batched(reqs, 2, fake, 1 << 20, None)
+    assert rc == L.SBR_E_ARG and b"request 0" in lib.sbr_last_error() and b"max_bounces" in lib.sbr_last_error()
+    assert lib.sbr_synth_if_batched(reqs, -1, fake, 1 << 20, None) == L.SBR_E_ARG
 
 
 def test_product_path_fails_loudly_without_library(tmp_path):

@@ -149,3 +149,86 @@ def test_threaded_loop_with_real_clock():
     sch.stop()
     assert all(r.status == "ok" for r in res)
     assert ex.peak_used <= 300
+
+
+class BatchExecutor(FakeExecutor):
+    """FakeExecutor with batched launches and a cache of `resident` idle bytes
+    that eviction frees."""
+
+    def __init__(self, clock, resident=0):
+        super().__init__(clock)
+        self.batches = []
+        self.resident = resident
+        self.evicted = 0
+
+    def launch_batch(self, reqs):
+        if any(getattr(r.scene, "fail_launch", False) for r in reqs):
+            raise RuntimeError("batch launch failed (forced)")
+        self.batches.append([r.rid for r in reqs])
+        return [FakeExecutor.launch(self, r) for r in reqs]
+
+    def resident_bytes(self):
+        return self.resident
+
+    def evict_idle(self, nbytes):
+        freed = min(nbytes, self.resident)
+        self.resident -= freed
+        self.evicted += freed
+        return freed
+
+
+def test_requests_admitted_together_share_one_batch():
+    clock = Clock()
+    ex = BatchExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=1000, max_active=8, clock=clock)
+    futs = [sch.submit(_req(i, 10, 0.05, arrival=0.0005)) for i in range(5)]
+    futs.append(sch.submit(_req(5, 10, 0.05, arrival=0.02)))
+    _run(sch, clock, 0.5)
+    assert all(f.result().status == "ok" for f in futs)
+    # the five that arrived together form one batch; the late one its own
+    assert ex.batches[0] == [0, 1, 2, 3, 4]
+    assert [5] in ex.batches or ex.launched[-1] == 5
+
+
+def test_idle_cache_bytes_reduce_the_free_budget_and_are_evicted():
+    clock = Clock()
+    ex = BatchExecutor(clock, resident=70)
+    sch = Scheduler(ex, budget_bytes=100, max_active=8, clock=clock)
+    assert sch.resident_bytes() == 70
+    f = sch.submit(_req(0, 50, 0.01, arrival=0.0005))
+    sch.tick()          # arrival not reached
+    clock.t = 0.001
+    sch.tick()          # 50 + 70 > 100: 20 bytes of idle cache are evicted to admit it
+    assert ex.evicted == 20 and ex.resident == 50
+    assert sch.used_bytes + sch.resident_bytes() <= 100
+    _run(sch, clock, 0.1)
+    assert f.result().status == "ok"
+
+
+def test_cache_that_cannot_shrink_holds_admission_back():
+    clock = Clock()
+
+    class Pinned(BatchExecutor):
+        def evict_idle(self, nbytes):      # nothing idle can go
+            return 0
+
+    ex = Pinned(clock, resident=70)
+    sch = Scheduler(ex, budget_bytes=100, max_active=8, clock=clock)
+    f = sch.submit(_req(0, 50, 0.01, arrival=0.0005))
+    _run(sch, clock, 0.05)
+    assert not f.done() and sch.used_bytes == 0   # 50 + 70 > 100: waits
+    ex.resident = 10
+    _run(sch, clock, 0.1)
+    assert f.result().status == "ok"
+
+
+def test_failed_batch_falls_back_to_single_launches():
+    clock = Clock()
+    ex = BatchExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=1000, max_active=8, clock=clock)
+    fa = sch.submit(_req(0, 10, 0.01, arrival=0.0005, fail_launch=True))
+    fb = sch.submit(_req(1, 10, 0.01, arrival=0.0005))
+    _run(sch, clock, 0.2)
+    assert fa.result().status == "failed" and "launch failed" in fa.result().error
+    assert fb.result().status == "ok"
+    assert sch.used_bytes == 0
