@@ -242,6 +242,20 @@ int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_a
                    int32_t window, int32_t direction, float *out, void *scratch,
                    size_t scratch_bytes, void *stream);
 
+/* sbr_radar_cube without a scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the staging buffers are a file-scope
+ * device array of SBR_NOALLOC_SCRATCH_BYTES that each GPU the library runs on
+ * holds until the process ends; nothing is allocated or freed.  Arguments,
+ * result and limits as sbr_radar_cube, and sizes whose staging
+ * (sbr_scratch_bytes(SBR_OP_RADAR_CUBE, ...) for that n_angle) exceeds the
+ * array are refused with SBR_E_SCRATCH before anything is enqueued.  All
+ * calls on one GPU share its array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller. */
+#define SBR_NOALLOC_SCRATCH_BYTES (64 << 20)
+int sbr_radar_cube_noalloc(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_angle, int32_t window,
+                           int32_t direction, float *out, void *stream);
+
 /* The same map T for a planar array (Sec. 4's 20 TX x 20 RX class of radar):
  * the virtual antennas form a Vy x Vx grid, v = vy * Vx + vx (for example TX
  * t along one axis and RX m along the other: vy = t, vx = m).  Range and

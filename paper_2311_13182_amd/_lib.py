@@ -23,13 +23,14 @@ SBR_EXIT_ONLY = 4
 SBR_OP_BUILD_BVH, SBR_OP_SYNTH, SBR_OP_BACKWARD, SBR_OP_RADAR_CUBE, SBR_OP_CFAR = 0, 1, 2, 3, 4
 SBR_LOSS_SCRATCH_BYTES = 8192
 SBR_MAX_BATCH = 1024
+SBR_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # every function declared in include/sbr.h
 EXPORTS = ("sbr_bvh_bytes", "sbr_scratch_bytes", "sbr_build_bvh", "sbr_trace", "sbr_synth_if",
            "sbr_radar_cube", "sbr_cfar", "sbr_backward", "sbr_last_error", "sbr_loss_grad", "sbr_profile",
            "sbr_profile_read", "sbr_radar_cube_2d", "sbr_radar_cube_2d_bytes", "sbr_cloud",
            "sbr_angle_peaks", "sbr_angle_peaks_bytes", "sbr_batch_table_bytes", "sbr_synth_if_batched",
-           "sbr_backward_batched")
+           "sbr_backward_batched", "sbr_radar_cube_noalloc")
 PROF_SYNTH, PROF_SYNTH_ADJ, PROF_TRACE = 0, 1, 2
 
 
@@ -143,6 +144,8 @@ def load(path: str = LIB_PATH):
     L.sbr_synth_if_batched.argtypes = [P(sbr_request), i32, vp, sz, vp]
     L.sbr_backward_batched.restype = ct.c_int
     L.sbr_backward_batched.argtypes = [P(sbr_request), i32, vp, sz, vp]
+    L.sbr_radar_cube_noalloc.restype = ct.c_int
+    L.sbr_radar_cube_noalloc.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
     _lib = L
     return L
 

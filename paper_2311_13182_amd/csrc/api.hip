@@ -46,6 +46,7 @@ int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window,
 int cfar_launch(const float2 *cube, int Na, int C, int S, int guard, int train, double pfa, int32_t *points,
                 float *ratio_out, int maxp, int32_t *npts, void *scratch, hipStream_t s);
 int fill_zero_f32(float *p, size_t n, hipStream_t s);
+int noalloc_scratch(void **ptr);
 
 int resident_blocks(const void *kernel, int threads, size_t lds, int fallback) {
     static std::mutex mu;
@@ -515,6 +516,29 @@ int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_a
         set_error("radar cube scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
         return SBR_E_SCRATCH;
     }
+    return radar_cube_launch(reinterpret_cast<const float2 *>(in), V, C, S, n_angle, window, direction,
+                             reinterpret_cast<float2 *>(out), scratch, (hipStream_t)stream);
+}
+
+int sbr_radar_cube_noalloc(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_angle, int32_t window,
+                           int32_t direction, float *out, void *stream) {
+    clear_error();
+    SBR_CHECK_ARG(in && out, "in/out is NULL");
+    SBR_CHECK_ARG(V >= 1 && C >= 1 && S >= 1, "sizes must be >= 1 (V=%d C=%d S=%d)", V, C, S);
+    SBR_CHECK_ARG(V <= 4096 && C <= 4096 && S <= 4096 && n_angle <= 4096, "sizes must be <= 4096");
+    SBR_CHECK_ARG(n_angle >= V, "n_angle=%d < V=%d", n_angle, V);
+    SBR_CHECK_ARG(window == 0 || window == 1, "window must be 0 or 1");
+    SBR_CHECK_ARG(direction == 0 || direction == 1, "direction must be 0 or 1");
+    const size_t need = cube_scratch_bytes(V, C, S, n_angle);
+    if (need > (size_t)SBR_NOALLOC_SCRATCH_BYTES) {
+        set_error("radar cube of %d x %d x %d -> %d angles needs %zu bytes of staging, more than the %d bytes "
+                  "the scratch-free entry point holds; use sbr_radar_cube with a caller scratch",
+                  V, C, S, n_angle, need, SBR_NOALLOC_SCRATCH_BYTES);
+        return SBR_E_SCRATCH;
+    }
+    void *scratch = nullptr;
+    int rc;
+    if ((rc = noalloc_scratch(&scratch))) return rc;
     return radar_cube_launch(reinterpret_cast<const float2 *>(in), V, C, S, n_angle, window, direction,
                              reinterpret_cast<float2 *>(out), scratch, (hipStream_t)stream);
 }

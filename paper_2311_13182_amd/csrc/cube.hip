@@ -2,6 +2,8 @@
 // angle DFTs and their conjugate transpose; and the CA-CFAR point extraction.
 // Each DFT is a dense FP32 contraction with the DFT matrix on the matrix cores
 // (MFMA), twiddles by exact index (k n mod N) from an LDS table.
+#include <mutex>
+
 #include "sbr_internal.h"
 
 namespace sbr {
@@ -625,6 +627,35 @@ int radar_cube2_launch(const float2 *in, int Vx, int Vy, int C, int S, int Nax, 
 int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,
                       void *scratch, hipStream_t s) {
     return radar_cube2_launch(in, V, 1, C, S, Na, 1, window, dir, out, scratch, s);
+}
+
+// Staging buffers of sbr_radar_cube_noalloc: a file-scope device array that
+// every GPU the library runs on holds until the process ends.  In host code
+// `scratch` names a host-side stand-in, never a device address: kernels get
+// the per-device address hipGetSymbolAddress returns.
+static __device__ __align__(256) char scratch[SBR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+int noalloc_scratch(void **ptr) {
+    int dev = 0;
+    SBR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d beyond the %d the scratch-free entry point tracks", dev, kMaxDevices);
+        return SBR_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {   // once per device, with that device current
+        void *p = nullptr;
+        SBR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_noalloc_ptr[dev] = p;
+    }
+    *ptr = g_noalloc_ptr[dev];
+    return SBR_OK;
 }
 
 int cfar_launch(const float2 *cube, int Na, int C, int S, int guard, int train, double pfa, int32_t *points,

@@ -261,6 +261,15 @@ def sbr_radar_cube(x: torch.Tensor, V: int, C: int, Sn: int, n_angle: int, windo
                                   scratch.numel() * scratch.element_size(), _stream()))
 
 
+def sbr_radar_cube_noalloc(x: torch.Tensor, V: int, C: int, Sn: int, n_angle: int, window: int, direction: int,
+                           out: torch.Tensor):
+    """sbr_radar_cube with the library's own static staging buffers (no scratch)."""
+    nv, na = V * C * Sn * 2, n_angle * C * Sn * 2
+    xi = _buf(x, torch.float32, nv if direction == 0 else na, "x")
+    xo = _buf(out, torch.float32, na if direction == 0 else nv, "out")
+    L.check(_lib().sbr_radar_cube_noalloc(xi, V, C, Sn, n_angle, window, direction, xo, _stream()))
+
+
 def sbr_cfar(cube: torch.Tensor, Na: int, C: int, Sn: int, guard: int, train: int, pfa: float,
              points: torch.Tensor, ratio: Optional[torch.Tensor], n_points: torch.Tensor, scratch: torch.Tensor):
     mp = int(points.shape[0])
