@@ -24,6 +24,12 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 FLOP_PER_PATH_SAMPLE = {"synth": 8.0, "synth_adj": 20.0}
+# lane operations per second of the FP32 vector units: 256 CUs x 4 SIMDs x 32
+# lanes x 2.4 GHz (one VALU instruction per lane per clock; an FMA counts once)
+PEAK_VALU_LANE_OPS = 256 * 4 * 32 * 2.4e9
+# algorithmic VALU operations of the trace: a slab test of a node box, a
+# watertight ray-triangle test
+OPS_PER_NODE_TEST, OPS_PER_TRI_TEST = 14, 27
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__k_synth_adj__clutter_50k_fwd_bwd.md")
@@ -63,10 +69,22 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(scene, queries_full: int, budget_rows: int = 8, chirp_stride: int = 16):
     """The FP64 oracle (trace + paths + synthesis + synthesis adjoint) on a
     bounded sample: every `budget_rows`-th ray row and column, every
-    `chirp_stride`-th chirp; scaled linearly to the full workload."""
+    `chirp_stride`-th chirp; scaled linearly to the full workload.  Also its
+    brute-force ray-triangle tests/s and FP64 path-samples/s (Eq. 8 terms)."""
     import numpy as np
     from oracle import pyoracle as orc
     g = scene.grid
@@ -88,11 +106,15 @@ def cpu_baseline(scene, queries_full: int, budget_rows: int = 8, chirp_stride: i
     fc = scene.chirp.n_chirps / Cs
     est = (t1 - t0) * fr + (t3 - t1) * fr * fc
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    Vs, Ss = scene.radar.n_virtual, scene.chirp.n_samples
     return {
         "value": queries_full / est,
         "unit": "ray-bounces/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "tests_per_s": tr["queries"] * scene.nf / (t1 - t0),
+        "fp64_path_samples_per_s": len(p["amp"]) * Vs * Cs * Ss / (t2 - t1),
         "sample": (f"{len(rays)} of {g.n_rays} rays (every {budget_rows}th row/col), {Cs} of "
                    f"{scene.chirp.n_chirps} chirps, {len(p['amp'])} paths; measured {t3 - t0:.1f} s "
                    f"(trace {t1 - t0:.1f} s, synth {t2 - t1:.1f} s, adjoint {t3 - t2:.1f} s); "
@@ -108,7 +130,7 @@ def main():
     ap.add_argument("--workload", default="clutter_50k", choices=["clutter_50k", "icosphere_20k", "imaging_400"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-latency measurement")
-    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -167,7 +189,7 @@ def main():
     torch.cuda.synchronize()
     n_paths = sim.n_paths()
     cnt = sim.counters.cpu().numpy()
-    queries = int(cnt[0])
+    queries, node_tests, tri_tests = int(cnt[0]), int(cnt[1]), int(cnt[2])
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -225,6 +247,12 @@ def main():
         "if_path_samples_per_s": ps / (ms_step * 1e-3),
         "if_output_samples_per_s": V * C * Sn / (ms_step * 1e-3),
         "kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
+        "trace": {"ray_bounces_per_s": queries / (k_ms["trace"] * 1e-3), "node_tests": node_tests,
+                  "tri_tests": tri_tests,
+                  "alg_valu_ops_per_s": (OPS_PER_NODE_TEST * node_tests + OPS_PER_TRI_TEST * tri_tests) /
+                  (k_ms["trace"] * 1e-3),
+                  "frac_of_valu_peak": round((OPS_PER_NODE_TEST * node_tests + OPS_PER_TRI_TEST * tri_tests) /
+                                             (k_ms["trace"] * 1e-3) / PEAK_VALU_LANE_OPS, 4)},
         "wall_ms_per_step": (w1 - w0) * 1e3 / args.steps,
         "roofline": roof,
     }

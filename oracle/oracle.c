@@ -702,7 +702,7 @@ int orc_angle_peaks(const double *cube, int Nax, int Nay, int C, int S, const in
 
 /* ---------- textbook square-law cell-averaging CFAR ---------- */
 int orc_cfar(const double *cube, int Na, int C, int S, int guard, int train, double pfa,
-             unsigned char *status, int *argmax, double *power) {
+             unsigned char *status, int *argmax, double *power, double *ratio) {
     size_t plane = (size_t)C * S;
     double *pm = (double *)calloc(plane, sizeof(double));
     for (size_t e = 0; e < plane; e++) {
@@ -736,13 +736,16 @@ int orc_cfar(const double *cube, int Na, int C, int S, int guard, int train, dou
                 if (q > best) { best = q; am = a; }   /* ties: lowest index */
             }
             unsigned char st = 0;
+            double rt = 0.0;
             if (nt > 0) {
                 double mean = sum / nt;
                 double alpha = nt * (pow(pfa, -1.0 / nt) - 1.0);
                 double thr = alpha * mean;
                 if (pm[e] > thr) { st = 1; cnt++; }
                 if (fabs(pm[e] - thr) <= 1e-6 * thr) st |= 2;
+                rt = thr > 0.0 ? pm[e] / thr : 0.0;
             }
+            if (ratio) ratio[e] = rt;
             if (status) status[e] = st;
             if (argmax) argmax[e] = am;
             if (power) power[e] = pm[e];

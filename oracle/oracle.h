@@ -197,10 +197,11 @@ void orc_radar_cube2(const double *in, int Vx, int Vy, int C, int S, int Nax, in
  * Doppler axis circular, range axis truncated; alpha = N_t (pfa^(-1/N_t) - 1).
  * Per cell of the [C][S] map: status bit 0 = detected (P > alpha * mean),
  * bit 1 = borderline (|P - alpha*mean| <= 1e-6 alpha*mean); argmax over a
- * (lowest index on ties); power P.  Any output may be NULL.
- * Returns the number of detections. */
+ * (lowest index on ties); power P; ratio P / (alpha * mean).  Any output may
+ * be NULL.  Returns the number of detections. */
 int orc_cfar(const double *cube, int Na, int C, int S, int guard, int train,
-             double pfa, unsigned char *status, int *argmax, double *power);
+             double pfa, unsigned char *status, int *argmax, double *power,
+             double *ratio);
 
 /* Angle peaks of detected range-Doppler cells (several scatterers per cell,
  * as a radar's angle search reports them).  cube [Nay*Nax][C][S][2]; det

@@ -96,7 +96,7 @@ def lib():
         L.orc_cloud.argtypes = [ip, ct.c_int, ct.POINTER(_Radar), ct.POINTER(_Chirp), ct.c_int, ct.c_int, dp]
         L.orc_cfar.restype = ct.c_int
         L.orc_cfar.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_double,
-                               bp, ip, dp]
+                               bp, ip, dp, dp]
         _lib = L
     return _lib
 
@@ -316,9 +316,10 @@ def cfar(X, guard=2, train=8, pfa=1e-4):
     st = np.empty((C, S), np.uint8)
     am = np.empty((C, S), np.int32)
     pw = np.empty((C, S))
+    rt = np.empty((C, S))
     n = lib().orc_cfar(_p(inp, ct.c_double), Na, C, S, guard, train, pfa, _p(st, ct.c_ubyte),
-                       _p(am, ct.c_int), _p(pw, ct.c_double))
-    return {"count": n, "status": st, "argmax": am, "power": pw}
+                       _p(am, ct.c_int), _p(pw, ct.c_double), _p(rt, ct.c_double))
+    return {"count": n, "status": st, "argmax": am, "power": pw, "ratio": rt}
 
 
 def angle_peaks(X, n_ax, n_ay, det, rel, max_out=1 << 20):

@@ -190,6 +190,210 @@ __global__ __launch_bounds__(256) void k_dft_mid(const float2 *in, float2 *out, 
     }
 }
 
+// ---- FFT stages (power-of-two axes) and the direct angle stage ------------
+// For power-of-two lengths the range and Doppler DFTs run as Stockham FFTs
+// (decimation in frequency, self-sorting: no bit reversal) on the VALU with
+// the sequences held in LDS: O(N log N) work instead of the dense form's
+// O(N^2), which leaves these stages bound by their memory traffic.  A radix-r
+// stage with sub-length n (stride s = N / n, m = n / r) computes
+//   y[q + s (r p + k)] = e^{sign 2 pi j k p / n} sum_{i < r} x[q + s (p + i m)] e^{sign 2 pi j i k / r}
+// for p < m, q < s, k < r; radix-4 stages while 4 divides n, then one
+// radix-2 stage if n = 2 is left.  The twiddle e^{sign 2 pi j k p / n} is the
+// N-entry table's entry k p s (exact index).
+constexpr int kFftTile = 1024;   // complex elements per block (per LDS buffer)
+
+__device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd2(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub2(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// W independent sequences of length N = 2^logN in LDS, element n of sequence
+// j at n * sn + j * sj; x and y are two buffers of the same layout.  Returns
+// the buffer holding the result.
+__device__ float2 *lds_fft(float2 *x, float2 *y, int logN, int W, int sn, int sj, const float2 *tw, int sign) {
+    int ls = 0;   // log2 of the stride s
+    while (logN - ls >= 2) {   // radix 4: n = N / s divisible by 4
+        const int s = 1 << ls, lm = logN - ls - 2, m = 1 << lm;
+        const int total = W << (logN - 2);
+        for (int b = threadIdx.x; b < total; b += blockDim.x) {
+            const int j = b >> (logN - 2), r = b & ((1 << (logN - 2)) - 1);
+            const int p = r >> ls, q = r & (s - 1);
+            const int base = (q + s * p) * sn + j * sj, step = (s * m) * sn;
+            const float2 a = x[base], bb = x[base + step], c = x[base + 2 * step], d = x[base + 3 * step];
+            const float2 apc = cadd2(a, c), amc = csub2(a, c), bpd = cadd2(bb, d), t = csub2(bb, d);
+            // sign * j * (b - d)
+            const float2 jt = sign < 0 ? make_float2(t.y, -t.x) : make_float2(-t.y, t.x);
+            const int o = (q + s * 4 * p) * sn + j * sj, os = s * sn;
+            y[o] = cadd2(apc, bpd);
+            y[o + os] = cmul2(cadd2(amc, jt), tw[(p << ls)]);
+            y[o + 2 * os] = cmul2(csub2(apc, bpd), tw[(2 * p) << ls]);
+            y[o + 3 * os] = cmul2(csub2(amc, jt), tw[(3 * p) << ls]);
+        }
+        __syncthreads();
+        float2 *tmp = x;
+        x = y;
+        y = tmp;
+        ls += 2;
+    }
+    if (logN - ls == 1) {   // radix 2, n = 2: m = 1, p = 0, no twiddle
+        const int s = 1 << ls;
+        const int total = W << (logN - 1);
+        for (int b = threadIdx.x; b < total; b += blockDim.x) {
+            const int j = b >> (logN - 1), q = b & (s - 1);
+            const float2 a = x[q * sn + j * sj], c = x[(q + s) * sn + j * sj];
+            y[q * sn + j * sj] = cadd2(a, c);
+            y[(q + s) * sn + j * sj] = csub2(a, c);
+        }
+        __syncthreads();
+        x = y;
+    }
+    return x;
+}
+
+// LDS tables of an FFT block: N twiddles e^{sign 2 pi j k / N}, then the
+// window over the N samples (single precision: sincospi of an exact
+// argument 2k / N).
+__device__ void fft_tables(float2 *tw, float *wt, int N, int sign, int window) {
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        float sn, cs;
+        sincospif(2.0f * (float)k / (float)N, &sn, &cs);
+        tw[k] = make_float2(cs, sign * sn);
+        wt[k] = (window == 1 && N > 1) ? 0.5f - 0.5f * cospif(2.0f * (float)k / (float)(N - 1)) : 1.0f;
+    }
+    __syncthreads();
+}
+
+// FFT along the innermost axis: [rows][N] -> [rows][N], R = kFftTile / N rows
+// per block; the window multiplies the input (post = 0) or the output.
+__global__ __launch_bounds__(256) void k_fft_inner(const float2 *in, float2 *out, int rows, int logN, int sign,
+                                                   int window, int post) {
+    extern __shared__ float2 sm[];
+    const int N = 1 << logN, R = kFftTile >> logN;
+    float2 *tw = sm;
+    float *wt = reinterpret_cast<float *>(sm + N);
+    float2 *b0 = sm + N + (N + 1) / 2, *b1 = b0 + kFftTile;
+    fft_tables(tw, wt, N, sign, window);
+    const long long row0 = (long long)blockIdx.x * R;
+    for (int i = threadIdx.x; i < kFftTile; i += blockDim.x) {
+        const int r = i >> logN, n = i & (N - 1);
+        float2 v = make_float2(0.0f, 0.0f);
+        if (row0 + r < rows) {
+            v = in[(row0 + r) * N + n];
+            if (!post) v = make_float2(v.x * wt[n], v.y * wt[n]);
+        }
+        b0[i] = v;
+    }
+    __syncthreads();
+    const float2 *res = lds_fft(b0, b1, logN, R, 1, N, tw, sign);
+    for (int i = threadIdx.x; i < kFftTile; i += blockDim.x) {
+        const int r = i >> logN, k = i & (N - 1);
+        if (row0 + r < rows) {
+            float2 v = res[i];
+            if (post) v = make_float2(v.x * wt[k], v.y * wt[k]);
+            out[(row0 + r) * N + k] = v;
+        }
+    }
+}
+
+// FFT along a middle axis: [outer][N][inner] -> [outer][N][inner].  A block
+// takes one outer index and W = kFftTile / N consecutive inner columns (the
+// loads and stores run along the inner axis).
+__global__ __launch_bounds__(256) void k_fft_mid(const float2 *in, float2 *out, int outer, int logN, int inner,
+                                                 int sign, int window, int post) {
+    extern __shared__ float2 sm[];
+    const int N = 1 << logN, W = kFftTile >> logN;
+    float2 *tw = sm;
+    float *wt = reinterpret_cast<float *>(sm + N);
+    float2 *b0 = sm + N + (N + 1) / 2, *b1 = b0 + kFftTile;
+    fft_tables(tw, wt, N, sign, window);
+    const int ct = (inner + W - 1) / W;
+    const int o = blockIdx.x / ct, i0 = (blockIdx.x % ct) * W;
+    const float2 *src = in + (size_t)o * N * inner;
+    float2 *dst = out + (size_t)o * N * inner;
+    for (int i = threadIdx.x; i < kFftTile; i += blockDim.x) {
+        const int n = i / W, j = i - n * W;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (i0 + j < inner) {
+            v = src[(size_t)n * inner + i0 + j];
+            if (!post) v = make_float2(v.x * wt[n], v.y * wt[n]);
+        }
+        b0[i] = v;
+    }
+    __syncthreads();
+    const float2 *res = lds_fft(b0, b1, logN, W, W, 1, tw, sign);
+    for (int i = threadIdx.x; i < kFftTile; i += blockDim.x) {
+        const int k = i / W, j = i - k * W;
+        if (i0 + j < inner) {
+            float2 v = res[i];
+            if (post) v = make_float2(v.x * wt[k], v.y * wt[k]);
+            dst[(size_t)k * inner + i0 + j] = v;
+        }
+    }
+}
+
+constexpr int kAngleVMax = 32;   // antennas of the direct angle stage (registers)
+
+// Angle stage of a linear array as a direct DFT, one thread per (chirp,
+// sample) cell e, coalesced along e.  direction 0: out[a][e] = sum_{v < V}
+// w_a^v y[v][e] with w_a = e^{-2 pi j a / Na}, by Horner's rule in w_a (V - 1
+// complex multiply-adds per output, w_a from an LDS table), for the block
+// row's share of a; direction 1 (conjugate transpose): out[v][e] = sum_a
+// e^{+2 pi j (a v mod Na) / Na} y[a][e] for every v, twiddles by exact index.
+__global__ __launch_bounds__(256) void k_angle(const float2 *y, float2 *out, int V, int Na, long long CS, int dir,
+                                               int a_per) {
+    extern __shared__ float2 tw[];
+    for (int k = threadIdx.x; k < Na; k += blockDim.x) {
+        float sn, cs;
+        sincospif(2.0f * (float)k / (float)Na, &sn, &cs);
+        tw[k] = make_float2(cs, dir == 0 ? -sn : sn);
+    }
+    __syncthreads();
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= CS) return;
+    if (dir == 0) {
+        float2 yv[kAngleVMax];
+#pragma unroll
+        for (int v = 0; v < kAngleVMax; v++)
+            yv[v] = v < V ? y[(size_t)v * CS + e] : make_float2(0.0f, 0.0f);
+        const int a0 = blockIdx.y * a_per, a1 = min(Na, a0 + a_per);
+        for (int a = a0; a < a1; a++) {
+            const float2 w = tw[a];
+            float sr = 0.0f, si = 0.0f;
+#pragma unroll
+            for (int v = kAngleVMax - 1; v >= 0; v--) {
+                if (v < V) {   // acc = acc w + y_v
+                    const float nr = fmaf(sr, w.x, fmaf(-si, w.y, yv[v].x));
+                    si = fmaf(sr, w.y, fmaf(si, w.x, yv[v].y));
+                    sr = nr;
+                }
+            }
+            out[(size_t)a * CS + e] = make_float2(sr, si);
+        }
+    } else {
+        float2 acc[kAngleVMax];
+#pragma unroll
+        for (int v = 0; v < kAngleVMax; v++) acc[v] = make_float2(0.0f, 0.0f);
+        for (int a = 0; a < Na; a++) {
+            const float2 x = y[(size_t)a * CS + e];
+            int idx = 0;
+#pragma unroll
+            for (int v = 0; v < kAngleVMax; v++) {
+                if (v < V) {
+                    const float2 w = tw[idx];
+                    acc[v].x = fmaf(w.x, x.x, fmaf(-w.y, x.y, acc[v].x));
+                    acc[v].y = fmaf(w.x, x.y, fmaf(w.y, x.x, acc[v].y));
+                    idx += a;
+                    if (idx >= Na) idx -= Na;
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < kAngleVMax; v++)
+            if (v < V) out[(size_t)v * CS + e] = acc[v];
+    }
+}
+
 // ---- CFAR ------------------------------------------------------------------
 // Power map P[e] = sum_a |X[a][e]|^2 and its argmax over a (lowest index on
 // ties).  The angle range is split over kPowSplit block rows and 4 lanes per
@@ -594,6 +798,59 @@ static int launch_mid(const float2 *in, float2 *out, int outer, int N, int M, in
     return SBR_OK;
 }
 
+static int log2_exact(int n) {
+    if (n < 2 || (n & (n - 1)) != 0 || n > kFftTile) return -1;
+    int l = 0;
+    while ((1 << l) < n) l++;
+    return l;
+}
+
+static size_t fft_lds_bytes(int N) { return sizeof(float2) * ((size_t)N + (N + 1) / 2 + 2 * (size_t)kFftTile); }
+
+// Range stage: FFT for power-of-two S (<= 1024), else the dense contraction.
+static int launch_range(const float2 *in, float2 *out, int rows, int S, int sign, int window, int post,
+                        hipStream_t s) {
+    const int lg = log2_exact(S);
+    if (lg < 0) return launch_inner(in, out, rows, S, sign, window, post, s);
+    const int R = kFftTile >> lg;
+    hipLaunchKernelGGL(k_fft_inner, dim3((unsigned)((rows + R - 1) / R)), dim3(256), fft_lds_bytes(S), s, in, out,
+                       rows, lg, sign, window, post);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+// Doppler stage: FFT for power-of-two C (<= 1024), else the dense contraction.
+static int launch_doppler(const float2 *in, float2 *out, int V, int C, int S, int sign, int window, int post,
+                          hipStream_t s) {
+    const int lg = log2_exact(C);
+    if (lg < 0) return launch_mid(in, out, V, C, C, C, S, sign, window, post, s);
+    const int W = kFftTile >> lg;
+    const long long blocks = (long long)V * ((S + W - 1) / W);
+    hipLaunchKernelGGL(k_fft_mid, dim3((unsigned)blocks), dim3(256), fft_lds_bytes(C), s, in, out, V, lg, S, sign,
+                       window, post);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+// Angle stage of a linear array: direct DFT for V <= 32, else the dense
+// contraction.  dir 0: [V][CS] -> [Na][CS]; dir 1: [Na][CS] -> [V][CS].
+static int launch_angle(const float2 *in, float2 *out, int V, int Na, long long CS, int dir, hipStream_t s) {
+    if (V > kAngleVMax) {
+        if (dir == 0) return launch_mid(in, out, 1, V, Na, Na, (int)CS, -1, 0, 0, s);
+        return launch_mid(in, out, 1, Na, V, Na, (int)CS, +1, 0, 0, s);
+    }
+    // split the angles of the forward stage over block rows so that small
+    // cubes still fill the chip
+    const long long bx = (CS + 255) / 256;
+    int groups = dir == 0 ? (int)std::max(1LL, std::min<long long>(Na, 512 / std::max(1LL, bx))) : 1;
+    const int a_per = (Na + groups - 1) / groups;
+    groups = (Na + a_per - 1) / a_per;
+    hipLaunchKernelGGL(k_angle, dim3((unsigned)bx, (unsigned)groups), dim3(256), sizeof(float2) * Na, s, in, out, V,
+                       Na, CS, dir, a_per);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
 // Planar array: virtual antenna v = vy * Vx + vx; angle index a = ay * Nax + ax.
 // Range and Doppler as for the linear array, then the angle DFT along vx
 // (zero-padded to Nax) and along vy (to Nay): separable, each a middle-axis
@@ -608,20 +865,20 @@ int radar_cube2_launch(const float2 *in, int Vx, int Vy, int C, int S, int Nax, 
     const bool planar = Vy > 1 || Nay > 1;
     int rc;
     if (dir == 0) {
-        if ((rc = launch_inner(in, y1, V * C, S, -1, window, 0, s))) return rc;
-        if ((rc = launch_mid(y1, y2, V, C, C, C, S, -1, window, 0, s))) return rc;
-        if (!planar) return launch_mid(y2, out, 1, Vx, Nax, Nax, CS, -1, 0, 0, s);
+        if ((rc = launch_range(in, y1, V * C, S, -1, window, 0, s))) return rc;
+        if ((rc = launch_doppler(y1, y2, V, C, S, -1, window, 0, s))) return rc;
+        if (!planar) return launch_angle(y2, out, Vx, Nax, CS, 0, s);
         if ((rc = launch_mid(y2, y1, Vy, Vx, Nax, Nax, CS, -1, 0, 0, s))) return rc;   // [Vy][Nax][CS]
         return launch_mid(y1, out, 1, Vy, Nay, Nay, Nax * CS, -1, 0, 0, s);          // [Nay][Nax][CS]
     }
     if (!planar) {
-        if ((rc = launch_mid(in, y2, 1, Nax, Vx, Nax, CS, +1, 0, 0, s))) return rc;
+        if ((rc = launch_angle(in, y2, Vx, Nax, CS, 1, s))) return rc;
     } else {
         if ((rc = launch_mid(in, y1, 1, Nay, Vy, Nay, Nax * CS, +1, 0, 0, s))) return rc;   // [Vy][Nax][CS]
         if ((rc = launch_mid(y1, y2, Vy, Nax, Vx, Nax, CS, +1, 0, 0, s))) return rc;        // [Vy][Vx][CS]
     }
-    if ((rc = launch_mid(y2, y1, V, C, C, C, S, +1, window, 1, s))) return rc;
-    return launch_inner(y1, out, V * C, S, +1, window, 1, s);
+    if ((rc = launch_doppler(y2, y1, V, C, S, +1, window, 1, s))) return rc;
+    return launch_range(y1, out, V * C, S, +1, window, 1, s);
 }
 
 int radar_cube_launch(const float2 *in, int V, int C, int S, int Na, int window, int dir, float2 *out,

@@ -513,6 +513,7 @@ def _np_cfar(P, guard, train, pfa):
     C, S_ = P.shape
     w = guard + train
     status = np.zeros((C, S_), np.uint8)
+    ratio = np.zeros((C, S_))
     for d in range(C):
         for r in range(S_):
             rows = [(d + dd) % C for dd in range(-w, w + 1)]
@@ -526,7 +527,8 @@ def _np_cfar(P, guard, train, pfa):
             nt = len(vals)
             thr = nt * (pfa ** (-1.0 / nt) - 1.0) * np.mean(vals)
             status[d, r] = P[d, r] > thr
-    return status
+            ratio[d, r] = P[d, r] / thr
+    return status, ratio
 
 
 def test_cfar_injected_targets_and_bruteforce(orc):
@@ -540,9 +542,10 @@ def test_cfar_injected_targets_and_bruteforce(orc):
     for d, r, a in targets:
         assert out["status"][d, r] & 1 and out["argmax"][d, r] == a
     P = (np.abs(X) ** 2).sum(0)
-    ref = _np_cfar(P, 1, 3, 1e-4)
+    ref, ratio = _np_cfar(P, 1, 3, 1e-4)
     mask = (out["status"] & 2) == 0
     assert np.array_equal((out["status"] & 1)[mask], ref[mask])
+    assert np.allclose(out["ratio"], ratio, rtol=1e-12, atol=0)
     assert out["count"] <= len(targets) + 3
 
 
