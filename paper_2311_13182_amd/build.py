@@ -15,6 +15,9 @@ HIPCC_FLAGS = [
     "-munsafe-fp-atomics",
     # no packed FP32 code generation: plain scalar FP32 VALU only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs (no accumulator-register
+    # copies in the synthesis loop)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

@@ -423,6 +423,148 @@ __global__ __launch_bounds__(256) void k_synth(const SynthArgs *__restrict__ arg
     synth_block<L>(a, local % a.gx, local / a.gx, rot_list);
 }
 
+// ---- Eq. (8) on the matrix cores ------------------------------------------
+// For one antenna v and chirp c, a 256-sample run s = s_base + 16 s1 + s2
+// (s1, s2 < 16) of the sum over paths factors into a complex matrix product
+// with the paths as the contracted axis:
+//   S[s1][s2] = sum_p U[s1][p] W[p][s2],
+//   U[s1][p] = A_p e^{2 pi j (alpha_p + c beta_p + (s_base + 16 s1) delta_p)},
+//   W[p][s2] = e^{2 pi j s2 delta_p},  delta_p = gamma_p + c eps_p,
+// the first chirp's factors from exactly reduced phases, each later chirp's
+// by one complex rotation of the previous one (no recurrence along samples,
+// so accurate at every beat frequency).  Four paths at a time feed
+// v_mfma_f32_16x16x4_f32 (three real products for the complex one): lane l
+// supplies U[l % 16][l / 16] and W[l / 16][l % 16] and holds
+// D[4 (l / 16) + j][l % 16].  The VALU only forms the 2 x 16 x 4 factors per
+// path quadruple and chirp; the matrix cores do the 8 flops of every
+// path-sample.  A wavefront owns one antenna, kMfmaChirps chirps and one
+// 256-sample run, over a chunk of paths.
+constexpr int kMfmaChirps = 8;
+constexpr int kMfmaRun = 256;   // samples per run (16 x 16)
+
+typedef float f32x4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void synth_mfma_block(const SynthArgs &a, const int bx, const int chunk) {
+    const int wv = __builtin_amdgcn_readfirstlane(bx * 4 + (int)(threadIdx.x >> 6));
+    const int v = __builtin_amdgcn_readfirstlane(wv / a.tiles_per_v);
+    if (v >= a.V) return;   // wave-uniform; the kernel has no block barrier
+    const int rem = wv - v * a.tiles_per_v;
+    const int cg = rem / a.SB, run = rem - cg * a.SB;
+    const int c0 = cg * kMfmaChirps;
+    const int lane = threadIdx.x & 63, k = lane >> 4, i = lane & 15;
+    const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
+    const long long per = ((long long)P + a.n_chunks - 1) / a.n_chunks;
+    const int p0 = (int)min((long long)P, per * chunk);
+    const int p1 = (int)min((long long)P, per * (chunk + 1));
+    const auto al = gmem(a.rec.alpha + (size_t)v * a.rec.cap);
+    const auto ga = gmem(a.rec.gamma + (size_t)v * a.rec.cap);
+    const auto amp = gmem(a.rec.amp);
+    const auto bet = gmem(a.rec.beta);
+    const auto eps = gmem(a.rec.epsd);
+    const float su = (float)(run * kMfmaRun + 16 * i);   // first sample of this lane's U row
+    const float sw = (float)i;                           // this lane's W column
+    f32x4s k1[kMfmaChirps], k2[kMfmaChirps], k3[kMfmaChirps];
+#pragma unroll
+    for (int g = 0; g < kMfmaChirps; g++) {
+        k1[g] = (f32x4s){0.f, 0.f, 0.f, 0.f};
+        k2[g] = k1[g];
+        k3[g] = k1[g];
+    }
+    const float c0f = (float)c0;
+    // the records of the next path quadruple are fetched while the current
+    // one is turned into factors and products
+    float n_al = 0.f, n_ga = 0.f, n_be = 0.f, n_ep = 0.f;
+    F2 n_A = {0.f, 0.f};
+    if (p0 + k < p1) {
+        n_al = al[p0 + k];
+        n_ga = ga[p0 + k];
+        n_be = bet[p0 + k];
+        n_ep = eps[p0 + k];
+        n_A = amp[p0 + k];
+    }
+    for (int p = p0; p < p1; p += 4) {
+        const float alpha = n_al, gamma = n_ga, beta = n_be, epsd = n_ep;
+        const float Ax = n_A.x, Ay = n_A.y;   // zero past the chunk's last path
+        const int pn = p + 4 + k;
+        n_al = n_ga = n_be = n_ep = 0.f;
+        n_A = F2{0.f, 0.f};
+        if (pn < p1) {
+            n_al = al[pn];
+            n_ga = ga[pn];
+            n_be = bet[pn];
+            n_ep = eps[pn];
+            n_A = amp[pn];
+        }
+        // factors of the first chirp c0 from reduced phases; each later chirp
+        // multiplies them by e^{2 pi j (beta + su eps)} (U) and
+        // e^{2 pi j sw eps} (W), the change of their phases per chirp
+        const float delta = fmaf(c0f, epsd, gamma);   // cycles per sample
+        float ph = alpha + frac_mul(c0f, beta) + frac_mul(su, delta);
+        ph = ph - rintf(ph);
+        const float pw = frac_mul(sw, delta);
+        float qu = beta + frac_mul(su, epsd);
+        qu = qu - rintf(qu);
+        const float qw = frac_mul(sw, epsd);
+        const float s_u = __builtin_amdgcn_sinf(ph), c_u = __builtin_amdgcn_cosf(ph);
+        const float s_w = __builtin_amdgcn_sinf(pw), c_w = __builtin_amdgcn_cosf(pw);
+        const float s_ru = __builtin_amdgcn_sinf(qu), c_ru = __builtin_amdgcn_cosf(qu);
+        const float s_rw = __builtin_amdgcn_sinf(qw), c_rw = __builtin_amdgcn_cosf(qw);
+        float ur[kMfmaChirps], ui[kMfmaChirps], wr[kMfmaChirps], wi[kMfmaChirps];
+        ur[0] = Ax * c_u - Ay * s_u;
+        ui[0] = Ax * s_u + Ay * c_u;
+        wr[0] = c_w;
+        wi[0] = s_w;
+#pragma unroll
+        for (int g = 1; g < kMfmaChirps; g++) {
+            ur[g] = fmaf(ur[g - 1], c_ru, -ui[g - 1] * s_ru);
+            ui[g] = fmaf(ur[g - 1], s_ru, ui[g - 1] * c_ru);
+            wr[g] = fmaf(wr[g - 1], c_rw, -wi[g - 1] * s_rw);
+            wi[g] = fmaf(wr[g - 1], s_rw, wi[g - 1] * c_rw);
+        }
+        // three real products per chirp (Gauss): with U = a + jb, W = c + jd,
+        // K1 += (a + b) c, K2 += a (d - c), K3 += b (c + d); then
+        // Re = K1 - K3, Im = K1 + K2.  Ordered so that products into one
+        // accumulator are kMfmaChirps instructions apart (a group's chirps
+        // past C are computed too and never stored)
+#pragma unroll
+        for (int g = 0; g < kMfmaChirps; g++)
+            k1[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[g] + ui[g], wr[g], k1[g], 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g < kMfmaChirps; g++)
+            k2[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[g], wi[g] - wr[g], k2[g], 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g < kMfmaChirps; g++)
+            k3[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[g], wr[g] + wi[g], k3[g], 0, 0, 0);
+    }
+    const size_t row0 = ((size_t)chunk * a.V + v) * (size_t)a.C;
+    const auto out = gmem(a.partial);
+#pragma unroll
+    for (int g = 0; g < kMfmaChirps; g++) {
+        const int c = c0 + g;
+        if (c >= a.C) break;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int s = run * kMfmaRun + 16 * (4 * k + j) + i;
+            out[(row0 + c) * a.S + s] = F2{k1[g][j] - k3[g][j], k1[g][j] + k2[g][j]};
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_synth_mfma(const SynthArgs *__restrict__ args,
+                                                    const int32_t *__restrict__ first,
+                                                    const int32_t *__restrict__ idx, int n) {
+    const int blk = (int)blockIdx.x;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    const SynthArgs &a = args[idx[lo]];
+    const int local = blk - first[lo];
+    synth_mfma_block(a, local % a.gx, local / a.gx);
+}
+
 __global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, float2 *out) {
     size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -454,26 +596,37 @@ constexpr int kSynthL = 64;   // samples per lane (128 measured slower: occupanc
 // Blocks of 256 threads of k_synth<L> the device holds at once (256 CUs x 3
 // where the runtime cannot answer).
 static int resident_synth_blocks(int L) {
-    const void *k = L == 64 ? (const void *)k_synth<64> : L == 32 ? (const void *)k_synth<32>
-                                                                  : (const void *)k_synth<16>;
+    const void *k = L == kMfmaRun ? (const void *)k_synth_mfma
+                    : L == 64     ? (const void *)k_synth<64>
+                    : L == 32     ? (const void *)k_synth<32>
+                                  : (const void *)k_synth<16>;
     return resident_blocks(k, 256, 0, 256 * 3);
 }
 
 // Paths are split into n_chunks chunks.  Every wave of the grid does the same
 // work, so the chunk count is chosen to make the grid a whole number of
-// device-fulls of resident blocks (about 16k waves in all): a partly filled
-// last round leaves most of the chip idle for one wave's run time.  The plan
+// device-fulls of resident blocks (about 16k waves in all, 64k for the
+// matrix-core form, whose accumulators then sum about 4x fewer paths each in
+// FP32): a partly filled last round leaves most of the chip idle for one
+// wave's run time.  The plan
 // depends only on the request's own sizes (and the device), so a request
 // runs the same waves alone and in a batch.
 SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
     SynthPlan p;
-    p.L = S >= kSynthL ? kSynthL : (S >= 32 ? 32 : 16);
-    p.SB = (S + p.L - 1) / p.L;
-    p.tiles_per_v = (C * p.SB + 63) / 64;
+    if (S % kMfmaRun == 0) {   // matrix-core form: SB runs per chirp row, waves per antenna
+        p.L = kMfmaRun;
+        p.SB = S / kMfmaRun;
+        p.tiles_per_v = (C + kMfmaChirps - 1) / kMfmaChirps * p.SB;
+    } else {
+        p.L = S >= kSynthL ? kSynthL : (S >= 32 ? 32 : 16);
+        p.SB = (S + p.L - 1) / p.L;
+        p.tiles_per_v = (C * p.SB + 63) / 64;
+    }
     long long waves = (long long)V * p.tiles_per_v;
     long long grid_x = (waves + 3) / 4;
     long long cap = (long long)R * K;
-    long long want = (16384 + waves - 1) / waves;
+    const long long target = p.L == kMfmaRun ? 65536 : 16384;
+    long long want = (target + waves - 1) / waves;
     long long maxc = (cap + 63) / 64;
     const long long res = resident_synth_blocks(p.L);
     long long rounds = std::max(1LL, (long long)std::llround((double)want * grid_x / res));
@@ -502,18 +655,19 @@ SynthArgs synth_args(const PathStage &st, const SynthPlan &p, int32_t V, int32_t
 }
 
 // Device table of a batched synthesis: the requests' arguments, then per
-// sample-run length L (16, 32, 64) the requests using it and their first blocks.
+// kernel form (VALU runs of L = 16, 32, 64 samples per lane; the matrix-core
+// form, L = 256) the requests using it and their first blocks.
 struct SynthTable {
     SynthArgs *args;
-    int32_t *idx[3];
-    int32_t *first[3];
+    int32_t *idx[4];
+    int32_t *first[4];
 };
 
 static SynthTable synth_table(void *buf, int n, size_t *bytes) {
     Carver cv(buf);
     SynthTable t;
     t.args = cv.take<SynthArgs>(n);
-    for (int g = 0; g < 3; g++) {
+    for (int g = 0; g < 4; g++) {
         t.idx[g] = cv.take<int32_t>(n);
         t.first[g] = cv.take<int32_t>((size_t)n + 1);
     }
@@ -533,8 +687,8 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
     SynthTable t = synth_table(table, n, nullptr);
     int rc = put_table(t.args, args, sizeof(SynthArgs) * n, s);
     if (rc) return rc;
-    static const int kLs[3] = {16, 32, 64};
-    for (int g = 0; g < 3; g++) {
+    static const int kLs[4] = {16, 32, 64, kMfmaRun};
+    for (int g = 0; g < 4; g++) {
         std::vector<int32_t> idx, first(1, 0);
         for (int i = 0; i < n; i++) {
             if (L[i] != kLs[g]) continue;
@@ -552,7 +706,9 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
         const int m = (int)idx.size();
         const dim3 grid((unsigned)first.back());
         ProfScope ps(kProfSynth, s);
-        if (kLs[g] == 64)
+        if (kLs[g] == kMfmaRun)
+            hipLaunchKernelGGL(k_synth_mfma, grid, dim3(256), 0, s, t.args, t.first[g], t.idx[g], m);
+        else if (kLs[g] == 64)
             hipLaunchKernelGGL(k_synth<64>, grid, dim3(256), 0, s, t.args, t.first[g], t.idx[g], m);
         else if (kLs[g] == 32)
             hipLaunchKernelGGL(k_synth<32>, grid, dim3(256), 0, s, t.args, t.first[g], t.idx[g], m);

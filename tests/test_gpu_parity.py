@@ -1076,12 +1076,14 @@ def test_platform_presets_synth_and_backward(torch_cuda, orc, name):
     assert e <= 1e-4 and eg <= GRAD_TOL
 
 
+@pytest.mark.parametrize("samples", [256, 192])
 @pytest.mark.parametrize("case", ["near_dc_24g", "near_nyquist_77g"])
-def test_synth_low_and_high_beat_frequency(torch_cuda, orc, case):
+def test_synth_low_and_high_beat_frequency(torch_cuda, orc, case, samples):
     """Beat frequencies near 0 and near f_s / 2 per sample, where a real
     three-term recurrence cos-coefficient is ill-conditioned: a plate at 0.5 m
     seen by the 24 GHz ranging radar (0.0026 cycles per sample), and one at
-    12.4 m seen by the 77 GHz radar (0.496 cycles per sample)."""
+    12.4 m seen by the 77 GHz radar (0.496 cycles per sample).  256 samples
+    per chirp take the matrix-core form, 192 the VALU form."""
     if case == "near_dc_24g":
         radar, chirp = S.platform("ranging_24g")
         dist, size = 0.5, 0.05
@@ -1090,8 +1092,8 @@ def test_synth_low_and_high_beat_frequency(torch_cuda, orc, case):
         dist, size = 12.4, 1.0
     v, f = S.plate(size, dist)
     th = 0.6 * size / dist
-    sc = S.Scene(case, v.astype(np.float32), f.astype(np.int32), radar, dataclasses.replace(chirp, n_chirps=2),
-                 S.Grid(40, 40, th, th, 1))
+    sc = S.Scene(case, v.astype(np.float32), f.astype(np.int32), radar,
+                 dataclasses.replace(chirp, n_chirps=2, n_samples=samples), S.Grid(40, 40, th, th, 1))
     o = orc.trace(sc)
     p = orc.paths(sc, o["tri"], o["flags"])
     want = orc.synth(sc, p)
@@ -1104,15 +1106,17 @@ def test_synth_low_and_high_beat_frequency(torch_cuda, orc, case):
     assert len(p["amp"]) > 100 and e <= 1e-4
 
 
-def test_synth_many_near_dc_paths_per_wavefront(torch_cuda, orc):
+@pytest.mark.parametrize("samples", [256, 192])
+def test_synth_many_near_dc_paths_per_wavefront(torch_cuda, orc, samples):
     """A million paths, all near 0 cycles per sample (a plate filling the
-    1024^2 grid at 0.5 m, 24 GHz ranging radar): each wavefront meets more
-    near-DC paths than it can remember, so the rotation pass rescans its chunk.
-    Sampled cube rows vs the oracle."""
+    1024^2 grid at 0.5 m, 24 GHz ranging radar).  256 samples take the
+    matrix-core form (every factor from its own reduced phase); 192 the VALU
+    form, where each wavefront meets more near-DC paths than it can remember,
+    so the rotation pass rescans its chunk.  Sampled cube rows vs the oracle."""
     radar, chirp = S.platform("ranging_24g")
     v, f = S.plate(0.6, 0.5)
     sc = S.Scene("plate_near_dc", v.astype(np.float32), f.astype(np.int32), radar,
-                 dataclasses.replace(chirp, n_chirps=2), S.Grid(1024, 1024, 0.5, 0.5, 1))
+                 dataclasses.replace(chirp, n_chirps=2, n_samples=samples), S.Grid(1024, 1024, 0.5, 0.5, 1))
     o = orc.trace(sc)
     p = orc.paths(sc, o["tri"], o["flags"])
     assert len(p["amp"]) > 600 * 1024   # more than 512 per wavefront at the 1024-chunk cap
