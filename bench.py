@@ -35,6 +35,7 @@ OPS_PER_NODE_TEST, OPS_PER_TRI_TEST = 14, 27
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__k_synth_adj__clutter_50k_fwd_bwd.md")
 KERNEL_SOURCES = {
     "k_synth_adj": ["backward.hip", "sbr_internal.h", "sbr_device.h"],
+    "k_synth_mfma": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
     "k_synth": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
 }
 
@@ -216,14 +217,16 @@ def main():
     ps = float(n_paths) * V * C * Sn          # path-samples per launch
     dominant = max(("synth", "synth_adj"), key=lambda k: k_ms[k])
     achieved = FLOP_PER_PATH_SAMPLE[dominant] * ps / (k_ms[dominant] * 1e-3) / 1e12
+    # the synthesis runs on the matrix cores for runs of 256 samples, else on the VALU
+    synth_kernel = "k_synth_mfma" if Sn % 256 == 0 else "k_synth"
     roof = {
         "bound": "alu",
-        "kernel": "k_synth_adj" if dominant == "synth_adj" else "k_synth",
+        "kernel": "k_synth_adj" if dominant == "synth_adj" else synth_kernel,
         "achieved": round(achieved, 3),
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-        "traffic": measured_traffic("k_synth_adj" if dominant == "synth_adj" else "k_synth", args.workload),
+        "traffic": measured_traffic("k_synth_adj" if dominant == "synth_adj" else synth_kernel, args.workload),
     }
     out = {
         "metric": "ray-bounces/s fwd+bwd",
@@ -247,6 +250,8 @@ def main():
         "if_path_samples_per_s": ps / (ms_step * 1e-3),
         "if_output_samples_per_s": V * C * Sn / (ms_step * 1e-3),
         "kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
+        "synth_frac_of_fp32_peak": round(FLOP_PER_PATH_SAMPLE["synth"] * ps / (k_ms["synth"] * 1e-3) / 1e12 /
+                                         PEAK_FP32_TFLOPS, 4),
         "trace": {"ray_bounces_per_s": queries / (k_ms["trace"] * 1e-3), "node_tests": node_tests,
                   "tri_tests": tri_tests,
                   "alg_valu_ops_per_s": (OPS_PER_NODE_TEST * node_tests + OPS_PER_TRI_TEST * tri_tests) /
