@@ -48,6 +48,7 @@ __global__ void k_bounds(const float *verts, const int32_t *faces, int nf, uint3
     if (threadIdx.x < 6) red[threadIdx.x] = threadIdx.x < 3 ? 0xffffffffu : 0u;
     __syncthreads();
     int f = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t v[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
     if (f < nf) {
         float3 a = load_vert(verts, faces[3 * f]);
         float3 b = load_vert(verts, faces[3 * f + 1]);
@@ -55,12 +56,24 @@ __global__ void k_bounds(const float *verts, const int32_t *faces, int nf, uint3
         float cx = (a.x + b.x + c.x) * (1.0f / 3.0f);
         float cy = (a.y + b.y + c.y) * (1.0f / 3.0f);
         float cz = (a.z + b.z + c.z) * (1.0f / 3.0f);
-        atomicMin(&red[0], f2ord(cx));
-        atomicMin(&red[1], f2ord(cy));
-        atomicMin(&red[2], f2ord(cz));
-        atomicMax(&red[3], f2ord(cx));
-        atomicMax(&red[4], f2ord(cy));
-        atomicMax(&red[5], f2ord(cz));
+        v[0] = v[3] = f2ord(cx);
+        v[1] = v[4] = f2ord(cy);
+        v[2] = v[5] = f2ord(cz);
+    }
+    // wavefront min / max first, then one LDS atomic per wavefront and value
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            v[q] = min(v[q], (uint32_t)__shfl_xor((int)v[q], off));
+            v[3 + q] = max(v[3 + q], (uint32_t)__shfl_xor((int)v[3 + q], off));
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        for (int q = 0; q < 3; q++) {
+            atomicMin(&red[q], v[q]);
+            atomicMax(&red[3 + q], v[3 + q]);
+        }
     }
     __syncthreads();
     if (threadIdx.x < 3) atomicMin(&bounds[threadIdx.x], red[threadIdx.x]);

@@ -565,16 +565,28 @@ __global__ __launch_bounds__(256) void k_synth_mfma(const SynthArgs *__restrict_
     synth_mfma_block(a, local % a.gx, local / a.gx);
 }
 
+// Fixed-order sum of the chunk partials: four running sums over the chunks
+// c = 0, 1, 2, 3 (mod 4), so that four loads are in flight, then
+// (s0 + s1) + (s2 + s3).
 __global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, float2 *out) {
     size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    float sr = 0.0f, si = 0.0f;
-    for (int c = 0; c < n_chunks; c++) {
-        float2 x = partial[(size_t)c * n + e];
-        sr += x.x;
-        si += x.y;
+    float2 s[4] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    int c = 0;
+    for (; c + 4 <= n_chunks; c += 4) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const float2 x = partial[(size_t)(c + q) * n + e];
+            s[q].x += x.x;
+            s[q].y += x.y;
+        }
     }
-    out[e] = make_float2(sr, si);
+    for (int q = 0; c + q < n_chunks; q++) {
+        const float2 x = partial[(size_t)(c + q) * n + e];
+        s[q].x += x.x;
+        s[q].y += x.y;
+    }
+    out[e] = make_float2((s[0].x + s[1].x) + (s[2].x + s[3].x), (s[0].y + s[1].y) + (s[2].y + s[3].y));
 }
 
 }  // namespace
@@ -627,7 +639,10 @@ SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
     long long cap = (long long)R * K;
     const long long target = p.L == kMfmaRun ? 65536 : 16384;
     long long want = (target + waves - 1) / waves;
+    // at least 64 path slots per chunk (1024 for the matrix-core form, whose
+    // waves each write 8 chirps x 256 samples of partials)
     long long maxc = (cap + 63) / 64;
+    if (p.L == kMfmaRun) maxc = (cap + 1023) / 1024;
     const long long res = resident_synth_blocks(p.L);
     long long rounds = std::max(1LL, (long long)std::llround((double)want * grid_x / res));
     long long nch = (rounds * res + grid_x - 1) / grid_x;
