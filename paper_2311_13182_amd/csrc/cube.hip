@@ -1,7 +1,10 @@
 // The signal-to-image map T of the spatial loss (Eq. 16): range, Doppler and
 // angle DFTs and their conjugate transpose; and the CA-CFAR point extraction.
-// Each DFT is a dense FP32 contraction with the DFT matrix on the matrix cores
-// (MFMA), twiddles by exact index (k n mod N) from an LDS table.
+// Power-of-two range and Doppler lengths run as Stockham FFTs in LDS; the
+// angle stage of a linear array is a direct DFT by Horner's rule, fused with
+// the range FFT in the forward map when one Doppler bin fits in LDS; other
+// lengths and the planar angle stage are dense FP32 contractions with the DFT
+// matrix on the matrix cores (MFMA), twiddles by exact index (k n mod N).
 #include <mutex>
 
 #include "sbr_internal.h"
@@ -200,7 +203,8 @@ __global__ __launch_bounds__(256) void k_dft_mid(const float2 *in, float2 *out, 
 // for p < m, q < s, k < r; radix-4 stages while 4 divides n, then one
 // radix-2 stage if n = 2 is left.  The twiddle e^{sign 2 pi j k p / n} is the
 // N-entry table's entry k p s (exact index).
-constexpr int kFftTile = 1024;   // complex elements per block (per LDS buffer)
+constexpr int kFftLogTile = 10;
+constexpr int kFftTile = 1 << kFftLogTile;   // complex elements per block (per LDS buffer)
 
 __device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -208,16 +212,24 @@ __device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
 __device__ __forceinline__ float2 cadd2(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub2(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// W independent sequences of length N = 2^logN in LDS, element n of sequence
-// j at n * sn + j * sj; x and y are two buffers of the same layout.  Returns
-// the buffer holding the result.
-__device__ float2 *lds_fft(float2 *x, float2 *y, int logN, int W, int sn, int sj, const float2 *tw, int sign) {
+// W independent sequences of length N = 2^logN in LDS, element n of
+// sequence j at n * sn + j * sj; x and y are two buffers of the same layout.
+// Returns the buffer holding the result.  Consecutive threads take
+// consecutive butterflies of one sequence (sn = 1) or the same butterfly of
+// consecutive sequences (sj = 1, JFAST): either way neighbouring lanes touch
+// neighbouring LDS words.
+// W is any count for the sequence-major form (JFAST false) and 2^logW for
+// JFAST.
+template <bool JFAST>
+__device__ float2 *lds_fft(float2 *x, float2 *y, int logN, int W, int logW, int sn, int sj, const float2 *tw,
+                           int sign) {
     int ls = 0;   // log2 of the stride s
     while (logN - ls >= 2) {   // radix 4: n = N / s divisible by 4
         const int s = 1 << ls, lm = logN - ls - 2, m = 1 << lm;
         const int total = W << (logN - 2);
         for (int b = threadIdx.x; b < total; b += blockDim.x) {
-            const int j = b >> (logN - 2), r = b & ((1 << (logN - 2)) - 1);
+            const int j = JFAST ? (b & (W - 1)) : (b >> (logN - 2));
+            const int r = JFAST ? (b >> logW) : (b & ((1 << (logN - 2)) - 1));
             const int p = r >> ls, q = r & (s - 1);
             const int base = (q + s * p) * sn + j * sj, step = (s * m) * sn;
             const float2 a = x[base], bb = x[base + step], c = x[base + 2 * step], d = x[base + 3 * step];
@@ -240,7 +252,8 @@ __device__ float2 *lds_fft(float2 *x, float2 *y, int logN, int W, int sn, int sj
         const int s = 1 << ls;
         const int total = W << (logN - 1);
         for (int b = threadIdx.x; b < total; b += blockDim.x) {
-            const int j = b >> (logN - 1), q = b & (s - 1);
+            const int j = JFAST ? (b & (W - 1)) : (b >> (logN - 1));
+            const int q = JFAST ? (b >> logW) : (b & (s - 1));
             const float2 a = x[q * sn + j * sj], c = x[(q + s) * sn + j * sj];
             y[q * sn + j * sj] = cadd2(a, c);
             y[(q + s) * sn + j * sj] = csub2(a, c);
@@ -266,26 +279,33 @@ __device__ void fft_tables(float2 *tw, float *wt, int N, int sign, int window) {
 
 // FFT along the innermost axis: [rows][N] -> [rows][N], R = kFftTile / N rows
 // per block; the window multiplies the input (post = 0) or the output.
-__global__ __launch_bounds__(256) void k_fft_inner(const float2 *in, float2 *out, int rows, int logN, int sign,
-                                                   int window, int post) {
+// The global loads of a block are issued before its tables are built, so
+// the table work hides under their latency.
+constexpr int kFftThreads = 256;
+constexpr int kFftPer = kFftTile / kFftThreads;
+
+__global__ __launch_bounds__(kFftThreads) void k_fft_inner(const float2 *in, float2 *out, int rows, int logN,
+                                                           int sign, int window, int post) {
     extern __shared__ float2 sm[];
     const int N = 1 << logN, R = kFftTile >> logN;
     float2 *tw = sm;
     float *wt = reinterpret_cast<float *>(sm + N);
     float2 *b0 = sm + N + (N + 1) / 2, *b1 = b0 + kFftTile;
-    fft_tables(tw, wt, N, sign, window);
     const long long row0 = (long long)blockIdx.x * R;
-    for (int i = threadIdx.x; i < kFftTile; i += blockDim.x) {
-        const int r = i >> logN, n = i & (N - 1);
-        float2 v = make_float2(0.0f, 0.0f);
-        if (row0 + r < rows) {
-            v = in[(row0 + r) * N + n];
-            if (!post) v = make_float2(v.x * wt[n], v.y * wt[n]);
-        }
-        b0[i] = v;
+    float2 v[kFftPer];
+#pragma unroll
+    for (int u = 0; u < kFftPer; u++) {
+        const int i = threadIdx.x + u * kFftThreads, r = i >> logN, n = i & (N - 1);
+        v[u] = row0 + r < rows ? in[(row0 + r) * N + n] : make_float2(0.0f, 0.0f);
+    }
+    fft_tables(tw, wt, N, sign, window);
+#pragma unroll
+    for (int u = 0; u < kFftPer; u++) {
+        const int i = threadIdx.x + u * kFftThreads, n = i & (N - 1);
+        b0[i] = post ? v[u] : make_float2(v[u].x * wt[n], v[u].y * wt[n]);
     }
     __syncthreads();
-    const float2 *res = lds_fft(b0, b1, logN, R, 1, N, tw, sign);
+    const float2 *res = lds_fft<false>(b0, b1, logN, R, 0, 1, N, tw, sign);
     for (int i = threadIdx.x; i < kFftTile; i += blockDim.x) {
         const int r = i >> logN, k = i & (N - 1);
         if (row0 + r < rows) {
@@ -299,31 +319,33 @@ __global__ __launch_bounds__(256) void k_fft_inner(const float2 *in, float2 *out
 // FFT along a middle axis: [outer][N][inner] -> [outer][N][inner].  A block
 // takes one outer index and W = kFftTile / N consecutive inner columns (the
 // loads and stores run along the inner axis).
-__global__ __launch_bounds__(256) void k_fft_mid(const float2 *in, float2 *out, int outer, int logN, int inner,
-                                                 int sign, int window, int post) {
+__global__ __launch_bounds__(kFftThreads) void k_fft_mid(const float2 *in, float2 *out, int outer, int logN,
+                                                         int inner, int sign, int window, int post) {
     extern __shared__ float2 sm[];
-    const int N = 1 << logN, W = kFftTile >> logN;
+    const int N = 1 << logN, logW = kFftLogTile - logN, W = 1 << logW;
     float2 *tw = sm;
     float *wt = reinterpret_cast<float *>(sm + N);
     float2 *b0 = sm + N + (N + 1) / 2, *b1 = b0 + kFftTile;
-    fft_tables(tw, wt, N, sign, window);
     const int ct = (inner + W - 1) / W;
     const int o = blockIdx.x / ct, i0 = (blockIdx.x % ct) * W;
     const float2 *src = in + (size_t)o * N * inner;
     float2 *dst = out + (size_t)o * N * inner;
-    for (int i = threadIdx.x; i < kFftTile; i += blockDim.x) {
-        const int n = i / W, j = i - n * W;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (i0 + j < inner) {
-            v = src[(size_t)n * inner + i0 + j];
-            if (!post) v = make_float2(v.x * wt[n], v.y * wt[n]);
-        }
-        b0[i] = v;
+    float2 v[kFftPer];
+#pragma unroll
+    for (int u = 0; u < kFftPer; u++) {
+        const int i = threadIdx.x + u * kFftThreads, n = i >> logW, j = i & (W - 1);
+        v[u] = i0 + j < inner ? src[(size_t)n * inner + i0 + j] : make_float2(0.0f, 0.0f);
+    }
+    fft_tables(tw, wt, N, sign, window);
+#pragma unroll
+    for (int u = 0; u < kFftPer; u++) {
+        const int i = threadIdx.x + u * kFftThreads, n = i >> logW;
+        b0[i] = post ? v[u] : make_float2(v[u].x * wt[n], v[u].y * wt[n]);
     }
     __syncthreads();
-    const float2 *res = lds_fft(b0, b1, logN, W, W, 1, tw, sign);
+    const float2 *res = lds_fft<true>(b0, b1, logN, W, logW, W, 1, tw, sign);
     for (int i = threadIdx.x; i < kFftTile; i += blockDim.x) {
-        const int k = i / W, j = i - k * W;
+        const int k = i >> logW, j = i & (W - 1);
         if (i0 + j < inner) {
             float2 v = res[i];
             if (post) v = make_float2(v.x * wt[k], v.y * wt[k]);
@@ -333,65 +355,316 @@ __global__ __launch_bounds__(256) void k_fft_mid(const float2 *in, float2 *out, 
 }
 
 constexpr int kAngleVMax = 32;   // antennas of the direct angle stage (registers)
+constexpr int kAngleGroup = 8;   // angle bins per thread of the forward stage
 
-// Angle stage of a linear array as a direct DFT, one thread per (chirp,
-// sample) cell e, coalesced along e.  direction 0: out[a][e] = sum_{v < V}
-// w_a^v y[v][e] with w_a = e^{-2 pi j a / Na}, by Horner's rule in w_a (V - 1
-// complex multiply-adds per output, w_a from an LDS table), for the block
-// row's share of a; direction 1 (conjugate transpose): out[v][e] = sum_a
-// e^{+2 pi j (a v mod Na) / Na} y[a][e] for every v, twiddles by exact index.
-__global__ __launch_bounds__(256) void k_angle(const float2 *y, float2 *out, int V, int Na, long long CS, int dir,
-                                               int a_per) {
+// acc_k = acc_k w_k + y for the thread's kAngleGroup angle bins: independent
+// complex multiply-adds, so the chains interleave.
+__device__ __forceinline__ void horner_step(float2 (&acc)[kAngleGroup], const float2 (&w)[kAngleGroup], float2 y) {
+#pragma unroll
+    for (int k = 0; k < kAngleGroup; k++) {
+        const float nr = fmaf(acc[k].x, w[k].x, fmaf(-acc[k].y, w[k].y, y.x));
+        acc[k].y = fmaf(acc[k].x, w[k].y, fmaf(acc[k].y, w[k].x, y.y));
+        acc[k].x = nr;
+    }
+}
+
+// Forward angle stage of a linear array as a direct DFT:
+//   out[a][e] = sum_{v < V} w_a^v y[v][e],  w_a = e^{-2 pi j a / Na},
+// by Horner's rule in w_a (V - 1 complex multiply-adds per output).  A thread
+// owns one (chirp, sample) cell e (coalesced along e) and the block row's
+// kAngleGroup consecutive angle bins.  The antenna values sit in registers.
+// EXACT instances have V = VB and straight-line steps; otherwise each
+// unrolled step is guarded by the wave-uniform test v < V (a branch, so no
+// step runs for antennas beyond V; VB is only the register bound).
+template <int VB, bool EXACT>
+__global__ __launch_bounds__(256) void k_angle(const float2 *y, float2 *out, int V, int Na, long long CS) {
+    __shared__ float2 w_s[kAngleGroup];
+    const int a0 = blockIdx.y * kAngleGroup;
+    if (threadIdx.x < kAngleGroup) {
+        float sn, cs;
+        sincospif(2.0f * (float)(a0 + (int)threadIdx.x) / (float)Na, &sn, &cs);
+        w_s[threadIdx.x] = make_float2(cs, -sn);
+    }
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool live = e < CS;
+    float2 yv[VB];
+#pragma unroll
+    for (int v = 0; v < VB; v++)
+        if (EXACT || v < V) yv[v] = live ? y[(size_t)v * CS + e] : make_float2(0.0f, 0.0f);
+    __syncthreads();
+    if (!live) return;
+    float2 w[kAngleGroup], acc[kAngleGroup];
+#pragma unroll
+    for (int k = 0; k < kAngleGroup; k++) {
+        w[k] = w_s[k];
+        acc[k] = make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int v = VB - 1; v >= 0; v--)
+        if (EXACT || v < V) horner_step(acc, w, yv[v]);
+#pragma unroll
+    for (int k = 0; k < kAngleGroup; k++)
+        if (a0 + k < Na) out[(size_t)(a0 + k) * CS + e] = acc[k];
+}
+
+// Conjugate transpose of the angle stage: out[v][e] = sum_a
+// e^{+2 pi j (a v mod Na) / Na} y[a][e] for every v < V, twiddles by exact
+// index from an LDS table; one thread per cell.
+template <int VB>
+__global__ __launch_bounds__(256) void k_angle_adj(const float2 *y, float2 *out, int V, int Na, long long CS) {
     extern __shared__ float2 tw[];
     for (int k = threadIdx.x; k < Na; k += blockDim.x) {
         float sn, cs;
         sincospif(2.0f * (float)k / (float)Na, &sn, &cs);
-        tw[k] = make_float2(cs, dir == 0 ? -sn : sn);
+        tw[k] = make_float2(cs, sn);
     }
     __syncthreads();
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= CS) return;
-    if (dir == 0) {
-        float2 yv[kAngleVMax];
+    float2 acc[VB];
 #pragma unroll
-        for (int v = 0; v < kAngleVMax; v++)
-            yv[v] = v < V ? y[(size_t)v * CS + e] : make_float2(0.0f, 0.0f);
-        const int a0 = blockIdx.y * a_per, a1 = min(Na, a0 + a_per);
-        for (int a = a0; a < a1; a++) {
-            const float2 w = tw[a];
-            float sr = 0.0f, si = 0.0f;
+    for (int v = 0; v < VB; v++) acc[v] = make_float2(0.0f, 0.0f);
+    for (int a = 0; a < Na; a++) {
+        const float2 x = y[(size_t)a * CS + e];
+        int idx = 0;
 #pragma unroll
-            for (int v = kAngleVMax - 1; v >= 0; v--) {
-                if (v < V) {   // acc = acc w + y_v
-                    const float nr = fmaf(sr, w.x, fmaf(-si, w.y, yv[v].x));
-                    si = fmaf(sr, w.y, fmaf(si, w.x, yv[v].y));
-                    sr = nr;
-                }
-            }
-            out[(size_t)a * CS + e] = make_float2(sr, si);
+        for (int v = 0; v < VB; v++) {
+            if (v >= V) continue;
+            const float2 w = tw[idx];
+            acc[v].x = fmaf(w.x, x.x, fmaf(-w.y, x.y, acc[v].x));
+            acc[v].y = fmaf(w.x, x.y, fmaf(w.y, x.x, acc[v].y));
+            idx += a;
+            if (idx >= Na) idx -= Na;
         }
-    } else {
-        float2 acc[kAngleVMax];
-#pragma unroll
-        for (int v = 0; v < kAngleVMax; v++) acc[v] = make_float2(0.0f, 0.0f);
-        for (int a = 0; a < Na; a++) {
-            const float2 x = y[(size_t)a * CS + e];
-            int idx = 0;
-#pragma unroll
-            for (int v = 0; v < kAngleVMax; v++) {
-                if (v < V) {
-                    const float2 w = tw[idx];
-                    acc[v].x = fmaf(w.x, x.x, fmaf(-w.y, x.y, acc[v].x));
-                    acc[v].y = fmaf(w.x, x.y, fmaf(w.y, x.x, acc[v].y));
-                    idx += a;
-                    if (idx >= Na) idx -= Na;
-                }
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < kAngleVMax; v++)
-            if (v < V) out[(size_t)v * CS + e] = acc[v];
     }
+#pragma unroll
+    for (int v = 0; v < VB; v++)
+        if (v < V) out[(size_t)v * CS + e] = acc[v];
+}
+
+// ---- Forward range FFT + angle DFT, fused (256 samples) -------------------
+// cos and sin of 2 pi m / 16, m < 16
+constexpr float kCos16[16] = {1.0f, 0.92387953f, 0.70710678f, 0.38268343f, 0.0f, -0.38268343f,
+                                 -0.70710678f, -0.92387953f, -1.0f, -0.92387953f, -0.70710678f, -0.38268343f,
+                                 0.0f, 0.38268343f, 0.70710678f, 0.92387953f};
+constexpr float kSin16[16] = {0.0f, 0.38268343f, 0.70710678f, 0.92387953f, 1.0f, 0.92387953f,
+                                 0.70710678f, 0.38268343f, 0.0f, -0.38268343f, -0.70710678f, -0.92387953f,
+                                 -1.0f, -0.92387953f, -0.70710678f, -0.38268343f};
+
+// Forward 4-point DFT (e^{-2 pi j n k / 4}) of a0..a3, in place.
+__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
+    const float2 t0 = cadd2(a0, a2), t1 = csub2(a0, a2), t2 = cadd2(a1, a3), t3 = csub2(a1, a3);
+    a0 = cadd2(t0, t2);
+    a2 = csub2(t0, t2);
+    a1 = make_float2(t1.x + t3.y, t1.y - t3.x);   // t1 - j t3
+    a3 = make_float2(t1.x - t3.y, t1.y + t3.x);   // t1 + j t3
+}
+
+// Forward 16-point DFT of x in registers, result in natural order:
+// n = 4 n1 + n2, k = k1 + 4 k2; a 4-point DFT over n1 for each n2, the
+// twiddle e^{-2 pi j n2 k1 / 16}, then a 4-point DFT over n2 for each k1.
+__device__ __forceinline__ void dft16(float2 (&x)[16]) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; n2++) dft4(x[n2], x[4 + n2], x[8 + n2], x[12 + n2]);   // x[4 k1 + n2]
+#pragma unroll
+    for (int n2 = 1; n2 < 4; n2++)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; k1++) {
+            const int m = n2 * k1;
+            x[4 * k1 + n2] = cmul2(x[4 * k1 + n2], make_float2(kCos16[m], -kSin16[m]));
+        }
+    float2 y[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; k1++) {
+        float2 a0 = x[4 * k1], a1 = x[4 * k1 + 1], a2 = x[4 * k1 + 2], a3 = x[4 * k1 + 3];
+        dft4(a0, a1, a2, a3);   // over n2 -> k2
+        y[k1] = a0;
+        y[k1 + 4] = a1;
+        y[k1 + 8] = a2;
+        y[k1 + 12] = a3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = y[i];
+}
+
+// Forward 2- and 8-point DFTs in registers (natural order); the 8-point one
+// as n = 2 n1 + n2, k = k1 + 4 k2.
+__device__ __forceinline__ void dft2(float2 &a0, float2 &a1) {
+    const float2 t = a0;
+    a0 = cadd2(t, a1);
+    a1 = csub2(t, a1);
+}
+
+template <int P>
+__device__ __forceinline__ void dft_small(float2 (&v)[P]);
+template <>
+__device__ __forceinline__ void dft_small<2>(float2 (&v)[2]) { dft2(v[0], v[1]); }
+template <>
+__device__ __forceinline__ void dft_small<4>(float2 (&v)[4]) { dft4(v[0], v[1], v[2], v[3]); }
+template <>
+__device__ __forceinline__ void dft_small<8>(float2 (&v)[8]) {
+    dft4(v[0], v[2], v[4], v[6]);   // n2 = 0: v[2 k1]
+    dft4(v[1], v[3], v[5], v[7]);   // n2 = 1: v[2 k1 + 1]
+#pragma unroll
+    for (int k1 = 1; k1 < 4; k1++) v[2 * k1 + 1] = cmul2(v[2 * k1 + 1], make_float2(kCos16[2 * k1], -kSin16[2 * k1]));
+    float2 y[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; k1++) {
+        y[k1] = cadd2(v[2 * k1], v[2 * k1 + 1]);
+        y[k1 + 4] = csub2(v[2 * k1], v[2 * k1 + 1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = y[i];
+}
+template <>
+__device__ __forceinline__ void dft_small<16>(float2 (&v)[16]) { dft16(v); }
+
+// Forward Doppler FFT (windowed, [V][C][S] -> [V][C][S]) for C = 16 P chirps:
+// chirp n = t + P m.  Thread (column s, t) holds its 16 values in registers,
+// takes the 16-point DFT over m and multiplies by e^{-2 pi j t k1 / C}; after
+// one exchange through LDS (column index fastest, so both sides are
+// conflict-free) the same thread takes the P-point DFTs over t of its 16 / P
+// values of k1, giving Doppler bin k1 + 16 k2.  Lanes run along the samples,
+// so loads and stores are coalesced rows.
+constexpr int kDopThreads = 128;
+
+template <int P>
+__global__ __launch_bounds__(kDopThreads) void k_doppler(const float2 *in, float2 *out, int S, int window) {
+    constexpr int C = 16 * P, NCOL = kDopThreads / P, PER = 16 / P;
+    __shared__ float2 tw[C];
+    __shared__ float wt[C];
+    __shared__ float2 ex[16 * P * NCOL];
+    const int tid = threadIdx.x, j = tid % NCOL, t = tid / NCOL;
+    const int sblocks = (S + NCOL - 1) / NCOL;
+    const int v = blockIdx.x / sblocks, s = (blockIdx.x % sblocks) * NCOL + j;
+    const bool live = s < S;
+    const float2 *src = in + (size_t)v * C * S;
+    float2 x[16];
+#pragma unroll
+    for (int m = 0; m < 16; m++) x[m] = live ? src[(size_t)(t + P * m) * S + s] : make_float2(0.0f, 0.0f);
+    for (int i = tid; i < C; i += kDopThreads) {
+        float sn, cs;
+        sincospif(2.0f * (float)i / (float)C, &sn, &cs);
+        tw[i] = make_float2(cs, -sn);
+        wt[i] = window == 1 ? 0.5f - 0.5f * cospif(2.0f * (float)i / (float)(C - 1)) : 1.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; m++) {
+        const float w = wt[t + P * m];
+        x[m] = make_float2(x[m].x * w, x[m].y * w);
+    }
+    dft16(x);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; k1++) ex[(k1 * P + t) * NCOL + j] = k1 == 0 ? x[0] : cmul2(x[k1], tw[t * k1]);
+    __syncthreads();
+    float2 *dst = out + (size_t)v * C * S;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int k1 = t * PER + q;
+        float2 u[P];
+#pragma unroll
+        for (int tt = 0; tt < P; tt++) u[tt] = ex[(k1 * P + tt) * NCOL + j];
+        dft_small<P>(u);
+        if (live) {
+#pragma unroll
+            for (int k2 = 0; k2 < P; k2++) dst[(size_t)(k1 + 16 * k2) * S + s] = u[k2];
+        }
+    }
+}
+
+// A block takes Doppler bin k (the Doppler stage has already run; the DFT
+// axes commute): the V <= 16 rows in[v][k][*] of 256 samples, windowed.  The
+// range FFT splits each row as n = t + 16 m: thread (row r, t) holds its 16
+// values in registers, takes the 16-point DFT over m, multiplies by
+// e^{-2 pi j t k1 / 256} and leaves them in LDS; thread (r, k1) then takes
+// the 16-point DFT over t, giving range bin k1 + 16 k2.  LDS rows are padded
+// (kRaRow) and the exchange uses a stride of 17, so neither access pattern
+// has lanes on one bank.  Then one thread per range bin s writes out[a][k][s]
+// for the block's kRangeAngleBins angle bins by Horner's rule over the
+// antennas, in passes of kAngleGroup bins (coalesced rows of 256 values).
+constexpr int kRaS = 256;              // samples per row
+constexpr int kRaRow = 16 * 17;        // padded LDS row (complex values)
+constexpr int kRaVMax = 16;            // rows (antennas) of one block
+constexpr int kRangeAngleBins = 16;    // angle bins per block
+
+template <int VB, bool EXACT>
+__global__ __launch_bounds__(256) void k_range_angle(const float2 *in, float2 *out, int V, int C, int Na,
+                                                     int window) {
+    extern __shared__ float2 sm[];
+    float2 *tw = sm;                              // e^{-2 pi j i / 256}
+    float2 *wa = tw + kRaS;                       // angle steps of the block's bins
+    float *wt = reinterpret_cast<float *>(wa + kRangeAngleBins);
+    float2 *buf = wa + kRangeAngleBins + kRaS / 2;   // V rows of kRaRow
+    const int k = blockIdx.x, a_lo = blockIdx.y * kRangeAngleBins, tid = threadIdx.x;
+    const int r = tid >> 4, t = tid & 15;
+    const bool fft = r < V;
+    float2 x[16];
+    if (fft) {
+        const float2 *row = in + ((size_t)r * C + k) * kRaS;
+#pragma unroll
+        for (int m = 0; m < 16; m++) x[m] = row[t + 16 * m];
+    }
+    {
+        float sn, cs;
+        sincospif(2.0f * (float)tid / (float)kRaS, &sn, &cs);
+        tw[tid] = make_float2(cs, -sn);
+        wt[tid] = window == 1 ? 0.5f - 0.5f * cospif(2.0f * (float)tid / (float)(kRaS - 1)) : 1.0f;
+        if (tid < kRangeAngleBins) {
+            sincospif(2.0f * (float)(a_lo + tid) / (float)Na, &sn, &cs);
+            wa[tid] = make_float2(cs, -sn);
+        }
+    }
+    __syncthreads();
+    if (fft) {
+#pragma unroll
+        for (int m = 0; m < 16; m++) {
+            const float w = wt[t + 16 * m];
+            x[m] = make_float2(x[m].x * w, x[m].y * w);
+        }
+        dft16(x);
+#pragma unroll
+        for (int k1 = 0; k1 < 16; k1++)
+            buf[r * kRaRow + k1 * 17 + t] = k1 == 0 ? x[0] : cmul2(x[k1], tw[t * k1]);
+    }
+    __syncthreads();
+    if (fft) {
+#pragma unroll
+        for (int u = 0; u < 16; u++) x[u] = buf[r * kRaRow + t * 17 + u];   // k1 = t, over u = t'
+    }
+    __syncthreads();
+    if (fft) {
+        dft16(x);
+#pragma unroll
+        for (int k2 = 0; k2 < 16; k2++) buf[r * kRaRow + t + 16 * k2] = x[k2];   // range bin t + 16 k2
+    }
+    __syncthreads();
+    const int sb = tid;   // range bin
+    float2 yv[VB];
+#pragma unroll
+    for (int a = 0; a < VB; a++)
+        if (EXACT || a < V) yv[a] = buf[a * kRaRow + sb];
+    const size_t plane = (size_t)C * kRaS;
+    for (int g = 0; g < kRangeAngleBins; g += kAngleGroup) {
+        const int a0 = a_lo + g;
+        if (a0 >= Na) break;
+        float2 w[kAngleGroup], acc[kAngleGroup];
+#pragma unroll
+        for (int q = 0; q < kAngleGroup; q++) {
+            w[q] = wa[g + q];
+            acc[q] = make_float2(0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int a = VB - 1; a >= 0; a--)
+            if (EXACT || a < V) horner_step(acc, w, yv[a]);
+#pragma unroll
+        for (int q = 0; q < kAngleGroup; q++)
+            if (a0 + q < Na) out[(size_t)(a0 + q) * plane + (size_t)k * kRaS + sb] = acc[q];
+    }
+}
+
+static size_t range_angle_lds(int V) {
+    return sizeof(float2) * ((size_t)kRaS + kRangeAngleBins + kRaS / 2 + (size_t)V * kRaRow);
 }
 
 // ---- CFAR ------------------------------------------------------------------
@@ -832,6 +1105,48 @@ static int launch_doppler(const float2 *in, float2 *out, int V, int C, int S, in
     return SBR_OK;
 }
 
+// Launch an angle-stage kernel template K<VB, EXACT> for V antennas: the
+// exact instance for V <= kAngleExact, else the guarded one with room for
+// kAngleVMax.
+constexpr int kAngleExact = 16;
+
+template <template <int, bool> class K, int VV = 1>
+struct AngleDispatch {
+    template <typename... A>
+    static void run(int V, dim3 grid, size_t lds, hipStream_t s, A... args) {
+        if (V == VV)
+            K<VV, true>::launch(grid, lds, s, args...);
+        else
+            AngleDispatch<K, VV + 1>::run(V, grid, lds, s, args...);
+    }
+};
+template <template <int, bool> class K>
+struct AngleDispatch<K, kAngleExact + 1> {
+    template <typename... A>
+    static void run(int, dim3 grid, size_t lds, hipStream_t s, A... args) {
+        K<kAngleVMax, false>::launch(grid, lds, s, args...);
+    }
+};
+
+template <int VB, bool EXACT>
+struct AngleFwd {
+    static void launch(dim3 grid, size_t lds, hipStream_t s, const float2 *in, float2 *out, int V, int Na,
+                       long long CS) {
+        hipLaunchKernelGGL((k_angle<VB, EXACT>), grid, dim3(256), lds, s, in, out, V, Na, CS);
+    }
+};
+
+template <int VB, bool EXACT>
+struct RangeAngle {
+    static void launch(dim3 grid, size_t lds, hipStream_t s, const float2 *in, float2 *out, int V, int C, int Na,
+                       int window) {
+        // the guarded instance of the dispatcher (V > kAngleExact) is never
+        // launched: the fused path takes at most kRaVMax = kAngleExact rows
+        if constexpr (EXACT) hipLaunchKernelGGL((k_range_angle<VB, true>), grid, dim3(256), lds, s, in, out, V, C, Na,
+                                                window);
+    }
+};
+
 // Angle stage of a linear array: direct DFT for V <= 32, else the dense
 // contraction.  dir 0: [V][CS] -> [Na][CS]; dir 1: [Na][CS] -> [V][CS].
 static int launch_angle(const float2 *in, float2 *out, int V, int Na, long long CS, int dir, hipStream_t s) {
@@ -839,14 +1154,17 @@ static int launch_angle(const float2 *in, float2 *out, int V, int Na, long long 
         if (dir == 0) return launch_mid(in, out, 1, V, Na, Na, (int)CS, -1, 0, 0, s);
         return launch_mid(in, out, 1, Na, V, Na, (int)CS, +1, 0, 0, s);
     }
-    // split the angles of the forward stage over block rows so that small
-    // cubes still fill the chip
-    const long long bx = (CS + 255) / 256;
-    int groups = dir == 0 ? (int)std::max(1LL, std::min<long long>(Na, 512 / std::max(1LL, bx))) : 1;
-    const int a_per = (Na + groups - 1) / groups;
-    groups = (Na + a_per - 1) / a_per;
-    hipLaunchKernelGGL(k_angle, dim3((unsigned)bx, (unsigned)groups), dim3(256), sizeof(float2) * Na, s, in, out, V,
-                       Na, CS, dir, a_per);
+    const unsigned bx = (unsigned)((CS + 255) / 256);
+    if (dir == 0) {
+        const dim3 grid(bx, (unsigned)((Na + kAngleGroup - 1) / kAngleGroup));
+        AngleDispatch<AngleFwd>::run(V, grid, 0, s, in, out, V, Na, CS);
+    } else {
+        if (V <= 16)
+            hipLaunchKernelGGL(k_angle_adj<16>, dim3(bx), dim3(256), sizeof(float2) * Na, s, in, out, V, Na, CS);
+        else
+            hipLaunchKernelGGL(k_angle_adj<kAngleVMax>, dim3(bx), dim3(256), sizeof(float2) * Na, s, in, out, V,
+                               Na, CS);
+    }
     SBR_LAUNCHED();
     return SBR_OK;
 }
@@ -864,6 +1182,26 @@ int radar_cube2_launch(const float2 *in, int Vx, int Vy, int C, int S, int Nax, 
     const int V = Vx * Vy, CS = C * S;
     const bool planar = Vy > 1 || Nay > 1;
     int rc;
+    static_assert(kRaVMax == kAngleExact, "fused rows are dispatched by exact antenna count");
+    if (dir == 0 && !planar && Vx <= kRaVMax && S == kRaS && log2_exact(C) >= 0) {
+        // Doppler first, then range and angle in one pass per Doppler bin
+        const int P = C / 16;
+        const bool reg = C % 16 == 0 && (P == 2 || P == 4 || P == 8 || P == 16);
+        if (reg) {
+            const unsigned blocks = (unsigned)V * (unsigned)((S + kDopThreads / P - 1) / (kDopThreads / P));
+            if (P == 2) hipLaunchKernelGGL(k_doppler<2>, dim3(blocks), dim3(kDopThreads), 0, s, in, y1, S, window);
+            if (P == 4) hipLaunchKernelGGL(k_doppler<4>, dim3(blocks), dim3(kDopThreads), 0, s, in, y1, S, window);
+            if (P == 8) hipLaunchKernelGGL(k_doppler<8>, dim3(blocks), dim3(kDopThreads), 0, s, in, y1, S, window);
+            if (P == 16) hipLaunchKernelGGL(k_doppler<16>, dim3(blocks), dim3(kDopThreads), 0, s, in, y1, S, window);
+        } else if ((rc = launch_doppler(in, y1, V, C, S, -1, window, 0, s))) {
+            return rc;
+        }
+        const dim3 grid((unsigned)C, (unsigned)((Nax + kRangeAngleBins - 1) / kRangeAngleBins));
+        AngleDispatch<RangeAngle>::run(Vx, grid, range_angle_lds(Vx), s, (const float2 *)y1, out, Vx, C, Nax,
+                                       window);
+        SBR_LAUNCHED();
+        return SBR_OK;
+    }
     if (dir == 0) {
         if ((rc = launch_range(in, y1, V * C, S, -1, window, 0, s))) return rc;
         if ((rc = launch_doppler(y1, y2, V, C, S, -1, window, 0, s))) return rc;

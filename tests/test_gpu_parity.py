@@ -171,13 +171,21 @@ def test_empty_grid_and_all_miss(torch_cuda, orc):
 
 
 # ----------------------------------------------------------------- radar cube + CFAR
-@pytest.mark.parametrize("shape,window", [((12, 16, 64), 0), ((5, 7, 40), 1), ((12, 128, 256), 0),
-                                          ((12, 128, 256), 1), ((3, 1024, 32), 1), ((33, 8, 16), 0),
-                                          ((2, 4, 2048), 1), ((1, 2, 2), 0)])
-def test_radar_cube_vs_naive_dft(torch_cuda, orc, shape, window):
+@pytest.mark.parametrize("shape,window,na", [((12, 16, 64), 0, 64), ((5, 7, 40), 1, 64), ((12, 128, 256), 0, 64),
+                                             ((12, 128, 256), 1, 64), ((3, 1024, 32), 1, 64), ((33, 8, 16), 0, 64),
+                                             ((2, 4, 2048), 1, 64), ((1, 2, 2), 0, 64), ((20, 16, 64), 1, 64),
+                                             ((12, 16, 64), 0, 37), ((16, 8, 32), 1, 16), ((1, 32, 256), 0, 64),
+                                             ((4, 64, 256), 1, 37), ((2, 256, 256), 1, 64), ((16, 128, 256), 0, 64),
+                                             ((17, 128, 256), 1, 64)])
+def test_radar_cube_vs_naive_dft(torch_cuda, orc, shape, window, na):
     """Power-of-two range / Doppler lengths up to 1024 run as FFTs, others
     (and 2048) as dense contractions; up to 32 antennas take the direct angle
-    stage, more the dense one."""
+    stage (an instance per antenna count up to 16, a guarded one up to 32;
+    angle bins in groups of 8, so counts that are not a multiple of 8 leave a
+    partial group), more the dense one.  The forward map of up to 16 antennas
+    with 256 samples and 32, 64, 128 or 256 chirps runs as the register
+    Doppler FFT and the fused range + angle stage (one Doppler bin per block
+    row, 16 angle bins per block); 17 antennas take the staged form."""
     import torch
     V, C, Sn = shape
     rng = np.random.default_rng(3)
@@ -185,16 +193,19 @@ def test_radar_cube_vs_naive_dft(torch_cuda, orc, shape, window):
     sc = S.icosphere_scene(level=1, n_rays=8, n_chirps=C).with_chirp(n_samples=Sn)
     sc = dataclasses.replace(sc, radar=S.default_radar(1, V) if V <= 20 else S.default_radar(3, V // 3))
     assert sc.radar.n_virtual == V
-    sim = _sim(sc)
+    from paper_2311_13182_amd.sbr import Simulator
+    sim = Simulator(sc, "cuda", n_angle=na)
+    assert sim.n_angle == max(na, V)
+    na = sim.n_angle
     X = sim.radar_cube(torch.as_tensor(x, device="cuda"), window=window)
     torch.cuda.synchronize()
-    ref = orc.radar_cube(x.astype(np.complex128), n_angle=64, window=window)
+    ref = orc.radar_cube(x.astype(np.complex128), n_angle=na, window=window)
     e = rel_l2(X.cpu().numpy(), ref)
-    log(f"cube {shape} w={window}: rel L2 {e:.3e}")
+    log(f"cube {shape} -> {na} angles, w={window}: rel L2 {e:.3e}")
     assert e <= CUBE_TOL
-    y = (rng.normal(size=(64, C, Sn)) + 1j * rng.normal(size=(64, C, Sn))).astype(np.complex64)
+    y = (rng.normal(size=(na, C, Sn)) + 1j * rng.normal(size=(na, C, Sn))).astype(np.complex64)
     Y = sim.radar_cube(torch.as_tensor(y, device="cuda"), direction=1, window=window)
-    refa = orc.radar_cube(y.astype(np.complex128), n_angle=64, window=window, direction=1, V=V)
+    refa = orc.radar_cube(y.astype(np.complex128), n_angle=na, window=window, direction=1, V=V)
     ea = rel_l2(Y.cpu().numpy(), refa)
     assert ea <= CUBE_TOL
     lhs = np.vdot(y.astype(np.complex128), X.cpu().numpy().astype(np.complex128))
