@@ -429,6 +429,42 @@ size_t sbr_batch_table_bytes(int32_t n_requests) {
     return std::max(synth_table_bytes(n_requests), adj_table_bytes(n_requests));
 }
 
+// Batched calls: no two requests may write the same device bytes (scratch,
+// IF cube, gradient).  The written ranges are sorted by start address and
+// neighbours compared; a shared range is an argument error naming both.
+namespace {
+struct Span {
+    uintptr_t lo, hi;
+    int req;
+    const char *what;
+};
+
+int check_disjoint(std::vector<Span> &sp) {
+    std::sort(sp.begin(), sp.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    uintptr_t end = 0;
+    int owner = -1;
+    const char *what = "";
+    for (const Span &x : sp) {
+        if (x.hi <= x.lo) continue;
+        if (owner >= 0 && x.lo < end && x.req != owner) {
+            set_error("requests %d and %d share device memory (%s of %d overlaps %s of %d)", owner, x.req, what,
+                      owner, x.what, x.req);
+            return SBR_E_ARG;
+        }
+        if (x.hi > end || owner < 0) {
+            end = x.hi;
+            owner = x.req;
+            what = x.what;
+        }
+    }
+    return SBR_OK;
+}
+
+size_t cube_bytes_of(const sbr_request &q) {
+    return (size_t)q.radar->n_tx * q.radar->n_rx * q.chirp->n_chirps * q.chirp->n_samples * 2 * sizeof(float);
+}
+}  // namespace
+
 int sbr_synth_if_batched(const sbr_request *reqs, int32_t n, void *table, size_t table_bytes, void *stream) {
     clear_error();
     SBR_CHECK_ARG(n >= 0 && n <= SBR_MAX_BATCH, "n=%d out of [0, %d]", n, SBR_MAX_BATCH);
@@ -448,6 +484,15 @@ int sbr_synth_if_batched(const sbr_request *reqs, int32_t n, void *table, size_t
             set_error("request %d: %s", i, msg.c_str());
             return rc;
         }
+    }
+    {
+        std::vector<Span> sp;
+        for (int i = 0; i < n; i++) {
+            const sbr_request &q = reqs[i];
+            sp.push_back({(uintptr_t)q.scratch, (uintptr_t)q.scratch + q.scratch_bytes, i, "scratch"});
+            sp.push_back({(uintptr_t)q.if_cube, (uintptr_t)q.if_cube + cube_bytes_of(q), i, "if_cube"});
+        }
+        if ((rc = check_disjoint(sp))) return rc;
     }
     hipStream_t s = (hipStream_t)stream;
     std::vector<SynthArgs> args;
@@ -487,6 +532,16 @@ int sbr_backward_batched(const sbr_request *reqs, int32_t n, void *table, size_t
             set_error("request %d: %s", i, msg.c_str());
             return rc;
         }
+    }
+    {
+        std::vector<Span> sp;
+        for (int i = 0; i < n; i++) {
+            const sbr_request &q = reqs[i];
+            sp.push_back({(uintptr_t)q.scratch, (uintptr_t)q.scratch + q.scratch_bytes, i, "scratch"});
+            sp.push_back({(uintptr_t)q.grad_verts, (uintptr_t)q.grad_verts + (size_t)q.mesh->nv * 3 * sizeof(float),
+                          i, "grad_verts"});
+        }
+        if ((rc = check_disjoint(sp))) return rc;
     }
     hipStream_t s = (hipStream_t)stream;
     std::vector<BackwardReq> qs;

@@ -1110,40 +1110,43 @@ static int launch_doppler(const float2 *in, float2 *out, int V, int C, int S, in
 // kAngleVMax.
 constexpr int kAngleExact = 16;
 
+// run() returns whether a kernel was launched.
 template <template <int, bool> class K, int VV = 1>
 struct AngleDispatch {
     template <typename... A>
-    static void run(int V, dim3 grid, size_t lds, hipStream_t s, A... args) {
-        if (V == VV)
-            K<VV, true>::launch(grid, lds, s, args...);
-        else
-            AngleDispatch<K, VV + 1>::run(V, grid, lds, s, args...);
+    static bool run(int V, dim3 grid, size_t lds, hipStream_t s, A... args) {
+        if (V == VV) return K<VV, true>::launch(grid, lds, s, args...);
+        return AngleDispatch<K, VV + 1>::run(V, grid, lds, s, args...);
     }
 };
 template <template <int, bool> class K>
 struct AngleDispatch<K, kAngleExact + 1> {
     template <typename... A>
-    static void run(int, dim3 grid, size_t lds, hipStream_t s, A... args) {
-        K<kAngleVMax, false>::launch(grid, lds, s, args...);
+    static bool run(int, dim3 grid, size_t lds, hipStream_t s, A... args) {
+        return K<kAngleVMax, false>::launch(grid, lds, s, args...);
     }
 };
 
 template <int VB, bool EXACT>
 struct AngleFwd {
-    static void launch(dim3 grid, size_t lds, hipStream_t s, const float2 *in, float2 *out, int V, int Na,
+    static bool launch(dim3 grid, size_t lds, hipStream_t s, const float2 *in, float2 *out, int V, int Na,
                        long long CS) {
         hipLaunchKernelGGL((k_angle<VB, EXACT>), grid, dim3(256), lds, s, in, out, V, Na, CS);
+        return true;
     }
 };
 
 template <int VB, bool EXACT>
 struct RangeAngle {
-    static void launch(dim3 grid, size_t lds, hipStream_t s, const float2 *in, float2 *out, int V, int C, int Na,
+    static bool launch(dim3 grid, size_t lds, hipStream_t s, const float2 *in, float2 *out, int V, int C, int Na,
                        int window) {
-        // the guarded instance of the dispatcher (V > kAngleExact) is never
-        // launched: the fused path takes at most kRaVMax = kAngleExact rows
-        if constexpr (EXACT) hipLaunchKernelGGL((k_range_angle<VB, true>), grid, dim3(256), lds, s, in, out, V, C, Na,
-                                                window);
+        // the fused kernel holds at most kRaVMax = kAngleExact rows: there is
+        // no guarded instance, and the caller reports the miss
+        if constexpr (EXACT) {
+            hipLaunchKernelGGL((k_range_angle<VB, true>), grid, dim3(256), lds, s, in, out, V, C, Na, window);
+            return true;
+        }
+        return false;
     }
 };
 
@@ -1157,7 +1160,7 @@ static int launch_angle(const float2 *in, float2 *out, int V, int Na, long long 
     const unsigned bx = (unsigned)((CS + 255) / 256);
     if (dir == 0) {
         const dim3 grid(bx, (unsigned)((Na + kAngleGroup - 1) / kAngleGroup));
-        AngleDispatch<AngleFwd>::run(V, grid, 0, s, in, out, V, Na, CS);
+        (void)AngleDispatch<AngleFwd>::run(V, grid, 0, s, in, out, V, Na, CS);   // every count has an instance
     } else {
         if (V <= 16)
             hipLaunchKernelGGL(k_angle_adj<16>, dim3(bx), dim3(256), sizeof(float2) * Na, s, in, out, V, Na, CS);
@@ -1197,8 +1200,11 @@ int radar_cube2_launch(const float2 *in, int Vx, int Vy, int C, int S, int Nax, 
             return rc;
         }
         const dim3 grid((unsigned)C, (unsigned)((Nax + kRangeAngleBins - 1) / kRangeAngleBins));
-        AngleDispatch<RangeAngle>::run(Vx, grid, range_angle_lds(Vx), s, (const float2 *)y1, out, Vx, C, Nax,
-                                       window);
+        if (!AngleDispatch<RangeAngle>::run(Vx, grid, range_angle_lds(Vx), s, (const float2 *)y1, out, Vx, C, Nax,
+                                            window)) {
+            set_error("fused range + angle stage has no instance for %d antennas", Vx);
+            return SBR_E_UNSUPPORTED;
+        }
         SBR_LAUNCHED();
         return SBR_OK;
     }

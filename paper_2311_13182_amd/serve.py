@@ -82,6 +82,7 @@ class Scheduler:
         self._pending: Deque = collections.deque()
         self._active: List = []
         self._used = 0
+        self._admitting = 0          # requests taken off the queue, not yet in _active or finished
         self._footprints: Dict[int, int] = {}
         self._lock = threading.Lock()
         self._stop = threading.Event()
@@ -131,7 +132,16 @@ class Scheduler:
                 req, fut = self._pending[0]
                 fp = self._footprints.get(req.rid)
                 if fp is None:
-                    fp = self._footprints[req.rid] = self.ex.footprint(req)
+                    try:
+                        fp = self._footprints[req.rid] = int(self.ex.footprint(req))
+                    except Exception as e:   # a request that cannot be sized fails alone
+                        self._pending.popleft()
+                        res = Result(req.rid, "failed", t_arrival=req.arrival, t_done=now,
+                                     error=f"footprint: {e!r}")
+                        self.log.append(res)
+                        fut.set_result(res)
+                        progressed = True
+                        continue
                 if fp > self.budget:
                     self._pending.popleft()
                     res = Result(req.rid, "rejected", t_arrival=req.arrival, t_done=now, footprint=fp,
@@ -148,10 +158,15 @@ class Scheduler:
                     if self._used + fp + self.resident_bytes() > self.budget:
                         break
                 self._pending.popleft()
+                self._admitting += 1
             self._used += fp
             admitted.append((req, fut, fp))
         if admitted:
-            self._launch(admitted)
+            try:
+                self._launch(admitted)
+            finally:
+                with self._lock:
+                    self._admitting -= len(admitted)
             progressed = True
         return progressed
 
@@ -211,7 +226,7 @@ class Scheduler:
 
     def idle(self) -> bool:
         with self._lock:
-            return not self._pending and not self._active
+            return not self._pending and not self._admitting and not self._active
 
     @property
     def used_bytes(self) -> int:

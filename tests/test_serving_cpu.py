@@ -232,3 +232,41 @@ def test_failed_batch_falls_back_to_single_launches():
     assert fa.result().status == "failed" and "launch failed" in fa.result().error
     assert fb.result().status == "ok"
     assert sch.used_bytes == 0
+
+
+def test_request_that_cannot_be_sized_fails_alone():
+    clock = Clock()
+
+    class Picky(FakeExecutor):
+        def footprint(self, req):
+            if getattr(req.scene, "unsizable", False):
+                raise ValueError("no footprint (forced)")
+            return req.scene.fp
+
+    ex = Picky(clock)
+    sch = Scheduler(ex, budget_bytes=100, clock=clock)
+    fa = sch.submit(_req(0, 10, 0.01, arrival=0.0005, unsizable=True))
+    fb = sch.submit(_req(1, 10, 0.01, arrival=0.0006))
+    _run(sch, clock, 0.1)
+    assert fa.result().status == "failed" and "no footprint" in fa.result().error
+    assert fb.result().status == "ok"
+    assert sch.used_bytes == 0 and sch.idle()
+
+
+def test_idle_is_false_while_a_batch_is_being_launched():
+    """A request taken off the queue counts as work until it is active, so a
+    draining stop() cannot end the loop between the two."""
+    clock = Clock()
+    seen = []
+
+    class Watch(BatchExecutor):
+        def launch_batch(self, reqs):
+            seen.append(sch.idle())
+            return super().launch_batch(reqs)
+
+    ex = Watch(clock)
+    sch = Scheduler(ex, budget_bytes=1000, clock=clock)
+    futs = [sch.submit(_req(i, 10, 0.01, arrival=0.0005)) for i in range(3)]
+    _run(sch, clock, 0.1)
+    assert seen == [False]
+    assert all(f.result().status == "ok" for f in futs)
