@@ -581,19 +581,24 @@ __global__ __launch_bounds__(kDopThreads) void k_doppler(const float2 *in, float
 // the 16-point DFT over t, giving range bin k1 + 16 k2.  LDS rows are padded
 // (kRaRow) and the exchange uses a stride of 17, so neither access pattern
 // has lanes on one bank.  Then one thread per range bin s writes out[a][k][s]
-// for the block's kRangeAngleBins angle bins by Horner's rule over the
-// antennas, in passes of kAngleGroup bins (coalesced rows of 256 values).
+// for the block's kRangeAngleBins angle bins (coalesced rows of 256 values).
+// When Na = 16 q, bins a = a1 + q a2 (a2 < 16) are the 16-point DFT over v
+// (zero-padded) of y_v e^{-2 pi j a1 v / Na}; block row y takes a1 in
+// [y kRaSplit, (y + 1) kRaSplit).  Other angle counts take kRangeAngleBins
+// consecutive bins per block row by Horner's rule over the antennas, in
+// passes of kAngleGroup bins.
 constexpr int kRaS = 256;              // samples per row
 constexpr int kRaRow = 16 * 17;        // padded LDS row (complex values)
 constexpr int kRaVMax = 16;            // rows (antennas) of one block
 constexpr int kRangeAngleBins = 16;    // angle bins per block
+constexpr int kRaSplit = kRangeAngleBins / 16;   // 16-point angle DFTs per block (split form)
 
 template <int VB, bool EXACT>
 __global__ __launch_bounds__(256) void k_range_angle(const float2 *in, float2 *out, int V, int C, int Na,
                                                      int window) {
     extern __shared__ float2 sm[];
     float2 *tw = sm;                              // e^{-2 pi j i / 256}
-    float2 *wa = tw + kRaS;                       // angle steps of the block's bins
+    float2 *wa = tw + kRaS;                       // angle steps, or the antenna twiddles of a1
     float *wt = reinterpret_cast<float *>(wa + kRangeAngleBins);
     float2 *buf = wa + kRangeAngleBins + kRaS / 2;   // V rows of kRaRow
     const int k = blockIdx.x, a_lo = blockIdx.y * kRangeAngleBins, tid = threadIdx.x;
@@ -611,7 +616,10 @@ __global__ __launch_bounds__(256) void k_range_angle(const float2 *in, float2 *o
         tw[tid] = make_float2(cs, -sn);
         wt[tid] = window == 1 ? 0.5f - 0.5f * cospif(2.0f * (float)tid / (float)(kRaS - 1)) : 1.0f;
         if (tid < kRangeAngleBins) {
-            sincospif(2.0f * (float)(a_lo + tid) / (float)Na, &sn, &cs);
+            // split form: e^{-2 pi j a1 v / Na} for antenna v = tid % 16 of the
+            // block's a1 = blockIdx.y kRaSplit + tid / 16
+            const int e = Na % 16 == 0 ? ((int)blockIdx.y * kRaSplit + tid / 16) * (tid % 16) % Na : a_lo + tid;
+            sincospif(2.0f * (float)e / (float)Na, &sn, &cs);
             wa[tid] = make_float2(cs, -sn);
         }
     }
@@ -645,6 +653,23 @@ __global__ __launch_bounds__(256) void k_range_angle(const float2 *in, float2 *o
     for (int a = 0; a < VB; a++)
         if (EXACT || a < V) yv[a] = buf[a * kRaRow + sb];
     const size_t plane = (size_t)C * kRaS;
+    if (Na % 16 == 0) {
+        static_assert(kRangeAngleBins % 16 == 0 && VB <= 16, "split form: 16-point DFTs over the antennas");
+        const int q = Na / 16;
+        for (int j = 0; j < kRaSplit; j++) {
+            const int a1 = (int)blockIdx.y * kRaSplit + j;
+            if (a1 >= q) break;
+            float2 z[16];
+#pragma unroll
+            for (int v = 0; v < 16; v++)
+                z[v] = v >= VB || !(EXACT || v < V) ? make_float2(0.0f, 0.0f)
+                                                     : v == 0 ? yv[0] : cmul2(yv[v], wa[16 * j + v]);
+            dft16(z);
+#pragma unroll
+            for (int a2 = 0; a2 < 16; a2++) out[(size_t)(a1 + q * a2) * plane + (size_t)k * kRaS + sb] = z[a2];
+        }
+        return;
+    }
     for (int g = 0; g < kRangeAngleBins; g += kAngleGroup) {
         const int a0 = a_lo + g;
         if (a0 >= Na) break;
