@@ -17,6 +17,8 @@ simulations of many requests on one GPU with continuous batching.
   meshes (same vertices, faces and materials) reuse a cached device copy: a
   request that hits the cache waits (on the device) for the event that ends
   the copy's upload and build on the stream that made it.
+* An optional per-request timeout fails a request that stays active too long
+  and releases what it holds.
 * Each request's launch shapes depend only on its own sizes, so its forward
   result is bit-identical alone and in the mix (the backward differs only in
   the order of floating-point atomics).
@@ -73,10 +75,15 @@ class Result:
 class Scheduler:
     """Admission + continuous batching over an executor.  Thread-safe submit."""
 
-    def __init__(self, executor, budget_bytes: int, max_active: int = 16, clock=time.perf_counter):
+    def __init__(self, executor, budget_bytes: int, max_active: int = 16, clock=time.perf_counter,
+                 request_timeout: Optional[float] = None):
+        """request_timeout: seconds a request may stay active (admitted, not
+        finished) before it is failed and its resources released; None waits
+        for ever."""
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
+        self.request_timeout = request_timeout
         self.clock = clock
         self.t0 = clock()
         self._pending: Deque = collections.deque()
@@ -110,6 +117,11 @@ class Scheduler:
                 done = self.ex.poll(h)
             except Exception as e:   # device-side failure of this request only
                 self._finish(req, fut, h, fp, t_admit, None, e)
+                progressed = True
+                continue
+            if not done and self.request_timeout is not None and self.now() - t_admit > self.request_timeout:
+                self._finish(req, fut, h, fp, t_admit, None,
+                             TimeoutError(f"request {req.rid} active for more than {self.request_timeout} s"))
                 progressed = True
                 continue
             if done:

@@ -270,3 +270,21 @@ def test_idle_is_false_while_a_batch_is_being_launched():
     _run(sch, clock, 0.1)
     assert seen == [False]
     assert all(f.result().status == "ok" for f in futs)
+
+
+def test_request_that_never_completes_times_out_and_frees_memory():
+    clock = Clock()
+
+    class Stuck(FakeExecutor):
+        def poll(self, h):
+            return False if getattr(h.req.scene, "stuck", False) else super().poll(h)
+
+    ex = Stuck(clock)
+    sch = Scheduler(ex, budget_bytes=100, clock=clock, request_timeout=0.05)
+    fa = sch.submit(_req(0, 60, 0.01, arrival=0.0005, stuck=True))
+    fb = sch.submit(_req(1, 60, 0.01, arrival=0.0006))   # waits for the stuck one's memory
+    _run(sch, clock, 0.2)
+    ra, rb = fa.result(), fb.result()
+    assert ra.status == "failed" and "TimeoutError" in ra.error
+    assert rb.status == "ok" and rb.t_admit >= ra.t_done - 1e-9
+    assert sch.used_bytes == 0 and not ex.live
