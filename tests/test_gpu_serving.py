@@ -97,6 +97,55 @@ def test_batched_entry_points_equal_single_calls(torch_cuda, orc):
     assert float(gb[4].abs().max()) == 0.0 and float(gb[5].abs().max()) == 0.0
 
 
+def test_batch_of_the_maximum_size(torch_cuda):
+    """SBR_MAX_BATCH requests in one batched call (every kernel form of the
+    synthesis, requests sharing traced inputs but not scratch or outputs):
+    each cube equals the single call bit for bit, each gradient within 1e-5."""
+    torch = torch_cuda
+    from paper_2311_13182_amd import _lib as L
+    from paper_2311_13182_amd.sbr import (Simulator, sbr_backward, sbr_backward_batched, sbr_batch_table_bytes,
+                                          sbr_synth_if, sbr_synth_if_batched)
+    base = S.trihedral_plate().with_grid(nx=16, ny=16)
+    variants = [base.with_chirp(n_samples=n, n_chirps=c) for n, c in ((256, 2), (200, 1), (48, 3), (20, 2))]
+    sims = [Simulator(sc, "cuda", cube=False) for sc in variants]
+    rng = np.random.default_rng(12)
+    single, single_g, G = [], [], []
+    for sim in sims:
+        sim.trace()
+        a = torch.empty((sim.V, sim.C, sim.S, 2), dtype=torch.float32, device="cuda")
+        sbr_synth_if(sim.mesh, sim.scene.radar, sim.scene.grid, sim.hits, sim.scene.chirp, sim.flags, a, sim.scratch)
+        single.append(a)
+        g = torch.as_tensor(rng.normal(size=(sim.V, sim.C, sim.S, 2)).astype(np.float32), device="cuda")
+        G.append(g)
+        gv = torch.zeros((sim.mesh.nv, 3), device="cuda")
+        sbr_backward(sim.mesh, sim.scene.radar, sim.scene.grid, sim.hits, sim.scene.chirp, sim.flags, g, gv,
+                     sim.scratch)
+        single_g.append(gv)
+    n = L.SBR_MAX_BATCH
+    which = [i % len(sims) for i in range(n)]
+    scratch = [torch.empty_like(sims[w].scratch) for w in which]
+    cubes = [torch.full_like(single[w], float("nan")) for w in which]
+    grads = [torch.zeros_like(single_g[w]) for w in which]
+    table = torch.empty(sbr_batch_table_bytes(n), dtype=torch.uint8, device="cuda")
+    items = []
+    for w, sc_, cb in zip(which, scratch, cubes):
+        sm = sims[w]
+        items.append((sm.mesh, sm.scene.radar, sm.scene.grid, sm.hits, sm.scene.chirp, sm.flags, cb, sc_))
+    sbr_synth_if_batched(items, table)
+    bitems = []
+    for w, sc_, gv in zip(which, scratch, grads):
+        sm = sims[w]
+        bitems.append((sm.mesh, sm.scene.radar, sm.scene.grid, sm.hits, sm.scene.chirp, sm.flags, G[w], gv, sc_))
+    sbr_backward_batched(bitems, table)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, w in enumerate(which):
+        assert torch.equal(cubes[i].view(torch.int32), single[w].view(torch.int32)), f"request {i}: cube differs"
+        worst = max(worst, rel_l2(grads[i].cpu().numpy(), single_g[w].cpu().numpy()))
+    log(f"batch of {n}: every cube bit-exact with its single call; gradients within {worst:.2e}")
+    assert worst <= 1e-5 and all(float(g.abs().max()) > 0 for g in single_g)
+
+
 def _small_requests(n=10, seed=77):
     return S.serving_requests(n=n, qps=1.0, seed=seed, grids=(48, 64, 96), nf_range=(300, 3000), chirps=(4, 8))
 

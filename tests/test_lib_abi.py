@@ -129,6 +129,7 @@ def test_argument_errors_are_reported(lib):
     rc = lib.sbr_backward_batched(reqs, 2, fake, 1 << 20, None)
     assert rc == L.SBR_E_ARG and b"request 0" in lib.sbr_last_error() and b"max_bounces" in lib.sbr_last_error()
     assert lib.sbr_synth_if_batched(reqs, -1, fake, 1 << 20, None) == L.SBR_E_ARG
+    assert lib.sbr_backward_batched(reqs, L.SBR_MAX_BATCH + 1, fake, 1 << 30, None) == L.SBR_E_ARG
     # two valid requests that write the same device bytes are refused before anything is enqueued
     reqs[0].rays = ct.pointer(g)
     for fn in (lib.sbr_synth_if_batched, lib.sbr_backward_batched):
