@@ -234,8 +234,10 @@ int sbr_synth_if(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats,
  * direction 0: in [V][C][S][2] -> out [Na][C][S][2].  direction 1 applies the
  * conjugate transpose: in [Na][C][S][2] -> out [V][C][S][2] (the gradient of
  * a real loss with respect to S, given its gradient with respect to X).
- * Each axis is a dense FP32 contraction with its DFT matrix on the matrix
- * cores.  V, C, S and n_angle are each at most 4096; scratch:
+ * FP32 throughout: power-of-two range and Doppler lengths run as FFTs, other
+ * lengths as dense contractions with the DFT matrix on the matrix cores;
+ * results agree with the direct sum to FP32 rounding, not bit for bit across
+ * shapes.  V, C, S and n_angle are each at most 4096; scratch:
  * sbr_scratch_bytes(SBR_OP_RADAR_CUBE, ...) for n_angle = max(64, V), else
  * sbr_radar_cube_2d_bytes(V, 1, C, S, n_angle, 1). */
 int sbr_radar_cube(const float *in, int32_t V, int32_t C, int32_t S, int32_t n_angle,
