@@ -540,6 +540,17 @@ int sbr_backward_batched(const sbr_request *reqs, int32_t n, void *table, size_t
             sp.push_back({(uintptr_t)q.scratch, (uintptr_t)q.scratch + q.scratch_bytes, i, "scratch"});
             sp.push_back({(uintptr_t)q.grad_verts, (uintptr_t)q.grad_verts + (size_t)q.mesh->nv * 3 * sizeof(float),
                           i, "grad_verts"});
+            if (q.params) {
+                const sbr_param_grads &g = *q.params;
+                const size_t nm = (size_t)(q.mats ? q.n_mats : 0);
+                sp.push_back({(uintptr_t)g.materials, (uintptr_t)g.materials + (g.materials ? 2 * nm * sizeof(float) : 0),
+                              i, "params.materials"});
+                sp.push_back({(uintptr_t)g.radar, (uintptr_t)g.radar + (g.radar ? 6 * sizeof(float) : 0), i,
+                              "params.radar"});
+                sp.push_back({(uintptr_t)g.rot, (uintptr_t)g.rot + (g.rot ? 9 * sizeof(float) : 0), i, "params.rot"});
+                sp.push_back({(uintptr_t)g.attenuation, (uintptr_t)g.attenuation + (g.attenuation ? sizeof(float) : 0),
+                              i, "params.attenuation"});
+            }
         }
         if ((rc = check_disjoint(sp))) return rc;
     }

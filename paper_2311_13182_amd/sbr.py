@@ -280,19 +280,27 @@ def sbr_cfar(cube: torch.Tensor, Na: int, C: int, Sn: int, guard: int, train: in
                             scratch.numel() * scratch.element_size(), _stream()))
 
 
+def _param_grads(mesh: DeviceMesh, bufs) -> Optional[L.sbr_param_grads]:
+    """sbr_param_grads for (materials, radar, rot, attenuation) gradient
+    buffers (each None or contiguous float32 device memory of 2 n_mats, 6, 9
+    and 1 elements), or None when all are None."""
+    if bufs is None or all(t is None for t in bufs):
+        return None
+    for t, n in zip(bufs, (2 * len(mesh.materials or []), 6, 9, 1)):
+        if t is not None:
+            _buf(t, torch.float32, n, "parameter gradient")
+            if t.numel() != n:
+                raise ValueError(f"parameter gradient buffer must be contiguous float32 with {n} elements")
+    return L.sbr_param_grads(*[t.data_ptr() if t is not None else None for t in bufs])
+
+
 def sbr_backward(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: S.Chirp, flags: int,
                  grad_if: torch.Tensor, grad_verts: torch.Tensor, scratch: torch.Tensor,
                  grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,
                  grad_rot: Optional[torch.Tensor] = None, grad_atten: Optional[torch.Tensor] = None):
     m, r, g, h, c = mesh.struct(), radar_struct(radar), rays_struct(rays), hits.struct(), chirp_struct(chirp)
     mats, nm = materials_struct(mesh.materials)
-    pg = None
-    bufs = (grad_materials, grad_radar, grad_rot, grad_atten)
-    if any(t is not None for t in bufs):
-        for t, n in zip(bufs, (2 * len(mesh.materials or []), 6, 9, 1)):
-            if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n):
-                raise ValueError(f"parameter gradient buffer must be contiguous float32 with {n} elements")
-        pg = L.sbr_param_grads(*[t.data_ptr() if t is not None else None for t in bufs])
+    pg = _param_grads(mesh, (grad_materials, grad_radar, grad_rot, grad_atten))
     _check_hits(hits, rays.max_bounces, rays.nx * rays.ny)
     gi = _buf(grad_if, torch.float32, 2 * radar.n_virtual * chirp.n_chirps * chirp.n_samples, "grad_if")
     gv = _buf(grad_verts, torch.float32, 3 * mesh.nv, "grad_verts")
@@ -320,7 +328,8 @@ def sbr_batch_table_bytes(n: int) -> int:
 
 def _request(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: S.Chirp, flags: int,
              scratch: torch.Tensor, keep: list, if_cube: Optional[torch.Tensor] = None,
-             grad_if: Optional[torch.Tensor] = None, grad_verts: Optional[torch.Tensor] = None) -> L.sbr_request:
+             grad_if: Optional[torch.Tensor] = None, grad_verts: Optional[torch.Tensor] = None,
+             params=None) -> L.sbr_request:
     """One sbr_request after the buffer checks of the single-request calls;
     `keep` holds the ctypes structs it points to for the duration of the call."""
     V, C, Sn = radar.n_virtual, chirp.n_chirps, chirp.n_samples
@@ -338,6 +347,10 @@ def _request(mesh: DeviceMesh, radar: S.Radar, rays: S.Grid, hits: Hits, chirp: 
     q.grad_verts = _buf(grad_verts, torch.float32, 3 * mesh.nv, "grad_verts") if grad_verts is not None else None
     q.scratch = _buf(scratch, torch.uint8, 0, "scratch")
     q.scratch_bytes = scratch.numel() * scratch.element_size()
+    pg = _param_grads(mesh, params)
+    if pg is not None:
+        keep.append(pg)
+        q.params = ct.pointer(pg)
     return q
 
 
@@ -354,12 +367,15 @@ def sbr_synth_if_batched(items: Sequence[tuple], table: torch.Tensor):
 
 def sbr_backward_batched(items: Sequence[tuple], table: torch.Tensor):
     """items: (mesh, radar, rays, hits, chirp, flags, grad_if, grad_verts,
-    scratch) per request; one batched backward pass on the current stream."""
+    scratch[, params]) per request, params an optional (grad_materials,
+    grad_radar, grad_rot, grad_atten) tuple as for sbr_backward; one batched
+    backward pass on the current stream."""
     keep: list = []
     arr = (L.sbr_request * max(1, len(items)))()
-    for i, (mesh, radar, rays, hits, chirp, flags, grad_if, grad_verts, scratch) in enumerate(items):
+    for i, it in enumerate(items):
+        mesh, radar, rays, hits, chirp, flags, grad_if, grad_verts, scratch = it[:9]
         arr[i] = _request(mesh, radar, rays, hits, chirp, flags, scratch, keep, grad_if=grad_if,
-                          grad_verts=grad_verts)
+                          grad_verts=grad_verts, params=it[9] if len(it) > 9 else None)
     L.check(_lib().sbr_backward_batched(arr, len(items), _buf(table, torch.uint8, 0, "table"),
                                         table.numel() * table.element_size(), _stream()))
 

@@ -146,6 +146,57 @@ def test_batch_of_the_maximum_size(torch_cuda):
     assert worst <= 1e-5 and all(float(g.abs().max()) > 0 for g in single_g)
 
 
+def test_batched_backward_parameter_gradients(torch_cuda):
+    """The batched adjoint fills each request's parameter gradients (material
+    table, radar origin and velocity, rotation, attenuation) as its single
+    call does; requests that would write the same parameter buffer are
+    refused."""
+    torch = torch_cuda
+    from paper_2311_13182_amd._lib import SbrError
+    from paper_2311_13182_amd.sbr import Simulator, sbr_backward, sbr_backward_batched, sbr_batch_table_bytes
+    ico = S.icosphere_scene(level=3, n_rays=48, n_chirps=4)
+    fres = dataclasses.replace(ico, materials=[(S.MAT_PEC, 1, 0), (S.MAT_TE, 3.0, 0.2), (S.MAT_TM, 6.0, 0.0)],
+                               mat_id=(np.arange(ico.nf) % 3).astype(np.uint16),
+                               radar=S.default_radar(3, 4, vel=(0.4, -0.3, 1.0)))
+    plate = S.trihedral_plate().with_chirp(n_samples=200, n_chirps=2)
+    scenes = [fres, plate, fres.with_chirp(n_samples=256, n_chirps=2)]
+    sims = [Simulator(sc, "cuda", cube=False) for sc in scenes]
+    rng = np.random.default_rng(21)
+
+    def bufs(sim):
+        nm = len(sim.scene.materials or [])
+        return (torch.zeros(2 * nm, device="cuda") if nm else None, torch.zeros(6, device="cuda"),
+                torch.zeros(9, device="cuda"), torch.zeros(1, device="cuda"))
+
+    G, single, batched, gv_s, gv_b = [], [], [], [], []
+    for sim in sims:
+        sim.trace()
+        G.append(torch.as_tensor(rng.normal(size=(sim.V, sim.C, sim.S, 2)).astype(np.float32), device="cuda"))
+        single.append(bufs(sim))
+        batched.append(bufs(sim))
+        gv_s.append(torch.zeros((sim.mesh.nv, 3), device="cuda"))
+        gv_b.append(torch.zeros((sim.mesh.nv, 3), device="cuda"))
+    for sim, g, gv, pb in zip(sims, G, gv_s, single):
+        sbr_backward(sim.mesh, sim.scene.radar, sim.scene.grid, sim.hits, sim.scene.chirp, sim.flags, g, gv,
+                     sim.scratch, *pb)
+    table = torch.empty(sbr_batch_table_bytes(len(sims)), dtype=torch.uint8, device="cuda")
+    sbr_backward_batched([(s.mesh, s.scene.radar, s.scene.grid, s.hits, s.scene.chirp, s.flags, g, gv, s.scratch, pb)
+                          for s, g, gv, pb in zip(sims, G, gv_b, batched)], table)
+    torch.cuda.synchronize()
+    for i in range(len(sims)):
+        assert rel_l2(gv_b[i].cpu().numpy(), gv_s[i].cpu().numpy()) <= 1e-5
+        for name, a, b in zip(("materials", "radar", "rot", "attenuation"), single[i], batched[i]):
+            if a is None:
+                continue
+            e = rel_l2(b.cpu().numpy(), a.cpu().numpy())
+            log(f"batched request {i}: dL/d{name} rel L2 {e:.2e} (|single| {float(a.abs().max()):.3e})")
+            assert float(a.abs().max()) > 0 and e <= 1e-5, (i, name)
+    shared = bufs(sims[0])
+    with pytest.raises(SbrError, match="share device memory"):
+        sbr_backward_batched([(s.mesh, s.scene.radar, s.scene.grid, s.hits, s.scene.chirp, s.flags, g, gv, s.scratch,
+                               (None, shared[1], None, None)) for s, g, gv in zip(sims[:2], G, gv_b)], table)
+
+
 def _small_requests(n=10, seed=77):
     return S.serving_requests(n=n, qps=1.0, seed=seed, grids=(48, 64, 96), nf_range=(300, 3000), chirps=(4, 8))
 
