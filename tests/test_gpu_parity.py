@@ -176,7 +176,7 @@ def test_empty_grid_and_all_miss(torch_cuda, orc):
                                              ((2, 4, 2048), 1, 64), ((1, 2, 2), 0, 64), ((20, 16, 64), 1, 64),
                                              ((12, 16, 64), 0, 37), ((16, 8, 32), 1, 16), ((1, 32, 256), 0, 48),
                                              ((4, 64, 256), 1, 37), ((2, 256, 256), 1, 64), ((16, 128, 256), 0, 64),
-                                             ((17, 128, 256), 1, 64)])
+                                             ((17, 128, 256), 1, 64), ((4, 16, 256), 1, 64), ((2, 512, 256), 0, 32)])
 def test_radar_cube_vs_naive_dft(torch_cuda, orc, shape, window, na):
     """Power-of-two range / Doppler lengths up to 1024 run as FFTs, others
     (and 2048) as dense contractions; up to 32 antennas take the direct angle
@@ -185,7 +185,9 @@ def test_radar_cube_vs_naive_dft(torch_cuda, orc, shape, window, na):
     partial group), more the dense one.  The forward map of up to 16 antennas
     with 256 samples and 32, 64, 128 or 256 chirps runs as the register
     Doppler FFT and the fused range + angle stage (one Doppler bin per block
-    row, 16 angle bins per block); 17 antennas take the staged form."""
+    row, 16 angle bins per block); other power-of-two chirp counts (16, 512)
+    take the LDS Doppler FFT before the fused stage; 17 antennas take the
+    staged form."""
     import torch
     V, C, Sn = shape
     rng = np.random.default_rng(3)
