@@ -252,6 +252,12 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
         "synth_frac_of_fp32_peak": round(FLOP_PER_PATH_SAMPLE["synth"] * ps / (k_ms["synth"] * 1e-3) / 1e12 /
                                          PEAK_FP32_TFLOPS, 4),
+        # the whole step against the FP32 peak: synthesis and adjoint flops of
+        # all path-samples over the step time (everything else in the step --
+        # BVH build, trace, path stage, radar cube, CFAR, loss, geometry
+        # adjoint -- counted as time, not as work)
+        "step_frac_of_fp32_peak": round(sum(FLOP_PER_PATH_SAMPLE.values()) * ps / (ms_step * 1e-3) / 1e12 /
+                                        PEAK_FP32_TFLOPS, 4),
         "trace": {"ray_bounces_per_s": queries / (k_ms["trace"] * 1e-3), "node_tests": node_tests,
                   "tri_tests": tri_tests,
                   "alg_valu_ops_per_s": (OPS_PER_NODE_TEST * node_tests + OPS_PER_TRI_TEST * tri_tests) /
