@@ -445,11 +445,11 @@ __global__ __launch_bounds__(256) void k_angle_adj(const float2 *y, float2 *out,
 // ---- Forward range FFT + angle DFT, fused (256 samples) -------------------
 // cos and sin of 2 pi m / 16, m < 16
 constexpr float kCos16[16] = {1.0f, 0.92387953f, 0.70710678f, 0.38268343f, 0.0f, -0.38268343f,
-                                 -0.70710678f, -0.92387953f, -1.0f, -0.92387953f, -0.70710678f, -0.38268343f,
-                                 0.0f, 0.38268343f, 0.70710678f, 0.92387953f};
+                              -0.70710678f, -0.92387953f, -1.0f, -0.92387953f, -0.70710678f, -0.38268343f,
+                              0.0f, 0.38268343f, 0.70710678f, 0.92387953f};
 constexpr float kSin16[16] = {0.0f, 0.38268343f, 0.70710678f, 0.92387953f, 1.0f, 0.92387953f,
-                                 0.70710678f, 0.38268343f, 0.0f, -0.38268343f, -0.70710678f, -0.92387953f,
-                                 -1.0f, -0.92387953f, -0.70710678f, -0.38268343f};
+                              0.70710678f, 0.38268343f, 0.0f, -0.38268343f, -0.70710678f, -0.92387953f,
+                              -1.0f, -0.92387953f, -0.70710678f, -0.38268343f};
 
 // Forward 4-point DFT (e^{-2 pi j n k / 4}) of a0..a3, in place.
 __device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
