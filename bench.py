@@ -283,13 +283,21 @@ def main():
                           "p99_latency_ms": round(m["server"]["p99_latency_ms"], 1),
                           "sequential_throughput_rps": round(m["sequential"]["throughput_rps"], 2),
                           "sequential_p50_latency_ms": round(m["sequential"]["p50_latency_ms"], 1),
-                          "sequential_p99_latency_ms": round(m["sequential"]["p99_latency_ms"], 1)}
+                          "sequential_p99_latency_ms": round(m["sequential"]["p99_latency_ms"], 1),
+                          "mean_batch": round(m["server"]["mean_batch"], 3)}
         lo = sv["low"]
         out["serving"]["low_load"] = {"qps": round(lo["qps"], 2),
                                       "p50_latency_ms": round(lo["server"]["p50_latency_ms"], 1),
                                       "p99_latency_ms": round(lo["server"]["p99_latency_ms"], 1),
                                       "sequential_p50_latency_ms": round(lo["sequential"]["p50_latency_ms"], 1),
-                                      "sequential_p99_latency_ms": round(lo["sequential"]["p99_latency_ms"], 1)}
+                                      "sequential_p99_latency_ms": round(lo["sequential"]["p99_latency_ms"], 1),
+                                      "mean_batch": round(lo["server"]["mean_batch"], 3)}
+        bu = sv["burst"]
+        out["serving"]["burst"] = {"requests": bu["requests"],
+                                   "throughput_rps": round(bu["server"]["throughput_rps"], 2),
+                                   "sequential_throughput_rps": round(bu["sequential"]["throughput_rps"], 2),
+                                   "mean_batch": round(bu["server"]["mean_batch"], 3),
+                                   "max_batch": bu["server"]["max_batch"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, queries)
     print(json.dumps(out), flush=True)

@@ -349,6 +349,7 @@ class GPUExecutor:
         self.next = 0
         self.cache: "collections.OrderedDict[str, _MeshEntry]" = collections.OrderedDict()
         self.cache_meshes = cache_meshes
+        self.batch_sizes: List[int] = []   # requests per launched batch, in launch order
 
     def footprint(self, req: Request) -> int:
         return request_footprint(req.scene, req.backward)
@@ -484,6 +485,7 @@ class GPUExecutor:
                 self._unref(key)
             raise
         self._trim()
+        self.batch_sizes.append(len(reqs))
         return hs
 
     def _unref(self, key):
@@ -540,11 +542,19 @@ def summarize(results: List[Result], wall: float) -> Dict[str, float]:
             "p50_latency_ms": float(np.percentile(lat, 50) * 1e3), "p99_latency_ms": float(np.percentile(lat, 99) * 1e3)}
 
 
+def _batch_stats(sizes: List[int]) -> Dict[str, float]:
+    return {"launches": len(sizes), "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
+            "max_batch": int(max(sizes)) if sizes else 0}
+
+
 def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_streams: int = 4,
                       max_active: int = 16, grids=(256, 512, 1024, 2048), nf_range=(1000, 200000),
-                      phases=(("main", 1.25), ("low", 0.5)), quiet: bool = False):
+                      phases=(("main", 1.25), ("low", 0.5)), quiet: bool = False, burst: int = 64):
     """Sequential FIFO solves vs the continuous-batching server on the same
-    Poisson request stream (QPS = 1.25 x the measured sequential rate)."""
+    Poisson request stream (QPS = 1.25 x the measured sequential rate), with
+    the server's batch sizes; then a burst of `burst` small forward requests
+    that all arrive at once (256^2 rays, 1k-20k triangles, 32 chirps), where
+    admitted requests share batched launches."""
     import sys
     import torch
 
@@ -583,13 +593,35 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
         seq_w = max(r.t_done for r in seq)
         sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active=max_active)
         futs = [sch.submit(r) for r in timed]
+        ex.batch_sizes.clear()
         sch.t0 = time.perf_counter()
         sch.start()
         res = [f.result() for f in futs]
         sch.stop()
         srv_w = max(r.t_done for r in res)
-        out[tag] = {"qps": qps, "sequential": summarize(seq, seq_w), "server": summarize(res, srv_w)}
+        out[tag] = {"qps": qps, "sequential": summarize(seq, seq_w),
+                    "server": {**summarize(res, srv_w), **_batch_stats(ex.batch_sizes)}}
         say(f"{tag}: {json.dumps(out[tag])}")
+    if burst > 0:
+        small = S.serving_requests(n=burst, qps=1.0, seed=seed + 2, grids=(256,), nf_range=(1000, 20000),
+                                   chirps=(32,))
+        reqs_b = [Request(r.rid, r.scene, False, None, 0.0) for r in small]
+        h = ex.launch(reqs_b[0])     # warm the shapes of this mix (untimed)
+        ex.collect(h)
+        ex.release(h)
+        seq = run_sequential(ex, reqs_b)
+        seq_w = max(r.t_done for r in seq)
+        sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active=max_active)
+        futs = [sch.submit(Request(r.rid, r.scene, False, None, 0.0)) for r in reqs_b]
+        ex.batch_sizes.clear()
+        sch.t0 = time.perf_counter()
+        sch.start()
+        res = [f.result() for f in futs]
+        sch.stop()
+        srv_w = max(r.t_done for r in res)
+        out["burst"] = {"requests": burst, "sequential": summarize(seq, seq_w),
+                        "server": {**summarize(res, srv_w), **_batch_stats(ex.batch_sizes)}}
+        say(f"burst: {json.dumps(out['burst'])}")
     return out
 
 
