@@ -134,19 +134,26 @@ class DeviceMesh:
     def from_scene(cls, sc: S.Scene, device="cuda", non_blocking: bool = False):
         if not non_blocking:
             return cls(sc.verts, sc.faces, sc.mat_id, sc.materials, device)
-        # pinned staging + asynchronous copies on the current stream; the
-        # staging tensors live as long as the mesh
+        # one pinned staging buffer for vertices, faces and material ids (a
+        # pinned allocation costs far more than the copy of a small mesh),
+        # then asynchronous copies on the current stream into the mesh's own
+        # device tensors; the staging buffer lives as long as the mesh
         self = cls.__new__(cls)
-        vs = torch.from_numpy(np.ascontiguousarray(sc.verts, np.float32)).pin_memory()
-        fs = torch.from_numpy(np.ascontiguousarray(sc.faces, np.int32)).pin_memory()
-        self.verts = vs.to(device, non_blocking=True)
-        self.faces = fs.to(device, non_blocking=True)
-        self._staging = [vs, fs]
-        self.mat_id = None
+        parts = [np.ascontiguousarray(sc.verts, np.float32).reshape(-1).view(np.uint8),
+                 np.ascontiguousarray(sc.faces, np.int32).reshape(-1).view(np.uint8)]
         if sc.mat_id is not None:
-            ms = torch.from_numpy(np.asarray(sc.mat_id).astype(np.int16)).pin_memory()
-            self.mat_id = ms.to(device, non_blocking=True)
-            self._staging.append(ms)
+            parts.append(np.asarray(sc.mat_id).astype(np.int16).reshape(-1).view(np.uint8))
+        offs = np.cumsum([0] + [(len(x) + 255) // 256 * 256 for x in parts])
+        st = torch.empty(int(offs[-1]), dtype=torch.uint8, pin_memory=True)
+        host = st.numpy()
+        for x, o in zip(parts, offs):
+            host[o:o + len(x)] = x
+        def up(i, dt, shape):
+            return st[int(offs[i]):int(offs[i]) + len(parts[i])].view(dt).view(shape).to(device, non_blocking=True)
+        self.verts = up(0, torch.float32, (-1, 3))
+        self.faces = up(1, torch.int32, (-1, 3))
+        self.mat_id = up(2, torch.int16, (-1,)) if sc.mat_id is not None else None
+        self._staging = [st]
         self.materials = list(sc.materials)
         return self
 

@@ -288,3 +288,13 @@ def test_request_that_never_completes_times_out_and_frees_memory():
     assert ra.status == "failed" and "TimeoutError" in ra.error
     assert rb.status == "ok" and rb.t_admit >= ra.t_done - 1e-9
     assert sch.used_bytes == 0 and not ex.live
+
+
+def test_admissions_of_one_tick_are_launched_in_groups_of_max_batch():
+    clock = Clock()
+    ex = BatchExecutor(clock)
+    sch = Scheduler(ex, budget_bytes=10 ** 6, max_active=64, clock=clock, max_batch=4)
+    futs = [sch.submit(_req(i, 10, 0.01, arrival=0.0005)) for i in range(10)]
+    _run(sch, clock, 0.2)
+    assert all(f.result().status == "ok" for f in futs)
+    assert ex.batches == [[0, 1, 2, 3], [4, 5, 6, 7], [8, 9]]
