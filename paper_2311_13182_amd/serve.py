@@ -88,6 +88,7 @@ class Scheduler:
         self.max_active = int(max_active)
         self.request_timeout = request_timeout
         self.max_batch = max_batch
+        self.batch_fallbacks: List[str] = []   # errors of batches relaunched one request at a time
         self.clock = clock
         self.t0 = clock()
         self._pending: Deque = collections.deque()
@@ -217,8 +218,8 @@ class Scheduler:
                 for (req, fut, fp), h in zip(admitted, hs):
                     self._active.append((req, fut, h, fp, t_admit))
                 return
-            except Exception:   # fall back to single launches below
-                pass
+            except Exception as e:   # fall back to single launches below
+                self.batch_fallbacks.append(repr(e))
         for req, fut, fp in admitted:
             try:
                 h = self.ex.launch(req)
@@ -619,7 +620,10 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
         sch.stop()
         srv_w = max(r.t_done for r in res)
         out[tag] = {"qps": qps, "sequential": summarize(seq, seq_w),
-                    "server": {**summarize(res, srv_w), **_batch_stats(ex.batch_sizes)}}
+                    "server": {**summarize(res, srv_w), **_batch_stats(ex.batch_sizes),
+                               "batch_fallbacks": len(sch.batch_fallbacks)}}
+        if sch.batch_fallbacks:
+            say(f"{tag}: batches relaunched one request at a time: {sch.batch_fallbacks[:3]}")
         say(f"{tag}: {json.dumps(out[tag])}")
     if burst > 0:
         # all requests admitted at once (max_active = burst), launched in
@@ -635,15 +639,16 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
             seq = run_sequential(ex, reqs_b)
             runs["sequential"].append(summarize(seq, max(r.t_done for r in seq)))
             sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active=burst, max_batch=16)
-            futs = [sch.submit(Request(r.rid, r.scene, False, None, 0.0)) for r in reqs_b]
             ex.batch_sizes.clear()
-            sch.t0 = time.perf_counter()
+            sch.t0 = time.perf_counter()   # every request arrives at time 0
+            futs = [sch.submit(Request(r.rid, r.scene, False, None, 1e-9)) for r in reqs_b]
             sch.start()
             res = [f.result() for f in futs]
             sch.stop()
             runs["server"].append({**summarize(res, max(r.t_done for r in res)), **_batch_stats(ex.batch_sizes)})
         med = {k: sorted(v, key=lambda r: r["throughput_rps"])[1] for k, v in runs.items()}
-        out["burst"] = {"requests": burst, "repetitions": 3, **med}
+        out["burst"] = {"requests": burst, "repetitions": 3, **med,
+                        "server_launches_per_repetition": [r["launches"] for r in runs["server"]]}
         say(f"burst: {json.dumps(out['burst'])}")
     return out
 
