@@ -7,12 +7,14 @@ simulations of many requests on one GPU with continuous batching.
   order; idle cache entries are evicted to make room; a request larger than
   the whole budget is rejected).
 * Continuous batching: at every scheduling tick the requests admitted since
-  the last one form a batch.  Their per-request stages (mesh upload, BVH
-  build, trace, path refinement) are enqueued on one HIP stream, then ONE
-  batched IF-synthesis launch covers the synthesis blocks of all of them
-  (sbr_synth_if_batched), and the forward+backward ones share ONE batched
-  adjoint launch (sbr_backward_batched).  Consecutive ticks go to different
-  streams, so a batch admitted while others run overlaps them on the device.
+  the last one form a batch (or several of at most max_batch requests).
+  Their per-request stages (mesh upload, BVH build, trace, path refinement)
+  are enqueued on one HIP stream, then ONE batched IF-synthesis launch covers
+  the synthesis blocks of all of them (sbr_synth_if_batched), and the
+  forward+backward ones share ONE batched adjoint launch
+  (sbr_backward_batched).  Consecutive batches go to different streams, so a
+  batch admitted while others run overlaps them on the device, and the host
+  prepares one batch while the device runs the previous one.
 * BVHs and meshes stay resident for the life of a request, and repeated
   meshes (same vertices, faces and materials) reuse a cached device copy: a
   request that hits the cache waits (on the device) for the event that ends
