@@ -134,9 +134,9 @@ class DeviceMesh:
     def from_scene(cls, sc: S.Scene, device="cuda", non_blocking: bool = False):
         if not non_blocking:
             return cls(sc.verts, sc.faces, sc.mat_id, sc.materials, device)
-        # one pinned staging buffer for vertices, faces and material ids (a
-        # pinned allocation costs far more than the copy of a small mesh),
-        # then asynchronous copies on the current stream into the mesh's own
+        # one pinned staging buffer for vertices, faces and material ids
+        # (one pinned allocation per mesh instead of one per array), then
+        # asynchronous copies on the current stream into the mesh's own
         # device tensors; the staging buffer lives as long as the mesh
         self = cls.__new__(cls)
         parts = [np.ascontiguousarray(sc.verts, np.float32).reshape(-1).view(np.uint8),

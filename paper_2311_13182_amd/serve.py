@@ -472,8 +472,8 @@ class GPUExecutor:
                                       gv, s.scratch))
                     sbr_backward_batched(items, table)
                 # one pinned host buffer per batch for every request's cube,
-                # gradient and path count (pinned allocations cost far more
-                # than device ones), sliced per request
+                # gradient and path count (instead of two or three pinned
+                # allocations per request), sliced per request
                 def span(n):   # slice lengths rounded up to 64 floats (256 B)
                     return (n + 63) // 64 * 64
                 n_f32 = sum(span(h["cube"].numel()) + (span(h["grad"].numel()) if "grad" in h else 0) for h in hs)
