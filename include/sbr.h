@@ -166,6 +166,11 @@ typedef struct {
                                 moving silhouettes then contribute.  The forward
                                 signal is the same; without the flag the gradient is
                                 the pathwise one with fixed ray directions. */
+#define SBR_ADJOINT_DIRECT 8 /* sbr_backward only: evaluate the per-path sums of
+                                Eqs. 11-12 by direct summation over the samples
+                                (Horner's rule) rather than by the non-uniform FFT
+                                (see sbr_backward); chirps of fewer than 16 or more
+                                than 1024 samples always use direct summation    */
 
 /* scratch-size queries */
 #define SBR_OP_BUILD_BVH 0
@@ -340,8 +345,16 @@ typedef struct {
  * the fixed-grid estimator: each path's geometry is recomputed per bounce
  * from the hit records (nothing of the forward synthesis is stored) and the
  * reverse sweep runs through path lengths, ray-plane intersections,
- * reflections, normals and Fresnel coefficients.  Arguments as for
- * sbr_synth_if; hits and flags must be those the forward used.  params: NULL,
+ * reflections, normals and Fresnel coefficients.  Per path, antenna v and
+ * chirp c the adjoint needs two finite Fourier series of the gradient row
+ * G[v][c][.] at the path's beat frequency g: P(g) = sum_s conj(G_s)
+ * e^{2 pi j s g} (Eq. 12) and the same sum weighted by fc + (slope/fs) s
+ * (Eq. 11).  For 16 <= S <= 1024 they are evaluated by a type-2 non-uniform
+ * FFT (one 2S-point transform per row, shared by all paths, then 7 kernel taps
+ * per path; exponential-of-semicircle kernel), whose error is below 1e-6 of
+ * sum_s |weighted G_s| at every g; with SBR_ADJOINT_DIRECT, or for other S, by
+ * direct summation.  Arguments as for sbr_synth_if; hits and flags must be
+ * those the forward used.  params: NULL,
  * or where to ADD the gradients of the material table (Eqs. 9-10 through
  * eps_c), of the radar origin (ray origins, TX and RX positions, return
  * distances), of the radar rotation (ray directions, TX and RX positions,

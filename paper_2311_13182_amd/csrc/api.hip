@@ -232,17 +232,17 @@ struct BackCarve {
     size_t bytes;
 };
 
-static BackCarve back_carve(void *scratch, int R, int K, int V) {
+static BackCarve back_carve(void *scratch, int R, int K, int V, int C, int S) {
     BackCarve c;
     Carver cv(scratch);
     c.st = carve_path_stage(cv, R, K, V);
-    c.extra = cv.take<char>(backward_extra_bytes(R, K, V));
+    c.extra = cv.take<char>(backward_extra_bytes(R, K, V, C, S));
     c.table = cv.take<char>(adj_table_bytes(1));
     c.bytes = align_up(cv.off, 256);
     return c;
 }
 
-static size_t backward_bytes(int R, int K, int V) { return back_carve(nullptr, R, K, V).bytes; }
+static size_t backward_bytes(int R, int K, int V, int C, int S) { return back_carve(nullptr, R, K, V, C, S).bytes; }
 
 // Checks of one sbr_synth_if request; 0 if it may be enqueued.
 static int check_synth(const sbr_mesh *mesh, const sbr_material *mats, int32_t n_mats, const sbr_radar *radar,
@@ -269,10 +269,12 @@ static int check_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_
     int rc;
     if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
     SBR_CHECK_ARG(grad_if && grad_verts, "grad_if/grad_verts is NULL");
-    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY)) == 0, "unknown flags 0x%x", flags);
+    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY | SBR_ADJOINT_DIRECT)) == 0,
+                  "unknown flags 0x%x", flags);
     SBR_CHECK_ARG(!params || !params->materials || (mats && n_mats > 0),
                   "material gradients requested without a material table");
-    const size_t need = backward_bytes(rays->nx * rays->ny, rays->max_bounces, radar->n_tx * radar->n_rx);
+    const size_t need = backward_bytes(rays->nx * rays->ny, rays->max_bounces, radar->n_tx * radar->n_rx,
+                                       chirp->n_chirps, chirp->n_samples);
     if (!scratch || scratch_bytes < need) {
         set_error("backward scratch too small: %zu bytes given, %zu needed", scratch_bytes, need);
         return SBR_E_SCRATCH;
@@ -317,7 +319,7 @@ static int enqueue_backward(const sbr_mesh *mesh, const sbr_material *mats, int3
         *skip = 1;
         return SBR_OK;
     }
-    BackCarve c = back_carve(scratch, R, K, V);
+    BackCarve c = back_carve(scratch, R, K, V, chirp->n_chirps, chirp->n_samples);
     q->mesh = mesh;
     q->mt = make_mats(mats, n_mats);
     q->rd = make_radar(radar);
@@ -364,7 +366,7 @@ size_t sbr_scratch_bytes(int32_t op, const sbr_mesh *mesh, const sbr_rays *rays,
         int V = radar->n_tx * radar->n_rx;
         if (op == SBR_OP_SYNTH)
             return synth_bytes((int)R, rays->max_bounces, V, chirp->n_chirps, chirp->n_samples);
-        return backward_bytes((int)R, rays->max_bounces, V);
+        return backward_bytes((int)R, rays->max_bounces, V, chirp->n_chirps, chirp->n_samples);
     }
     case SBR_OP_RADAR_CUBE: {
         if (!radar || !chirp) return 0;

@@ -15,18 +15,223 @@ struct AdjArgs {
     PathSoA rec;
     const float2 *G;       // [V][C][S]
     int32_t V, C, S;
-    int32_t rows;          // G rows per LDS stage
+    int32_t rows;          // G rows per LDS stage (direct form)
     int32_t Sp;            // S rounded up to a multiple of 8
     int32_t v_per;         // antennas per y-block
     int32_t nvs;           // y-blocks
+    int32_t ppl;           // paths per lane of the kernel that runs this request
     float fcf, sl_fs, tc;  // fc, slope / fs, chirp period
     float *tau_bar;        // [V][cap]
     float2 *abar_part;     // [nvs][cap]
     float *tdb_part;       // [nvs][cap] dL/d taudot partials
+    const float4 *nu_rows; // [V][C][2S + 8] non-uniform FFT rows (NULL: direct form)
 };
 
 constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time
-constexpr int kAdjPPL = 2;       // paths per lane
+constexpr int kAdjPPL = 2;       // paths per lane, direct form
+constexpr int kNuPPL = 2;        // paths per lane, non-uniform FFT form
+constexpr int kAdjQueueDirect = 32;   // work counter of the direct form (queue[0]: the other)
+
+// ---- Eqs. 11-12 by a type-2 non-uniform FFT -------------------------------
+// For each (v, c) the two sums of the adjoint are finite Fourier series of one
+// G row evaluated at a path's beat frequency g (cycles per sample, reduced to
+// [-1/2, 1/2]):
+//   P(g) = sum_s h1_s e^{2 pi j s g},  h1_s = conj(G_s)
+//   Q(g) = sum_s h2_s e^{2 pi j s g},  h2_s = conj(G_s) (fc + (slope/fs) s)
+// (Q = fc P + (slope/fs) x P'(x) of the direct form).  With the modes centred
+// (s' = s - S/2), a grid of M = 2S points and a kernel psi of width W grid
+// points whose Fourier transform is Psi,
+//   P(g) = e^{2 pi j g S/2} sum_l u_l psi(gM - l),
+//   u_l  = sum_s' (h_{s'+S/2} / Psi(s'/M)) e^{2 pi j s' l / M},
+// up to the kernel's aliasing error.  The rows u (one per (v, c), shared by
+// every path) cost one dense DFT each; a path then needs W taps per (v, c)
+// instead of S terms.  Kernel: exponential of semicircle,
+// psi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)), W = 7, beta = 2.3 W, for which
+// the evaluation error stays below 1e-6 of sum_s |h_s| at every g (two orders
+// of magnitude under the FP32 rounding of a 256-term direct sum).
+constexpr int kNuW = 7;
+constexpr int kNuHalf = (kNuW - 1) / 2;
+constexpr double kNuBeta = 2.30 * kNuW;
+constexpr int kNuMinS = 16;     // shorter chirps use the direct form (cheap there)
+constexpr int kNuMaxS = 1024;   // longer chirps use the direct form
+constexpr int kNuSteps = 16;    // trapezoid points per grid unit for Psi
+
+__host__ __device__ constexpr int nu_row_len(int S) { return 2 * S + 8; }   // l = -M/2-3 .. M/2+3, + 1 pad
+
+// float4's layout for address-space-qualified 16-byte loads of the rows
+struct alignas(16) F4 {
+    float x, y, z, w;
+};
+__device__ __forceinline__ SBR_GLOBAL_AS const F4 *gmem4(const float4 *p) { return (SBR_GLOBAL_AS const F4 *)p; }
+
+// frac(n f) for an integer-valued n < 2^24: the product is exact inside the fma
+__device__ __forceinline__ float frac_of_product(float n, float f) { return fmaf(n, f, -rintf(n * f)); }
+
+// 1 / Psi((s - S/2) / M), s < S, with Psi(xi) = int psi(z) e^{-2 pi j xi z} dz
+// by the trapezoid rule at kNuSteps points per grid unit (psi vanishes with
+// all its derivatives up to the order of e^{-beta} at the ends of its
+// support): Psi = h (psi(0) + 2 sum_n psi(nh) cos(2 pi xi n h)), h = 1/kNuSteps,
+// the cosines by the three-term recurrence in FP64.  Blocks of 256 modes.
+constexpr int kNuTaps = kNuW * kNuSteps / 2;   // n = 0 .. kNuTaps - 1 (|z| < W/2)
+__global__ __launch_bounds__(256) void k_nu_corr(int S, float *corr) {
+    __shared__ double kn[kNuTaps];
+    if (threadIdx.x < kNuTaps) {
+        const double x = 2.0 * threadIdx.x / (double)(kNuW * kNuSteps);
+        kn[threadIdx.x] = exp(kNuBeta * (sqrt(1.0 - x * x) - 1.0));
+    }
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const int M = 2 * S;
+    const double c1 = cospi(2.0 * (double)(s - S / 2) / (double)(M * kNuSteps));
+    double cp = 1.0, cc = c1, acc = kn[0] + 2.0 * kn[1] * c1;
+    for (int n = 2; n < kNuTaps; n++) {
+        const double cn = 2.0 * c1 * cc - cp;
+        cp = cc;
+        cc = cn;
+        acc += 2.0 * kn[n] * cn;
+    }
+    corr[s] = (float)((double)kNuSteps / acc);
+}
+
+// Row (v, c) = blockIdx.x: u1_l, u2_l (float4: u1.re, u1.im, u2.re, u2.im)
+// for l = -M/2 - 3 .. M/2 + 3 at index l + M/2 + 3, by a direct DFT over the
+// S deconvolved modes with twiddles e^{2 pi j k / M} from an exact-index LDS
+// table; the last entry of the row is zero padding.
+__global__ __launch_bounds__(256) void k_nu_rows(const float2 *__restrict__ G, int S, float fcf, float sl_fs,
+                                                 const float *__restrict__ corr, float4 *__restrict__ rows) {
+    extern __shared__ float4 nsh[];
+    const int M = 2 * S, RL = nu_row_len(S);
+    float4 *hb = nsh;                                         // [S] h1, h2 over Psi
+    float2 *tw = reinterpret_cast<float2 *>(nsh + S);         // [M]
+    const size_t row = blockIdx.x;
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * k / M, &sn, &cs);
+        tw[k] = make_float2((float)cs, (float)sn);
+    }
+    const float2 *g = G + row * S;
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        const float2 v = g[s];
+        const float r = corr[s];
+        const float w2 = fmaf(sl_fs, (float)s, fcf);
+        const float hr = v.x * r, hi = -v.y * r;   // conj(G_s) / Psi
+        hb[s] = make_float4(hr, hi, hr * w2, hi * w2);
+    }
+    __syncthreads();
+    float4 *out = rows + row * RL;
+    for (int i = threadIdx.x; i < RL; i += blockDim.x) {
+        float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
+        if (i < RL - 1) {
+            int lm = (i - (M / 2 + kNuHalf)) % M;   // l mod M
+            if (lm < 0) lm += M;
+            int k = (int)(((long long)(M - S / 2) * lm) % M);   // (s - S/2) l mod M at s = 0
+            for (int s = 0; s < S; s++) {
+                const float2 t = tw[k];
+                const float4 h = hb[s];
+                ar = fmaf(h.x, t.x, fmaf(-h.y, t.y, ar));
+                ai = fmaf(h.x, t.y, fmaf(h.y, t.x, ai));
+                br = fmaf(h.z, t.x, fmaf(-h.w, t.y, br));
+                bi = fmaf(h.z, t.y, fmaf(h.w, t.x, bi));
+                k += lm;
+                if (k >= M) k -= M;
+            }
+        }
+        out[i] = make_float4(ar, ai, br, bi);
+    }
+}
+
+// One work item of the non-uniform FFT form: per path and (v, c) the taps
+// l0 .. l0 + 6 around x = gM (l0 = rint(x) - 3) of both rows, kernel weights
+// from the hardware sqrt and exp2, and the same accumulation as the direct
+// form with z0 e^{2 pi j g S/2} as the phase factor.
+template <int PPL>
+__device__ __forceinline__ void adj_item_nu(const AdjArgs &a, const int P, const int grp, const int blk_p0) {
+    const auto amp = gmem(a.rec.amp);
+    const auto bet = gmem(a.rec.beta);
+    const auto eps = gmem(a.rec.epsd);
+    const auto alp = gmem(a.rec.alpha);
+    const auto gam = gmem(a.rec.gamma);
+    const auto tbar = gmem(a.tau_bar);
+    int pp[PPL];
+    bool act[PPL];
+    float Ax[PPL], Ay[PPL], beta[PPL], epsd[PPL], abr[PPL], abi[PPL], tdb[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; i++) {
+        pp[i] = blk_p0 + i * 256 + threadIdx.x;
+        act[i] = pp[i] < P;
+        const int pc = act[i] ? pp[i] : blk_p0;
+        const F2 A = amp[pc];
+        Ax[i] = A.x;
+        Ay[i] = A.y;
+        beta[i] = bet[pc];
+        epsd[i] = eps[pc];
+        abr[i] = abi[i] = tdb[i] = 0.0f;
+        pp[i] = pc;
+    }
+    const int S = a.S, M = 2 * S, RL = nu_row_len(S);
+    const float Mf = (float)M, halfS = (float)(S / 2);
+    const float zstep = 2.0f / kNuW;                           // kernel argument per grid point
+    const float kb = (float)(kNuBeta * 1.4426950408889634);    // beta log2(e)
+    const int v0 = grp * a.v_per, v1 = min(a.V, v0 + a.v_per);
+    for (int v = v0; v < v1; v++) {
+        float alpha[PPL], gamma[PPL], tb[PPL];
+#pragma unroll
+        for (int i = 0; i < PPL; i++) {
+            alpha[i] = alp[(size_t)v * a.rec.cap + pp[i]];
+            gamma[i] = gam[(size_t)v * a.rec.cap + pp[i]];
+            tb[i] = 0.0f;
+        }
+        const auto rows_v = gmem4(a.nu_rows) + (size_t)v * a.C * RL;
+        for (int c = 0; c < a.C; c++) {
+            const float cf = (float)c;
+            const auto row = rows_v + (size_t)c * RL;
+#pragma unroll
+            for (int i = 0; i < PPL; i++) {
+                const float f = fmaf(cf, epsd[i], gamma[i]);
+                const float g = f - rintf(f);   // [-1/2, 1/2]
+                const float x = g * Mf;         // exact
+                const float xr = rintf(x);
+                const int i0 = (int)xr + M / 2;   // row index of l0 = xr - 3
+                F4 u[kNuW];
+#pragma unroll
+                for (int t = 0; t < kNuW; t++) u[t] = row[i0 + t];
+                const float zt0 = (x - xr + (float)kNuHalf) * zstep;   // kernel argument of tap 0
+                float pr = 0.f, pi = 0.f, qr = 0.f, qi = 0.f;
+#pragma unroll
+                for (int t = 0; t < kNuW; t++) {
+                    const float z = fmaf(-(float)t, zstep, zt0);
+                    const float q = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+                    const float w = __builtin_amdgcn_exp2f(fmaf(kb, __builtin_amdgcn_sqrtf(q), -kb));
+                    pr = fmaf(w, u[t].x, pr);
+                    pi = fmaf(w, u[t].y, pi);
+                    qr = fmaf(w, u[t].z, qr);
+                    qi = fmaf(w, u[t].w, qi);
+                }
+                float th = alpha[i] + frac_of_product(cf, beta[i]) + frac_of_product(halfS, g);
+                th -= rintf(th);
+                const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
+                // Q0 = z0 P, m = z0 Q (z0 including e^{2 pi j g S/2})
+                const float q0r = zc * pr - zs * pi, q0i = zc * pi + zs * pr;
+                const float mr = zc * qr - zs * qi, mi = zc * qi + zs * qr;
+                abr[i] += q0r;
+                abi[i] -= q0i;
+                const float dq = -2.0f * (float)kPi * (Ax[i] * mi + Ay[i] * mr);
+                tb[i] += dq;
+                tdb[i] = fmaf(dq, cf * a.tc, tdb[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PPL; i++)
+            if (act[i]) tbar[(size_t)v * a.rec.cap + pp[i]] = tb[i];
+    }
+#pragma unroll
+    for (int i = 0; i < PPL; i++)
+        if (act[i]) {
+            gmem(a.abar_part)[(size_t)grp * a.rec.cap + pp[i]] = F2{abr[i], abi[i]};
+            gmem(a.tdb_part)[(size_t)grp * a.rec.cap + pp[i]] = tdb[i];
+        }
+}
 
 // Path-stationary adjoint of Eq. (8).  For each (path, v, c) the sums
 //   P(x) = sum_s conj(G_s) x^s,  P'(x)   with x = e^{2 pi j delta}
@@ -163,10 +368,11 @@ __device__ __forceinline__ void adj_item(const AdjArgs &a, float2 *gsh, const in
         }
 }
 
-// Work items of each request of a batch: (antenna groups) x (path tiles) for
-// its device-side path count; item_first[i] = first item of request i,
-// item_first[n] = total.  Also clears the work counter.  One block.
-__global__ __launch_bounds__(1024) void k_adj_items(const AdjArgs *args, int n, int ppl, uint32_t *item_first,
+// Work items of each request of a batch: (antenna groups) x (path tiles of
+// 256 x args[i].ppl paths) for its device-side path count; item_first[i] =
+// first item of request i, item_first[n] = total.  Also clears the work
+// counters of both adjoint forms.  One block.
+__global__ __launch_bounds__(1024) void k_adj_items(const AdjArgs *args, int n, uint32_t *item_first,
                                                     uint32_t *queue) {
     __shared__ uint32_t part[1024];
     const int t = threadIdx.x;
@@ -174,8 +380,8 @@ __global__ __launch_bounds__(1024) void k_adj_items(const AdjArgs *args, int n, 
     const int b = t * chunk, e = min(n, b + chunk);
     uint32_t sum = 0;
     for (int i = b; i < e; i++) {
-        const uint32_t P = (uint32_t)args[i].count[0];
-        sum += (P + 256u * ppl - 1u) / (256u * ppl) * (uint32_t)args[i].nvs;
+        const uint32_t P = (uint32_t)args[i].count[0], tile = 256u * (uint32_t)args[i].ppl;
+        sum += (P + tile - 1u) / tile * (uint32_t)args[i].nvs;
     }
     part[t] = sum;
     __syncthreads();
@@ -188,44 +394,74 @@ __global__ __launch_bounds__(1024) void k_adj_items(const AdjArgs *args, int n, 
     uint32_t run = part[t] - sum;
     for (int i = b; i < e; i++) {
         item_first[i] = run;
-        const uint32_t P = (uint32_t)args[i].count[0];
-        run += (P + 256u * ppl - 1u) / (256u * ppl) * (uint32_t)args[i].nvs;
+        const uint32_t P = (uint32_t)args[i].count[0], tile = 256u * (uint32_t)args[i].ppl;
+        run += (P + tile - 1u) / tile * (uint32_t)args[i].nvs;
     }
     if (t == 1023) item_first[n] = part[1023];
-    if (t == 0) queue[0] = 0u;
+    if (t == 0) {
+        queue[0] = 0u;
+        queue[kAdjQueueDirect] = 0u;
+    }
 }
 
-// Work items of all requests of a batch (one request for sbr_backward) are
-// taken from one atomic counter by about one device-full of blocks; an item
-// is mapped to its request by binary search over item_first, then to (antenna
-// group, path tile) exactly as in a launch of its own.  `slot` is the LDS
-// float2 offset of the work-item word (after the largest G-row stage).
+// Request of a work item: binary search over item_first[lo .. hi).
+__device__ __forceinline__ int adj_request(const uint32_t *item_first, int lo, int hi, uint32_t item) {
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_first[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Work items of requests [r0, r1) of a batch (one request for sbr_backward)
+// are taken from one atomic counter by about one device-full of blocks; an
+// item is mapped to its request by binary search over item_first, then to
+// (antenna group, path tile) exactly as in a launch of its own.  `slot` is
+// the LDS float2 offset of the work-item word (after the largest G-row stage).
 template <int PPL>
 __global__ __launch_bounds__(256) void k_synth_adj(const AdjArgs *__restrict__ args,
-                                                   const uint32_t *__restrict__ item_first, int n,
+                                                   const uint32_t *__restrict__ item_first, int r0, int r1,
                                                    uint32_t *queue, int slot) {
     // [rows][Sp] G rows, then the current work item.  No static LDS: it would
     // shift the dynamic area off the 16-byte alignment of the row reads.
     extern __shared__ float2 gsh[];
     uint32_t &s_item = *reinterpret_cast<uint32_t *>(gsh + slot);
-    const uint32_t total = item_first[n];
+    const uint32_t first = item_first[r0], total = item_first[r1];
     for (;;) {
         __syncthreads();   // the previous item is done with s_item and gsh
-        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
+        if (threadIdx.x == 0) s_item = first + atomicAdd(queue, 1u);
         __syncthreads();
         const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= total) break;   // uniform over the block
-        int lo = 0, hi = n;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (item_first[mid] <= item) lo = mid;
-            else hi = mid;
-        }
+        const int lo = adj_request(item_first, r0, r1, item);
         const AdjArgs &a = args[lo];
         const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
         const uint32_t tiles = (uint32_t)((P + 256 * PPL - 1) / (256 * PPL));
         const uint32_t local = item - item_first[lo];
         adj_item<PPL>(a, gsh, P, (int)(local / tiles), (int)(local % tiles) * 256 * PPL);
+    }
+}
+
+// The same work queue over requests [r0, r1) for the non-uniform FFT form.
+template <int PPL>
+__global__ __launch_bounds__(256) void k_synth_adj_nu(const AdjArgs *__restrict__ args,
+                                                      const uint32_t *__restrict__ item_first, int r0, int r1,
+                                                      uint32_t *queue) {
+    __shared__ uint32_t s_item;
+    const uint32_t first = item_first[r0], total = item_first[r1];
+    for (;;) {
+        __syncthreads();   // every wave has read the previous s_item
+        if (threadIdx.x == 0) s_item = first + atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= total) break;   // uniform over the block
+        const int lo = adj_request(item_first, r0, r1, item);
+        const AdjArgs &a = args[lo];
+        const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
+        const uint32_t tiles = (uint32_t)((P + 256 * PPL - 1) / (256 * PPL));
+        const uint32_t local = item - item_first[lo];
+        adj_item_nu<PPL>(a, P, (int)(local / tiles), (int)(local % tiles) * 256 * PPL);
     }
 }
 
@@ -671,16 +907,44 @@ static BackPlan back_plan(long long cap, int V) {
     return {nvs, v_per};
 }
 
-size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V) {
-    long long cap = (long long)R * K;
-    BackPlan bp = back_plan(cap, V);
-    Carver cv(nullptr);
-    cv.take<float>((size_t)V * cap);
-    cv.take<float2>((size_t)bp.nvs * cap);
-    cv.take<float2>(cap);
-    cv.take<float>((size_t)bp.nvs * cap);
-    cv.take<float>(cap);
-    return align_up(cv.off, 256);
+// Whether a request's adjoint sums run as the non-uniform FFT form.
+static bool nu_size(int32_t S) { return S >= kNuMinS && S <= kNuMaxS; }
+static bool use_nu(int32_t S, int32_t flags) { return nu_size(S) && !(flags & SBR_ADJOINT_DIRECT); }
+
+// Adjoint buffers after the path stage: tau_bar, Abar and taudot_bar partials
+// and sums, then (for chirps of kNuMinS .. kNuMaxS samples, whatever the
+// flags) the 1/Psi table and the non-uniform FFT rows.
+struct BackExtra {
+    float *tau_bar;
+    float2 *part, *abar;
+    float *tpart, *tdbar;
+    float *corr;
+    float4 *rows;
+    size_t bytes;
+};
+
+static BackExtra back_extra(void *buf, int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
+    const long long cap = (long long)R * K;
+    const BackPlan bp = back_plan(cap, V);
+    Carver cv(buf);
+    BackExtra e;
+    e.tau_bar = cv.take<float>((size_t)V * cap);
+    e.part = cv.take<float2>((size_t)bp.nvs * cap);
+    e.abar = cv.take<float2>(cap);
+    e.tpart = cv.take<float>((size_t)bp.nvs * cap);
+    e.tdbar = cv.take<float>(cap);
+    e.corr = nullptr;
+    e.rows = nullptr;
+    if (nu_size(S)) {
+        e.corr = cv.take<float>((size_t)S);
+        e.rows = cv.take<float4>((size_t)V * C * nu_row_len(S));
+    }
+    e.bytes = align_up(cv.off, 256);
+    return e;
+}
+
+size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
+    return back_extra(nullptr, R, K, V, C, S).bytes;
 }
 
 // Device table of a batched adjoint: the requests' arguments, their first
@@ -713,22 +977,26 @@ static int adj_rows(int Sp) { return std::max(1, std::min<int>(kAdjRowsMax, (655
 
 int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream_t s) {
     if (n <= 0) return SBR_OK;
+    // requests of the non-uniform FFT form first, then those of the direct one
+    std::vector<int> order;
+    for (int r = 0; r < n; r++)
+        if (use_nu(reqs[r].cd.S, reqs[r].flags)) order.push_back(r);
+    const int n_nu = (int)order.size();
+    for (int r = 0; r < n; r++)
+        if (!use_nu(reqs[r].cd.S, reqs[r].flags)) order.push_back(r);
     std::vector<AdjArgs> aa(n);
     std::vector<GeomArgs> gg(n);
+    std::vector<const float *> corr(n);
     size_t lds_f2 = 0;   // float2 words of the largest G-row stage
-    long long items_max = 0;
+    long long items_nu = 0, items_direct = 0;
     for (int r = 0; r < n; r++) {
-        const BackwardReq &q = reqs[r];
+        const BackwardReq &q = reqs[order[r]];
         const RadarDev &rd = q.rd;
         const int V = rd.n_tx * rd.n_rx;
         const long long cap = q.st.rec.cap;
+        const bool nu = r < n_nu;
         BackPlan bp = back_plan(cap, V);
-        Carver cv(q.extra);
-        float *tau_bar = cv.take<float>((size_t)V * cap);
-        float2 *part = cv.take<float2>((size_t)bp.nvs * cap);
-        float2 *abar = cv.take<float2>(cap);
-        float *tpart = cv.take<float>((size_t)bp.nvs * cap);
-        float *tdbar = cv.take<float>(cap);
+        const BackExtra e = back_extra(q.extra, q.gd.nx * q.gd.ny, q.gd.K, V, q.cd.C, q.cd.S);
         AdjArgs &a = aa[r];
         a.count = q.st.count;
         a.rec = q.st.rec;
@@ -738,16 +1006,23 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
         a.S = q.cd.S;
         a.v_per = bp.v_per;
         a.nvs = bp.nvs;
+        a.ppl = nu ? kNuPPL : kAdjPPL;
         a.fcf = (float)q.cd.fc;
         a.sl_fs = (float)(q.cd.slope / q.cd.fs);
         a.tc = (float)q.cd.tc;
-        a.tau_bar = tau_bar;
-        a.abar_part = part;
-        a.tdb_part = tpart;
+        a.tau_bar = e.tau_bar;
+        a.abar_part = e.part;
+        a.tdb_part = e.tpart;
+        a.nu_rows = nu ? e.rows : nullptr;
+        corr[r] = e.corr;
         a.Sp = (q.cd.S + 7) / 8 * 8;
         a.rows = adj_rows(a.Sp);
-        lds_f2 = std::max(lds_f2, (size_t)a.rows * a.Sp);
-        items_max += (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL) * bp.nvs;
+        if (nu) {
+            items_nu += (cap + 256 * kNuPPL - 1) / (256 * kNuPPL) * bp.nvs;
+        } else {
+            lds_f2 = std::max(lds_f2, (size_t)a.rows * a.Sp);
+            items_direct += (cap + 256 * kAdjPPL - 1) / (256 * kAdjPPL) * bp.nvs;
+        }
         GeomArgs &g = gg[r];
         const sbr_mesh *m = q.mesh;
         g.verts = m->verts;
@@ -767,9 +1042,9 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
         g.flags = q.hits->flags;
         g.drop = (q.flags & SBR_DROP_FLAGGED) ? 1 : 0;
         g.exit_only = (q.flags & SBR_EXIT_ONLY) ? 1 : 0;
-        g.abar = abar;
-        g.tau_bar = tau_bar;
-        g.tdbar = tdbar;
+        g.abar = e.abar;
+        g.tau_bar = e.tau_bar;
+        g.tdbar = e.tdbar;
         g.cap = (int32_t)cap;
         g.grad = q.grad;
         g.g_mats = q.params ? q.params->materials : nullptr;
@@ -785,15 +1060,31 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
     AdjTable t = adj_table(table, n, nullptr);
     int rc = put_table(t.args, aa.data(), sizeof(AdjArgs) * n, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, s, t.args, n, kAdjPPL, t.item_first, t.queue);
-    const size_t lds = sizeof(float2) * lds_f2 + 16;
-    // one device-full of blocks, or fewer if the path slots cannot fill it
-    dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_max, resident_blocks((const void *)k_synth_adj<kAdjPPL>,
-                                                                                      256, lds, 256 * 2))));
-    {
+    hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, s, t.args, n, t.item_first, t.queue);
+    SBR_LAUNCHED();
+    if (n_nu > 0) {
         ProfScope ps(kProfSynthAdj, s);
-        hipLaunchKernelGGL(k_synth_adj<kAdjPPL>, grid, dim3(256), lds, s, t.args, t.item_first, n, t.queue,
-                           (int)lds_f2);
+        for (int r = 0; r < n_nu; r++) {
+            const AdjArgs &a = aa[r];
+            float *cr = const_cast<float *>(corr[r]);
+            hipLaunchKernelGGL(k_nu_corr, dim3((unsigned)((a.S + 255) / 256)), dim3(256), 0, s, a.S, cr);
+            const size_t lds = sizeof(float4) * a.S + sizeof(float2) * 2 * a.S;
+            hipLaunchKernelGGL(k_nu_rows, dim3((unsigned)(a.V * a.C)), dim3(256), lds, s, a.G, a.S, a.fcf, a.sl_fs,
+                               cr, const_cast<float4 *>(a.nu_rows));
+        }
+        dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_nu, resident_blocks((const void *)k_synth_adj_nu<kNuPPL>,
+                                                                                         256, 0, 256 * 2))));
+        hipLaunchKernelGGL(k_synth_adj_nu<kNuPPL>, grid, dim3(256), 0, s, t.args, t.item_first, 0, n_nu, t.queue);
+    }
+    SBR_LAUNCHED();
+    if (n_nu < n) {
+        const size_t lds = sizeof(float2) * lds_f2 + 16;
+        // one device-full of blocks, or fewer if the path slots cannot fill it
+        dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_direct, resident_blocks((const void *)k_synth_adj<kAdjPPL>,
+                                                                                             256, lds, 256 * 2))));
+        ProfScope ps(kProfSynthAdj, s);
+        hipLaunchKernelGGL(k_synth_adj<kAdjPPL>, grid, dim3(256), lds, s, t.args, t.item_first, n_nu, n,
+                           t.queue + kAdjQueueDirect, (int)lds_f2);
     }
     SBR_LAUNCHED();
     for (int r = 0; r < n; r++) {

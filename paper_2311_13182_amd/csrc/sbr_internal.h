@@ -219,7 +219,7 @@ struct BackwardReq {
     const sbr_param_grads *params;
     int32_t flags;
 };
-size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V);
+size_t backward_extra_bytes(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S);
 // Device-table bytes of a batch of n adjoints.
 size_t adj_table_bytes(int n);
 // Synthesis adjoint of n requests as one work-queue launch over all their
