@@ -23,6 +23,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
+# LDS bandwidth from the unit counts: 256 CUs x 128 B per clock x 2.4 GHz
+PEAK_LDS_GBS = 256 * 128 * 2.4
+# the spreading of the non-uniform FFT synthesis: 7 taps x (re, im) 64-bit
+# LDS atomic adds per (path, antenna, chirp)
+LDS_BYTES_PER_PAC = 7 * 2 * 8
 FLOP_PER_PATH_SAMPLE = {"synth": 8.0, "synth_adj": 20.0}
 # lane operations per second of the FP32 vector units: 256 CUs x 4 SIMDs x 32
 # lanes x 2.4 GHz (one VALU instruction per lane per clock; an FMA counts once)
@@ -34,6 +39,8 @@ OPS_PER_NODE_TEST, OPS_PER_TRI_TEST = 14, 27
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__k_synth_adj__clutter_50k_fwd_bwd.md")
 KERNEL_SOURCES = {
+    "k_nu_spread": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
+    "k_synth_adj_nu": ["backward.hip", "sbr_internal.h", "sbr_device.h"],
     "k_synth_adj": ["backward.hip", "sbr_internal.h", "sbr_device.h"],
     "k_synth_mfma": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
     "k_synth": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
@@ -211,23 +218,29 @@ def main():
     ms_total = e0.elapsed_time(e1)
     ms_step = ms_total / args.steps
     k_ms = {}
-    for name, kid in (("synth", _lib.PROF_SYNTH), ("synth_adj", _lib.PROF_SYNTH_ADJ), ("trace", _lib.PROF_TRACE)):
+    for name, kid in (("synth", _lib.PROF_SYNTH), ("synth_adj", _lib.PROF_SYNTH_ADJ), ("trace", _lib.PROF_TRACE),
+                      ("nu_spread", _lib.PROF_NU_SPREAD), ("nu_taps", _lib.PROF_NU_TAPS)):
         tot, n = sbr_profile_read(kid)
         k_ms[name] = tot / max(n, 1)
     ps = float(n_paths) * V * C * Sn          # path-samples per launch
-    dominant = max(("synth", "synth_adj"), key=lambda k: k_ms[k])
-    achieved = FLOP_PER_PATH_SAMPLE[dominant] * ps / (k_ms[dominant] * 1e-3) / 1e12
-    # the synthesis runs on the matrix cores for runs of 256 samples, else on the VALU
-    synth_kernel = "k_synth_mfma" if Sn % 256 == 0 else "k_synth"
-    roof = {
-        "bound": "alu",
-        "kernel": "k_synth_adj" if dominant == "synth_adj" else synth_kernel,
-        "achieved": round(achieved, 3),
-        "peak": PEAK_FP32_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-        "traffic": measured_traffic("k_synth_adj" if dominant == "synth_adj" else synth_kernel, args.workload),
-    }
+    pac = float(n_paths) * V * C              # (path, antenna, chirp) per launch
+    nufft = 16 <= Sn <= 1024                  # both sums run as non-uniform FFTs
+    if nufft:
+        # the spreading kernel of the synthesis, bound by its 64-bit LDS atomics:
+        # their operand bytes against the LDS bandwidth of the unit counts
+        achieved = LDS_BYTES_PER_PAC * pac / (k_ms["nu_spread"] * 1e-3) / 1e9
+        roof = {"bound": "lds", "kernel": "k_nu_spread", "achieved": round(achieved, 1), "peak": PEAK_LDS_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_LDS_GBS, 4),
+                "traffic": measured_traffic("k_nu_spread", args.workload)}
+    else:
+        dominant = max(("synth", "synth_adj"), key=lambda k: k_ms[k])
+        achieved = FLOP_PER_PATH_SAMPLE[dominant] * ps / (k_ms[dominant] * 1e-3) / 1e12
+        # the synthesis runs on the matrix cores for runs of 256 samples, else on the VALU
+        synth_kernel = "k_synth_mfma" if Sn % 256 == 0 else "k_synth"
+        kern = "k_synth_adj" if dominant == "synth_adj" else synth_kernel
+        roof = {"bound": "alu", "kernel": kern, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": measured_traffic(kern, args.workload)}
     out = {
         "metric": "ray-bounces/s fwd+bwd",
         "value": queries / (ms_step * 1e-3),
@@ -250,14 +263,16 @@ def main():
         "if_path_samples_per_s": ps / (ms_step * 1e-3),
         "if_output_samples_per_s": V * C * Sn / (ms_step * 1e-3),
         "kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
-        "synth_frac_of_fp32_peak": round(FLOP_PER_PATH_SAMPLE["synth"] * ps / (k_ms["synth"] * 1e-3) / 1e12 /
-                                         PEAK_FP32_TFLOPS, 4),
-        # the synthesis adjoint (Eqs. 11-12) runs as a type-2 non-uniform FFT
-        # (row transforms + 7 kernel taps per path, antenna and chirp), so its
-        # time is reported per (path, antenna, chirp) and as the rate of the
-        # direct sums it replaces, not against the FP32 peak
-        "adjoint": {"form": "nufft" if 16 <= Sn <= 1024 else "direct", "ms": round(k_ms["synth_adj"], 4),
-                    "path_antenna_chirps_per_s": float(n_paths) * V * C / (k_ms["synth_adj"] * 1e-3),
+        # both sums of the path-sample work run as non-uniform FFTs for 16 <= S <= 1024:
+        # times per stage and the rates of the direct sums they replace (which a
+        # direct evaluation could reach at most at the FP32 peak)
+        "synth": {"form": "nufft" if nufft else "direct", "ms": round(k_ms["synth"], 4),
+                  "spread_ms": round(k_ms["nu_spread"], 4) if nufft else None,
+                  "direct_sum_equivalent_tflops": round(FLOP_PER_PATH_SAMPLE["synth"] * ps /
+                                                        (k_ms["synth"] * 1e-3) / 1e12, 2)},
+        "adjoint": {"form": "nufft" if nufft else "direct", "ms": round(k_ms["synth_adj"], 4),
+                    "taps_ms": round(k_ms["nu_taps"], 4) if nufft else None,
+                    "path_antenna_chirps_per_s": pac / (k_ms["synth_adj"] * 1e-3),
                     "direct_sum_equivalent_tflops": round(FLOP_PER_PATH_SAMPLE["synth_adj"] * ps /
                                                           (k_ms["synth_adj"] * 1e-3) / 1e12, 2)},
         "trace": {"ray_bounces_per_s": queries / (k_ms["trace"] * 1e-3), "node_tests": node_tests,

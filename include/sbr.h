@@ -166,11 +166,12 @@ typedef struct {
                                 moving silhouettes then contribute.  The forward
                                 signal is the same; without the flag the gradient is
                                 the pathwise one with fixed ray directions. */
-#define SBR_ADJOINT_DIRECT 8 /* sbr_backward only: evaluate the per-path sums of
-                                Eqs. 11-12 by direct summation over the samples
-                                (Horner's rule) rather than by the non-uniform FFT
-                                (see sbr_backward); chirps of fewer than 16 or more
-                                than 1024 samples always use direct summation    */
+#define SBR_DIRECT_SUMS 8    /* sum Eq. 8 (sbr_synth_if) and the per-path series of
+                                Eqs. 11-12 (sbr_backward) directly over paths and
+                                samples rather than by the non-uniform FFT forms
+                                described at those entry points; chirps of fewer
+                                than 16 or more than 1024 samples always use the
+                                direct sums                                        */
 
 /* scratch-size queries */
 #define SBR_OP_BUILD_BVH 0
@@ -223,6 +224,15 @@ int sbr_trace(const sbr_mesh *mesh, const void *bvh, const sbr_radar *radar,
  * L_k the unfolded path length, R_k = |x_k - origin|, theta_k the incidence
  * angle at the last hit and r_j the material reflection coefficients.
  *   if_cube[v][c][s] = sum_paths I^s exp(2 pi j (slope s / fs + fc) I^t_v(c))
+ * Each row if_cube[v][c][.] is a finite Fourier series in s whose terms sit at
+ * the paths' beat frequencies.  For 16 <= S <= 1024 it is formed by a type-1
+ * non-uniform FFT: every path's term is spread onto a 2S-point grid with 7
+ * exponential-of-semicircle kernel taps, each contribution rounded to an
+ * integer (a power-of-two scale of at least 2^30 / max(|Re I^s|, |Im I^s|))
+ * and accumulated exactly in 64-bit integers, so the result does not depend
+ * on the order of the additions; one DFT per row and the kernel's
+ * deconvolution follow.  Error below 1e-6 of sum_paths |I^s| per sample.
+ * With SBR_DIRECT_SUMS, or for other S, the sum is taken directly.
  * if_cube: device float [V][C][S][2], overwritten.  mats: host array of
  * n_mats (<= 64) entries, or NULL / 0 for all-conductor.  A hit id outside
  * [0, nf) ends its ray like a miss (no face outside the mesh is read). */
@@ -352,7 +362,7 @@ typedef struct {
  * (Eq. 11).  For 16 <= S <= 1024 they are evaluated by a type-2 non-uniform
  * FFT (one 2S-point transform per row, shared by all paths, then 7 kernel taps
  * per path; exponential-of-semicircle kernel), whose error is below 1e-6 of
- * sum_s |weighted G_s| at every g; with SBR_ADJOINT_DIRECT, or for other S, by
+ * sum_s |weighted G_s| at every g; with SBR_DIRECT_SUMS, or for other S, by
  * direct summation.  Arguments as for sbr_synth_if; hits and flags must be
  * those the forward used.  params: NULL,
  * or where to ADD the gradients of the material table (Eqs. 9-10 through
@@ -433,9 +443,12 @@ int sbr_backward_batched(const sbr_request *reqs, int32_t n, void *table, size_t
 int sbr_loss_grad(int32_t mode, const float *a, const float *b, int64_t n, float *grad,
                   float *loss, void *scratch, size_t scratch_bytes, void *stream);
 
-/* Kernel timing for benchmarks.  sbr_profile(1) starts bracketing every launch
- * of the IF synthesis kernel (id 0), the synthesis-adjoint kernel (id 1) and
- * the trace kernel (id 2) with HIP events on the launching stream;
+/* Kernel timing for benchmarks.  sbr_profile(1) starts bracketing, with HIP
+ * events on the launching stream, every IF synthesis (id 0: all kernels of
+ * one request's Eq. 8 stage), synthesis adjoint (id 1: all kernels of one
+ * request's Eqs. 11-12 stage), trace kernel (id 2), and within the
+ * non-uniform FFT forms the spreading kernel of the synthesis (id 3) and the
+ * tap kernel of the adjoint (id 4);
  * sbr_profile(0) stops; sbr_profile(2) discards what was recorded.
  * sbr_profile_read waits for the recorded events of one kernel id and returns
  * the summed milliseconds and the number of launches, then discards them. */

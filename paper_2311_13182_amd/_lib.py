@@ -20,7 +20,7 @@ SBR_RAYS_SHADOW, SBR_RAYS_JITTER = 1, 2
 SBR_DROP_FLAGGED = 1
 SBR_ATTACHED = 2
 SBR_EXIT_ONLY = 4
-SBR_ADJOINT_DIRECT = 8
+SBR_DIRECT_SUMS = 8
 SBR_OP_BUILD_BVH, SBR_OP_SYNTH, SBR_OP_BACKWARD, SBR_OP_RADAR_CUBE, SBR_OP_CFAR = 0, 1, 2, 3, 4
 SBR_LOSS_SCRATCH_BYTES = 8192
 SBR_MAX_BATCH = 1024
@@ -32,7 +32,7 @@ EXPORTS = ("sbr_bvh_bytes", "sbr_scratch_bytes", "sbr_build_bvh", "sbr_trace", "
            "sbr_profile_read", "sbr_radar_cube_2d", "sbr_radar_cube_2d_bytes", "sbr_cloud",
            "sbr_angle_peaks", "sbr_angle_peaks_bytes", "sbr_batch_table_bytes", "sbr_synth_if_batched",
            "sbr_backward_batched", "sbr_radar_cube_noalloc")
-PROF_SYNTH, PROF_SYNTH_ADJ, PROF_TRACE = 0, 1, 2
+PROF_SYNTH, PROF_SYNTH_ADJ, PROF_TRACE, PROF_NU_SPREAD, PROF_NU_TAPS = 0, 1, 2, 3, 4
 
 
 class SbrError(RuntimeError):

@@ -200,28 +200,42 @@ ChirpDev make_chirp(const sbr_chirp *c) {
     return d;
 }
 
-// Scratch of one synthesis: path stage, chunk partials, a one-request table.
+// Scratch of one synthesis: path stage, chunk partials (direct forms) or
+// fixed-point grids, 1/Psi table and amplitude word (non-uniform FFT form), a
+// one-request table.
 struct SynthCarve {
     PathStage st;
     SynthPlan p;
     float2 *partial;
+    long long *grid;
+    float *corr;
+    uint32_t *amax;
     void *table;
     size_t bytes;
 };
 
-static SynthCarve synth_carve(void *scratch, int R, int K, int V, int C, int S) {
+static SynthCarve synth_carve(void *scratch, int R, int K, int V, int C, int S, bool nu) {
     SynthCarve c;
     Carver cv(scratch);
     c.st = carve_path_stage(cv, R, K, V);
-    c.p = synth_plan(R, K, V, C, S);
-    c.partial = cv.take<float2>(synth_partial_elems(c.p, V, C, S));
+    c.p = synth_plan(R, K, V, C, S, nu);
+    c.partial = nu ? nullptr : cv.take<float2>(synth_partial_elems(c.p, V, C, S));
+    c.grid = nu ? cv.take<long long>(synth_grid_words(c.p, V, C, S)) : nullptr;
+    c.corr = nu ? cv.take<float>((size_t)S) : nullptr;
+    c.amax = nu ? cv.take<uint32_t>(64) : nullptr;
     c.table = cv.take<char>(synth_table_bytes(1));
     c.bytes = align_up(cv.off, 256);
     return c;
 }
 
+// Whether a synthesis request runs as the non-uniform FFT form.
+static bool synth_nu(int S, int32_t flags) { return nu_size(S) && !(flags & SBR_DIRECT_SUMS); }
+
+// Scratch bytes of a synthesis, whichever form its flags select.
 static size_t synth_bytes(int R, int K, int V, int C, int S) {
-    return synth_carve(nullptr, R, K, V, C, S).bytes;
+    size_t b = synth_carve(nullptr, R, K, V, C, S, false).bytes;
+    if (nu_size(S)) b = std::max(b, synth_carve(nullptr, R, K, V, C, S, true).bytes);
+    return b;
 }
 
 // Scratch of one backward pass: path stage, adjoint buffers, a one-request table.
@@ -251,7 +265,7 @@ static int check_synth(const sbr_mesh *mesh, const sbr_material *mats, int32_t n
     int rc;
     if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
     SBR_CHECK_ARG(if_cube, "if_cube is NULL");
-    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_EXIT_ONLY)) == 0, "unknown flags 0x%x", flags);
+    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_EXIT_ONLY | SBR_DIRECT_SUMS)) == 0, "unknown flags 0x%x", flags);
     const size_t need = synth_bytes(rays->nx * rays->ny, rays->max_bounces, radar->n_tx * radar->n_rx,
                                     chirp->n_chirps, chirp->n_samples);
     if (!scratch || scratch_bytes < need) {
@@ -269,7 +283,7 @@ static int check_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_
     int rc;
     if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
     SBR_CHECK_ARG(grad_if && grad_verts, "grad_if/grad_verts is NULL");
-    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY | SBR_ADJOINT_DIRECT)) == 0,
+    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY | SBR_DIRECT_SUMS)) == 0,
                   "unknown flags 0x%x", flags);
     SBR_CHECK_ARG(!params || !params->materials || (mats && n_mats > 0),
                   "material gradients requested without a material table");
@@ -295,12 +309,12 @@ static int enqueue_synth(const sbr_mesh *mesh, const sbr_material *mats, int32_t
         *skip = 1;
         return fill_zero_f32(if_cube, (size_t)2 * V * C * S, s);
     }
-    SynthCarve c = synth_carve(scratch, R, K, V, C, S);
+    SynthCarve c = synth_carve(scratch, R, K, V, C, S, synth_nu(S, flags));
     int rc;
     if ((rc = launch_paths(mesh, make_mats(mats, n_mats), make_radar(radar), make_grid(rays), make_chirp(chirp),
                            hits, flags, c.st, s)))
         return rc;
-    *args = synth_args(c.st, c.p, V, C, S, c.partial);
+    *args = synth_args(c.st, c.p, V, C, S, c.partial, c.grid, c.corr, c.amax);
     *L = c.p.L;
     if (table) *table = c.table;
     return SBR_OK;

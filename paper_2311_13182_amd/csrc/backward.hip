@@ -38,25 +38,15 @@ constexpr int kAdjQueueDirect = 32;   // work counter of the direct form (queue[
 // [-1/2, 1/2]):
 //   P(g) = sum_s h1_s e^{2 pi j s g},  h1_s = conj(G_s)
 //   Q(g) = sum_s h2_s e^{2 pi j s g},  h2_s = conj(G_s) (fc + (slope/fs) s)
-// (Q = fc P + (slope/fs) x P'(x) of the direct form).  With the modes centred
-// (s' = s - S/2), a grid of M = 2S points and a kernel psi of width W grid
-// points whose Fourier transform is Psi,
+// (Q = fc P + (slope/fs) x P'(x) of the direct form).  By the identity of the
+// non-uniform FFT forms (sbr_internal.h),
 //   P(g) = e^{2 pi j g S/2} sum_l u_l psi(gM - l),
-//   u_l  = sum_s' (h_{s'+S/2} / Psi(s'/M)) e^{2 pi j s' l / M},
-// up to the kernel's aliasing error.  The rows u (one per (v, c), shared by
-// every path) cost one dense DFT each; a path then needs W taps per (v, c)
-// instead of S terms.  Kernel: exponential of semicircle,
-// psi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)), W = 7, beta = 2.3 W, for which
-// the evaluation error stays below 1e-6 of sum_s |h_s| at every g (two orders
-// of magnitude under the FP32 rounding of a 256-term direct sum).
-constexpr int kNuW = 7;
-constexpr int kNuHalf = (kNuW - 1) / 2;
-constexpr double kNuBeta = 2.30 * kNuW;
-constexpr int kNuMinS = 16;     // shorter chirps use the direct form (cheap there)
-constexpr int kNuMaxS = 1024;   // longer chirps use the direct form
+//   u_l  = sum_s' (h_{s'+S/2} / Psi(s'/M)) e^{2 pi j s' l / M}:
+// the rows u (one per (v, c), shared by every path) cost one dense DFT each,
+// and a path then needs kNuW taps per (v, c) instead of S terms; the error
+// stays below 1e-6 of sum_s |h_s| at every g (two orders of magnitude under
+// the FP32 rounding of a 256-term direct sum).
 constexpr int kNuSteps = 16;    // trapezoid points per grid unit for Psi
-
-__host__ __device__ constexpr int nu_row_len(int S) { return 2 * S + 8; }   // l = -M/2-3 .. M/2+3, + 1 pad
 
 // float4's layout for address-space-qualified 16-byte loads of the rows
 struct alignas(16) F4 {
@@ -66,6 +56,8 @@ __device__ __forceinline__ SBR_GLOBAL_AS const F4 *gmem4(const float4 *p) { retu
 
 // frac(n f) for an integer-valued n < 2^24: the product is exact inside the fma
 __device__ __forceinline__ float frac_of_product(float n, float f) { return fmaf(n, f, -rintf(n * f)); }
+
+}  // namespace
 
 // 1 / Psi((s - S/2) / M), s < S, with Psi(xi) = int psi(z) e^{-2 pi j xi z} dz
 // by the trapezoid rule at kNuSteps points per grid unit (psi vanishes with
@@ -93,6 +85,14 @@ __global__ __launch_bounds__(256) void k_nu_corr(int S, float *corr) {
     }
     corr[s] = (float)((double)kNuSteps / acc);
 }
+
+int launch_nu_corr(int32_t S, float *corr, hipStream_t s) {
+    hipLaunchKernelGGL(k_nu_corr, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, corr);
+    SBR_LAUNCHED();
+    return SBR_OK;
+}
+
+namespace {
 
 // Row (v, c) = blockIdx.x: u1_l, u2_l (float4: u1.re, u1.im, u2.re, u2.im)
 // for l = -M/2 - 3 .. M/2 + 3 at index l + M/2 + 3, by a direct DFT over the
@@ -171,8 +171,7 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, const int P, const
     }
     const int S = a.S, M = 2 * S, RL = nu_row_len(S);
     const float Mf = (float)M, halfS = (float)(S / 2);
-    const float zstep = 2.0f / kNuW;                           // kernel argument per grid point
-    const float kb = (float)(kNuBeta * 1.4426950408889634);    // beta log2(e)
+    const float zstep = 2.0f / kNuW;   // kernel argument per grid point
     const int v0 = grp * a.v_per, v1 = min(a.V, v0 + a.v_per);
     for (int v = v0; v < v1; v++) {
         float alpha[PPL], gamma[PPL], tb[PPL];
@@ -192,7 +191,7 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, const int P, const
                 const float g = f - rintf(f);   // [-1/2, 1/2]
                 const float x = g * Mf;         // exact
                 const float xr = rintf(x);
-                const int i0 = (int)xr + M / 2;   // row index of l0 = xr - 3
+                const int i0 = min(max((int)xr + M / 2, 0), M);   // row index of l0 = xr - 3 (clamped: NaN-safe)
                 F4 u[kNuW];
 #pragma unroll
                 for (int t = 0; t < kNuW; t++) u[t] = row[i0 + t];
@@ -200,9 +199,7 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, const int P, const
                 float pr = 0.f, pi = 0.f, qr = 0.f, qi = 0.f;
 #pragma unroll
                 for (int t = 0; t < kNuW; t++) {
-                    const float z = fmaf(-(float)t, zstep, zt0);
-                    const float q = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
-                    const float w = __builtin_amdgcn_exp2f(fmaf(kb, __builtin_amdgcn_sqrtf(q), -kb));
+                    const float w = nu_weight(fmaf(-(float)t, zstep, zt0));
                     pr = fmaf(w, u[t].x, pr);
                     pi = fmaf(w, u[t].y, pi);
                     qr = fmaf(w, u[t].z, qr);
@@ -908,8 +905,7 @@ static BackPlan back_plan(long long cap, int V) {
 }
 
 // Whether a request's adjoint sums run as the non-uniform FFT form.
-static bool nu_size(int32_t S) { return S >= kNuMinS && S <= kNuMaxS; }
-static bool use_nu(int32_t S, int32_t flags) { return nu_size(S) && !(flags & SBR_ADJOINT_DIRECT); }
+static bool use_nu(int32_t S, int32_t flags) { return nu_size(S) && !(flags & SBR_DIRECT_SUMS); }
 
 // Adjoint buffers after the path stage: tau_bar, Abar and taudot_bar partials
 // and sums, then (for chirps of kNuMinS .. kNuMaxS samples, whatever the
@@ -1067,13 +1063,14 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
         for (int r = 0; r < n_nu; r++) {
             const AdjArgs &a = aa[r];
             float *cr = const_cast<float *>(corr[r]);
-            hipLaunchKernelGGL(k_nu_corr, dim3((unsigned)((a.S + 255) / 256)), dim3(256), 0, s, a.S, cr);
+            if ((rc = launch_nu_corr(a.S, cr, s))) return rc;
             const size_t lds = sizeof(float4) * a.S + sizeof(float2) * 2 * a.S;
             hipLaunchKernelGGL(k_nu_rows, dim3((unsigned)(a.V * a.C)), dim3(256), lds, s, a.G, a.S, a.fcf, a.sl_fs,
                                cr, const_cast<float4 *>(a.nu_rows));
         }
         dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_nu, resident_blocks((const void *)k_synth_adj_nu<kNuPPL>,
                                                                                          256, 0, 256 * 2))));
+        ProfScope pk(kProfNuTaps, s);
         hipLaunchKernelGGL(k_synth_adj_nu<kNuPPL>, grid, dim3(256), 0, s, t.args, t.item_first, 0, n_nu, t.queue);
     }
     SBR_LAUNCHED();

@@ -67,13 +67,13 @@ struct ProfRec {
 };
 std::mutex g_mu;
 bool g_on = false;
-std::vector<ProfRec> g_rec[3];
+std::vector<ProfRec> g_rec[kProfIds];
 
 }  // namespace
 
 ProfScope::ProfScope(int id, hipStream_t s) : id_(id), s_(s), active_(false) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_on || id < 0 || id > 2) return;
+    if (!g_on || id < 0 || id >= kProfIds) return;
     if (hipEventCreate(&a_) != hipSuccess) return;
     if (hipEventCreate(&b_) != hipSuccess) {
         (void)hipEventDestroy(a_);
@@ -185,7 +185,7 @@ int sbr_profile(int32_t op) {
 
 int sbr_profile_read(int32_t kernel, double *total_ms, int64_t *launches) {
     clear_error();
-    SBR_CHECK_ARG(kernel >= 0 && kernel <= 2, "kernel id must be 0, 1 or 2");
+    SBR_CHECK_ARG(kernel >= 0 && kernel < kProfIds, "kernel id must be in [0, %d)", kProfIds);
     SBR_CHECK_ARG(total_ms && launches, "outputs are NULL");
     std::vector<ProfRec> recs;
     {

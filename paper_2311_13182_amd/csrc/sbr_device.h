@@ -159,4 +159,14 @@ __device__ __forceinline__ uint32_t ray_path_mask(const int32_t *tri, const uint
     return mask;
 }
 
+
+// Kernel weight psi of the non-uniform FFT forms at the kernel argument z =
+// 2 (distance in grid points) / W, |z| <= 1 (clamped against rounding just
+// past 1): exp(beta (sqrt(1 - z^2) - 1)) from the hardware sqrt and exp2.
+__device__ __forceinline__ float nu_weight(float z) {
+    constexpr float kb = (float)(kNuBeta * 1.4426950408889634);   // beta log2(e)
+    const float q = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+    return __builtin_amdgcn_exp2f(fmaf(kb, __builtin_amdgcn_sqrtf(q), -kb));
+}
+
 }  // namespace sbr

@@ -157,6 +157,7 @@ constexpr int kPathBlock = 256;   // rays per block of the compaction kernels
 // chirp row, tiles_per_v wavefronts per antenna, n_chunks path chunks.
 struct SynthPlan {
     int32_t L, SB, tiles_per_v, n_chunks;
+    int32_t nu, cg;      // non-uniform FFT form (L = 0): chirps per spreading block
 };
 
 // A pointer read from a device table is generic; marking it global lets the
@@ -187,18 +188,28 @@ struct SynthArgs {
     int32_t tiles_per_v; // wavefront tiles per antenna
     int32_t n_chunks;
     int32_t gx;          // blocks per chunk (4 wavefronts each)
-    float2 *partial;     // [n_chunks][V][C][S]
+    float2 *partial;     // [n_chunks][V][C][S] (direct forms)
+    // non-uniform FFT form (nu = 1): chirps per spreading block, chirp groups;
+    // the max-amplitude word, the 1/Psi table and the fixed-point grids
+    int32_t nu, cg, ncg;
+    uint32_t *amax;      // [1] max over paths of max(|Re A|, |Im A|), float bits
+    float *corr;         // [S]
+    long long *grid;     // [n_chunks][V][C][re, im][nu_row_len(S)]
 };
 
 PathStage carve_path_stage(Carver &cv, int32_t R, int32_t K, int32_t V);
-SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S);
+SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S, bool nu);
 size_t synth_partial_elems(const SynthPlan &p, int32_t V, int32_t C, int32_t S);
-SynthArgs synth_args(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial);
+// Fixed-point grid words (long long) of the non-uniform FFT form.
+size_t synth_grid_words(const SynthPlan &p, int32_t V, int32_t C, int32_t S);
+SynthArgs synth_args(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial,
+                     long long *grid, float *corr, uint32_t *amax);
 // Device-table bytes of a batch of n syntheses.
 size_t synth_table_bytes(int n);
 // IF synthesis of n requests whose path stages are enqueued: one launch per
 // sample-run length over all their blocks (args[i] and L[i] = synth_plan's L),
-// then each request's fixed-order chunk reduction into out[i].
+// then each request's fixed-order chunk reduction into out[i]; requests of the
+// non-uniform FFT form (L[i] = 0) run their own spreading and row launches.
 int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, float2 *const *out,
                        hipStream_t s);
 
@@ -227,6 +238,27 @@ size_t adj_table_bytes(int n);
 // geometry adjoint.
 int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream_t s);
 
+// ---- non-uniform FFT forms of Eq. (8) (type 1) and Eqs. (11)-(12) (type 2)
+// A sum over the S samples of a chirp, sum_s h_s e^{2 pi j s g}, is a finite
+// Fourier series at the beat frequency g of a path.  With the modes centred
+// (s' = s - S/2), a grid of M = 2S points and a kernel psi of width kNuW grid
+// points whose Fourier transform is Psi:
+//   e^{2 pi j s' g} Psi(s'/M) = sum_l e^{2 pi j s' l / M} psi(gM - l)
+// up to the kernel's aliasing error, which is below 1e-6 of the sum of the
+// magnitudes of the terms for the exponential-of-semicircle kernel
+// psi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)), W = 7, beta = 2.3 W.  Rows of
+// grid values hold l = -M/2 - 3 .. M/2 + 3 at index l + M/2 + 3, plus one
+// padding entry.
+constexpr int kNuW = 7;
+constexpr int kNuHalf = (kNuW - 1) / 2;
+constexpr double kNuBeta = 2.30 * kNuW;
+constexpr int kNuMinS = 16;     // shorter chirps use the direct forms (cheap there)
+constexpr int kNuMaxS = 1024;   // longer chirps use the direct forms
+__host__ __device__ constexpr int nu_row_len(int S) { return 2 * S + 8; }
+static inline bool nu_size(int S) { return S >= kNuMinS && S <= kNuMaxS; }
+// Enqueue corr[s] = 1 / Psi((s - S/2) / 2S), s < S.
+int launch_nu_corr(int32_t S, float *corr, hipStream_t s);
+
 // Copy `bytes` (a multiple of 4) of host data into device memory on stream s
 // with fill kernels that carry the data as kernel arguments: no memcpy node,
 // and the host data need not outlive the call.
@@ -254,7 +286,7 @@ class ProfScope {
     bool active_;
     hipEvent_t a_{}, b_{};
 };
-enum { kProfSynth = 0, kProfSynthAdj = 1, kProfTrace = 2 };
+enum { kProfSynth = 0, kProfSynthAdj = 1, kProfTrace = 2, kProfNuSpread = 3, kProfNuTaps = 4, kProfIds = 5 };
 
 // Blocks of `kernel` (launched with `threads` threads and `lds` bytes of
 // dynamic LDS) the current device holds at once: CUs times the occupancy the

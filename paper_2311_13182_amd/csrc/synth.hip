@@ -589,6 +589,172 @@ __global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, f
     out[e] = make_float2((s[0].x + s[1].x) + (s[2].x + s[3].x), (s[0].y + s[1].y) + (s[2].y + s[3].y));
 }
 
+// ---- Eq. (8) by a type-1 non-uniform FFT ----------------------------------
+// Row [v][c][.] of the cube is sum_p w_p e^{2 pi j s g_p}, g_p = gamma_p +
+// c eps_p reduced to [-1/2, 1/2] and w_p = A_p e^{2 pi j (alpha_p + c beta_p)}.
+// With centred modes s' = s - S/2 and w'_p = w_p e^{2 pi j g_p S/2}, the
+// identity of the non-uniform FFT forms (sbr_internal.h) gives
+//   row[s' + S/2] = (1 / Psi(s'/M)) sum_l b_l e^{2 pi j s' l / M},
+//   b_l = sum_p w'_p psi(g_p M - l),
+// so each path adds kNuW weighted copies of w'_p to a grid of M = 2S points
+// (spreading), and one DFT per row and the deconvolution finish it.  The
+// spreading rounds every contribution to an integer of the scale
+// 2^(30 - e), max(|Re A|, |Im A|) < 2^e (so below 2^31 in magnitude), and
+// adds it to 64-bit integer cells: integer addition is exact, so the grid and
+// the cube do not depend on the order in which blocks, waves or lanes add.
+
+// max over the live paths of max(|Re A|, |Im A|), as the bits of a
+// non-negative float: an integer maximum, exact and order-independent.
+__global__ __launch_bounds__(256) void k_nu_amax(const int32_t *__restrict__ count, const float2 *__restrict__ amp,
+                                                 uint32_t *amax) {
+    const int P = *count;
+    uint32_t m = 0;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256) {
+        const float2 A = amp[p];
+        m = max(m, __float_as_uint(fmaxf(fabsf(A.x), fabsf(A.y))));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0 && m != 0u) atomicMax(amax, m);
+}
+
+// Fixed-point scale 2^(30 - e) with max(|Re A|, |Im A|) = amax < 2^e, so that
+// |A psi| <= sqrt(2) amax stays below 2^31 after scaling; e is held in
+// [-90, 128] so that the scale is a finite normal float.
+__device__ __forceinline__ float nu_scale(uint32_t amax_bits) {
+    int e = 0;
+    const float amax = __uint_as_float(amax_bits);
+    if (amax > 0.0f && amax_bits < 0x7f800000u) (void)frexpf(amax, &e);
+    return ldexpf(1.0f, 30 - max(e, -90));
+}
+
+constexpr int kNuSpreadThreads = 1024;
+
+// Spreading: block = (path chunk, antenna v, group of cg chirps), grid rows
+// [cg][re, im][nu_row_len(S)] of 64-bit cells in LDS (real and imaginary rows
+// apart, so that lanes at random cells spread over all banks); each thread
+// takes a contiguous share of the chunk (neighbouring paths come from
+// neighbouring rays and share their beat frequency, so lanes of a wave that
+// took neighbouring paths would all add to the same cells), and for each chirp
+// of the group adds its kNuW contributions with 64-bit integer LDS atomics;
+// the rows then go to the chunk's partial.
+__global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args, int idx) {
+    extern __shared__ long long nsp[];
+    const SynthArgs &a = args[idx];
+    const int S = a.S, M = 2 * S, RL = nu_row_len(S);
+    const int blk = (int)blockIdx.x;
+    const int cgi = blk % a.ncg, rest = blk / a.ncg;
+    const int v = rest % a.V, chunk = rest / a.V;
+    const int c0 = cgi * a.cg, nc = min(a.cg, a.C - c0);
+    for (int i = threadIdx.x; i < nc * RL * 2; i += blockDim.x) nsp[i] = 0;
+    __syncthreads();
+    const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
+    const long long per = ((long long)P + a.n_chunks - 1) / a.n_chunks;
+    const int p0 = (int)min((long long)P, per * chunk);
+    const int p1 = (int)min((long long)P, per * (chunk + 1));
+    const float sigma = nu_scale(*gmem(a.amax));
+    const auto al = gmem(a.rec.alpha + (size_t)v * a.rec.cap);
+    const auto ga = gmem(a.rec.gamma + (size_t)v * a.rec.cap);
+    const auto amp = gmem(a.rec.amp);
+    const auto bet = gmem(a.rec.beta);
+    const auto eps = gmem(a.rec.epsd);
+    const float Mf = (float)M, halfS = (float)(S / 2);
+    const float zstep = 2.0f / kNuW;   // kernel argument per grid point
+    const int share = (p1 - p0 + kNuSpreadThreads - 1) / kNuSpreadThreads;
+    const int q0 = p0 + (int)threadIdx.x * share, q1 = min(p1, q0 + share);
+    for (int p = q0; p < q1; p++) {
+        const float alpha = al[p], gamma = ga[p], beta = bet[p], epsd = eps[p];
+        const F2 A = amp[p];
+        const float Ax = A.x * sigma, Ay = A.y * sigma;
+        // each lane walks the group's chirps from its own starting row, so
+        // that the lanes of one instruction add to different rows: paths
+        // share few beat frequencies (a radar scene fills few range bins),
+        // and same-cell additions within one instruction serialise
+        int cl = (int)(threadIdx.x & 63) % nc;
+        for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
+            const float cf = (float)(c0 + cl);
+            const float f = fmaf(cf, epsd, gamma);
+            const float g = f - rintf(f);   // [-1/2, 1/2]
+            const float x = g * Mf;         // exact
+            const float xr = rintf(x);
+            const int j0 = min(max((int)xr + M / 2, 0), M);   // cell of l0 = xr - 3 (clamped: NaN-safe)
+            float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
+            th -= rintf(th);
+            const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
+            const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
+            const float zt0 = (x - xr + (float)kNuHalf) * zstep;   // kernel argument of tap 0
+            unsigned long long *cell = reinterpret_cast<unsigned long long *>(nsp) + (size_t)2 * cl * RL + j0;
+#pragma unroll
+            for (int t = 0; t < kNuW; t++) {
+                const float w = nu_weight(fmaf(-(float)t, zstep, zt0));
+                const long long yr = (long long)(int)rintf(wr * w), yi = (long long)(int)rintf(wi * w);
+                atomicAdd(cell + t, (unsigned long long)yr);
+                atomicAdd(cell + RL + t, (unsigned long long)yi);
+            }
+        }
+    }
+    __syncthreads();
+    long long *dst = a.grid + (((size_t)chunk * a.V + v) * a.C + c0) * (size_t)RL * 2;
+    for (int i = threadIdx.x; i < nc * RL * 2; i += blockDim.x) dst[i] = nsp[i];
+}
+
+// Row (v, c) = blockIdx.x of the non-uniform FFT form: the chunks' integer
+// cells summed and folded onto the periodic grid (cell l of l + M/2 + 3 and,
+// for the first 2 kNuHalf + 1 positions, of l + 3M/2 + 3), scaled back to FP64,
+// then the DFT to the S centred modes with exact-index twiddles and the
+// deconvolution 1/Psi.  A non-finite amplitude makes the row NaN, as the
+// direct sum would.
+__global__ __launch_bounds__(256) void k_nu_synth_rows(const SynthArgs *__restrict__ args, int idx,
+                                                       float2 *__restrict__ out) {
+    extern __shared__ double2 nrs[];
+    const SynthArgs &a = args[idx];
+    const int S = a.S, M = 2 * S, RL = nu_row_len(S);
+    double2 *b = nrs;        // [M]
+    double2 *tw = nrs + M;   // [M]
+    const size_t row = blockIdx.x;
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * k / M, &sn, &cs);
+        tw[k] = make_double2(cs, sn);
+    }
+    const uint32_t ab = *gmem(a.amax);
+    const double inv = 1.0 / (double)nu_scale(ab);
+    const size_t chunk_stride = (size_t)a.V * a.C * RL * 2;
+    for (int l = threadIdx.x; l < M; l += blockDim.x) {
+        const int j1 = (l + M / 2 + kNuHalf) % M;
+        const bool wrap = j1 + M < RL - 1;
+        long long re = 0, im = 0;
+        const long long *src = a.grid + row * RL * 2;   // real row, then imaginary row
+        for (int ch = 0; ch < a.n_chunks; ch++, src += chunk_stride) {
+            re += src[j1];
+            im += src[RL + j1];
+            if (wrap) {
+                re += src[j1 + M];
+                im += src[RL + j1 + M];
+            }
+        }
+        b[l] = make_double2((double)re * inv, (double)im * inv);
+    }
+    __syncthreads();
+    const bool bad = ab >= 0x7f800000u;
+    const auto corr = gmem(a.corr);
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        const int step = ((s - S / 2) % M + M) % M;   // s' mod M
+        int k = 0;
+        double fr = 0.0, fi = 0.0;
+        for (int l = 0; l < M; l++) {
+            const double2 t = tw[k], bb = b[l];
+            fr = fma(bb.x, t.x, fma(-bb.y, t.y, fr));
+            fi = fma(bb.x, t.y, fma(bb.y, t.x, fi));
+            k += step;
+            if (k >= M) k -= M;
+        }
+        const double cr = corr[s];
+        out[row * S + s] = bad ? make_float2(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000))
+                               : make_float2((float)(fr * cr), (float)(fi * cr));
+    }
+}
+
 }  // namespace
 
 __global__ void k_zero_f32(float *p, size_t n) {
@@ -623,8 +789,37 @@ static int resident_synth_blocks(int L) {
 // wave's run time.  The plan
 // depends only on the request's own sizes (and the device), so a request
 // runs the same waves alone and in a batch.
-SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
-    SynthPlan p;
+// LDS bytes a spreading block of the non-uniform FFT form may hold: the
+// device's per-block limit (160 KiB on gfx950), at most 160 KiB.
+static int nu_lds_budget() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        v = 65536;
+    return std::min(v, 160 * 1024);
+}
+
+// Non-uniform FFT form: as many chirps per spreading block as the LDS holds
+// (at most 16; each block reads its chunk's path records once for all of
+// them), and path chunks enough for about three blocks per CU over the
+// device, each of at least 2048 path slots.  Depends only on the request's
+// sizes and the device, so a request runs the same blocks alone and in a batch.
+static SynthPlan nu_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
+    SynthPlan p{};
+    p.nu = 1;
+    p.L = 0;
+    const long long row_bytes = (long long)nu_row_len(S) * 16;
+    p.cg = (int32_t)std::max(1LL, std::min<long long>({16LL, (long long)C, nu_lds_budget() / row_bytes}));
+    const long long ncg = (C + p.cg - 1) / p.cg;
+    const long long cap = (long long)R * K;
+    const long long want = (768 + (long long)V * ncg - 1) / ((long long)V * ncg);
+    p.n_chunks = (int32_t)std::max(1LL, std::min({want, (cap + 2047) / 2048, 256LL}));
+    return p;
+}
+
+SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S, bool nu) {
+    if (nu) return nu_plan(R, K, V, C, S);
+    SynthPlan p{};
     if (S % kMfmaRun == 0) {   // matrix-core form: SB runs per chirp row, waves per antenna
         p.L = kMfmaRun;
         p.SB = S / kMfmaRun;
@@ -651,11 +846,16 @@ SynthPlan synth_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
 }
 
 size_t synth_partial_elems(const SynthPlan &p, int32_t V, int32_t C, int32_t S) {
-    return (size_t)p.n_chunks * V * C * S;
+    return p.nu ? 0 : (size_t)p.n_chunks * V * C * S;
 }
 
-SynthArgs synth_args(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial) {
-    SynthArgs a;
+size_t synth_grid_words(const SynthPlan &p, int32_t V, int32_t C, int32_t S) {
+    return p.nu ? (size_t)p.n_chunks * V * C * nu_row_len(S) * 2 : 0;
+}
+
+SynthArgs synth_args(const PathStage &st, const SynthPlan &p, int32_t V, int32_t C, int32_t S, float2 *partial,
+                     long long *grid, float *corr, uint32_t *amax) {
+    SynthArgs a{};
     a.count = st.count;
     a.rec = st.rec;
     a.V = V;
@@ -666,6 +866,12 @@ SynthArgs synth_args(const PathStage &st, const SynthPlan &p, int32_t V, int32_t
     a.n_chunks = p.n_chunks;
     a.gx = (int32_t)(((long long)V * p.tiles_per_v + 3) / 4);
     a.partial = partial;
+    a.nu = p.nu;
+    a.cg = p.cg;
+    a.ncg = p.nu ? (C + p.cg - 1) / p.cg : 0;
+    a.grid = grid;
+    a.corr = corr;
+    a.amax = amax;
     return a;
 }
 
@@ -732,11 +938,37 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
     }
     SBR_LAUNCHED();
     for (int i = 0; i < n; i++) {
+        if (args[i].nu) continue;
         const size_t e = (size_t)args[i].V * args[i].C * args[i].S;
         hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, args[i].partial,
                            args[i].n_chunks, e, out[i]);
     }
     SBR_LAUNCHED();
+    // the non-uniform FFT form, request by request: amplitude bound, 1/Psi,
+    // spreading, row transforms
+    for (int i = 0; i < n; i++) {
+        const SynthArgs &a = args[i];
+        if (!a.nu) continue;
+        ProfScope ps(kProfSynth, s);
+        if ((rc = fill_zero_f32(reinterpret_cast<float *>(a.amax), 1, s))) return rc;
+        const long long cap = a.rec.cap;
+        hipLaunchKernelGGL(k_nu_amax, dim3((unsigned)std::max(1LL, std::min((cap + 255) / 256, 1024LL))), dim3(256), 0,
+                           s, a.count, a.rec.amp, a.amax);
+        SBR_LAUNCHED();
+        if ((rc = launch_nu_corr(a.S, a.corr, s))) return rc;
+        const size_t lds = (size_t)a.cg * nu_row_len(a.S) * 16;
+        if (lds > 65536)
+            SBR_HIP(hipFuncSetAttribute((const void *)k_nu_spread, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        const long long blocks = (long long)a.n_chunks * a.V * a.ncg;
+        {
+            ProfScope pk(kProfNuSpread, s);
+            hipLaunchKernelGGL(k_nu_spread, dim3((unsigned)blocks), dim3(kNuSpreadThreads), lds, s, t.args, i);
+        }
+        SBR_LAUNCHED();
+        hipLaunchKernelGGL(k_nu_synth_rows, dim3((unsigned)((size_t)a.V * a.C)), dim3(256),
+                           (size_t)2 * 2 * a.S * sizeof(double2), s, t.args, i, out[i]);
+        SBR_LAUNCHED();
+    }
     return SBR_OK;
 }
 

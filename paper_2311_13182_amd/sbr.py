@@ -487,10 +487,13 @@ class Simulator:
                   self.counters if count else None)
         return self.hits
 
-    def synth(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def synth(self, out: Optional[torch.Tensor] = None, direct_sums: bool = False) -> torch.Tensor:
+        """IF cube (Eq. 8) of the current hits.  direct_sums=True sums over the
+        paths directly instead of by the non-uniform FFT form."""
         if out is None:
             out = torch.empty((self.V, self.C, self.S, 2), dtype=torch.float32, device=self.device)
-        sbr_synth_if(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, self.flags, out,
+        flags = self.flags | (L.SBR_DIRECT_SUMS if direct_sums else 0)
+        sbr_synth_if(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, flags, out,
                      self.scratch)
         return out
 
@@ -564,18 +567,18 @@ class Simulator:
     def backward(self, grad_if: torch.Tensor, grad_verts: Optional[torch.Tensor] = None,
                  grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,
                  grad_rot: Optional[torch.Tensor] = None, attached: bool = False,
-                 grad_atten: Optional[torch.Tensor] = None, direct_adjoint: bool = False) -> torch.Tensor:
+                 grad_atten: Optional[torch.Tensor] = None, direct_sums: bool = False) -> torch.Tensor:
         """dL/dverts (accumulated into grad_verts); optionally also accumulates
         dL/d(eps_r, sigma) per material [n_mats,2], dL/d(origin, velocity) [6]
         dL/d rot [3,3] (radar -> world, row-major) and dL/d attenuation [1].  attached=True
         differentiates the reparameterised estimator (samples follow their
         first hit, Eqs. 6-7), so that moving silhouettes contribute.
-        direct_adjoint=True sums the per-path adjoint series of Eqs. 11-12
+        direct_sums=True sums the per-path adjoint series of Eqs. 11-12
         directly over the samples instead of by the non-uniform FFT."""
         gf = (torch.view_as_real(grad_if) if grad_if.is_complex() else grad_if).contiguous().to(torch.float32)
         if grad_verts is None:
             grad_verts = torch.zeros((self.mesh.nv, 3), dtype=torch.float32, device=self.device)
-        flags = self.flags | (L.SBR_ATTACHED if attached else 0) | (L.SBR_ADJOINT_DIRECT if direct_adjoint else 0)
+        flags = self.flags | (L.SBR_ATTACHED if attached else 0) | (L.SBR_DIRECT_SUMS if direct_sums else 0)
         sbr_backward(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, flags, gf,
                      grad_verts, self.scratch, grad_materials, grad_radar, grad_rot, grad_atten)
         return grad_verts

@@ -111,17 +111,20 @@ def _synth_case(name):
     raise KeyError(name)
 
 
+@pytest.mark.parametrize("form", ["nufft", "direct"])
 @pytest.mark.parametrize("case", ["trihedral_plate", "icosphere_128_c8", "fresnel_mixed", "ragged",
                                   "short_chirp"])
-def test_synth_on_oracle_hits(torch_cuda, orc, case):
+def test_synth_on_oracle_hits(torch_cuda, orc, case, form):
+    """IF cube vs the oracle's direct FP64 sum, by the non-uniform FFT form
+    (16 <= S <= 1024) and by the direct forms (SBR_DIRECT_SUMS)."""
     sc = _synth_case(case)
-    log(f"synth {case}: V={sc.radar.n_virtual} C={sc.chirp.n_chirps} S={sc.chirp.n_samples}")
+    log(f"synth {case} ({form}): V={sc.radar.n_virtual} C={sc.chirp.n_chirps} S={sc.chirp.n_samples}")
     o = orc.trace(sc)
     p = orc.paths(sc, o["tri"], o["flags"])
     ref = orc.synth(sc, p)
     sim = _sim(sc)
     sim.hits = device_hits_from_oracle(o)
-    out = sim.synth()
+    out = sim.synth(direct_sums=form == "direct")
     torch_cuda.cuda.synchronize()
     got = _cube_np(out)
     assert sim.n_paths() == len(p["amp"])
@@ -130,10 +133,12 @@ def test_synth_on_oracle_hits(torch_cuda, orc, case):
     assert e <= IF_TOL
 
 
-def test_synth_full_size_launch_sampled(torch_cuda, orc):
+@pytest.mark.parametrize("form", ["nufft", "direct"])
+def test_synth_full_size_launch_sampled(torch_cuda, orc, form):
     """50k-triangle scene in the benchmark's launch configuration (2048^2 rays,
     4 bounces, 12 x 128 x 256): the hit records hold the oracle's hits for a
-    sampled ray subset and misses elsewhere; sampled cube rows are compared."""
+    sampled ray subset and misses elsewhere; sampled cube rows are compared,
+    for the non-uniform FFT form and the matrix-core direct form."""
     sc = S.clutter_scene()
     nx = sc.grid.nx
     sub = np.arange(7, nx, 48)
@@ -146,7 +151,7 @@ def test_synth_full_size_launch_sampled(torch_cuda, orc):
     log(f"full-size synth: {len(rays)} rays, {len(p['amp'])} paths")
     sim = _sim(sc)
     sim.hits = device_hits_from_oracle(full)
-    out = sim.synth()
+    out = sim.synth(direct_sums=form == "direct")
     torch_cuda.cuda.synchronize()
     got = _cube_np(out).reshape(-1, sc.chirp.n_samples)[rows]
     e = rel_l2(got, ref)
@@ -1030,10 +1035,37 @@ def test_backward_full_size_launch_sampled(torch_cuda, orc):
 
 
 @pytest.mark.parametrize("case", ["clutter_full", "ico_s256", "ico_s200", "ico_s16", "ico_s1024", "ico_s8"])
+def test_synth_nufft_matches_direct_sums(torch_cuda, case):
+    """The IF cube (Eq. 8) by the non-uniform FFT form against the direct sums
+    (matrix-core form at S = 256 and 1024, VALU form at 200 and 16) on the
+    same traced hits; twice by the FFT form, bit for bit (the fixed-point
+    spreading does not depend on the order of its additions).  clutter_full is
+    the benchmark's launch (2048^2 rays, 4 bounces, 12 x 128 x 256, 7.37M
+    paths); at 8 samples both calls take the direct form."""
+    import torch
+    if case == "clutter_full":
+        sc = S.clutter_scene()
+    else:
+        ns = int(case.split("_s")[1])
+        sc = S.icosphere_scene(n_rays=256, n_chirps=16).with_chirp(n_samples=ns)
+    sim = _sim(sc)
+    sim.trace()
+    a = sim.synth().clone()
+    b = sim.synth().clone()
+    d = sim.synth(direct_sums=True).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    e = float((a.double() - d.double()).norm() / d.double().norm())
+    log(f"IF cube, non-uniform FFT vs direct ({case}, {sim.n_paths()} paths, S = {sc.chirp.n_samples}): "
+        f"rel L2 {e:.3e}; repeat bit-exact")
+    assert e <= (0.0 if sc.chirp.n_samples < 16 else 1e-5)
+
+
+@pytest.mark.parametrize("case", ["clutter_full", "ico_s256", "ico_s200", "ico_s16", "ico_s1024", "ico_s8"])
 def test_backward_nufft_matches_direct_sums(torch_cuda, case):
     """The adjoint's per-path series of Eqs. 11-12 by the non-uniform FFT
     against direct summation over the samples (the form the oracle tests pin
-    with SBR_ADJOINT_DIRECT), on the same traced hits and a random dL/dIF: the
+    with SBR_DIRECT_SUMS), on the same traced hits and a random dL/dIF: the
     vertex and origin/velocity gradients agree to the FFT's error level.
     clutter_full is the benchmark's launch (2048^2 rays, 4 bounces, 12 x 128 x
     256); the icosphere cases cover chirp lengths 16 (smallest of the FFT
@@ -1056,7 +1088,7 @@ def test_backward_nufft_matches_direct_sums(torch_cuda, case):
     out = []
     for direct in (False, True):
         gr = torch.zeros(6, dtype=torch.float32, device="cuda")
-        gv = sim.backward(G, grad_radar=gr, direct_adjoint=direct)
+        gv = sim.backward(G, grad_radar=gr, direct_sums=direct)
         torch.cuda.synchronize()
         out.append((gv.double().cpu(), gr.double().cpu()))
     (gv_nu, gr_nu), (gv_d, gr_d) = out
@@ -1129,14 +1161,16 @@ def test_platform_presets_synth_and_backward(torch_cuda, orc, name):
     assert e <= 1e-4 and eg <= GRAD_TOL
 
 
+@pytest.mark.parametrize("form", ["nufft", "direct"])
 @pytest.mark.parametrize("samples", [256, 192])
 @pytest.mark.parametrize("case", ["near_dc_24g", "near_nyquist_77g"])
-def test_synth_low_and_high_beat_frequency(torch_cuda, orc, case, samples):
+def test_synth_low_and_high_beat_frequency(torch_cuda, orc, case, samples, form):
     """Beat frequencies near 0 and near f_s / 2 per sample, where a real
     three-term recurrence cos-coefficient is ill-conditioned: a plate at 0.5 m
     seen by the 24 GHz ranging radar (0.0026 cycles per sample), and one at
-    12.4 m seen by the 77 GHz radar (0.496 cycles per sample).  256 samples
-    per chirp take the matrix-core form, 192 the VALU form."""
+    12.4 m seen by the 77 GHz radar (0.496 cycles per sample).  Direct sums:
+    256 samples per chirp take the matrix-core form, 192 the VALU form; the
+    non-uniform FFT form meets the grid's wrap-around at 1/2 cycle."""
     if case == "near_dc_24g":
         radar, chirp = S.platform("ranging_24g")
         dist, size = 0.5, 0.05
@@ -1153,19 +1187,22 @@ def test_synth_low_and_high_beat_frequency(torch_cuda, orc, case, samples):
     delta = chirp.slope * p["tau"].mean() / chirp.fs
     sim = _sim(sc)
     sim.hits = device_hits_from_oracle(o)
-    got = _cube_np(sim.synth())
+    got = _cube_np(sim.synth(direct_sums=form == "direct"))
     e = rel_l2(got, want)
-    log(f"{case}: {len(p['amp'])} paths, {delta:.4f} cycles per sample, synth rel L2 {e:.3e}")
+    log(f"{case} ({form}): {len(p['amp'])} paths, {delta:.4f} cycles per sample, synth rel L2 {e:.3e}")
     assert len(p["amp"]) > 100 and e <= 1e-4
 
 
+@pytest.mark.parametrize("form", ["nufft", "direct"])
 @pytest.mark.parametrize("samples", [256, 192])
-def test_synth_many_near_dc_paths_per_wavefront(torch_cuda, orc, samples):
+def test_synth_many_near_dc_paths_per_wavefront(torch_cuda, orc, samples, form):
     """A million paths, all near 0 cycles per sample (a plate filling the
-    1024^2 grid at 0.5 m, 24 GHz ranging radar).  256 samples take the
-    matrix-core form (every factor from its own reduced phase); 192 the VALU
-    form, where each wavefront meets more near-DC paths than it can remember,
-    so the rotation pass rescans its chunk.  Sampled cube rows vs the oracle."""
+    1024^2 grid at 0.5 m, 24 GHz ranging radar).  Direct sums: 256 samples
+    take the matrix-core form (every factor from its own reduced phase); 192
+    the VALU form, where each wavefront meets more near-DC paths than it can
+    remember, so the rotation pass rescans its chunk.  The non-uniform FFT
+    form adds every path into the same few grid cells.  Sampled cube rows vs
+    the oracle."""
     radar, chirp = S.platform("ranging_24g")
     v, f = S.plate(0.6, 0.5)
     sc = S.Scene("plate_near_dc", v.astype(np.float32), f.astype(np.int32), radar,
@@ -1177,16 +1214,19 @@ def test_synth_many_near_dc_paths_per_wavefront(torch_cuda, orc, samples):
     want = orc.synth(sc, p, rows=rows)
     sim = _sim(sc)
     sim.hits = device_hits_from_oracle(o)
-    got = _cube_np(sim.synth()).reshape(-1, sc.chirp.n_samples)[rows]
+    got = _cube_np(sim.synth(direct_sums=form == "direct")).reshape(-1, sc.chirp.n_samples)[rows]
     e = rel_l2(got, want)
-    log(f"many near-DC paths: {len(p['amp'])} paths, rows {list(rows)}: rel L2 {e:.3e}")
+    log(f"many near-DC paths ({form}): {len(p['amp'])} paths, rows {list(rows)}: rel L2 {e:.3e}")
     assert e <= 1e-4
 
 
+@pytest.mark.parametrize("form", ["nufft", "direct"])
 @pytest.mark.parametrize("case", ["near_dc_24g", "near_nyquist_77g"])
-def test_backward_low_and_high_beat_frequency(torch_cuda, orc, case):
-    """The synthesis adjoint's Horner sums at beat frequencies near 0 and 1/2
-    cycle per sample: vertex gradient vs the oracle's central differences."""
+def test_backward_low_and_high_beat_frequency(torch_cuda, orc, case, form):
+    """The synthesis adjoint's sums at beat frequencies near 0 and 1/2 cycle
+    per sample (the non-uniform FFT form at the grid's wrap-around; the direct
+    form's complex Horner steps): vertex gradient vs the oracle's central
+    differences."""
     import torch
     if case == "near_dc_24g":
         radar, chirp = S.platform("ranging_24g")
@@ -1206,7 +1246,8 @@ def test_backward_low_and_high_beat_frequency(torch_cuda, orc, case):
     tgt = 0.8 * Sx + 0.05 * np.abs(Sx).max() * (rng.normal(size=Sx.shape) + 1j * rng.normal(size=Sx.shape))
     sim = _sim(sc)
     sim.hits = device_hits_from_oracle(o)
-    g = sim.backward(torch.as_tensor((2.0 * (Sx - tgt)).astype(np.complex64), device="cuda"))
+    g = sim.backward(torch.as_tensor((2.0 * (Sx - tgt)).astype(np.complex64), device="cuda"),
+                     direct_sums=form == "direct")
     got = g.cpu().numpy().astype(np.float64)
     fd = orc.fd_grad(sc, o["tri"], o["flags"], tgt, h=1e-9).reshape(-1, 3)
     e = rel_l2(got, fd)
