@@ -631,22 +631,27 @@ __device__ __forceinline__ float nu_scale(uint32_t amax_bits) {
 constexpr int kNuSpreadThreads = 1024;
 
 // Spreading: block = (path chunk, antenna v, group of cg chirps), grid rows
-// [cg][re, im][nu_row_len(S)] of 64-bit cells in LDS (real and imaginary rows
-// apart, so that lanes at random cells spread over all banks); each thread
-// takes a contiguous share of the chunk (neighbouring paths come from
-// neighbouring rays and share their beat frequency, so lanes of a wave that
-// took neighbouring paths would all add to the same cells), and for each chirp
-// of the group adds its kNuW contributions with 64-bit integer LDS atomics;
-// the rows then go to the chunk's partial.
+// [cg][re, im] of nu_row_len(S) 64-bit cells in LDS (one cell of padding per
+// row, so that consecutive rows start one bank pair apart); for each chirp
+// of the group a path adds its kNuW contributions with 64-bit integer LDS
+// atomics; the rows then go to the chunk's partial.  Paths of a radar scene
+// share few beat frequencies (neighbouring paths come from neighbouring rays,
+// and the scene fills few range bins), and additions to one cell, or to one
+// bank, within an instruction serialise.  So the chunk is taken in tiles of
+// kNuTile paths, lane l of wave w handling the 4 consecutive paths at
+// 64 l + 4 w (lanes a quarter tile row apart, records read once per tile from
+// L2), and each lane walks the group's chirps from its own starting row.
+constexpr int kNuTile = 4096;
+
 __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args, int idx) {
     extern __shared__ long long nsp[];
     const SynthArgs &a = args[idx];
-    const int S = a.S, M = 2 * S, RL = nu_row_len(S);
+    const int S = a.S, M = 2 * S, RL = nu_row_len(S), RLs = RL + 1;
     const int blk = (int)blockIdx.x;
     const int cgi = blk % a.ncg, rest = blk / a.ncg;
     const int v = rest % a.V, chunk = rest / a.V;
     const int c0 = cgi * a.cg, nc = min(a.cg, a.C - c0);
-    for (int i = threadIdx.x; i < nc * RL * 2; i += blockDim.x) nsp[i] = 0;
+    for (int i = threadIdx.x; i < nc * RLs * 2; i += blockDim.x) nsp[i] = 0;
     __syncthreads();
     const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
     const long long per = ((long long)P + a.n_chunks - 1) / a.n_chunks;
@@ -660,42 +665,45 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
     const auto eps = gmem(a.rec.epsd);
     const float Mf = (float)M, halfS = (float)(S / 2);
     const float zstep = 2.0f / kNuW;   // kernel argument per grid point
-    const int share = (p1 - p0 + kNuSpreadThreads - 1) / kNuSpreadThreads;
-    const int q0 = p0 + (int)threadIdx.x * share, q1 = min(p1, q0 + share);
-    for (int p = q0; p < q1; p++) {
-        const float alpha = al[p], gamma = ga[p], beta = bet[p], epsd = eps[p];
-        const F2 A = amp[p];
-        const float Ax = A.x * sigma, Ay = A.y * sigma;
-        // each lane walks the group's chirps from its own starting row, so
-        // that the lanes of one instruction add to different rows: paths
-        // share few beat frequencies (a radar scene fills few range bins),
-        // and same-cell additions within one instruction serialise
-        int cl = (int)(threadIdx.x & 63) % nc;
-        for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
-            const float cf = (float)(c0 + cl);
-            const float f = fmaf(cf, epsd, gamma);
-            const float g = f - rintf(f);   // [-1/2, 1/2]
-            const float x = g * Mf;         // exact
-            const float xr = rintf(x);
-            const int j0 = min(max((int)xr + M / 2, 0), M);   // cell of l0 = xr - 3 (clamped: NaN-safe)
-            float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
-            th -= rintf(th);
-            const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
-            const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
-            const float zt0 = (x - xr + (float)kNuHalf) * zstep;   // kernel argument of tap 0
-            unsigned long long *cell = reinterpret_cast<unsigned long long *>(nsp) + (size_t)2 * cl * RL + j0;
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int first_row = lane % nc;
+    for (int tile = p0; tile < p1; tile += kNuTile) {
+        for (int r = 0; r < kNuTile / kNuSpreadThreads; r++) {
+            const int p = tile + 64 * lane + (kNuTile / kNuSpreadThreads) * wave + r;
+            if (p >= p1) continue;
+            const float alpha = al[p], gamma = ga[p], beta = bet[p], epsd = eps[p];
+            const F2 A = amp[p];
+            const float Ax = A.x * sigma, Ay = A.y * sigma;
+            int cl = first_row;
+            for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
+                const float cf = (float)(c0 + cl);
+                const float f = fmaf(cf, epsd, gamma);
+                const float g = f - rintf(f);   // [-1/2, 1/2]
+                const float x = g * Mf;         // exact
+                const float xr = rintf(x);
+                const int j0 = min(max((int)xr + M / 2, 0), M);   // cell of l0 = xr - 3 (clamped: NaN-safe)
+                float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
+                th -= rintf(th);
+                const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
+                const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
+                const float zt0 = (x - xr + (float)kNuHalf) * zstep;   // kernel argument of tap 0
+                unsigned long long *cell = reinterpret_cast<unsigned long long *>(nsp) + (size_t)2 * cl * RLs + j0;
 #pragma unroll
-            for (int t = 0; t < kNuW; t++) {
-                const float w = nu_weight(fmaf(-(float)t, zstep, zt0));
-                const long long yr = (long long)(int)rintf(wr * w), yi = (long long)(int)rintf(wi * w);
-                atomicAdd(cell + t, (unsigned long long)yr);
-                atomicAdd(cell + RL + t, (unsigned long long)yi);
+                for (int t = 0; t < kNuW; t++) {
+                    const float w = nu_weight(fmaf(-(float)t, zstep, zt0));
+                    const long long yr = (long long)(int)rintf(wr * w), yi = (long long)(int)rintf(wi * w);
+                    atomicAdd(cell + t, (unsigned long long)yr);
+                    atomicAdd(cell + RLs + t, (unsigned long long)yi);
+                }
             }
         }
     }
     __syncthreads();
     long long *dst = a.grid + (((size_t)chunk * a.V + v) * a.C + c0) * (size_t)RL * 2;
-    for (int i = threadIdx.x; i < nc * RL * 2; i += blockDim.x) dst[i] = nsp[i];
+    for (int i = threadIdx.x; i < nc * RL * 2; i += blockDim.x) {
+        const int row = i / RL, j = i - row * RL;   // row = 2 (chirp) + (re, im)
+        dst[i] = nsp[row * RLs + j];
+    }
 }
 
 // Row (v, c) = blockIdx.x of the non-uniform FFT form: the chunks' integer
@@ -808,7 +816,7 @@ static SynthPlan nu_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) 
     SynthPlan p{};
     p.nu = 1;
     p.L = 0;
-    const long long row_bytes = (long long)nu_row_len(S) * 16;
+    const long long row_bytes = (long long)(nu_row_len(S) + 1) * 16;
     p.cg = (int32_t)std::max(1LL, std::min<long long>({16LL, (long long)C, nu_lds_budget() / row_bytes}));
     const long long ncg = (C + p.cg - 1) / p.cg;
     const long long cap = (long long)R * K;
@@ -956,7 +964,7 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
                            s, a.count, a.rec.amp, a.amax);
         SBR_LAUNCHED();
         if ((rc = launch_nu_corr(a.S, a.corr, s))) return rc;
-        const size_t lds = (size_t)a.cg * nu_row_len(a.S) * 16;
+        const size_t lds = (size_t)a.cg * (nu_row_len(a.S) + 1) * 16;
         if (lds > 65536)
             SBR_HIP(hipFuncSetAttribute((const void *)k_nu_spread, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         const long long blocks = (long long)a.n_chunks * a.V * a.ncg;

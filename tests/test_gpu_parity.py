@@ -1073,7 +1073,8 @@ def test_backward_nufft_matches_direct_sums(torch_cuda, case):
     the difference is mostly the direct form's own FP32 rounding, which grows
     with the number of terms (the FFT form's error does not), hence 3e-4 there.
     At 8 samples both calls take the direct form and differ only by the order
-    of the vertex-gradient atomics."""
+    of the floating-point atomics that sum the vertex and radar gradients over
+    rays (measured 8e-7 ... 1e-6 on the 6 origin/velocity entries)."""
     import torch
     if case == "clutter_full":
         sc = S.clutter_scene()
@@ -1097,7 +1098,7 @@ def test_backward_nufft_matches_direct_sums(torch_cuda, case):
     e_w = float((gr_nu[3:] - gr_d[3:]).norm() / gr_d[3:].norm())
     log(f"adjoint series, non-uniform FFT vs direct ({case}, {sim.n_paths()} paths, S = {sc.chirp.n_samples}): "
         f"vertex {e_v:.3e}, origin {e_o:.3e}, velocity {e_w:.3e}")
-    tol = 1e-6 if sc.chirp.n_samples < 16 else (3e-4 if sc.chirp.n_samples > 256 else 1e-4)
+    tol = 1e-5 if sc.chirp.n_samples < 16 else (3e-4 if sc.chirp.n_samples > 256 else 1e-4)
     assert e_v <= tol and e_o <= tol and e_w <= tol
 
 
