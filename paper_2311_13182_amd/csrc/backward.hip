@@ -29,7 +29,7 @@ struct AdjArgs {
 
 constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time
 constexpr int kAdjPPL = 2;       // paths per lane, direct form
-constexpr int kNuPPL = 2;        // paths per lane, non-uniform FFT form
+constexpr int kNuPPL = 4;        // paths per lane, non-uniform FFT form
 constexpr int kAdjQueueDirect = 32;   // work counter of the direct form (queue[0]: the other)
 
 // ---- Eqs. 11-12 by a type-2 non-uniform FFT -------------------------------
@@ -53,6 +53,10 @@ struct alignas(16) F4 {
     float x, y, z, w;
 };
 __device__ __forceinline__ SBR_GLOBAL_AS const F4 *gmem4(const float4 *p) { return (SBR_GLOBAL_AS const F4 *)p; }
+
+// Chirp rows per LDS stage of the non-uniform FFT adjoint: about 36 KiB
+// (4 rows at S = 256), 1 .. 8 rows.
+__host__ __device__ inline int nu_stage(int S) { return max(1, min(8, 36864 / (nu_row_len(S) * 16))); }
 
 // frac(n f) for an integer-valued n < 2^24: the product is exact inside the fma
 __device__ __forceinline__ float frac_of_product(float n, float f) { return fmaf(n, f, -rintf(n * f)); }
@@ -144,9 +148,13 @@ __global__ __launch_bounds__(256) void k_nu_rows(const float2 *__restrict__ G, i
 // One work item of the non-uniform FFT form: per path and (v, c) the taps
 // l0 .. l0 + 6 around x = gM (l0 = rint(x) - 3) of both rows, kernel weights
 // from the hardware sqrt and exp2, and the same accumulation as the direct
-// form with z0 e^{2 pi j g S/2} as the phase factor.
+// form with z0 e^{2 pi j g S/2} as the phase factor.  The rows of `stage`
+// chirps at a time are copied to LDS by the whole block (coalesced 16-byte
+// loads), so that each row read from L2 serves the item's 256 PPL paths, and
+// paths of similar beat frequency read the same LDS words.
 template <int PPL>
-__device__ __forceinline__ void adj_item_nu(const AdjArgs &a, const int P, const int grp, const int blk_p0) {
+__device__ __forceinline__ void adj_item_nu(const AdjArgs &a, float4 *rsh, const int stage, const int P,
+                                            const int grp, const int blk_p0) {
     const auto amp = gmem(a.rec.amp);
     const auto bet = gmem(a.rec.beta);
     const auto eps = gmem(a.rec.epsd);
@@ -182,40 +190,47 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, const int P, const
             tb[i] = 0.0f;
         }
         const auto rows_v = gmem4(a.nu_rows) + (size_t)v * a.C * RL;
-        for (int c = 0; c < a.C; c++) {
-            const float cf = (float)c;
-            const auto row = rows_v + (size_t)c * RL;
+        for (int c0 = 0; c0 < a.C; c0 += stage) {
+            const int nr = min(stage, a.C - c0);
+            __syncthreads();   // the previous stage has been read
+            for (int i = threadIdx.x; i < nr * RL; i += 256) {
+                const F4 u = rows_v[(size_t)c0 * RL + i];
+                rsh[i] = make_float4(u.x, u.y, u.z, u.w);
+            }
+            __syncthreads();
+            for (int cc = 0; cc < nr; cc++) {
+                const float cf = (float)(c0 + cc);
+                const float4 *row = rsh + cc * RL;
 #pragma unroll
-            for (int i = 0; i < PPL; i++) {
-                const float f = fmaf(cf, epsd[i], gamma[i]);
-                const float g = f - rintf(f);   // [-1/2, 1/2]
-                const float x = g * Mf;         // exact
-                const float xr = rintf(x);
-                const int i0 = min(max((int)xr + M / 2, 0), M);   // row index of l0 = xr - 3 (clamped: NaN-safe)
-                F4 u[kNuW];
+                for (int i = 0; i < PPL; i++) {
+                    const float f = fmaf(cf, epsd[i], gamma[i]);
+                    const float g = f - rintf(f);   // [-1/2, 1/2]
+                    const float x = g * Mf;         // exact
+                    const float xr = rintf(x);
+                    const int i0 = min(max((int)xr + M / 2, 0), M);   // row index of l0 = xr - 3 (clamped: NaN-safe)
+                    const float zt0 = (x - xr + (float)kNuHalf) * zstep;   // kernel argument of tap 0
+                    float pr = 0.f, pi = 0.f, qr = 0.f, qi = 0.f;
 #pragma unroll
-                for (int t = 0; t < kNuW; t++) u[t] = row[i0 + t];
-                const float zt0 = (x - xr + (float)kNuHalf) * zstep;   // kernel argument of tap 0
-                float pr = 0.f, pi = 0.f, qr = 0.f, qi = 0.f;
-#pragma unroll
-                for (int t = 0; t < kNuW; t++) {
-                    const float w = nu_weight(fmaf(-(float)t, zstep, zt0));
-                    pr = fmaf(w, u[t].x, pr);
-                    pi = fmaf(w, u[t].y, pi);
-                    qr = fmaf(w, u[t].z, qr);
-                    qi = fmaf(w, u[t].w, qi);
+                    for (int t = 0; t < kNuW; t++) {
+                        const float4 u = row[i0 + t];
+                        const float w = nu_weight(fmaf(-(float)t, zstep, zt0));
+                        pr = fmaf(w, u.x, pr);
+                        pi = fmaf(w, u.y, pi);
+                        qr = fmaf(w, u.z, qr);
+                        qi = fmaf(w, u.w, qi);
+                    }
+                    float th = alpha[i] + frac_of_product(cf, beta[i]) + frac_of_product(halfS, g);
+                    th -= rintf(th);
+                    const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
+                    // Q0 = z0 P, m = z0 Q (z0 including e^{2 pi j g S/2})
+                    const float q0r = zc * pr - zs * pi, q0i = zc * pi + zs * pr;
+                    const float mr = zc * qr - zs * qi, mi = zc * qi + zs * qr;
+                    abr[i] += q0r;
+                    abi[i] -= q0i;
+                    const float dq = -2.0f * (float)kPi * (Ax[i] * mi + Ay[i] * mr);
+                    tb[i] += dq;
+                    tdb[i] = fmaf(dq, cf * a.tc, tdb[i]);
                 }
-                float th = alpha[i] + frac_of_product(cf, beta[i]) + frac_of_product(halfS, g);
-                th -= rintf(th);
-                const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
-                // Q0 = z0 P, m = z0 Q (z0 including e^{2 pi j g S/2})
-                const float q0r = zc * pr - zs * pi, q0i = zc * pi + zs * pr;
-                const float mr = zc * qr - zs * qi, mi = zc * qi + zs * qr;
-                abr[i] += q0r;
-                abi[i] -= q0i;
-                const float dq = -2.0f * (float)kPi * (Ax[i] * mi + Ay[i] * mr);
-                tb[i] += dq;
-                tdb[i] = fmaf(dq, cf * a.tc, tdb[i]);
             }
         }
 #pragma unroll
@@ -440,15 +455,18 @@ __global__ __launch_bounds__(256) void k_synth_adj(const AdjArgs *__restrict__ a
     }
 }
 
-// The same work queue over requests [r0, r1) for the non-uniform FFT form.
+// The same work queue over requests [r0, r1) for the non-uniform FFT form;
+// `stage` rows of nu_row_len(S) float4 per LDS stage, the work-item word
+// after the largest stage (float4 offset `slot`).
 template <int PPL>
 __global__ __launch_bounds__(256) void k_synth_adj_nu(const AdjArgs *__restrict__ args,
                                                       const uint32_t *__restrict__ item_first, int r0, int r1,
-                                                      uint32_t *queue) {
-    __shared__ uint32_t s_item;
+                                                      uint32_t *queue, int slot) {
+    extern __shared__ float4 rsh[];
+    uint32_t &s_item = *reinterpret_cast<uint32_t *>(rsh + slot);
     const uint32_t first = item_first[r0], total = item_first[r1];
     for (;;) {
-        __syncthreads();   // every wave has read the previous s_item
+        __syncthreads();   // the previous item is done with s_item and the rows
         if (threadIdx.x == 0) s_item = first + atomicAdd(queue, 1u);
         __syncthreads();
         const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
@@ -458,7 +476,7 @@ __global__ __launch_bounds__(256) void k_synth_adj_nu(const AdjArgs *__restrict_
         const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
         const uint32_t tiles = (uint32_t)((P + 256 * PPL - 1) / (256 * PPL));
         const uint32_t local = item - item_first[lo];
-        adj_item_nu<PPL>(a, P, (int)(local / tiles), (int)(local % tiles) * 256 * PPL);
+        adj_item_nu<PPL>(a, rsh, nu_stage(a.S), P, (int)(local / tiles), (int)(local % tiles) * 256 * PPL);
     }
 }
 
@@ -1068,10 +1086,14 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
             hipLaunchKernelGGL(k_nu_rows, dim3((unsigned)(a.V * a.C)), dim3(256), lds, s, a.G, a.S, a.fcf, a.sl_fs,
                                cr, const_cast<float4 *>(a.nu_rows));
         }
+        size_t slot = 0;   // float4 words of the largest row stage
+        for (int r = 0; r < n_nu; r++) slot = std::max(slot, (size_t)nu_stage(aa[r].S) * nu_row_len(aa[r].S));
+        const size_t lds = sizeof(float4) * slot + 16;
         dim3 grid((unsigned)std::max(1LL, std::min<long long>(items_nu, resident_blocks((const void *)k_synth_adj_nu<kNuPPL>,
-                                                                                         256, 0, 256 * 2))));
+                                                                                         256, lds, 256 * 2))));
         ProfScope pk(kProfNuTaps, s);
-        hipLaunchKernelGGL(k_synth_adj_nu<kNuPPL>, grid, dim3(256), 0, s, t.args, t.item_first, 0, n_nu, t.queue);
+        hipLaunchKernelGGL(k_synth_adj_nu<kNuPPL>, grid, dim3(256), lds, s, t.args, t.item_first, 0, n_nu, t.queue,
+                           (int)slot);
     }
     SBR_LAUNCHED();
     if (n_nu < n) {
