@@ -179,7 +179,6 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, float4 *rsh, const
     }
     const int S = a.S, M = 2 * S, RL = nu_row_len(S);
     const float Mf = (float)M, halfS = (float)(S / 2);
-    const float zstep = 2.0f / kNuW;   // kernel argument per grid point
     const int v0 = grp * a.v_per, v1 = min(a.V, v0 + a.v_per);
     for (int v = v0; v < v1; v++) {
         float alpha[PPL], gamma[PPL], tb[PPL];
@@ -208,16 +207,16 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, float4 *rsh, const
                     const float x = g * Mf;         // exact
                     const float xr = rintf(x);
                     const int i0 = min(max((int)xr + M / 2, 0), M);   // row index of l0 = xr - 3 (clamped: NaN-safe)
-                    const float zt0 = (x - xr + (float)kNuHalf) * zstep;   // kernel argument of tap 0
+                    float w[kNuW];
+                    nu_weights(x - xr, w);
                     float pr = 0.f, pi = 0.f, qr = 0.f, qi = 0.f;
 #pragma unroll
                     for (int t = 0; t < kNuW; t++) {
                         const float4 u = row[i0 + t];
-                        const float w = nu_weight(fmaf(-(float)t, zstep, zt0));
-                        pr = fmaf(w, u.x, pr);
-                        pi = fmaf(w, u.y, pi);
-                        qr = fmaf(w, u.z, qr);
-                        qi = fmaf(w, u.w, qi);
+                        pr = fmaf(w[t], u.x, pr);
+                        pi = fmaf(w[t], u.y, pi);
+                        qr = fmaf(w[t], u.z, qr);
+                        qi = fmaf(w[t], u.w, qi);
                     }
                     float th = alpha[i] + frac_of_product(cf, beta[i]) + frac_of_product(halfS, g);
                     th -= rintf(th);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "sbr_internal.h"
+#include "nu_weights.h"
 
 namespace sbr {
 
@@ -160,13 +161,27 @@ __device__ __forceinline__ uint32_t ray_path_mask(const int32_t *tri, const uint
 }
 
 
-// Kernel weight psi of the non-uniform FFT forms at the kernel argument z =
-// 2 (distance in grid points) / W, |z| <= 1 (clamped against rounding just
-// past 1): exp(beta (sqrt(1 - z^2) - 1)) from the hardware sqrt and exp2.
-__device__ __forceinline__ float nu_weight(float z) {
-    constexpr float kb = (float)(kNuBeta * 1.4426950408889634);   // beta log2(e)
-    const float q = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
-    return __builtin_amdgcn_exp2f(fmaf(kb, __builtin_amdgcn_sqrtf(q), -kb));
+// The kNuW tap weights of the non-uniform FFT kernel for a point at grid
+// coordinate x = rint(x) + u, u in [-1/2, 1/2]: w[t] = psi(u + 3 - t) for the
+// taps l = rint(x) - 3 + t, from the polynomial forms of nu_weights.h (even
+// and odd parts in u, so that mirrored taps share them); no transcendentals.
+__device__ __forceinline__ void nu_weights(float u, float w[kNuW]) {
+    const float u2 = u * u;
+#pragma unroll
+    for (int t = 0; t <= kNuHalf; t++) {
+        float e = kNuPolyE[t][4];
+#pragma unroll
+        for (int k = 3; k >= 0; k--) e = fmaf(e, u2, kNuPolyE[t][k]);
+        if (t == kNuHalf) {
+            w[t] = e;
+        } else {
+            float o = kNuPolyO[t][3];
+#pragma unroll
+            for (int k = 2; k >= 0; k--) o = fmaf(o, u2, kNuPolyO[t][k]);
+            w[t] = fmaf(u, o, e);
+            w[kNuW - 1 - t] = fmaf(-u, o, e);
+        }
+    }
 }
 
 }  // namespace sbr

@@ -642,12 +642,19 @@ constexpr int kNuSpreadThreads = 1024;
 // 64 l + 4 w (lanes a quarter tile row apart, records read once per tile from
 // L2), and each lane walks the group's chirps from its own starting row.
 constexpr int kNuTile = 4096;
+constexpr int kXcds = 8;   // accelerator complex dies of the MI355X, each with its own L2
 
 __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args, int idx) {
     extern __shared__ long long nsp[];
     const SynthArgs &a = args[idx];
     const int S = a.S, M = 2 * S, RL = nu_row_len(S), RLs = RL + 1;
-    const int blk = (int)blockIdx.x;
+    // the hardware deals consecutive blocks to the 8 XCDs in turn; logical
+    // blocks (chunk, v, chirp group), chirp group fastest, are assigned so
+    // that each XCD runs a contiguous range of them, and the chirp groups of
+    // one (chunk, v) -- which read the same path records -- share its L2
+    const int nb = (int)gridDim.x, hw = (int)blockIdx.x;
+    const int per_xcd = nb / kXcds, xcd = hw % kXcds, slot = hw / kXcds;
+    const int blk = hw < per_xcd * kXcds ? xcd * per_xcd + slot : hw;
     const int cgi = blk % a.ncg, rest = blk / a.ncg;
     const int v = rest % a.V, chunk = rest / a.V;
     const int c0 = cgi * a.cg, nc = min(a.cg, a.C - c0);
@@ -664,7 +671,6 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
     const auto bet = gmem(a.rec.beta);
     const auto eps = gmem(a.rec.epsd);
     const float Mf = (float)M, halfS = (float)(S / 2);
-    const float zstep = 2.0f / kNuW;   // kernel argument per grid point
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     const int first_row = lane % nc;
     for (int tile = p0; tile < p1; tile += kNuTile) {
@@ -686,12 +692,12 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
                 th -= rintf(th);
                 const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
                 const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
-                const float zt0 = (x - xr + (float)kNuHalf) * zstep;   // kernel argument of tap 0
+                float w[kNuW];
+                nu_weights(x - xr, w);
                 unsigned long long *cell = reinterpret_cast<unsigned long long *>(nsp) + (size_t)2 * cl * RLs + j0;
 #pragma unroll
                 for (int t = 0; t < kNuW; t++) {
-                    const float w = nu_weight(fmaf(-(float)t, zstep, zt0));
-                    const long long yr = (long long)(int)rintf(wr * w), yi = (long long)(int)rintf(wi * w);
+                    const long long yr = (long long)(int)rintf(wr * w[t]), yi = (long long)(int)rintf(wi * w[t]);
                     atomicAdd(cell + t, (unsigned long long)yr);
                     atomicAdd(cell + RLs + t, (unsigned long long)yi);
                 }
