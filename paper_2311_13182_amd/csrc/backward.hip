@@ -25,6 +25,7 @@ struct AdjArgs {
     float2 *abar_part;     // [nvs][cap]
     float *tdb_part;       // [nvs][cap] dL/d taudot partials
     const float4 *nu_rows; // [V][C][2S + 8] non-uniform FFT rows (NULL: direct form)
+    float *nu_corr;        // [S] its 1/Psi table
 };
 
 constexpr int kAdjRowsMax = 8;   // G rows staged in LDS at a time
@@ -46,8 +47,6 @@ constexpr int kAdjQueueDirect = 32;   // work counter of the direct form (queue[
 // and a path then needs kNuW taps per (v, c) instead of S terms; the error
 // stays below 1e-6 of sum_s |h_s| at every g (two orders of magnitude under
 // the FP32 rounding of a 256-term direct sum).
-constexpr int kNuSteps = 16;    // trapezoid points per grid unit for Psi
-
 // float4's layout for address-space-qualified 16-byte loads of the rows
 struct alignas(16) F4 {
     float x, y, z, w;
@@ -61,54 +60,43 @@ __host__ __device__ inline int nu_stage(int S) { return max(1, min(8, 36864 / (n
 // frac(n f) for an integer-valued n < 2^24: the product is exact inside the fma
 __device__ __forceinline__ float frac_of_product(float n, float f) { return fmaf(n, f, -rintf(n * f)); }
 
-}  // namespace
-
-// 1 / Psi((s - S/2) / M), s < S, with Psi(xi) = int psi(z) e^{-2 pi j xi z} dz
-// by the trapezoid rule at kNuSteps points per grid unit (psi vanishes with
-// all its derivatives up to the order of e^{-beta} at the ends of its
-// support): Psi = h (psi(0) + 2 sum_n psi(nh) cos(2 pi xi n h)), h = 1/kNuSteps,
-// the cosines by the three-term recurrence in FP64.  Blocks of 256 modes.
-constexpr int kNuTaps = kNuW * kNuSteps / 2;   // n = 0 .. kNuTaps - 1 (|z| < W/2)
-__global__ __launch_bounds__(256) void k_nu_corr(int S, float *corr) {
+// 1 / Psi((s - S/2) / 2S) for s < S (nu_corr_value) of request blockIdx.y of an
+// adjoint batch, blocks of 256 modes.
+__global__ __launch_bounds__(256) void k_nu_corr_adj(const AdjArgs *__restrict__ args) {
     __shared__ double kn[kNuTaps];
-    if (threadIdx.x < kNuTaps) {
-        const double x = 2.0 * threadIdx.x / (double)(kNuW * kNuSteps);
-        kn[threadIdx.x] = exp(kNuBeta * (sqrt(1.0 - x * x) - 1.0));
-    }
+    if (threadIdx.x < kNuTaps) kn[threadIdx.x] = nu_kernel_sample((int)threadIdx.x);
     __syncthreads();
+    const AdjArgs &a = args[blockIdx.y];
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    const int M = 2 * S;
-    const double c1 = cospi(2.0 * (double)(s - S / 2) / (double)(M * kNuSteps));
-    double cp = 1.0, cc = c1, acc = kn[0] + 2.0 * kn[1] * c1;
-    for (int n = 2; n < kNuTaps; n++) {
-        const double cn = 2.0 * c1 * cc - cp;
-        cp = cc;
-        cc = cn;
-        acc += 2.0 * kn[n] * cn;
-    }
-    corr[s] = (float)((double)kNuSteps / acc);
+    if (s < a.S) a.nu_corr[s] = nu_corr_value(a.S, s, kn);
 }
 
-int launch_nu_corr(int32_t S, float *corr, hipStream_t s) {
-    hipLaunchKernelGGL(k_nu_corr, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, corr);
-    SBR_LAUNCHED();
-    return SBR_OK;
-}
 
-namespace {
-
-// Row (v, c) = blockIdx.x: u1_l, u2_l (float4: u1.re, u1.im, u2.re, u2.im)
+// Gradient row (v, c) of a request of the batch (blocks [first[j], first[j + 1])
+// are request j's rows, v major): u1_l, u2_l (float4: u1.re, u1.im, u2.re, u2.im)
 // for l = -M/2 - 3 .. M/2 + 3 at index l + M/2 + 3, by a direct DFT over the
 // S deconvolved modes with twiddles e^{2 pi j k / M} from an exact-index LDS
 // table; the last entry of the row is zero padding.
-__global__ __launch_bounds__(256) void k_nu_rows(const float2 *__restrict__ G, int S, float fcf, float sl_fs,
-                                                 const float *__restrict__ corr, float4 *__restrict__ rows) {
+__global__ __launch_bounds__(256) void k_nu_rows(const AdjArgs *__restrict__ args, const int32_t *__restrict__ first,
+                                                 int m) {
     extern __shared__ float4 nsh[];
+    // request j of the batch owns blocks (rows) [first[j], first[j + 1])
+    int j = 0, hi = m;
+    while (hi - j > 1) {
+        const int mid = (j + hi) >> 1;
+        if (first[mid] <= (int)blockIdx.x) j = mid;
+        else hi = mid;
+    }
+    const AdjArgs &a = args[j];
+    const float2 *__restrict__ G = a.G;
+    const float *__restrict__ corr = a.nu_corr;
+    float4 *__restrict__ rows = const_cast<float4 *>(a.nu_rows);
+    const int S = a.S;
+    const float fcf = a.fcf, sl_fs = a.sl_fs;
     const int M = 2 * S, RL = nu_row_len(S);
     float4 *hb = nsh;                                         // [S] h1, h2 over Psi
     float2 *tw = reinterpret_cast<float2 *>(nsh + S);         // [M]
-    const size_t row = blockIdx.x;
+    const size_t row = (size_t)((int)blockIdx.x - first[j]);
     for (int k = threadIdx.x; k < M; k += blockDim.x) {
         double sn, cs;
         sincospi(2.0 * k / M, &sn, &cs);
@@ -966,6 +954,7 @@ struct AdjTable {
     AdjArgs *args;
     uint32_t *item_first;
     uint32_t *queue;
+    int32_t *row_first;   // first G row of each request of the non-uniform FFT form
 };
 
 static AdjTable adj_table(void *buf, int n, size_t *bytes) {
@@ -974,6 +963,7 @@ static AdjTable adj_table(void *buf, int n, size_t *bytes) {
     t.args = cv.take<AdjArgs>(n);
     t.item_first = cv.take<uint32_t>((size_t)n + 1);
     t.queue = cv.take<uint32_t>(64);
+    t.row_first = cv.take<int32_t>((size_t)n + 1);
     if (bytes) *bytes = align_up(cv.off, 256);
     return t;
 }
@@ -999,7 +989,6 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
         if (!use_nu(reqs[r].cd.S, reqs[r].flags)) order.push_back(r);
     std::vector<AdjArgs> aa(n);
     std::vector<GeomArgs> gg(n);
-    std::vector<const float *> corr(n);
     size_t lds_f2 = 0;   // float2 words of the largest G-row stage
     long long items_nu = 0, items_direct = 0;
     for (int r = 0; r < n; r++) {
@@ -1027,7 +1016,7 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
         a.abar_part = e.part;
         a.tdb_part = e.tpart;
         a.nu_rows = nu ? e.rows : nullptr;
-        corr[r] = e.corr;
+        a.nu_corr = nu ? e.corr : nullptr;
         a.Sp = (q.cd.S + 7) / 8 * 8;
         a.rows = adj_rows(a.Sp);
         if (nu) {
@@ -1076,15 +1065,26 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
     hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, s, t.args, n, t.item_first, t.queue);
     SBR_LAUNCHED();
     if (n_nu > 0) {
-        ProfScope ps(kProfSynthAdj, s);
+        // all requests of this form: 1/Psi tables, then the row transforms
+        std::vector<int32_t> row_first(1, 0);
+        int max_s = 0;
         for (int r = 0; r < n_nu; r++) {
-            const AdjArgs &a = aa[r];
-            float *cr = const_cast<float *>(corr[r]);
-            if ((rc = launch_nu_corr(a.S, cr, s))) return rc;
-            const size_t lds = sizeof(float4) * a.S + sizeof(float2) * 2 * a.S;
-            hipLaunchKernelGGL(k_nu_rows, dim3((unsigned)(a.V * a.C)), dim3(256), lds, s, a.G, a.S, a.fcf, a.sl_fs,
-                               cr, const_cast<float4 *>(a.nu_rows));
+            const long long rows = (long long)aa[r].V * aa[r].C;
+            if (row_first.back() + rows > 0x7fffffffLL) {
+                set_error("batched backward: more than 2^31 gradient rows in one launch");
+                return SBR_E_ARG;
+            }
+            row_first.push_back(row_first.back() + (int32_t)rows);
+            max_s = std::max(max_s, (int)aa[r].S);
         }
+        if ((rc = put_table(t.row_first, row_first.data(), sizeof(int32_t) * (n_nu + 1), s))) return rc;
+        ProfScope ps(kProfSynthAdj, s);
+        hipLaunchKernelGGL(k_nu_corr_adj, dim3((unsigned)((max_s + 255) / 256), (unsigned)n_nu), dim3(256), 0, s,
+                           t.args);
+        const size_t lds_rows = sizeof(float4) * max_s + sizeof(float2) * 2 * max_s;
+        hipLaunchKernelGGL(k_nu_rows, dim3((unsigned)row_first.back()), dim3(256), lds_rows, s, t.args, t.row_first,
+                           n_nu);
+        SBR_LAUNCHED();
         size_t slot = 0;   // float4 words of the largest row stage
         for (int r = 0; r < n_nu; r++) slot = std::max(slot, (size_t)nu_stage(aa[r].S) * nu_row_len(aa[r].S));
         const size_t lds = sizeof(float4) * slot + 16;

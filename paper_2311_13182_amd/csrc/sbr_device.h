@@ -161,6 +161,32 @@ __device__ __forceinline__ uint32_t ray_path_mask(const int32_t *tri, const uint
 }
 
 
+// Deconvolution of the non-uniform FFT forms: 1 / Psi((s - S/2) / 2S) for
+// mode s < S, with Psi(xi) = int psi(z) e^{-2 pi j xi z} dz by the trapezoid
+// rule at kNuSteps points per grid unit (psi vanishes with all its
+// derivatives up to the order of e^{-beta} at the ends of its support):
+// Psi = h (psi(0) + 2 sum_n psi(nh) cos(2 pi xi n h)), h = 1/kNuSteps, the
+// cosines by the three-term recurrence, all in FP64.  kn holds the kernel
+// samples psi(n h), n < kNuTaps (nu_kernel_sample).
+constexpr int kNuSteps = 16;
+constexpr int kNuTaps = kNuW * kNuSteps / 2;   // n h < W/2
+__device__ inline double nu_kernel_sample(int n) {
+    const double x = 2.0 * n / (double)(kNuW * kNuSteps);
+    return exp(kNuBeta * (sqrt(1.0 - x * x) - 1.0));
+}
+__device__ inline float nu_corr_value(int S, int s, const double *kn) {
+    const int M = 2 * S;
+    const double c1 = cospi(2.0 * (double)(s - S / 2) / (double)(M * kNuSteps));
+    double cp = 1.0, cc = c1, acc = kn[0] + 2.0 * kn[1] * c1;
+    for (int n = 2; n < kNuTaps; n++) {
+        const double cn = 2.0 * c1 * cc - cp;
+        cp = cc;
+        cc = cn;
+        acc += 2.0 * kn[n] * cn;
+    }
+    return (float)((double)kNuSteps / acc);
+}
+
 // The kNuW tap weights of the non-uniform FFT kernel for a point at grid
 // coordinate x = rint(x) + u, u in [-1/2, 1/2]: w[t] = psi(u + 3 - t) for the
 // taps l = rint(x) - 3 + t, from the polynomial forms of nu_weights.h (even

@@ -195,6 +195,7 @@ struct SynthArgs {
     uint32_t *amax;      // [1] max over paths of max(|Re A|, |Im A|), float bits
     float *corr;         // [S]
     long long *grid;     // [n_chunks][V][C][re, im][nu_row_len(S)]
+    float2 *out;         // [V][C][S] the IF cube (set by launch_synth_batch)
 };
 
 PathStage carve_path_stage(Carver &cv, int32_t R, int32_t K, int32_t V);
@@ -256,8 +257,6 @@ constexpr int kNuMinS = 16;     // shorter chirps use the direct forms (cheap th
 constexpr int kNuMaxS = 1024;   // longer chirps use the direct forms
 __host__ __device__ constexpr int nu_row_len(int S) { return 2 * S + 8; }
 static inline bool nu_size(int S) { return S >= kNuMinS && S <= kNuMaxS; }
-// Enqueue corr[s] = 1 / Psi((s - S/2) / 2S), s < S.
-int launch_nu_corr(int32_t S, float *corr, hipStream_t s);
 
 // Copy `bytes` (a multiple of 4) of host data into device memory on stream s
 // with fill kernels that carry the data as kernel arguments: no memcpy node,

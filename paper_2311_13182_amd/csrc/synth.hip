@@ -603,19 +603,52 @@ __global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, f
 // adds it to 64-bit integer cells: integer addition is exact, so the grid and
 // the cube do not depend on the order in which blocks, waves or lanes add.
 
-// max over the live paths of max(|Re A|, |Im A|), as the bits of a
-// non-negative float: an integer maximum, exact and order-independent.
-__global__ __launch_bounds__(256) void k_nu_amax(const int32_t *__restrict__ count, const float2 *__restrict__ amp,
-                                                 uint32_t *amax) {
-    const int P = *count;
+// Request of a block of a batched launch: binary search over first[0..m]
+// (request j owns blocks [first[j], first[j + 1])).
+__device__ __forceinline__ int nu_request(const int32_t *first, int m, int blk) {
+    int lo = 0, hi = m;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The amplitude words of the batch's requests of this form, cleared before
+// k_nu_amax runs.
+__global__ void k_nu_zero(const SynthArgs *__restrict__ args, const int32_t *__restrict__ nidx, int m) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) *args[nidx[j]].amax = 0u;
+}
+
+// Request nidx[blockIdx.y]: max over the live paths of max(|Re A|, |Im A|),
+// as the bits of a non-negative float: an integer maximum, exact and
+// order-independent.
+__global__ __launch_bounds__(256) void k_nu_amax(const SynthArgs *__restrict__ args,
+                                                 const int32_t *__restrict__ nidx) {
+    const SynthArgs &a = args[nidx[blockIdx.y]];
+    const int P = *gmem(a.count);
+    const auto amp = gmem(a.rec.amp);
     uint32_t m = 0;
     for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256) {
-        const float2 A = amp[p];
+        const F2 A = amp[p];
         m = max(m, __float_as_uint(fmaxf(fabsf(A.x), fabsf(A.y))));
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-    if ((threadIdx.x & 63) == 0 && m != 0u) atomicMax(amax, m);
+    if ((threadIdx.x & 63) == 0 && m != 0u) atomicMax(a.amax, m);
+}
+
+// Request nidx[blockIdx.y]: its 1/Psi table (nu_corr_value), 256 modes a block.
+__global__ __launch_bounds__(256) void k_nu_corr_batch(const SynthArgs *__restrict__ args,
+                                                       const int32_t *__restrict__ nidx) {
+    __shared__ double kn[kNuTaps];
+    if (threadIdx.x < kNuTaps) kn[threadIdx.x] = nu_kernel_sample((int)threadIdx.x);
+    __syncthreads();
+    const SynthArgs &a = args[nidx[blockIdx.y]];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < a.S) a.corr[s] = nu_corr_value(a.S, s, kn);
 }
 
 // Fixed-point scale 2^(30 - e) with max(|Re A|, |Im A|) = amax < 2^e, so that
@@ -642,19 +675,18 @@ constexpr int kNuSpreadThreads = 1024;
 // 64 l + 4 w (lanes a quarter tile row apart, records read once per tile from
 // L2), and each lane walks the group's chirps from its own starting row.
 constexpr int kNuTile = 4096;
-constexpr int kXcds = 8;   // accelerator complex dies of the MI355X, each with its own L2
 
-__global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args, int idx) {
+__global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args,
+                                                                 const int32_t *__restrict__ nidx,
+                                                                 const int32_t *__restrict__ first, int m) {
     extern __shared__ long long nsp[];
-    const SynthArgs &a = args[idx];
+    // blocks in hardware order (dealt to the 8 XCDs in turn, so every
+    // request of a batch spreads over all of them): request, then chunk, v,
+    // chirp group with the chirp group fastest
+    const int j = nu_request(first, m, (int)blockIdx.x);
+    const SynthArgs &a = args[nidx[j]];
+    const int blk = (int)blockIdx.x - first[j];
     const int S = a.S, M = 2 * S, RL = nu_row_len(S), RLs = RL + 1;
-    // the hardware deals consecutive blocks to the 8 XCDs in turn; logical
-    // blocks (chunk, v, chirp group), chirp group fastest, are assigned so
-    // that each XCD runs a contiguous range of them, and the chirp groups of
-    // one (chunk, v) -- which read the same path records -- share its L2
-    const int nb = (int)gridDim.x, hw = (int)blockIdx.x;
-    const int per_xcd = nb / kXcds, xcd = hw % kXcds, slot = hw / kXcds;
-    const int blk = hw < per_xcd * kXcds ? xcd * per_xcd + slot : hw;
     const int cgi = blk % a.ncg, rest = blk / a.ncg;
     const int v = rest % a.V, chunk = rest / a.V;
     const int c0 = cgi * a.cg, nc = min(a.cg, a.C - c0);
@@ -718,14 +750,17 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
 // then the DFT to the S centred modes with exact-index twiddles and the
 // deconvolution 1/Psi.  A non-finite amplitude makes the row NaN, as the
 // direct sum would.
-__global__ __launch_bounds__(256) void k_nu_synth_rows(const SynthArgs *__restrict__ args, int idx,
-                                                       float2 *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_nu_synth_rows(const SynthArgs *__restrict__ args,
+                                                       const int32_t *__restrict__ nidx,
+                                                       const int32_t *__restrict__ first, int m) {
     extern __shared__ double2 nrs[];
-    const SynthArgs &a = args[idx];
+    const int j = nu_request(first, m, (int)blockIdx.x);
+    const SynthArgs &a = args[nidx[j]];
+    float2 *out = a.out;
     const int S = a.S, M = 2 * S, RL = nu_row_len(S);
     double2 *b = nrs;        // [M]
     double2 *tw = nrs + M;   // [M]
-    const size_t row = blockIdx.x;
+    const size_t row = (size_t)((int)blockIdx.x - first[j]);
     for (int k = threadIdx.x; k < M; k += blockDim.x) {
         double sn, cs;
         sincospi(2.0 * k / M, &sn, &cs);
@@ -896,6 +931,9 @@ struct SynthTable {
     SynthArgs *args;
     int32_t *idx[4];
     int32_t *first[4];
+    int32_t *nidx;     // requests of the non-uniform FFT form
+    int32_t *nfirst;   // their first spreading blocks
+    int32_t *rfirst;   // their first cube rows
 };
 
 static SynthTable synth_table(void *buf, int n, size_t *bytes) {
@@ -906,6 +944,9 @@ static SynthTable synth_table(void *buf, int n, size_t *bytes) {
         t.idx[g] = cv.take<int32_t>(n);
         t.first[g] = cv.take<int32_t>((size_t)n + 1);
     }
+    t.nidx = cv.take<int32_t>(n);
+    t.nfirst = cv.take<int32_t>((size_t)n + 1);
+    t.rfirst = cv.take<int32_t>((size_t)n + 1);
     if (bytes) *bytes = align_up(cv.off, 256);
     return t;
 }
@@ -920,7 +961,9 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
                        hipStream_t s) {
     if (n <= 0) return SBR_OK;
     SynthTable t = synth_table(table, n, nullptr);
-    int rc = put_table(t.args, args, sizeof(SynthArgs) * n, s);
+    std::vector<SynthArgs> aa(args, args + n);
+    for (int i = 0; i < n; i++) aa[i].out = out[i];
+    int rc = put_table(t.args, aa.data(), sizeof(SynthArgs) * n, s);
     if (rc) return rc;
     static const int kLs[4] = {16, 32, 64, kMfmaRun};
     for (int g = 0; g < 4; g++) {
@@ -958,29 +1001,48 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
                            args[i].n_chunks, e, out[i]);
     }
     SBR_LAUNCHED();
-    // the non-uniform FFT form, request by request: amplitude bound, 1/Psi,
-    // spreading, row transforms
+    // the non-uniform FFT form, all its requests in five launches: amplitude
+    // words cleared, amplitude bounds, 1/Psi tables, spreading, row transforms
+    std::vector<int32_t> nidx, nfirst(1, 0), rfirst(1, 0);
+    size_t lds_spread = 0, lds_rows = 0;
+    int max_s = 0;
     for (int i = 0; i < n; i++) {
         const SynthArgs &a = args[i];
         if (!a.nu) continue;
+        const long long blocks = (long long)a.n_chunks * a.V * a.ncg, rows = (long long)a.V * a.C;
+        if (nfirst.back() + blocks > 0x7fffffffLL || rfirst.back() + rows > 0x7fffffffLL) {
+            set_error("batched synthesis: more than 2^31 blocks in one launch");
+            return SBR_E_ARG;
+        }
+        nidx.push_back(i);
+        nfirst.push_back(nfirst.back() + (int32_t)blocks);
+        rfirst.push_back(rfirst.back() + (int32_t)rows);
+        lds_spread = std::max(lds_spread, (size_t)a.cg * (nu_row_len(a.S) + 1) * 16);
+        lds_rows = std::max(lds_rows, (size_t)2 * 2 * a.S * sizeof(double2));
+        max_s = std::max(max_s, (int)a.S);
+    }
+    if (!nidx.empty()) {
+        const int m = (int)nidx.size();
+        if ((rc = put_table(t.nidx, nidx.data(), sizeof(int32_t) * m, s))) return rc;
+        if ((rc = put_table(t.nfirst, nfirst.data(), sizeof(int32_t) * (m + 1), s))) return rc;
+        if ((rc = put_table(t.rfirst, rfirst.data(), sizeof(int32_t) * (m + 1), s))) return rc;
         ProfScope ps(kProfSynth, s);
-        if ((rc = fill_zero_f32(reinterpret_cast<float *>(a.amax), 1, s))) return rc;
-        const long long cap = a.rec.cap;
-        hipLaunchKernelGGL(k_nu_amax, dim3((unsigned)std::max(1LL, std::min((cap + 255) / 256, 1024LL))), dim3(256), 0,
-                           s, a.count, a.rec.amp, a.amax);
+        hipLaunchKernelGGL(k_nu_zero, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, t.args, t.nidx, m);
+        hipLaunchKernelGGL(k_nu_amax, dim3(256, (unsigned)m), dim3(256), 0, s, t.args, t.nidx);
+        hipLaunchKernelGGL(k_nu_corr_batch, dim3((unsigned)((max_s + 255) / 256), (unsigned)m), dim3(256), 0, s,
+                           t.args, t.nidx);
         SBR_LAUNCHED();
-        if ((rc = launch_nu_corr(a.S, a.corr, s))) return rc;
-        const size_t lds = (size_t)a.cg * (nu_row_len(a.S) + 1) * 16;
-        if (lds > 65536)
-            SBR_HIP(hipFuncSetAttribute((const void *)k_nu_spread, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        const long long blocks = (long long)a.n_chunks * a.V * a.ncg;
+        if (lds_spread > 65536)
+            SBR_HIP(hipFuncSetAttribute((const void *)k_nu_spread, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds_spread));
         {
             ProfScope pk(kProfNuSpread, s);
-            hipLaunchKernelGGL(k_nu_spread, dim3((unsigned)blocks), dim3(kNuSpreadThreads), lds, s, t.args, i);
+            hipLaunchKernelGGL(k_nu_spread, dim3((unsigned)nfirst.back()), dim3(kNuSpreadThreads), lds_spread, s,
+                               t.args, t.nidx, t.nfirst, m);
         }
         SBR_LAUNCHED();
-        hipLaunchKernelGGL(k_nu_synth_rows, dim3((unsigned)((size_t)a.V * a.C)), dim3(256),
-                           (size_t)2 * 2 * a.S * sizeof(double2), s, t.args, i, out[i]);
+        hipLaunchKernelGGL(k_nu_synth_rows, dim3((unsigned)rfirst.back()), dim3(256), lds_rows, s, t.args, t.nidx,
+                           t.rfirst, m);
         SBR_LAUNCHED();
     }
     return SBR_OK;
