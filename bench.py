@@ -37,7 +37,7 @@ PEAK_VALU_LANE_OPS = 256 * 4 * 32 * 2.4e9
 OPS_PER_NODE_TEST, OPS_PER_TRI_TEST = 14, 27
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__k_synth_adj__clutter_50k_fwd_bwd.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__k_nu_spread__clutter_50k_fwd_bwd.md")
 KERNEL_SOURCES = {
     "k_nu_spread": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
     "k_synth_adj_nu": ["backward.hip", "sbr_internal.h", "sbr_device.h"],

@@ -670,11 +670,12 @@ constexpr int kNuSpreadThreads = 1024;
 // atomics; the rows then go to the chunk's partial.  Paths of a radar scene
 // share few beat frequencies (neighbouring paths come from neighbouring rays,
 // and the scene fills few range bins), and additions to one cell, or to one
-// bank, within an instruction serialise.  So the chunk is taken in tiles of
-// kNuTile paths, lane l of wave w handling the 4 consecutive paths at
-// 64 l + 4 w (lanes a quarter tile row apart, records read once per tile from
-// L2), and each lane walks the group's chirps from its own starting row.
-constexpr int kNuTile = 4096;
+// bank, within an instruction serialise.  So the block takes its chunk 1024
+// paths at a time, lane l of wave w the path at 16 l + w (lanes of a wave 16
+// paths apart, the block's records of one step 4 KiB per array, so that they
+// are read from L2 while still there), and each lane walks the group's chirps
+// from its own starting row (the lanes of an instruction that share a row are
+// 256 paths apart).
 
 __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args,
                                                                  const int32_t *__restrict__ nidx,
@@ -705,34 +706,32 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
     const float Mf = (float)M, halfS = (float)(S / 2);
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     const int first_row = lane % nc;
-    for (int tile = p0; tile < p1; tile += kNuTile) {
-        for (int r = 0; r < kNuTile / kNuSpreadThreads; r++) {
-            const int p = tile + 64 * lane + (kNuTile / kNuSpreadThreads) * wave + r;
-            if (p >= p1) continue;
-            const float alpha = al[p], gamma = ga[p], beta = bet[p], epsd = eps[p];
-            const F2 A = amp[p];
-            const float Ax = A.x * sigma, Ay = A.y * sigma;
-            int cl = first_row;
-            for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
-                const float cf = (float)(c0 + cl);
-                const float f = fmaf(cf, epsd, gamma);
-                const float g = f - rintf(f);   // [-1/2, 1/2]
-                const float x = g * Mf;         // exact
-                const float xr = rintf(x);
-                const int j0 = min(max((int)xr + M / 2, 0), M);   // cell of l0 = xr - 3 (clamped: NaN-safe)
-                float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
-                th -= rintf(th);
-                const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
-                const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
-                float w[kNuW];
-                nu_weights(x - xr, w);
-                unsigned long long *cell = reinterpret_cast<unsigned long long *>(nsp) + (size_t)2 * cl * RLs + j0;
+    for (int base = p0; base < p1; base += kNuSpreadThreads) {
+        const int p = base + 16 * lane + wave;
+        if (p >= p1) continue;
+        const float alpha = al[p], gamma = ga[p], beta = bet[p], epsd = eps[p];
+        const F2 A = amp[p];
+        const float Ax = A.x * sigma, Ay = A.y * sigma;
+        int cl = first_row;
+        for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
+            const float cf = (float)(c0 + cl);
+            const float f = fmaf(cf, epsd, gamma);
+            const float g = f - rintf(f);   // [-1/2, 1/2]
+            const float x = g * Mf;         // exact
+            const float xr = rintf(x);
+            const int j0 = min(max((int)xr + M / 2, 0), M);   // cell of l0 = xr - 3 (clamped: NaN-safe)
+            float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
+            th -= rintf(th);
+            const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
+            const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
+            float w[kNuW];
+            nu_weights(x - xr, w);
+            unsigned long long *cell = reinterpret_cast<unsigned long long *>(nsp) + (size_t)2 * cl * RLs + j0;
 #pragma unroll
-                for (int t = 0; t < kNuW; t++) {
-                    const long long yr = (long long)(int)rintf(wr * w[t]), yi = (long long)(int)rintf(wi * w[t]);
-                    atomicAdd(cell + t, (unsigned long long)yr);
-                    atomicAdd(cell + RLs + t, (unsigned long long)yi);
-                }
+            for (int t = 0; t < kNuW; t++) {
+                const long long yr = (long long)(int)rintf(wr * w[t]), yi = (long long)(int)rintf(wi * w[t]);
+                atomicAdd(cell + t, (unsigned long long)yr);
+                atomicAdd(cell + RLs + t, (unsigned long long)yi);
             }
         }
     }
