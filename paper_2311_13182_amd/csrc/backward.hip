@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_nu_rows(const AdjArgs *__restrict__ arg
 
 // One work item of the non-uniform FFT form: per path and (v, c) the taps
 // l0 .. l0 + 6 around x = gM (l0 = rint(x) - 3) of both rows, kernel weights
-// from the hardware sqrt and exp2, and the same accumulation as the direct
+// from their polynomial forms (nu_weights), and the same accumulation as the direct
 // form with z0 e^{2 pi j g S/2} as the phase factor.  The rows of `stage`
 // chirps at a time are copied to LDS by the whole block (coalesced 16-byte
 // loads), so that each row read from L2 serves the item's 256 PPL paths, and
