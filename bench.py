@@ -25,9 +25,9 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 # LDS bandwidth from the unit counts: 256 CUs x 128 B per clock x 2.4 GHz
 PEAK_LDS_GBS = 256 * 128 * 2.4
-# the spreading of the non-uniform FFT synthesis: 7 taps x (re, im) 64-bit
-# LDS atomic adds per (path, antenna, chirp)
-LDS_BYTES_PER_PAC = 7 * 2 * 8
+# the spreading of the non-uniform FFT synthesis: 7 taps, each one 64-bit LDS
+# atomic add of the packed (re, im) pair, per (path, antenna, chirp)
+LDS_BYTES_PER_PAC = 7 * 8
 FLOP_PER_PATH_SAMPLE = {"synth": 8.0, "synth_adj": 20.0}
 # lane operations per second of the FP32 vector units: 256 CUs x 4 SIMDs x 32
 # lanes x 2.4 GHz (one VALU instruction per lane per clock; an FMA counts once)
@@ -39,8 +39,8 @@ OPS_PER_NODE_TEST, OPS_PER_TRI_TEST = 14, 27
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__k_nu_spread__clutter_50k_fwd_bwd.md")
 KERNEL_SOURCES = {
-    "k_nu_spread": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
-    "k_synth_adj_nu": ["backward.hip", "sbr_internal.h", "sbr_device.h"],
+    "k_nu_spread": ["synth.hip", "sbr_internal.h", "sbr_device.h", "nu_weights.h"],
+    "k_synth_adj_nu": ["backward.hip", "sbr_internal.h", "sbr_device.h", "nu_weights.h"],
     "k_synth_adj": ["backward.hip", "sbr_internal.h", "sbr_device.h"],
     "k_synth_mfma": ["synth.hip", "sbr_internal.h", "sbr_device.h"],
     "k_synth": ["synth.hip", "sbr_internal.h", "sbr_device.h"],

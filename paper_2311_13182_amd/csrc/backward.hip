@@ -135,11 +135,16 @@ __global__ __launch_bounds__(256) void k_nu_rows(const AdjArgs *__restrict__ arg
 
 // One work item of the non-uniform FFT form: per path and (v, c) the taps
 // l0 .. l0 + 6 around x = gM (l0 = rint(x) - 3) of both rows, kernel weights
-// from their polynomial forms (nu_weights), and the same accumulation as the direct
-// form with z0 e^{2 pi j g S/2} as the phase factor.  The rows of `stage`
-// chirps at a time are copied to LDS by the whole block (coalesced 16-byte
-// loads), so that each row read from L2 serves the item's 256 PPL paths, and
-// paths of similar beat frequency read the same LDS words.
+// from their polynomial forms (nu_weights), and the same accumulation as the
+// direct form with z0 e^{2 pi j g S/2} as the phase factor.  That phase is
+// alpha + c beta + (S/2) g = alpha + (S/2) gamma + c (beta + (S/2) eps) up to
+// an integer ((S/2) times the integer that reduces g), so from one chirp to
+// the next the factor turns by r = e^{2 pi j (beta + (S/2) eps)}: it is
+// computed exactly at the first chirp of each stage and rotated by r for the
+// others (at most 7 rotations).  The rows of `stage` chirps at a time are
+// copied to LDS by the whole block (coalesced 16-byte loads), so that each
+// row read from L2 serves the item's 256 PPL paths, and paths of similar beat
+// frequency read the same LDS words.
 template <int PPL>
 __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, float4 *rsh, const int stage, const int P,
                                             const int grp, const int blk_p0) {
@@ -151,7 +156,9 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, float4 *rsh, const
     const auto tbar = gmem(a.tau_bar);
     int pp[PPL];
     bool act[PPL];
-    float Ax[PPL], Ay[PPL], beta[PPL], epsd[PPL], abr[PPL], abi[PPL], tdb[PPL];
+    float Ax[PPL], Ay[PPL], beta[PPL], epsd[PPL], abr[PPL], abi[PPL], tdb[PPL], rc[PPL], rs[PPL];
+    const int S = a.S, M = 2 * S, RL = nu_row_len(S);
+    const float Mf = (float)M, halfS = (float)(S / 2);
 #pragma unroll
     for (int i = 0; i < PPL; i++) {
         pp[i] = blk_p0 + i * 256 + threadIdx.x;
@@ -164,9 +171,11 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, float4 *rsh, const
         epsd[i] = eps[pc];
         abr[i] = abi[i] = tdb[i] = 0.0f;
         pp[i] = pc;
+        float rt = beta[i] + frac_of_product(halfS, epsd[i]);   // turn per chirp
+        rt -= rintf(rt);
+        rs[i] = __builtin_amdgcn_sinf(rt);
+        rc[i] = __builtin_amdgcn_cosf(rt);
     }
-    const int S = a.S, M = 2 * S, RL = nu_row_len(S);
-    const float Mf = (float)M, halfS = (float)(S / 2);
     const int v0 = grp * a.v_per, v1 = min(a.V, v0 + a.v_per);
     for (int v = v0; v < v1; v++) {
         float alpha[PPL], gamma[PPL], tb[PPL];
@@ -185,6 +194,7 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, float4 *rsh, const
                 rsh[i] = make_float4(u.x, u.y, u.z, u.w);
             }
             __syncthreads();
+            float zc[PPL], zs[PPL];   // phase factor of the current chirp
             for (int cc = 0; cc < nr; cc++) {
                 const float cf = (float)(c0 + cc);
                 const float4 *row = rsh + cc * RL;
@@ -206,12 +216,19 @@ __device__ __forceinline__ void adj_item_nu(const AdjArgs &a, float4 *rsh, const
                         qr = fmaf(w[t], u.z, qr);
                         qi = fmaf(w[t], u.w, qi);
                     }
-                    float th = alpha[i] + frac_of_product(cf, beta[i]) + frac_of_product(halfS, g);
-                    th -= rintf(th);
-                    const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
+                    if (cc == 0) {   // block-uniform
+                        float th = alpha[i] + frac_of_product(cf, beta[i]) + frac_of_product(halfS, g);
+                        th -= rintf(th);
+                        zs[i] = __builtin_amdgcn_sinf(th);
+                        zc[i] = __builtin_amdgcn_cosf(th);
+                    } else {
+                        const float tc = zc[i] * rc[i] - zs[i] * rs[i];
+                        zs[i] = zc[i] * rs[i] + zs[i] * rc[i];
+                        zc[i] = tc;
+                    }
                     // Q0 = z0 P, m = z0 Q (z0 including e^{2 pi j g S/2})
-                    const float q0r = zc * pr - zs * pi, q0i = zc * pi + zs * pr;
-                    const float mr = zc * qr - zs * qi, mi = zc * qi + zs * qr;
+                    const float q0r = zc[i] * pr - zs[i] * pi, q0i = zc[i] * pi + zs[i] * pr;
+                    const float mr = zc[i] * qr - zs[i] * qi, mi = zc[i] * qi + zs[i] * qr;
                     abr[i] += q0r;
                     abi[i] -= q0i;
                     const float dq = -2.0f * (float)kPi * (Ax[i] * mi + Ay[i] * mr);

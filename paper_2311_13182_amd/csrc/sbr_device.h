@@ -195,15 +195,15 @@ __device__ __forceinline__ void nu_weights(float u, float w[kNuW]) {
     const float u2 = u * u;
 #pragma unroll
     for (int t = 0; t <= kNuHalf; t++) {
-        float e = kNuPolyE[t][4];
+        float e = kNuPolyE[t][kNuPolyNE - 1];
 #pragma unroll
-        for (int k = 3; k >= 0; k--) e = fmaf(e, u2, kNuPolyE[t][k]);
+        for (int k = kNuPolyNE - 2; k >= 0; k--) e = fmaf(e, u2, kNuPolyE[t][k]);
         if (t == kNuHalf) {
             w[t] = e;
         } else {
-            float o = kNuPolyO[t][3];
+            float o = kNuPolyO[t][kNuPolyNO - 1];
 #pragma unroll
-            for (int k = 2; k >= 0; k--) o = fmaf(o, u2, kNuPolyO[t][k]);
+            for (int k = kNuPolyNO - 2; k >= 0; k--) o = fmaf(o, u2, kNuPolyO[t][k]);
             w[t] = fmaf(u, o, e);
             w[kNuW - 1 - t] = fmaf(-u, o, e);
         }

@@ -599,9 +599,9 @@ __global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, f
 // so each path adds kNuW weighted copies of w'_p to a grid of M = 2S points
 // (spreading), and one DFT per row and the deconvolution finish it.  The
 // spreading rounds every contribution to an integer of the scale
-// 2^(30 - e), max(|Re A|, |Im A|) < 2^e (so below 2^31 in magnitude), and
-// adds it to 64-bit integer cells: integer addition is exact, so the grid and
-// the cube do not depend on the order in which blocks, waves or lanes add.
+// 2^(20 - e), max(|Re A|, |Im A|) < 2^e (so below 2^20.5 in magnitude), and
+// sums them as integers: integer addition is exact, so the grid and the cube
+// do not depend on the order in which blocks, waves or lanes add.
 
 // Request of a block of a batched launch: binary search over first[0..m]
 // (request j owns blocks [first[j], first[j + 1])).
@@ -651,36 +651,50 @@ __global__ __launch_bounds__(256) void k_nu_corr_batch(const SynthArgs *__restri
     if (s < a.S) a.corr[s] = nu_corr_value(a.S, s, kn);
 }
 
-// Fixed-point scale 2^(30 - e) with max(|Re A|, |Im A|) = amax < 2^e, so that
-// |A psi| <= sqrt(2) amax stays below 2^31 after scaling; e is held in
-// [-90, 128] so that the scale is a finite normal float.
+// Fixed-point scale 2^(20 - e) with max(|Re A|, |Im A|) = amax < 2^e, so that
+// |A psi| <= sqrt(2) amax stays below 2^20.5 after scaling (and 1024 such
+// contributions below 2^31); e is held in [-100, 128] so that the scale is a
+// finite normal float.
 __device__ __forceinline__ float nu_scale(uint32_t amax_bits) {
     int e = 0;
     const float amax = __uint_as_float(amax_bits);
     if (amax > 0.0f && amax_bits < 0x7f800000u) (void)frexpf(amax, &e);
-    return ldexpf(1.0f, 30 - max(e, -90));
+    return ldexpf(1.0f, 20 - max(e, -100));
+}
+
+// rint(a b) for |a b| < 2^22 as an integer: the fused a b + 1.5 2^23 is
+// rounded once to a float of unit spacing whose low mantissa bits hold
+// 2^22 + rint(a b).
+__device__ __forceinline__ int rint_product(float a, float b) {
+    return __float_as_int(fmaf(a, b, 12582912.0f)) - 0x4B400000;
 }
 
 constexpr int kNuSpreadThreads = 1024;
 
-// Spreading: block = (path chunk, antenna v, group of cg chirps), grid rows
-// [cg][re, im] of nu_row_len(S) 64-bit cells in LDS (one cell of padding per
-// row, so that consecutive rows start one bank pair apart); for each chirp
-// of the group a path adds its kNuW contributions with 64-bit integer LDS
-// atomics; the rows then go to the chunk's partial.  Paths of a radar scene
-// share few beat frequencies (neighbouring paths come from neighbouring rays,
-// and the scene fills few range bins), and additions to one cell, or to one
-// bank, within an instruction serialise.  So the block takes its chunk 1024
-// paths at a time, lane l of wave w the path at 16 l + w (lanes of a wave 16
-// paths apart, the block's records of one step 4 KiB per array, so that they
-// are read from L2 while still there), and each lane walks the group's chirps
-// from its own starting row (the lanes of an instruction that share a row are
-// 256 paths apart).
+// Spreading: block = (path chunk, antenna v, group of cg chirps).  A
+// contribution (re, im), both integers below 2^20.5 in magnitude, is added as
+// the single 64-bit integer im 2^32 + re to a cell of the block's grid rows
+// in LDS ([cg][nu_row_len(S) + 1]: one cell of padding makes the row stride
+// odd, so that 32 consecutive rows start on 32 different bank pairs), halving
+// the LDS atomics of
+// separate real and imaginary cells.  A cell takes at most one contribution
+// per path, so after 1024 paths its sum of real parts RE is below 2^31 in
+// magnitude and (RE, IM) is recovered exactly from the low word (as a signed
+// 32-bit value) and the rest; at that point every cell is moved into 64-bit
+// accumulators held in registers (cell tid + 1024 k of thread tid) and
+// cleared.  Paths of a radar scene share few beat frequencies (neighbouring
+// paths come from neighbouring rays, and the scene fills few range bins), and
+// additions to one cell, or to one bank, within an instruction serialise.  So
+// the block takes its chunk 1024 paths at a time, lane l of wave w the path
+// at 16 l + w (lanes of a wave 16 paths apart), and each lane walks the
+// group's chirps from its own starting row (with 32 chirps, the two lanes of
+// an instruction that share a row are 512 paths apart).
+constexpr int kNuCells = 17;   // grid cells per thread: cg (nu_row_len(S) + 1) <= 1024 kNuCells
 
 __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args,
                                                                  const int32_t *__restrict__ nidx,
                                                                  const int32_t *__restrict__ first, int m) {
-    extern __shared__ long long nsp[];
+    extern __shared__ unsigned long long nsp[];
     // blocks in hardware order (dealt to the 8 XCDs in turn, so every
     // request of a batch spreads over all of them): request, then chunk, v,
     // chirp group with the chirp group fastest
@@ -691,7 +705,11 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
     const int cgi = blk % a.ncg, rest = blk / a.ncg;
     const int v = rest % a.V, chunk = rest / a.V;
     const int c0 = cgi * a.cg, nc = min(a.cg, a.C - c0);
-    for (int i = threadIdx.x; i < nc * RLs * 2; i += blockDim.x) nsp[i] = 0;
+    const int ncell = nc * RLs, tid = (int)threadIdx.x;
+    for (int i = tid; i < ncell; i += kNuSpreadThreads) nsp[i] = 0ull;
+    long long acc_re[kNuCells], acc_im[kNuCells];
+#pragma unroll
+    for (int k = 0; k < kNuCells; k++) acc_re[k] = acc_im[k] = 0;
     __syncthreads();
     const int P = __builtin_amdgcn_readfirstlane(*gmem(a.count));
     const long long per = ((long long)P + a.n_chunks - 1) / a.n_chunks;
@@ -704,42 +722,65 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
     const auto bet = gmem(a.rec.beta);
     const auto eps = gmem(a.rec.epsd);
     const float Mf = (float)M, halfS = (float)(S / 2);
-    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int lane = tid & 63, wave = tid >> 6;
     const int first_row = lane % nc;
-    for (int base = p0; base < p1; base += kNuSpreadThreads) {
+    for (int base = p0; base < p1; base += kNuSpreadThreads) {   // block-uniform trip count
         const int p = base + 16 * lane + wave;
-        if (p >= p1) continue;
-        const float alpha = al[p], gamma = ga[p], beta = bet[p], epsd = eps[p];
-        const F2 A = amp[p];
-        const float Ax = A.x * sigma, Ay = A.y * sigma;
-        int cl = first_row;
-        for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
-            const float cf = (float)(c0 + cl);
-            const float f = fmaf(cf, epsd, gamma);
-            const float g = f - rintf(f);   // [-1/2, 1/2]
-            const float x = g * Mf;         // exact
-            const float xr = rintf(x);
-            const int j0 = min(max((int)xr + M / 2, 0), M);   // cell of l0 = xr - 3 (clamped: NaN-safe)
-            float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
-            th -= rintf(th);
-            const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
-            const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
-            float w[kNuW];
-            nu_weights(x - xr, w);
-            unsigned long long *cell = reinterpret_cast<unsigned long long *>(nsp) + (size_t)2 * cl * RLs + j0;
+        if (p < p1) {
+            const float alpha = al[p], gamma = ga[p], beta = bet[p], epsd = eps[p];
+            const F2 A = amp[p];
+            const float Ax = A.x * sigma, Ay = A.y * sigma;
+            int cl = first_row;
+            for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
+                const float cf = (float)(c0 + cl);
+                const float f = fmaf(cf, epsd, gamma);
+                const float g = f - rintf(f);   // [-1/2, 1/2]
+                const float x = g * Mf;         // exact
+                const float xr = rintf(x);
+                const int j0 = min(max((int)xr + M / 2, 0), M);   // cell of l0 = xr - 3 (clamped: NaN-safe)
+                float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
+                th -= rintf(th);
+                const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
+                const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
+                float w[kNuW];
+                nu_weights(x - xr, w);
+                unsigned long long *cell = nsp + (size_t)cl * RLs + j0;
 #pragma unroll
-            for (int t = 0; t < kNuW; t++) {
-                const long long yr = (long long)(int)rintf(wr * w[t]), yi = (long long)(int)rintf(wi * w[t]);
-                atomicAdd(cell + t, (unsigned long long)yr);
-                atomicAdd(cell + RLs + t, (unsigned long long)yi);
+                for (int t = 0; t < kNuW; t++) {
+                    const int re = rint_product(wr, w[t]), im = rint_product(wi, w[t]);
+                    // im 2^32 + re as one 64-bit two's-complement word
+                    const unsigned long long word =
+                        ((unsigned long long)(uint32_t)(im + (re >> 31)) << 32) | (uint32_t)re;
+                    atomicAdd(cell + t, word);
+                }
             }
         }
+        __syncthreads();   // the step's additions are done
+#pragma unroll
+        for (int k = 0; k < kNuCells; k++) {
+            const int i = tid + k * kNuSpreadThreads;
+            if (i < ncell) {
+                const unsigned long long word = nsp[i];
+                nsp[i] = 0ull;
+                const long long re = (int32_t)(uint32_t)word;
+                acc_re[k] += re;
+                acc_im[k] += ((long long)word - re) >> 32;
+            }
+        }
+        __syncthreads();   // cleared before the next step adds
     }
-    __syncthreads();
+    // the chunk's rows [c][re, im][RL] of request j's partial
     long long *dst = a.grid + (((size_t)chunk * a.V + v) * a.C + c0) * (size_t)RL * 2;
-    for (int i = threadIdx.x; i < nc * RL * 2; i += blockDim.x) {
-        const int row = i / RL, j = i - row * RL;   // row = 2 (chirp) + (re, im)
-        dst[i] = nsp[row * RLs + j];
+#pragma unroll
+    for (int k = 0; k < kNuCells; k++) {
+        const int i = tid + k * kNuSpreadThreads;
+        if (i < ncell) {
+            const int row = i / RLs, jj = i - row * RLs;
+            if (jj < RL) {
+                dst[(size_t)(2 * row) * RL + jj] = acc_re[k];
+                dst[(size_t)(2 * row + 1) * RL + jj] = acc_im[k];
+            }
+        }
     }
 }
 
@@ -847,17 +888,18 @@ static int nu_lds_budget() {
     return std::min(v, 160 * 1024);
 }
 
-// Non-uniform FFT form: as many chirps per spreading block as the LDS holds
-// (at most 16; each block reads its chunk's path records once for all of
-// them), and path chunks enough for about three blocks per CU over the
-// device, each of at least 2048 path slots.  Depends only on the request's
+// Non-uniform FFT form: as many chirps per spreading block as the LDS and
+// the threads' accumulators hold (at most 32; each block reads its chunk's
+// path records once for all of them), and path chunks enough for about
+// three blocks per CU over the device, each of at least 2048 path slots.  Depends only on the request's
 // sizes and the device, so a request runs the same blocks alone and in a batch.
 static SynthPlan nu_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
     SynthPlan p{};
     p.nu = 1;
     p.L = 0;
-    const long long row_bytes = (long long)(nu_row_len(S) + 1) * 16;
-    p.cg = (int32_t)std::max(1LL, std::min<long long>({16LL, (long long)C, nu_lds_budget() / row_bytes}));
+    const long long row_cells = nu_row_len(S) + 1;
+    p.cg = (int32_t)std::max(1LL, std::min<long long>({32LL, (long long)C, nu_lds_budget() / (row_cells * 8),
+                                                       (long long)kNuCells * kNuSpreadThreads / row_cells}));
     const long long ncg = (C + p.cg - 1) / p.cg;
     const long long cap = (long long)R * K;
     const long long want = (768 + (long long)V * ncg - 1) / ((long long)V * ncg);
@@ -1013,10 +1055,14 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
             set_error("batched synthesis: more than 2^31 blocks in one launch");
             return SBR_E_ARG;
         }
+        if ((long long)a.cg * (nu_row_len(a.S) + 1) > (long long)kNuCells * kNuSpreadThreads) {
+            set_error("batched synthesis: spreading rows exceed the accumulators");
+            return SBR_E_ARG;
+        }
         nidx.push_back(i);
         nfirst.push_back(nfirst.back() + (int32_t)blocks);
         rfirst.push_back(rfirst.back() + (int32_t)rows);
-        lds_spread = std::max(lds_spread, (size_t)a.cg * (nu_row_len(a.S) + 1) * 16);
+        lds_spread = std::max(lds_spread, (size_t)a.cg * (nu_row_len(a.S) + 1) * 8);
         lds_rows = std::max(lds_rows, (size_t)2 * 2 * a.S * sizeof(double2));
         max_s = std::max(max_s, (int)a.S);
     }

@@ -285,8 +285,11 @@ class Scheduler:
 
 # --------------------------------------------------------------------------- GPU executor
 def _dev_bytes(n: int) -> int:
-    """Bytes the caching allocator books for an n-byte tensor (512-byte blocks)."""
-    return (int(n) + 511) // 512 * 512
+    """Most bytes the caching allocator books for an n-byte tensor: blocks of
+    512 bytes, and a block of its large pool (over 1 MiB) keeps the rest of
+    the segment it comes from when that rest is 1 MiB or less."""
+    r = (int(n) + 511) // 512 * 512
+    return r if r <= (1 << 20) else r + (1 << 20)
 
 
 def mesh_bytes(scene: S.Scene) -> int:
