@@ -28,6 +28,9 @@ PEAK_LDS_GBS = 256 * 128 * 2.4
 # the spreading of the non-uniform FFT synthesis: 7 taps, each one 64-bit LDS
 # atomic add of the packed (re, im) pair, per (path, antenna, chirp)
 LDS_BYTES_PER_PAC = 7 * 8
+# the tap kernel of the non-uniform FFT adjoint: 7 float4 row reads from LDS
+# per (path, antenna, chirp)
+LDS_READ_BYTES_PER_PAC = 7 * 16
 FLOP_PER_PATH_SAMPLE = {"synth": 8.0, "synth_adj": 20.0}
 # lane operations per second of the FP32 vector units: 256 CUs x 4 SIMDs x 32
 # lanes x 2.4 GHz (one VALU instruction per lane per clock; an FMA counts once)
@@ -273,6 +276,12 @@ def main():
         "adjoint": {"form": "nufft" if nufft else "direct", "ms": round(k_ms["synth_adj"], 4),
                     "taps_ms": round(k_ms["nu_taps"], 4) if nufft else None,
                     "path_antenna_chirps_per_s": pac / (k_ms["synth_adj"] * 1e-3),
+                    # the tap kernel's row reads from LDS (7 float4 per (path, antenna,
+                    # chirp)) against the LDS bandwidth of the unit counts
+                    "taps_lds_read_gbs": round(LDS_READ_BYTES_PER_PAC * pac / (k_ms["nu_taps"] * 1e-3) / 1e9, 1)
+                    if nufft else None,
+                    "taps_lds_frac": round(LDS_READ_BYTES_PER_PAC * pac / (k_ms["nu_taps"] * 1e-3) / 1e9 /
+                                           PEAK_LDS_GBS, 4) if nufft else None,
                     "direct_sum_equivalent_tflops": round(FLOP_PER_PATH_SAMPLE["synth_adj"] * ps /
                                                           (k_ms["synth_adj"] * 1e-3) / 1e12, 2)},
         "trace": {"ray_bounces_per_s": queries / (k_ms["trace"] * 1e-3), "node_tests": node_tests,
