@@ -599,7 +599,7 @@ __global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, f
 // so each path adds kNuW weighted copies of w'_p to a grid of M = 2S points
 // (spreading), and one DFT per row and the deconvolution finish it.  The
 // spreading rounds every contribution to an integer of the scale
-// 2^(20 - e), max(|Re A|, |Im A|) < 2^e (so below 2^20.5 in magnitude), and
+// 2^(19 - e), max(|Re A|, |Im A|) < 2^e (so below 2^19.5 in magnitude), and
 // sums them as integers: integer addition is exact, so the grid and the cube
 // do not depend on the order in which blocks, waves or lanes add.
 
@@ -651,15 +651,15 @@ __global__ __launch_bounds__(256) void k_nu_corr_batch(const SynthArgs *__restri
     if (s < a.S) a.corr[s] = nu_corr_value(a.S, s, kn);
 }
 
-// Fixed-point scale 2^(20 - e) with max(|Re A|, |Im A|) = amax < 2^e, so that
-// |A psi| <= sqrt(2) amax stays below 2^20.5 after scaling (and 1024 such
+// Fixed-point scale 2^(19 - e) with max(|Re A|, |Im A|) = amax < 2^e, so that
+// |A psi| <= sqrt(2) amax stays below 2^19.5 after scaling (and 2048 such
 // contributions below 2^31); e is held in [-100, 128] so that the scale is a
 // finite normal float.
 __device__ __forceinline__ float nu_scale(uint32_t amax_bits) {
     int e = 0;
     const float amax = __uint_as_float(amax_bits);
     if (amax > 0.0f && amax_bits < 0x7f800000u) (void)frexpf(amax, &e);
-    return ldexpf(1.0f, 20 - max(e, -100));
+    return ldexpf(1.0f, 19 - max(e, -100));
 }
 
 // rint(a b) for |a b| < 2^22 as an integer: the fused a b + 1.5 2^23 is
@@ -672,23 +672,25 @@ __device__ __forceinline__ int rint_product(float a, float b) {
 constexpr int kNuSpreadThreads = 1024;
 
 // Spreading: block = (path chunk, antenna v, group of cg chirps).  A
-// contribution (re, im), both integers below 2^20.5 in magnitude, is added as
+// contribution (re, im), both integers below 2^19.5 in magnitude, is added as
 // the single 64-bit integer im 2^32 + re to a cell of the block's grid rows
 // in LDS ([cg][nu_row_len(S) + 1]: one cell of padding makes the row stride
 // odd, so that 32 consecutive rows start on 32 different bank pairs), halving
-// the LDS atomics of
-// separate real and imaginary cells.  A cell takes at most one contribution
-// per path, so after 1024 paths its sum of real parts RE is below 2^31 in
-// magnitude and (RE, IM) is recovered exactly from the low word (as a signed
-// 32-bit value) and the rest; at that point every cell is moved into 64-bit
-// accumulators held in registers (cell tid + 1024 k of thread tid) and
-// cleared.  Paths of a radar scene share few beat frequencies (neighbouring
-// paths come from neighbouring rays, and the scene fills few range bins), and
-// additions to one cell, or to one bank, within an instruction serialise.  So
-// the block takes its chunk 1024 paths at a time, lane l of wave w the path
-// at 16 l + w (lanes of a wave 16 paths apart), and each lane walks the
-// group's chirps from its own starting row (with 32 chirps, the two lanes of
-// an instruction that share a row are 512 paths apart).
+// the LDS atomics of separate real and imaginary cells.  A cell takes at most
+// one contribution per path, so after 2048 paths its sum of real parts RE is
+// below 2^31 in magnitude and (RE, IM) is recovered exactly from the low word
+// (as a signed 32-bit value) and the rest; at that point every cell is moved
+// into 64-bit accumulators held in registers (cell tid + 1024 k of thread
+// tid) and cleared.  Paths of a radar scene share few beat frequencies
+// (neighbouring paths come from neighbouring rays, and the scene fills few
+// range bins), and additions to one cell, or to one bank, within an
+// instruction serialise.  So the block takes its chunk 1024 paths at a time,
+// lane l of wave w the path at 16 l + w (lanes of a wave 16 paths apart), and
+// each lane walks the group's chirps from its own starting row (with 32
+// chirps, the two lanes of an instruction that share a row are 512 paths
+// apart).  The phase factor e^{2 pi j (alpha + c beta + g S/2)} is computed
+// exactly at every eighth chirp of the walk and turned in between (g S/2
+// changes by (S/2) eps from chirp to chirp, up to an integer).
 constexpr int kNuCells = 17;   // grid cells per thread: cg (nu_row_len(S) + 1) <= 1024 kNuCells
 
 __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args,
@@ -724,12 +726,23 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
     const float Mf = (float)M, halfS = (float)(S / 2);
     const int lane = tid & 63, wave = tid >> 6;
     const int first_row = lane % nc;
-    for (int base = p0; base < p1; base += kNuSpreadThreads) {   // block-uniform trip count
+    int step = 0;
+    for (int base = p0; base < p1; base += kNuSpreadThreads, step++) {   // block-uniform trip count
         const int p = base + 16 * lane + wave;
         if (p < p1) {
             const float alpha = al[p], gamma = ga[p], beta = bet[p], epsd = eps[p];
             const F2 A = amp[p];
             const float Ax = A.x * sigma, Ay = A.y * sigma;
+            // the phase factor turns by r = e^{2 pi j (beta + (S/2) eps)} from one
+            // chirp to the next, and by r^-(nc-1) from the group's last chirp to its first
+            float rho = beta + frac_mul(halfS, epsd);
+            rho -= rintf(rho);
+            float rw = -(float)(nc - 1) * rho;
+            rw = fmaf(-(float)(nc - 1), rho, -rintf(rw));   // frac(-(nc - 1) rho), exact product
+            rw -= rintf(rw);
+            const float rs = __builtin_amdgcn_sinf(rho), rc = __builtin_amdgcn_cosf(rho);
+            const float ws = __builtin_amdgcn_sinf(rw), wc = __builtin_amdgcn_cosf(rw);
+            float zs = 0.0f, zc = 1.0f;
             int cl = first_row;
             for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
                 const float cf = (float)(c0 + cl);
@@ -738,9 +751,17 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
                 const float x = g * Mf;         // exact
                 const float xr = rintf(x);
                 const int j0 = min(max((int)xr + M / 2, 0), M);   // cell of l0 = xr - 3 (clamped: NaN-safe)
-                float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
-                th -= rintf(th);
-                const float zs = __builtin_amdgcn_sinf(th), zc = __builtin_amdgcn_cosf(th);
+                if ((k & 7) == 0) {   // wave-uniform: exact every 8 chirps
+                    float th = alpha + frac_mul(cf, beta) + frac_mul(halfS, g);
+                    th -= rintf(th);
+                    zs = __builtin_amdgcn_sinf(th);
+                    zc = __builtin_amdgcn_cosf(th);
+                } else {
+                    const float ms = cl == 0 ? ws : rs, mc = cl == 0 ? wc : rc;
+                    const float tc = zc * mc - zs * ms;
+                    zs = zc * ms + zs * mc;
+                    zc = tc;
+                }
                 const float wr = Ax * zc - Ay * zs, wi = Ax * zs + Ay * zc;
                 float w[kNuW];
                 nu_weights(x - xr, w);
@@ -755,19 +776,21 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
                 }
             }
         }
-        __syncthreads();   // the step's additions are done
+        if ((step & 1) == 1 || base + kNuSpreadThreads >= p1) {   // block-uniform: every 2048 paths
+            __syncthreads();   // the steps' additions are done
 #pragma unroll
-        for (int k = 0; k < kNuCells; k++) {
-            const int i = tid + k * kNuSpreadThreads;
-            if (i < ncell) {
-                const unsigned long long word = nsp[i];
-                nsp[i] = 0ull;
-                const long long re = (int32_t)(uint32_t)word;
-                acc_re[k] += re;
-                acc_im[k] += ((long long)word - re) >> 32;
+            for (int k = 0; k < kNuCells; k++) {
+                const int i = tid + k * kNuSpreadThreads;
+                if (i < ncell) {
+                    const unsigned long long word = nsp[i];
+                    nsp[i] = 0ull;
+                    const long long re = (int32_t)(uint32_t)word;
+                    acc_re[k] += re;
+                    acc_im[k] += ((long long)word - re) >> 32;
+                }
             }
+            __syncthreads();   // cleared before the next step adds
         }
-        __syncthreads();   // cleared before the next step adds
     }
     // the chunk's rows [c][re, im][RL] of request j's partial
     long long *dst = a.grid + (((size_t)chunk * a.V + v) * a.C + c0) * (size_t)RL * 2;
