@@ -74,9 +74,12 @@ __global__ __launch_bounds__(256) void k_nu_corr_adj(const AdjArgs *__restrict__
 
 // Gradient row (v, c) of a request of the batch (blocks [first[j], first[j + 1])
 // are request j's rows, v major): u1_l, u2_l (float4: u1.re, u1.im, u2.re, u2.im)
-// for l = -M/2 - 3 .. M/2 + 3 at index l + M/2 + 3, by a direct DFT over the
-// S deconvolved modes with twiddles e^{2 pi j k / M} from an exact-index LDS
-// table; the last entry of the row is zero padding.
+// for l = -M/2 - 3 .. M/2 + 3 at index l + M/2 + 3, the DFT of the S
+// deconvolved modes (mode s' = s - S/2 at position s' mod M of an M-point
+// sequence, zero elsewhere) with twiddles e^{2 pi j k / M} from an
+// exact-index LDS table: for M a power of two an in-place radix-2 FFT in LDS
+// (both sequences in the same butterflies), otherwise a direct sum per
+// output; the last entry of the row is zero padding.
 __global__ __launch_bounds__(256) void k_nu_rows(const AdjArgs *__restrict__ args, const int32_t *__restrict__ first,
                                                  int m) {
     extern __shared__ float4 nsh[];
@@ -94,8 +97,7 @@ __global__ __launch_bounds__(256) void k_nu_rows(const AdjArgs *__restrict__ arg
     const int S = a.S;
     const float fcf = a.fcf, sl_fs = a.sl_fs;
     const int M = 2 * S, RL = nu_row_len(S);
-    float4 *hb = nsh;                                         // [S] h1, h2 over Psi
-    float2 *tw = reinterpret_cast<float2 *>(nsh + S);         // [M]
+    float2 *tw = reinterpret_cast<float2 *>(nsh + M);        // [M], after the M-point sequence
     const size_t row = (size_t)((int)blockIdx.x - first[j]);
     for (int k = threadIdx.x; k < M; k += blockDim.x) {
         double sn, cs;
@@ -103,6 +105,50 @@ __global__ __launch_bounds__(256) void k_nu_rows(const AdjArgs *__restrict__ arg
         tw[k] = make_float2((float)cs, (float)sn);
     }
     const float2 *g = G + row * S;
+    float4 *out = rows + row * RL;
+    if ((M & (M - 1)) == 0) {
+        // a[n] = h_{s}, n = (s - S/2) mod M (zero for the other half), stored
+        // at bit-reversed positions; X[l] = sum_n a[n] e^{2 pi j n l / M}
+        float4 *a4 = nsh;   // [M]
+        const int lg = 31 - __clz(M);
+        for (int n = threadIdx.x; n < M; n += blockDim.x) {
+            const int s = (n + S / 2) % M;
+            float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (s < S) {
+                const float2 v = g[s];
+                const float r = corr[s];
+                const float w2 = fmaf(sl_fs, (float)s, fcf);
+                const float hr = v.x * r, hi = -v.y * r;   // conj(G_s) / Psi
+                h = make_float4(hr, hi, hr * w2, hi * w2);
+            }
+            a4[__brev((uint32_t)n) >> (32 - lg)] = h;
+        }
+        __syncthreads();
+        for (int half = 1; half < M; half <<= 1) {
+            const int tstep = M / (2 * half);
+            for (int i = threadIdx.x; i < M / 2; i += blockDim.x) {
+                const int pos = i & (half - 1), j0 = ((i - pos) << 1) + pos, j1 = j0 + half;
+                const float2 w = tw[pos * tstep];
+                const float4 u = a4[j0], v = a4[j1];
+                const float4 vw = make_float4(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x,
+                                              v.z * w.x - v.w * w.y, v.z * w.y + v.w * w.x);
+                a4[j0] = make_float4(u.x + vw.x, u.y + vw.y, u.z + vw.z, u.w + vw.w);
+                a4[j1] = make_float4(u.x - vw.x, u.y - vw.y, u.z - vw.z, u.w - vw.w);
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < RL; i += blockDim.x) {
+            if (i < RL - 1) {
+                int lm = (i - (M / 2 + kNuHalf)) % M;   // l mod M
+                if (lm < 0) lm += M;
+                out[i] = a4[lm];
+            } else {
+                out[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        return;
+    }
+    float4 *hb = nsh;   // [S] h1, h2 over Psi
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
         const float2 v = g[s];
         const float r = corr[s];
@@ -111,7 +157,6 @@ __global__ __launch_bounds__(256) void k_nu_rows(const AdjArgs *__restrict__ arg
         hb[s] = make_float4(hr, hi, hr * w2, hi * w2);
     }
     __syncthreads();
-    float4 *out = rows + row * RL;
     for (int i = threadIdx.x; i < RL; i += blockDim.x) {
         float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
         if (i < RL - 1) {
@@ -1098,7 +1143,7 @@ int launch_backward_batch(const BackwardReq *reqs, int n, void *table, hipStream
         ProfScope ps(kProfSynthAdj, s);
         hipLaunchKernelGGL(k_nu_corr_adj, dim3((unsigned)((max_s + 255) / 256), (unsigned)n_nu), dim3(256), 0, s,
                            t.args);
-        const size_t lds_rows = sizeof(float4) * max_s + sizeof(float2) * 2 * max_s;
+        const size_t lds_rows = sizeof(float4) * 2 * max_s + sizeof(float2) * 2 * max_s;   // sequence + twiddles
         hipLaunchKernelGGL(k_nu_rows, dim3((unsigned)row_first.back()), dim3(256), lds_rows, s, t.args, t.row_first,
                            n_nu);
         SBR_LAUNCHED();

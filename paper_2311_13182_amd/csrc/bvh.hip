@@ -318,8 +318,9 @@ __global__ void k_leaves(const float *verts, const int32_t *faces, BvhView bv) {
         nd->hi[k] = hi[k];
     }
     int p = bv.parent[x];
+    // the acquire-release counter orders this thread's box stores before the
+    // sibling thread's reads of them (no separate fence)
     while (p >= 0) {
-        __threadfence();
         uint32_t prev = __hip_atomic_fetch_add(&bv.visits[p], 1u, __ATOMIC_ACQ_REL,
                                                __HIP_MEMORY_SCOPE_AGENT);
         if (prev == 0) return;  // sibling subtree not finished; it will continue

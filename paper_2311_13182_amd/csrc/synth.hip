@@ -810,9 +810,10 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
 // Row (v, c) = blockIdx.x of the non-uniform FFT form: the chunks' integer
 // cells summed and folded onto the periodic grid (cell l of l + M/2 + 3 and,
 // for the first 2 kNuHalf + 1 positions, of l + 3M/2 + 3), scaled back to FP64,
-// then the DFT to the S centred modes with exact-index twiddles and the
-// deconvolution 1/Psi.  A non-finite amplitude makes the row NaN, as the
-// direct sum would.
+// then the DFT to the S centred modes and the deconvolution 1/Psi.  For M a
+// power of two the DFT is an in-place radix-2 FFT in LDS (grid points stored
+// at bit-reversed positions), otherwise a direct sum with exact-index
+// twiddles.  A non-finite amplitude makes the row NaN, as the direct sum would.
 __global__ __launch_bounds__(256) void k_nu_synth_rows(const SynthArgs *__restrict__ args,
                                                        const int32_t *__restrict__ nidx,
                                                        const int32_t *__restrict__ first, int m) {
@@ -832,6 +833,8 @@ __global__ __launch_bounds__(256) void k_nu_synth_rows(const SynthArgs *__restri
     const uint32_t ab = *gmem(a.amax);
     const double inv = 1.0 / (double)nu_scale(ab);
     const size_t chunk_stride = (size_t)a.V * a.C * RL * 2;
+    const bool pow2 = (M & (M - 1)) == 0;
+    const int lg = 31 - __clz(M);
     for (int l = threadIdx.x; l < M; l += blockDim.x) {
         const int j1 = (l + M / 2 + kNuHalf) % M;
         const bool wrap = j1 + M < RL - 1;
@@ -845,11 +848,32 @@ __global__ __launch_bounds__(256) void k_nu_synth_rows(const SynthArgs *__restri
                 im += src[RL + j1 + M];
             }
         }
-        b[l] = make_double2((double)re * inv, (double)im * inv);
+        b[pow2 ? (int)(__brev((uint32_t)l) >> (32 - lg)) : l] = make_double2((double)re * inv, (double)im * inv);
     }
     __syncthreads();
     const bool bad = ab >= 0x7f800000u;
     const auto corr = gmem(a.corr);
+    if (pow2) {
+        // X[k] = sum_l b_l e^{2 pi j k l / M}, decimation in time
+        for (int half = 1; half < M; half <<= 1) {
+            const int tstep = M / (2 * half);
+            for (int i = threadIdx.x; i < M / 2; i += blockDim.x) {
+                const int pos = i & (half - 1), j0 = ((i - pos) << 1) + pos, j1 = j0 + half;
+                const double2 w = tw[pos * tstep], u = b[j0], v = b[j1];
+                const double2 vw = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+                b[j0] = make_double2(u.x + vw.x, u.y + vw.y);
+                b[j1] = make_double2(u.x - vw.x, u.y - vw.y);
+            }
+            __syncthreads();
+        }
+        for (int s = threadIdx.x; s < S; s += blockDim.x) {
+            const double2 f = b[((s - S / 2) % M + M) % M];   // mode s' = s - S/2
+            const double cr = corr[s];
+            out[row * S + s] = bad ? make_float2(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000))
+                                   : make_float2((float)(f.x * cr), (float)(f.y * cr));
+        }
+        return;
+    }
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
         const int step = ((s - S / 2) % M + M) % M;   // s' mod M
         int k = 0;
