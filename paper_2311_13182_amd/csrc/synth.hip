@@ -938,7 +938,9 @@ static int nu_lds_budget() {
 // Non-uniform FFT form: as many chirps per spreading block as the LDS and
 // the threads' accumulators hold (at most 32; each block reads its chunk's
 // path records once for all of them), and path chunks enough for about
-// three blocks per CU over the device, each of at least 2048 path slots.  Depends only on the request's
+// three blocks per CU over the device, each of at least 8192 path slots (a
+// chunk's partial grid rows cost as much to write and sum as a few thousand
+// paths take to spread, so small requests take few chunks).  Depends only on the request's
 // sizes and the device, so a request runs the same blocks alone and in a batch.
 static SynthPlan nu_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) {
     SynthPlan p{};
@@ -950,7 +952,7 @@ static SynthPlan nu_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) 
     const long long ncg = (C + p.cg - 1) / p.cg;
     const long long cap = (long long)R * K;
     const long long want = (768 + (long long)V * ncg - 1) / ((long long)V * ncg);
-    p.n_chunks = (int32_t)std::max(1LL, std::min({want, (cap + 2047) / 2048, 256LL}));
+    p.n_chunks = (int32_t)std::max(1LL, std::min({want, (cap + 8191) / 8192, 256LL}));
     return p;
 }
 
