@@ -686,9 +686,12 @@ constexpr int kNuSpreadThreads = 1024;
 // range bins), and additions to one cell, or to one bank, within an
 // instruction serialise.  So the block takes its chunk 1024 paths at a time,
 // lane l of wave w the path at 16 l + w (lanes of a wave 16 paths apart), and
-// each lane walks the group's chirps from its own starting row (with 32
-// chirps, the two lanes of an instruction that share a row are 512 paths
-// apart).  The phase factor e^{2 pi j (alpha + c beta + g S/2)} is computed
+// each lane walks the group's chirps from a starting row chosen so that its
+// cell of the first chirp lies on bank pair l mod 32: row r of column j sits
+// on bank pair (r (RLs mod 32) + j) mod 32, and RLs is odd, so the row is
+// (l - j) times the inverse of RLs mod 32.  With 32 chirps every step of the
+// walk then puts the 64 lanes of an instruction on all 32 bank pairs, two
+// each, as long as the paths' columns stay put from chirp to chirp.  The phase factor e^{2 pi j (alpha + c beta + g S/2)} is computed
 // exactly at every eighth chirp of the walk and turned in between (g S/2
 // changes by (S/2) eps from chirp to chirp, up to an integer).
 constexpr int kNuCells = 17;   // grid cells per thread: cg (nu_row_len(S) + 1) <= 1024 kNuCells
@@ -725,7 +728,11 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
     const auto eps = gmem(a.rec.epsd);
     const float Mf = (float)M, halfS = (float)(S / 2);
     const int lane = tid & 63, wave = tid >> 6;
-    const int first_row = lane % nc;
+    // rows start (RLs mod 32) bank pairs apart; its inverse mod 32 (odd)
+    const int rs32 = RLs & 31;
+    int inv = rs32;
+#pragma unroll
+    for (int it = 0; it < 4; it++) inv = (inv * (2 - rs32 * inv)) & 31;
     int step = 0;
     for (int base = p0; base < p1; base += kNuSpreadThreads, step++) {   // block-uniform trip count
         const int p = base + 16 * lane + wave;
@@ -743,7 +750,15 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
             const float rs = __builtin_amdgcn_sinf(rho), rc = __builtin_amdgcn_cosf(rho);
             const float ws = __builtin_amdgcn_sinf(rw), wc = __builtin_amdgcn_cosf(rw);
             float zs = 0.0f, zc = 1.0f;
-            int cl = first_row;
+            // starting row: bank pair of (row, j0) = lane mod 32 at the group's first
+            // chirp, so the lanes of an instruction spread over all bank pairs
+            int cl;
+            {
+                const float f0 = fmaf((float)c0, epsd, gamma);
+                const float x0 = (f0 - rintf(f0)) * Mf;
+                const int jj = min(max((int)rintf(x0) + M / 2, 0), M);
+                cl = (((lane - jj) * inv) & 31) % nc;
+            }
             for (int k = 0; k < nc; k++, cl = cl + 1 == nc ? 0 : cl + 1) {
                 const float cf = (float)(c0 + cl);
                 const float f = fmaf(cf, epsd, gamma);
