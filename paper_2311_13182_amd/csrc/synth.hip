@@ -691,9 +691,10 @@ constexpr int kNuSpreadThreads = 1024;
 // on bank pair (r (RLs mod 32) + j) mod 32, and RLs is odd, so the row is
 // (l - j) times the inverse of RLs mod 32.  With 32 chirps every step of the
 // walk then puts the 64 lanes of an instruction on all 32 bank pairs, two
-// each, as long as the paths' columns stay put from chirp to chirp.  The phase factor e^{2 pi j (alpha + c beta + g S/2)} is computed
-// exactly at every eighth chirp of the walk and turned in between (g S/2
-// changes by (S/2) eps from chirp to chirp, up to an integer).
+// each, as long as the paths' columns stay put from chirp to chirp.  The
+// phase factor e^{2 pi j (alpha + c beta + g S/2)} is computed exactly at
+// every eighth chirp of the walk and turned in between (g S/2 changes by
+// (S/2) eps from chirp to chirp, up to an integer).
 constexpr int kNuCells = 17;   // grid cells per thread: cg (nu_row_len(S) + 1) <= 1024 kNuCells
 
 __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs *__restrict__ args,
