@@ -184,7 +184,9 @@ def main():
         sim.cfar(X, max_points=4096)
         sim.loss_grad(cube, target, grad, loss)
         gv.zero_()
-        sim.backward(grad, gv)
+        # the backward pass takes the path records of this step's synthesis
+        # from the scratch (same mesh, hits and radar) instead of recomputing them
+        sim.backward(grad, gv, reuse_paths=True)
 
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)

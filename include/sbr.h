@@ -166,6 +166,16 @@ typedef struct {
                                 moving silhouettes then contribute.  The forward
                                 signal is the same; without the flag the gradient is
                                 the pathwise one with fixed ray directions. */
+#define SBR_PATHS_IN_SCRATCH 16 /* sbr_backward only: skip the path stage (FP64
+                                path records and their ray-major compaction) and
+                                use the records already in `scratch`.  The caller
+                                vouches that the last call that wrote this scratch
+                                was an sbr_synth_if with the same mesh, materials,
+                                radar, rays, hits, chirp and SBR_DROP_FLAGGED /
+                                SBR_EXIT_ONLY flags (both entry points lay the
+                                records out alike); the library cannot check this.
+                                It saves recomputing identical records when a
+                                backward pass follows its forward pass.            */
 #define SBR_DIRECT_SUMS 8    /* sum Eq. 8 (sbr_synth_if) and the per-path series of
                                 Eqs. 11-12 (sbr_backward) directly over paths and
                                 samples rather than by the non-uniform FFT forms
@@ -366,7 +376,8 @@ typedef struct {
  * per path; exponential-of-semicircle kernel), whose error is below 1e-6 of
  * sum_s |weighted G_s| at every g; with SBR_DIRECT_SUMS, or for other S, by
  * direct summation.  Arguments as for sbr_synth_if; hits and flags must be
- * those the forward used.  params: NULL,
+ * those the forward used (plus SBR_ATTACHED, and SBR_PATHS_IN_SCRATCH when
+ * the scratch still holds that forward's path records).  params: NULL,
  * or where to ADD the gradients of the material table (Eqs. 9-10 through
  * eps_c), of the radar origin (ray origins, TX and RX positions, return
  * distances), of the radar rotation (ray directions, TX and RX positions,

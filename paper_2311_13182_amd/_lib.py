@@ -21,6 +21,7 @@ SBR_DROP_FLAGGED = 1
 SBR_ATTACHED = 2
 SBR_EXIT_ONLY = 4
 SBR_DIRECT_SUMS = 8
+SBR_PATHS_IN_SCRATCH = 16
 SBR_OP_BUILD_BVH, SBR_OP_SYNTH, SBR_OP_BACKWARD, SBR_OP_RADAR_CUBE, SBR_OP_CFAR = 0, 1, 2, 3, 4
 SBR_LOSS_SCRATCH_BYTES = 8192
 SBR_MAX_BATCH = 1024

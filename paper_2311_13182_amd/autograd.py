@@ -32,6 +32,7 @@ class SBRFunction(torch.autograd.Function):
         sim.trace()
         cube = torch.view_as_complex(sim.synth())
         ctx.sim = sim
+        ctx.paths_token = sim.paths_token   # this synthesis's path records in the scratch
         ctx.attached = attached
         ctx.hits = sim.hits
         ctx.verts = sim.mesh.verts.clone()
@@ -45,7 +46,9 @@ class SBRFunction(torch.autograd.Function):
         sim.hits = ctx.hits
         sim.mesh.verts.copy_(ctx.verts)
         try:
-            g = sim.backward(grad_cube.contiguous(), attached=ctx.attached)
+            # reuse the path records if nothing has replaced them since this forward
+            reuse = sim.paths_token is not None and sim.paths_token == ctx.paths_token
+            g = sim.backward(grad_cube.contiguous(), attached=ctx.attached, reuse_paths=reuse)
         finally:
             sim.hits = cur_hits
             sim.mesh.verts.copy_(cur_verts)

@@ -283,7 +283,8 @@ static int check_backward(const sbr_mesh *mesh, const sbr_material *mats, int32_
     int rc;
     if ((rc = check_common(mesh, mats, n_mats, radar, rays, hits, chirp))) return rc;
     SBR_CHECK_ARG(grad_if && grad_verts, "grad_if/grad_verts is NULL");
-    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY | SBR_DIRECT_SUMS)) == 0,
+    SBR_CHECK_ARG((flags & ~(SBR_DROP_FLAGGED | SBR_ATTACHED | SBR_EXIT_ONLY | SBR_DIRECT_SUMS |
+                             SBR_PATHS_IN_SCRATCH)) == 0,
                   "unknown flags 0x%x", flags);
     SBR_CHECK_ARG(!params || !params->materials || (mats && n_mats > 0),
                   "material gradients requested without a material table");
@@ -348,6 +349,7 @@ static int enqueue_backward(const sbr_mesh *mesh, const sbr_material *mats, int3
     q->params = params;
     q->flags = flags;
     if (table) *table = c.table;
+    if (flags & SBR_PATHS_IN_SCRATCH) return SBR_OK;   // records of the preceding synthesis
     return launch_paths(mesh, q->mt, q->rd, q->gd, q->cd, hits, flags, q->st, s);
 }
 

@@ -413,40 +413,52 @@ def _angle_grid(rd: S.Radar, n_angle: int):
     return n, 1, n
 
 
-def simulator_scratch_bytes(scene: S.Scene, nf: Optional[int] = None, backward: bool = True, cube: bool = True,
-                            n_angle: int = 64) -> int:
-    """Bytes of the one scratch buffer a Simulator allocates: the largest of
-    the stages it may run (BVH build and synthesis always; the backward pass
-    and the radar cube + CFAR when asked for)."""
+def _scratch_parts(scene: S.Scene, nf: Optional[int], backward: bool, cube: bool, n_angle: int):
+    """(main, cube) bytes of a Simulator's two scratch buffers: the main one
+    for the BVH build, the synthesis and (when asked for) the backward pass,
+    which lay their path records out alike; the other for the radar cube and
+    CFAR (when asked for), kept apart so that those stages do not overwrite
+    the records between a synthesis and its backward pass."""
     g, rd, ch = scene.grid, scene.radar, scene.chirp
     nf = scene.nf if nf is None else nf
     m = L.sbr_mesh(None, scene.nv, None, nf, None)
     lib = _lib()
     rs, rr, cs = rays_struct(g), radar_struct(rd), chirp_struct(ch)
-    need = max(int(lib.sbr_scratch_bytes(L.SBR_OP_BUILD_BVH, ct.byref(m), None, None, None)),
+    main = max(int(lib.sbr_scratch_bytes(L.SBR_OP_BUILD_BVH, ct.byref(m), None, None, None)),
                int(lib.sbr_scratch_bytes(L.SBR_OP_SYNTH, ct.byref(m), ct.byref(rs), ct.byref(rr), ct.byref(cs))))
     if backward:
-        need = max(need, int(lib.sbr_scratch_bytes(L.SBR_OP_BACKWARD, ct.byref(m), ct.byref(rs), ct.byref(rr),
+        main = max(main, int(lib.sbr_scratch_bytes(L.SBR_OP_BACKWARD, ct.byref(m), ct.byref(rs), ct.byref(rr),
                                                    ct.byref(cs))))
+    cb = 0
     if cube:
         n_ax, n_ay, na = _angle_grid(rd, n_angle)
         C, Sn = ch.n_chirps, ch.n_samples
-        need = max(need, int(lib.sbr_scratch_bytes(L.SBR_OP_RADAR_CUBE, None, ct.byref(rs), ct.byref(rr),
-                                                   ct.byref(cs))),
-                   int(lib.sbr_scratch_bytes(L.SBR_OP_CFAR, None, ct.byref(rs), ct.byref(rr), ct.byref(cs))))
+        cb = max(int(lib.sbr_scratch_bytes(L.SBR_OP_RADAR_CUBE, None, ct.byref(rs), ct.byref(rr), ct.byref(cs))),
+                 int(lib.sbr_scratch_bytes(L.SBR_OP_CFAR, None, ct.byref(rs), ct.byref(rr), ct.byref(cs))))
         # the cube stage needs room for max(V, n_angle) planes
         if getattr(rd, "planar", False):
-            need = max(need, sbr_radar_cube_2d_bytes(rd.n_rx, rd.n_tx, C, Sn, n_ax, n_ay))
+            cb = max(cb, sbr_radar_cube_2d_bytes(rd.n_rx, rd.n_tx, C, Sn, n_ax, n_ay))
         else:
-            need = max(need, 2 * 8 * na * C * Sn + 1024)
-    return need
+            cb = max(cb, 2 * 8 * na * C * Sn + 1024)
+    return main, cb
+
+
+def simulator_scratch_bytes(scene: S.Scene, nf: Optional[int] = None, backward: bool = True, cube: bool = True,
+                            n_angle: int = 64) -> int:
+    """Bytes of the scratch a Simulator allocates: the largest of the stages
+    it may run (BVH build and synthesis always, the backward pass when asked
+    for) plus, when asked for, a separate buffer for the radar cube and CFAR."""
+    main, cb = _scratch_parts(scene, nf, backward, cube, n_angle)
+    return main + cb
 
 
 class Simulator:
-    """One scene resident on the device: mesh, BVH, hit records, one scratch
-    buffer shared by all stages (stages on one stream run in order).  The
-    scratch is sized for the stages asked for: `backward` (sbr_backward) and
-    `cube` (radar cube, CFAR, point clouds); BVH build and synthesis always."""
+    """One scene resident on the device: mesh, BVH, hit records and scratch
+    (stages on one stream run in order).  The main scratch serves the BVH
+    build, the synthesis and, with `backward`, sbr_backward; with `cube` a
+    second one serves the radar cube, CFAR and point clouds, so that the path
+    records of a synthesis survive them and its backward pass can reuse them
+    (`backward(..., reuse_paths=True)`)."""
 
     def __init__(self, scene: S.Scene, device="cuda", drop_flagged: bool = True, n_angle: int = 64,
                  mesh: Optional[DeviceMesh] = None, bvh: Optional[torch.Tensor] = None, exit_only: bool = False,
@@ -460,8 +472,13 @@ class Simulator:
         self.V, self.C, self.S = rd.n_virtual, ch.n_chirps, ch.n_samples
         self.planar = bool(getattr(rd, "planar", False))
         self.n_ax, self.n_ay, self.n_angle = _angle_grid(rd, n_angle)
-        need = simulator_scratch_bytes(scene, self.mesh.nf, backward, cube, n_angle)
-        self.scratch = torch.empty(need, dtype=torch.uint8, device=self.device)
+        main, cb = _scratch_parts(scene, self.mesh.nf, backward, cube, n_angle)
+        self.scratch = torch.empty(main, dtype=torch.uint8, device=self.device)
+        self.cube_scratch = torch.empty(cb, dtype=torch.uint8, device=self.device) if cube else None
+        # identifies the synthesis whose path records the main scratch holds;
+        # None once the mesh, BVH or hits may have changed since
+        self.paths_token: Optional[int] = None
+        self._n_synth = 0
         self.bvh = bvh if bvh is not None else torch.empty(max(1, sbr_bvh_bytes(self.mesh.nf)), dtype=torch.uint8,
                                                            device=self.device)
         self.hits = Hits.empty(self.K, self.R, self.device)
@@ -471,6 +488,7 @@ class Simulator:
 
     # ---- geometry
     def set_verts(self, verts: torch.Tensor):
+        self.paths_token = None
         self.mesh.verts.copy_(verts.detach().to(torch.float32).reshape(-1, 3))
 
     def build(self, refit: bool = False):
@@ -478,11 +496,13 @@ class Simulator:
             return
         sbr_build_bvh(self.mesh, self.bvh, 1 if (refit and self.built) else 0, self.scratch)
         self.built = True
+        self.paths_token = None
 
     # ---- forward
     def trace(self, count: bool = False):
         if not self.built:
             self.build()
+        self.paths_token = None
         sbr_trace(self.mesh, self.bvh if self.mesh.nf else None, self.scene.radar, self.scene.grid, self.hits,
                   self.counters if count else None)
         return self.hits
@@ -495,11 +515,18 @@ class Simulator:
         flags = self.flags | (L.SBR_DIRECT_SUMS if direct_sums else 0)
         sbr_synth_if(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, flags, out,
                      self.scratch)
+        self._n_synth += 1
+        self.paths_token = self._n_synth
         return out
 
     def forward(self) -> torch.Tensor:
         self.trace()
         return torch.view_as_complex(self.synth())
+
+    def _cube_scratch(self) -> torch.Tensor:
+        if self.cube_scratch is None:
+            raise RuntimeError("this Simulator was made with cube=False (no radar-cube scratch)")
+        return self.cube_scratch
 
     def radar_cube(self, x: torch.Tensor, direction: int = 0, window: int = 0) -> torch.Tensor:
         xf = torch.view_as_real(x) if x.is_complex() else x
@@ -511,9 +538,9 @@ class Simulator:
         if self.planar:
             rd = self.scene.radar
             sbr_radar_cube_2d(xf, rd.n_rx, rd.n_tx, self.C, self.S, self.n_ax, self.n_ay, window, direction, out,
-                              self.scratch)
+                              self._cube_scratch())
         else:
-            sbr_radar_cube(xf, self.V, self.C, self.S, self.n_angle, window, direction, out, self.scratch)
+            sbr_radar_cube(xf, self.V, self.C, self.S, self.n_angle, window, direction, out, self._cube_scratch())
         return torch.view_as_complex(out)
 
     def cfar(self, X: torch.Tensor, guard=2, train=8, pfa=1e-4, max_points=65536):
@@ -521,7 +548,7 @@ class Simulator:
         pts = torch.empty((max_points, 4), dtype=torch.int32, device=self.device)
         ratio = torch.empty(max_points, dtype=torch.float32, device=self.device)
         n = torch.zeros(1, dtype=torch.int32, device=self.device)
-        sbr_cfar(xf, int(xf.shape[0]), self.C, self.S, guard, train, pfa, pts, ratio, n, self.scratch)
+        sbr_cfar(xf, int(xf.shape[0]), self.C, self.S, guard, train, pfa, pts, ratio, n, self._cube_scratch())
         return pts, ratio, n
 
     def cloud(self, points: torch.Tensor, n_points: torch.Tensor) -> torch.Tensor:
@@ -567,18 +594,27 @@ class Simulator:
     def backward(self, grad_if: torch.Tensor, grad_verts: Optional[torch.Tensor] = None,
                  grad_materials: Optional[torch.Tensor] = None, grad_radar: Optional[torch.Tensor] = None,
                  grad_rot: Optional[torch.Tensor] = None, attached: bool = False,
-                 grad_atten: Optional[torch.Tensor] = None, direct_sums: bool = False) -> torch.Tensor:
+                 grad_atten: Optional[torch.Tensor] = None, direct_sums: bool = False,
+                 reuse_paths: bool = False) -> torch.Tensor:
         """dL/dverts (accumulated into grad_verts); optionally also accumulates
         dL/d(eps_r, sigma) per material [n_mats,2], dL/d(origin, velocity) [6]
         dL/d rot [3,3] (radar -> world, row-major) and dL/d attenuation [1].  attached=True
         differentiates the reparameterised estimator (samples follow their
         first hit, Eqs. 6-7), so that moving silhouettes contribute.
         direct_sums=True sums the per-path adjoint series of Eqs. 11-12
-        directly over the samples instead of by the non-uniform FFT."""
+        directly over the samples instead of by the non-uniform FFT.
+        reuse_paths=True takes the path records of the last synth() from the
+        scratch instead of recomputing them (SBR_PATHS_IN_SCRATCH); it is an
+        error once build(), trace() or set_verts() has run since.  The scene's
+        radar and chirp must be the ones that synthesis used."""
         gf = (torch.view_as_real(grad_if) if grad_if.is_complex() else grad_if).contiguous().to(torch.float32)
         if grad_verts is None:
             grad_verts = torch.zeros((self.mesh.nv, 3), dtype=torch.float32, device=self.device)
         flags = self.flags | (L.SBR_ATTACHED if attached else 0) | (L.SBR_DIRECT_SUMS if direct_sums else 0)
+        if reuse_paths:
+            if self.paths_token is None:
+                raise RuntimeError("reuse_paths: the scratch holds no path records of the current hits")
+            flags |= L.SBR_PATHS_IN_SCRATCH
         sbr_backward(self.mesh, self.scene.radar, self.scene.grid, self.hits, self.scene.chirp, flags, gf,
                      grad_verts, self.scratch, grad_materials, grad_radar, grad_rot, grad_atten)
         return grad_verts

@@ -1061,6 +1061,39 @@ def test_synth_nufft_matches_direct_sums(torch_cuda, case):
     assert e <= (0.0 if sc.chirp.n_samples < 16 else 1e-5)
 
 
+def test_backward_reuses_the_synthesis_path_records(torch_cuda):
+    """sbr_backward with SBR_PATHS_IN_SCRATCH (Simulator.backward(...,
+    reuse_paths=True)) takes the path records that the synthesis left in the
+    scratch; with a radar cube and CFAR run in between (their own scratch) the
+    gradients equal those of a backward pass that recomputes the records, up
+    to the order of the floating-point atomics that sum vertex and radar
+    gradients over rays.  Once trace() has run again the reuse is refused."""
+    import torch
+    sc = S.icosphere_scene(n_rays=256, n_chirps=16)
+    sim = _sim(sc)
+    sim.trace()
+    cube = sim.synth()
+    X = sim.radar_cube(cube)
+    sim.cfar(X, max_points=1024)
+    rng = np.random.default_rng(43)
+    shape = (sc.radar.n_virtual, sc.chirp.n_chirps, sc.chirp.n_samples, 2)
+    G = torch.as_tensor(rng.normal(size=shape).astype(np.float32), device="cuda")
+    out = []
+    for reuse in (True, False, False):
+        gr = torch.zeros(6, dtype=torch.float32, device="cuda")
+        gv = sim.backward(G, grad_radar=gr, reuse_paths=reuse)
+        torch.cuda.synchronize()
+        out.append(torch.cat([gv.reshape(-1), gr]).double().cpu())
+    e = float((out[0] - out[1]).norm() / out[1].norm())
+    noise = float((out[2] - out[1]).norm() / out[1].norm())
+    log(f"backward with the synthesis's path records vs recomputed: rel L2 {e:.3e} "
+        f"(two recomputing passes: {noise:.3e}); {sim.n_paths()} paths")
+    assert e <= 1e-6
+    sim.trace()
+    with pytest.raises(RuntimeError, match="reuse_paths"):
+        sim.backward(G, reuse_paths=True)
+
+
 @pytest.mark.parametrize("case", ["clutter_full", "ico_s256", "ico_s200", "ico_s16", "ico_s1024", "ico_s8"])
 def test_backward_nufft_matches_direct_sums(torch_cuda, case):
     """The adjoint's per-path series of Eqs. 11-12 by the non-uniform FFT

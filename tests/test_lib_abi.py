@@ -81,6 +81,13 @@ def test_argument_errors_are_reported(lib):
     rc = lib.sbr_backward(ct.byref(m), None, 0, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
                           fake, None, fake, 16, None)
     assert rc == L.SBR_E_SCRATCH
+    # SBR_PATHS_IN_SCRATCH belongs to sbr_backward only
+    rc = lib.sbr_synth_if(ct.byref(m), None, 0, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c),
+                          1 | L.SBR_PATHS_IN_SCRATCH, fake, fake, 1 << 40, None)
+    assert rc == L.SBR_E_ARG and b"unknown flags" in lib.sbr_last_error()
+    rc = lib.sbr_backward(ct.byref(m), None, 0, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c),
+                          1 | L.SBR_PATHS_IN_SCRATCH, fake, fake, None, fake, 16, None)
+    assert rc == L.SBR_E_SCRATCH
     pg = L.sbr_param_grads(0x10000, None)     # material gradients need a material table
     rc = lib.sbr_backward(ct.byref(m), None, 0, ct.byref(r), ct.byref(g), ct.byref(h), ct.byref(c), 1, fake,
                           fake, ct.byref(pg), fake, 1 << 30, None)
