@@ -239,11 +239,12 @@ int sbr_trace(const sbr_mesh *mesh, const void *bvh, const sbr_radar *radar,
  * non-uniform FFT: every path's term is spread onto a 2S-point grid with 7
  * exponential-of-semicircle kernel taps, each contribution rounded to an
  * integer (a power-of-two scale between 2^18 and 2^19 over the largest
- * max(|Re I^s|, |Im I^s|) of the call) and accumulated exactly in 64-bit
- * integers, so the result does not depend on the order of the additions;
- * one DFT per row and the kernel's deconvolution follow.  The kernel's error
- * is below 1e-6 of sum_paths |I^s| per sample; each tap's rounding adds at
- * most 2^-19 of that largest component.
+ * max(|Re I^s|, |Im I^s|) of its chunk of paths; the chunks depend only on the
+ * call's sizes) and accumulated exactly in 64-bit integers, so the result
+ * does not depend on the order of the additions; one DFT per row and the
+ * kernel's deconvolution follow.  The kernel's error is below 1e-6 of
+ * sum_paths |I^s| per sample; each tap's rounding adds at most 2^-19 of that
+ * largest component of its chunk.
  * With SBR_DIRECT_SUMS, or for other S, the sum is taken directly.
  * if_cube: device float [V][C][S][2], overwritten.  mats: host array of
  * n_mats (<= 64) entries, or NULL / 0 for all-conductor.  A hit id outside

@@ -222,7 +222,7 @@ static SynthCarve synth_carve(void *scratch, int R, int K, int V, int C, int S, 
     c.partial = nu ? nullptr : cv.take<float2>(synth_partial_elems(c.p, V, C, S));
     c.grid = nu ? cv.take<long long>(synth_grid_words(c.p, V, C, S)) : nullptr;
     c.corr = nu ? cv.take<float>((size_t)S) : nullptr;
-    c.amax = nu ? cv.take<uint32_t>(64) : nullptr;
+    c.amax = nu ? cv.take<uint32_t>(kNuMaxChunks) : nullptr;
     c.table = cv.take<char>(synth_table_bytes(1));
     c.bytes = align_up(cv.off, 256);
     return c;

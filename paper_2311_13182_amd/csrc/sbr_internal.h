@@ -192,7 +192,7 @@ struct SynthArgs {
     // non-uniform FFT form (nu = 1): chirps per spreading block, chirp groups;
     // the max-amplitude word, the 1/Psi table and the fixed-point grids
     int32_t nu, cg, ncg;
-    uint32_t *amax;      // [1] max over paths of max(|Re A|, |Im A|), float bits
+    uint32_t *amax;      // [kNuMaxChunks] per path chunk: max over its paths of max(|Re A|, |Im A|), float bits
     float *corr;         // [S]
     long long *grid;     // [n_chunks][V][C][re, im][nu_row_len(S)]
     float2 *out;         // [V][C][S] the IF cube (set by launch_synth_batch)
@@ -255,6 +255,7 @@ constexpr int kNuHalf = (kNuW - 1) / 2;
 constexpr double kNuBeta = 2.30 * kNuW;
 constexpr int kNuMinS = 16;     // shorter chirps use the direct forms (cheap there)
 constexpr int kNuMaxS = 1024;   // longer chirps use the direct forms
+constexpr int kNuMaxChunks = 256;   // path chunks of a spreading launch, each with its own scale
 __host__ __device__ constexpr int nu_row_len(int S) { return 2 * S + 8; }
 static inline bool nu_size(int S) { return S >= kNuMinS && S <= kNuMaxS; }
 

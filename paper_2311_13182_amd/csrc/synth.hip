@@ -599,9 +599,10 @@ __global__ void k_reduce_chunks(const float2 *partial, int n_chunks, size_t n, f
 // so each path adds kNuW weighted copies of w'_p to a grid of M = 2S points
 // (spreading), and one DFT per row and the deconvolution finish it.  The
 // spreading rounds every contribution to an integer of the scale
-// 2^(19 - e), max(|Re A|, |Im A|) < 2^e (so below 2^19.5 in magnitude), and
-// sums them as integers: integer addition is exact, so the grid and the cube
-// do not depend on the order in which blocks, waves or lanes add.
+// 2^(19 - e), max(|Re A|, |Im A|) < 2^e over the paths of its chunk (so below
+// 2^19.5 in magnitude; a strong path costs precision only in its own chunk),
+// and sums them as integers: integer addition is exact, so the grid and the
+// cube do not depend on the order in which blocks, waves or lanes add.
 
 // Request of a block of a batched launch: binary search over first[0..m]
 // (request j owns blocks [first[j], first[j + 1])).
@@ -615,29 +616,38 @@ __device__ __forceinline__ int nu_request(const int32_t *first, int m, int blk) 
     return lo;
 }
 
-// The amplitude words of the batch's requests of this form, cleared before
+// The per-chunk amplitude words of request nidx[blockIdx.x], cleared before
 // k_nu_amax runs.
-__global__ void k_nu_zero(const SynthArgs *__restrict__ args, const int32_t *__restrict__ nidx, int m) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < m) *args[nidx[j]].amax = 0u;
+__global__ void k_nu_zero(const SynthArgs *__restrict__ args, const int32_t *__restrict__ nidx) {
+    const SynthArgs &a = args[nidx[blockIdx.x]];
+    for (int c = threadIdx.x; c < a.n_chunks; c += blockDim.x) a.amax[c] = 0u;
 }
 
-// Request nidx[blockIdx.y]: max over the live paths of max(|Re A|, |Im A|),
-// as the bits of a non-negative float: an integer maximum, exact and
+// Blocks per path chunk of k_nu_amax.
+constexpr int kNuAmaxSub = 16;
+
+// Request nidx[blockIdx.y], chunk blockIdx.x / kNuAmaxSub (the chunks of
+// k_nu_spread): max over the chunk's live paths of max(|Re A|, |Im A|), as
+// the bits of a non-negative float: an integer maximum, exact and
 // order-independent.
 __global__ __launch_bounds__(256) void k_nu_amax(const SynthArgs *__restrict__ args,
                                                  const int32_t *__restrict__ nidx) {
     const SynthArgs &a = args[nidx[blockIdx.y]];
+    const int chunk = (int)blockIdx.x / kNuAmaxSub, sub = (int)blockIdx.x % kNuAmaxSub;
+    if (chunk >= a.n_chunks) return;   // block-uniform
     const int P = *gmem(a.count);
+    const long long per = ((long long)P + a.n_chunks - 1) / a.n_chunks;
+    const int p0 = (int)min((long long)P, per * chunk);
+    const int p1 = (int)min((long long)P, per * (chunk + 1));
     const auto amp = gmem(a.rec.amp);
     uint32_t m = 0;
-    for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256) {
+    for (int p = p0 + sub * 256 + (int)threadIdx.x; p < p1; p += kNuAmaxSub * 256) {
         const F2 A = amp[p];
         m = max(m, __float_as_uint(fmaxf(fabsf(A.x), fabsf(A.y))));
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-    if ((threadIdx.x & 63) == 0 && m != 0u) atomicMax(a.amax, m);
+    if ((threadIdx.x & 63) == 0 && m != 0u) atomicMax(a.amax + chunk, m);
 }
 
 // Request nidx[blockIdx.y]: its 1/Psi table (nu_corr_value), 256 modes a block.
@@ -721,7 +731,7 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
     const long long per = ((long long)P + a.n_chunks - 1) / a.n_chunks;
     const int p0 = (int)min((long long)P, per * chunk);
     const int p1 = (int)min((long long)P, per * (chunk + 1));
-    const float sigma = nu_scale(*gmem(a.amax));
+    const float sigma = nu_scale(gmem(a.amax)[chunk]);
     const auto al = gmem(a.rec.alpha + (size_t)v * a.rec.cap);
     const auto ga = gmem(a.rec.gamma + (size_t)v * a.rec.cap);
     const auto amp = gmem(a.rec.amp);
@@ -826,7 +836,9 @@ __global__ __launch_bounds__(kNuSpreadThreads) void k_nu_spread(const SynthArgs 
 // Row (v, c) = blockIdx.x of the non-uniform FFT form: the chunks' integer
 // cells summed and folded onto the periodic grid (cell l of l + M/2 + 3 and,
 // for the first 2 kNuHalf + 1 positions, of l + 3M/2 + 3), scaled back to FP64,
-// then the DFT to the S centred modes and the deconvolution 1/Psi.  For M a
+// each chunk's cells scaled by its own fixed-point scale and summed in FP64
+// in chunk order, then the DFT to the S centred modes and the deconvolution
+// 1/Psi.  For M a
 // power of two the DFT is an in-place radix-2 FFT in LDS (grid points stored
 // at bit-reversed positions), otherwise a direct sum with exact-index
 // twiddles.  A non-finite amplitude makes the row NaN, as the direct sum would.
@@ -846,28 +858,37 @@ __global__ __launch_bounds__(256) void k_nu_synth_rows(const SynthArgs *__restri
         sincospi(2.0 * k / M, &sn, &cs);
         tw[k] = make_double2(cs, sn);
     }
-    const uint32_t ab = *gmem(a.amax);
-    const double inv = 1.0 / (double)nu_scale(ab);
+    __shared__ double inv_s[kNuMaxChunks];   // 1 / scale of each chunk
+    __shared__ int bad_s;
+    if (threadIdx.x == 0) bad_s = 0;
+    __syncthreads();
+    for (int ch = threadIdx.x; ch < a.n_chunks; ch += blockDim.x) {
+        const uint32_t ab = gmem(a.amax)[ch];
+        inv_s[ch] = 1.0 / (double)nu_scale(ab);
+        if (ab >= 0x7f800000u) bad_s = 1;
+    }
+    __syncthreads();
     const size_t chunk_stride = (size_t)a.V * a.C * RL * 2;
     const bool pow2 = (M & (M - 1)) == 0;
     const int lg = 31 - __clz(M);
     for (int l = threadIdx.x; l < M; l += blockDim.x) {
         const int j1 = (l + M / 2 + kNuHalf) % M;
         const bool wrap = j1 + M < RL - 1;
-        long long re = 0, im = 0;
+        double re = 0.0, im = 0.0;
         const long long *src = a.grid + row * RL * 2;   // real row, then imaginary row
         for (int ch = 0; ch < a.n_chunks; ch++, src += chunk_stride) {
-            re += src[j1];
-            im += src[RL + j1];
+            long long cr = src[j1], ci = src[RL + j1];
             if (wrap) {
-                re += src[j1 + M];
-                im += src[RL + j1 + M];
+                cr += src[j1 + M];
+                ci += src[RL + j1 + M];
             }
+            re = fma((double)cr, inv_s[ch], re);   // exact products (power-of-two scales)
+            im = fma((double)ci, inv_s[ch], im);
         }
-        b[pow2 ? (int)(__brev((uint32_t)l) >> (32 - lg)) : l] = make_double2((double)re * inv, (double)im * inv);
+        b[pow2 ? (int)(__brev((uint32_t)l) >> (32 - lg)) : l] = make_double2(re, im);
     }
     __syncthreads();
-    const bool bad = ab >= 0x7f800000u;
+    const bool bad = bad_s != 0;
     const auto corr = gmem(a.corr);
     if (pow2) {
         // X[k] = sum_l b_l e^{2 pi j k l / M}, decimation in time
@@ -968,7 +989,7 @@ static SynthPlan nu_plan(int32_t R, int32_t K, int32_t V, int32_t C, int32_t S) 
     const long long ncg = (C + p.cg - 1) / p.cg;
     const long long cap = (long long)R * K;
     const long long want = (768 + (long long)V * ncg - 1) / ((long long)V * ncg);
-    p.n_chunks = (int32_t)std::max(1LL, std::min({want, (cap + 8191) / 8192, 256LL}));
+    p.n_chunks = (int32_t)std::max(1LL, std::min({want, (cap + 8191) / 8192, (long long)kNuMaxChunks}));
     return p;
 }
 
@@ -1111,7 +1132,7 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
     // words cleared, amplitude bounds, 1/Psi tables, spreading, row transforms
     std::vector<int32_t> nidx, nfirst(1, 0), rfirst(1, 0);
     size_t lds_spread = 0, lds_rows = 0;
-    int max_s = 0;
+    int max_s = 0, max_chunks = 1;
     for (int i = 0; i < n; i++) {
         const SynthArgs &a = args[i];
         if (!a.nu) continue;
@@ -1130,6 +1151,7 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
         lds_spread = std::max(lds_spread, (size_t)a.cg * (nu_row_len(a.S) + 1) * 8);
         lds_rows = std::max(lds_rows, (size_t)2 * 2 * a.S * sizeof(double2));
         max_s = std::max(max_s, (int)a.S);
+        max_chunks = std::max(max_chunks, (int)a.n_chunks);
     }
     if (!nidx.empty()) {
         const int m = (int)nidx.size();
@@ -1137,8 +1159,9 @@ int launch_synth_batch(const SynthArgs *args, const int *L, int n, void *table, 
         if ((rc = put_table(t.nfirst, nfirst.data(), sizeof(int32_t) * (m + 1), s))) return rc;
         if ((rc = put_table(t.rfirst, rfirst.data(), sizeof(int32_t) * (m + 1), s))) return rc;
         ProfScope ps(kProfSynth, s);
-        hipLaunchKernelGGL(k_nu_zero, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, t.args, t.nidx, m);
-        hipLaunchKernelGGL(k_nu_amax, dim3(256, (unsigned)m), dim3(256), 0, s, t.args, t.nidx);
+        hipLaunchKernelGGL(k_nu_zero, dim3((unsigned)m), dim3(256), 0, s, t.args, t.nidx);
+        hipLaunchKernelGGL(k_nu_amax, dim3((unsigned)(kNuAmaxSub * max_chunks), (unsigned)m), dim3(256), 0, s,
+                           t.args, t.nidx);
         hipLaunchKernelGGL(k_nu_corr_batch, dim3((unsigned)((max_s + 255) / 256), (unsigned)m), dim3(256), 0, s,
                            t.args, t.nidx);
         SBR_LAUNCHED();
