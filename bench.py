@@ -305,7 +305,8 @@ def main():
         from paper_2311_13182_amd.serve import serving_benchmark
         sv = serving_benchmark(n=args.serving_requests, phases=(("main", 1.25), ("low", 0.5)), quiet=True)
         m = sv["main"]
-        out["serving"] = {"requests": args.serving_requests, "qps": round(m["qps"], 2),
+        out["serving"] = {"requests": args.serving_requests, "collect_workers": sv["collect_workers"],
+                          "qps": round(m["qps"], 2),
                           "throughput_rps": round(m["server"]["throughput_rps"], 2),
                           "p50_latency_ms": round(m["server"]["p50_latency_ms"], 1),
                           "p99_latency_ms": round(m["server"]["p99_latency_ms"], 1),

@@ -78,13 +78,20 @@ class Scheduler:
     """Admission + continuous batching over an executor.  Thread-safe submit."""
 
     def __init__(self, executor, budget_bytes: int, max_active: int = 16, clock=time.perf_counter,
-                 request_timeout: Optional[float] = None, max_batch: Optional[int] = None):
+                 request_timeout: Optional[float] = None, max_batch: Optional[int] = None,
+                 collect_workers: int = 0):
         """request_timeout: seconds a request may stay active (admitted, not
         finished) before it is failed and its resources released; None waits
         for ever.  max_batch: most requests per batched launch; the requests
         admitted in one tick are launched in groups of at most that many
         (None: one group), so the host prepares one group while the device
-        runs the previous one."""
+        runs the previous one.  collect_workers: threads that copy finished
+        requests' results out of the executor's host buffers (0: the
+        scheduler thread copies them itself).  The copy into fresh client
+        memory costs about as much host time as a launch, and NumPy drops the
+        GIL while it runs, so with workers it overlaps the next launches; the
+        scheduler thread still releases each request and settles its budget
+        and future once its copy is done."""
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
@@ -102,6 +109,9 @@ class Scheduler:
         self._stop = threading.Event()
         self._thread: Optional[threading.Thread] = None
         self.log: List[Result] = []
+        self._collector = (concurrent.futures.ThreadPoolExecutor(int(collect_workers),
+                                                                thread_name_prefix="sbr-collect")
+                           if collect_workers > 0 else None)
 
     def now(self) -> float:
         return self.clock() - self.t0
@@ -119,7 +129,15 @@ class Scheduler:
         progressed = False
         still = []
         for item in self._active:
-            req, fut, h, fp, t_admit = item
+            req, fut, h, fp, t_admit, cf = item
+            if cf is not None:   # results being copied out by a worker
+                if cf.done():
+                    err = cf.exception()
+                    self._finish(req, fut, h, fp, t_admit, None if err is not None else cf.result(), err)
+                    progressed = True
+                else:
+                    still.append(item)
+                continue
             try:
                 done = self.ex.poll(h)
             except Exception as e:   # device-side failure of this request only
@@ -131,7 +149,10 @@ class Scheduler:
                              TimeoutError(f"request {req.rid} active for more than {self.request_timeout} s"))
                 progressed = True
                 continue
-            if done:
+            if done and self._collector is not None:
+                still.append((req, fut, h, fp, t_admit, self._collector.submit(self.ex.collect, h)))
+                progressed = True
+            elif done:
                 try:
                     out = self.ex.collect(h)
                     self._finish(req, fut, h, fp, t_admit, out, None)
@@ -218,7 +239,7 @@ class Scheduler:
             try:
                 hs = batch([a[0] for a in admitted])
                 for (req, fut, fp), h in zip(admitted, hs):
-                    self._active.append((req, fut, h, fp, t_admit))
+                    self._active.append((req, fut, h, fp, t_admit, None))
                 return
             except Exception as e:   # fall back to single launches below
                 self.batch_fallbacks.append(repr(e))
@@ -228,7 +249,7 @@ class Scheduler:
             except Exception as e:
                 self._fail_launch(req, fut, fp, t_admit, e)
                 continue
-            self._active.append((req, fut, h, fp, t_admit))
+            self._active.append((req, fut, h, fp, t_admit, None))
 
     def _finish(self, req, fut, h, fp, t_admit, out, err):
         try:
@@ -271,10 +292,16 @@ class Scheduler:
         self._stop.set()
         if self._thread:
             self._thread.join()
-        # anything left is failed explicitly (never silently dropped)
-        for req, fut, h, fp, t_admit in self._active:
+        # anything left is failed explicitly (never silently dropped), after
+        # any copy of its results still reading the executor's buffers
+        for req, fut, h, fp, t_admit, cf in self._active:
+            if cf is not None:
+                concurrent.futures.wait([cf])
             self._finish(req, fut, h, fp, t_admit, None, RuntimeError("scheduler stopped"))
         self._active = []
+        if self._collector is not None:
+            self._collector.shutdown(wait=True)
+            self._collector = None
         with self._lock:
             while self._pending:
                 req, fut = self._pending.popleft()
@@ -574,12 +601,14 @@ def _batch_stats(sizes: List[int]) -> Dict[str, float]:
 
 def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_streams: int = 4,
                       max_active: int = 16, grids=(256, 512, 1024, 2048), nf_range=(1000, 200000),
-                      phases=(("main", 1.25), ("low", 0.5)), quiet: bool = False, burst: int = 128):
+                      phases=(("main", 1.25), ("low", 0.5)), quiet: bool = False, burst: int = 128,
+                      collect_workers: int = 2):
     """Sequential FIFO solves vs the continuous-batching server on the same
     Poisson request stream (QPS = 1.25 x the measured sequential rate), with
     the server's batch sizes; then a burst of `burst` small forward requests
     that all arrive at once (256^2 rays, 1k-20k triangles, 32 chirps), where
-    admitted requests share batched launches of up to 16."""
+    admitted requests share batched launches of up to 16.  The server copies
+    results out on `collect_workers` threads."""
     import sys
     import torch
 
@@ -608,7 +637,7 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
     seq_wall = time.perf_counter() - t0
     mu = n / seq_wall
     say(f"sequential service rate {mu:.2f} req/s")
-    out = {"mu_seq_rps": mu, "n_backward": sum(r.backward for r in reqs)}
+    out = {"mu_seq_rps": mu, "n_backward": sum(r.backward for r in reqs), "collect_workers": collect_workers}
     for tag, factor in phases:
         qps = factor * mu
         rng = np.random.default_rng(seed + 1)
@@ -616,7 +645,7 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
         timed = [Request(r.rid, r.scene, r.backward, r.target, float(a)) for r, a in zip(reqs, arr)]
         seq = run_sequential(ex, timed)
         seq_w = max(r.t_done for r in seq)
-        sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active=max_active)
+        sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active=max_active, collect_workers=collect_workers)
         futs = [sch.submit(r) for r in timed]
         ex.batch_sizes.clear()
         sch.t0 = time.perf_counter()
@@ -643,7 +672,8 @@ def serving_benchmark(n: int = 512, seed: int = 5, budget_gb: float = 64.0, n_st
         for _ in range(3):
             seq = run_sequential(ex, reqs_b)
             runs["sequential"].append(summarize(seq, max(r.t_done for r in seq)))
-            sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active=burst, max_batch=16)
+            sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active=burst, max_batch=16,
+                            collect_workers=collect_workers)
             ex.batch_sizes.clear()
             sch.t0 = time.perf_counter()   # every request arrives at time 0
             futs = [sch.submit(Request(r.rid, r.scene, False, None, 1e-9)) for r in reqs_b]
@@ -666,9 +696,11 @@ def main(argv=None):
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--collect-workers", type=int, default=2)
     args = ap.parse_args(argv)
     print(json.dumps(serving_benchmark(args.requests, n_streams=args.streams, max_active=args.max_active,
-                                       budget_gb=args.budget_gb)), flush=True)
+                                       budget_gb=args.budget_gb, collect_workers=args.collect_workers)),
+          flush=True)
 
 
 if __name__ == "__main__":

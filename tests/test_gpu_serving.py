@@ -202,10 +202,11 @@ def _small_requests(n=10, seed=77):
 
 
 def test_served_results_equal_alone_and_oracle(torch_cuda, orc):
-    """Every served cube equals the alone run bit for bit and the oracle
-    (its own trace, union of both sides' flags) within 1e-4; every served
-    gradient equals the alone run within 1e-5 and the oracle's central
-    differences along two random directions within 1e-2."""
+    """Served with results copied out on worker threads: every served cube
+    equals the alone run bit for bit and the oracle (its own trace, union of
+    both sides' flags) within 1e-4; every served gradient equals the alone
+    run within 1e-5 and the oracle's central differences along two random
+    directions within 1e-2."""
     torch = torch_cuda
     from paper_2311_13182_amd.serve import GPUExecutor, Request, Scheduler, run_sequential
     reqs = _small_requests()
@@ -220,7 +221,7 @@ def test_served_results_equal_alone_and_oracle(torch_cuda, orc):
     ex = GPUExecutor(n_streams=3, extra_flags=lambda q: otr[q.rid]["flags"], return_hits=True)
     plain = [Request(r.rid, r.scene, r.backward, r.target, 0.0) for r in reqs]
     alone = run_sequential(ex, plain)
-    sch = Scheduler(ex, budget_bytes=8 << 30, max_active=6)
+    sch = Scheduler(ex, budget_bytes=8 << 30, max_active=6, collect_workers=2)   # copies on worker threads
     sch.start()
     futs = [sch.submit(Request(r.rid, r.scene, r.backward, r.target, 0.0)) for r in reqs]
     mix = [f.result(timeout=300) for f in futs]

@@ -298,3 +298,71 @@ def test_admissions_of_one_tick_are_launched_in_groups_of_max_batch():
     _run(sch, clock, 0.2)
     assert all(f.result().status == "ok" for f in futs)
     assert ex.batches == [[0, 1, 2, 3], [4, 5, 6, 7], [8, 9]]
+
+
+class SlowCollectExecutor(BatchExecutor):
+    """BatchExecutor whose collect takes wall time, may fail (.fail_collect),
+    and records the thread it ran on and whether a handle was released while
+    its collect was still running."""
+
+    def __init__(self, clock, collect_s=0.003):
+        super().__init__(clock)
+        import threading
+        self.collect_s = collect_s
+        self.threads = set()
+        self.in_collect = set()
+        self.released_early = []
+        self.lock = threading.Lock()
+
+    def collect(self, h):
+        import threading
+        import time
+        with self.lock:
+            self.threads.add(threading.current_thread().name)
+            self.in_collect.add(id(h))
+        try:
+            time.sleep(self.collect_s)
+            if getattr(h.req.scene, "fail_collect", False):
+                raise RuntimeError("copy failed (forced)")
+            return FakeExecutor.collect(self, h)
+        finally:
+            with self.lock:
+                self.in_collect.discard(id(h))
+
+    def release(self, h):
+        with self.lock:
+            if id(h) in self.in_collect:
+                self.released_early.append(h.req.rid)
+        FakeExecutor.release(self, h)
+
+
+def test_collect_workers_copy_results_off_the_scheduler_thread():
+    import time
+    ex = SlowCollectExecutor(time.perf_counter)
+    sch = Scheduler(ex, budget_bytes=10 ** 6, max_active=16, max_batch=4, collect_workers=2)
+    sch.start()
+    futs = [sch.submit(_req(i, 100, 0.001, fail_collect=(i == 5))) for i in range(24)]
+    res = [f.result(timeout=10) for f in futs]
+    sch.stop()
+    assert [r.rid for r in res] == list(range(24))
+    assert [r.status for r in res] == ["failed" if i == 5 else "ok" for i in range(24)]
+    assert "copy failed" in res[5].error
+    assert all(r.cube == ("cube", r.rid) and r.n_paths == r.rid for r in res if r.status == "ok")
+    assert ex.threads and all(t.startswith("sbr-collect") for t in ex.threads)
+    assert ex.released_early == [] and not ex.live and sch.used_bytes == 0
+
+
+def test_stop_waits_for_copies_in_flight():
+    import time
+    ex = SlowCollectExecutor(time.perf_counter, collect_s=0.2)
+    sch = Scheduler(ex, budget_bytes=10 ** 6, max_active=4, collect_workers=1)
+    futs = [sch.submit(_req(i, 100, 0.0)) for i in range(2)]
+    sch.tick()                 # admit and launch both
+    time.sleep(0.001)
+    sch.tick()                 # both done on the device: their copies start
+    assert len(sch._active) == 2 and all(item[5] is not None for item in sch._active)
+    sch.stop(drain=False)
+    res = [f.result(timeout=10) for f in futs]
+    assert [r.status for r in res] == ["failed", "failed"]
+    assert all("scheduler stopped" in r.error for r in res)
+    assert ex.released_early == [] and not ex.live and sch.used_bytes == 0
