@@ -1,4 +1,5 @@
-"""Build libsbr.so (all HIP sources, gfx950) in-tree with hipcc."""
+"""Build libsbr.so (all HIP sources, gfx950) in-tree with hipcc, and the
+standalone LDS rate probe (csrc/probe, not part of the library)."""
 from __future__ import annotations
 
 import glob
@@ -9,6 +10,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libsbr.so")
+PROBE = os.path.join(PKG, "lds_rate_probe")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -35,7 +37,23 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The executable that measures LDS atomic and store rates (random and
+    conflict-free addresses) at the kernel's own clock."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = PROBE + ".tmp"
+    cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-munsafe-fp-atomics",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
+           "-o", tmp, os.path.join(PKG, "csrc", "probe", "lds_rate.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":
