@@ -69,6 +69,25 @@ def measured_traffic(kernel: str, workload: str):
     return float(kv["traffic_bytes"])
 
 
+LDS_RATE_FILE = os.path.join(ROOT, "profiles", "lds_rate__probe_512x1024.md")
+
+
+def measured_lds_atomic_peak():
+    """LDS bandwidth of 64-bit atomic adds at conflict-free addresses, in GB/s at
+    2.4 GHz on 256 CUs (the basis of the nominal LDS peak): the rate the
+    committed LDS probe summary gives for "ds_add_u64 linear", in lanes per clock
+    per CU times 8 bytes; None when the summary is missing."""
+    import re
+    if not os.path.exists(LDS_RATE_FILE):
+        return None
+    for line in open(LDS_RATE_FILE):
+        if line.startswith("ds_add_u64 linear"):
+            m = re.search(r"([0-9.]+) lanes/clk/CU", line)
+            if m:
+                return float(m.group(1)) * 8 * 256 * 2.4
+    return None
+
+
 def make_workload(name: str):
     from paper_2311_13182_amd import scenes as S
     if name == "clutter_50k":
@@ -237,6 +256,12 @@ def main():
         roof = {"bound": "lds", "kernel": "k_nu_spread", "achieved": round(achieved, 1), "peak": PEAK_LDS_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_LDS_GBS, 4),
                 "traffic": measured_traffic("k_nu_spread", args.workload)}
+        # beside it, the rate 64-bit LDS atomic adds reach at all (the LDS probe,
+        # conflict-free addresses)
+        ceil = measured_lds_atomic_peak()
+        roof["atomic_ceiling"] = None if ceil is None else {
+            "peak": round(ceil, 1), "frac": round(achieved / ceil, 4),
+            "source": "LDS probe, ds_add_u64 at conflict-free addresses"}
     else:
         dominant = max(("synth", "synth_adj"), key=lambda k: k_ms[k])
         achieved = FLOP_PER_PATH_SAMPLE[dominant] * ps / (k_ms[dominant] * 1e-3) / 1e12
